@@ -1,0 +1,202 @@
+/*
+ * slm.h -- C ABI of the MI355X (gfx950) implementation of the Synchronised
+ * Louvain Method (Chiem, Havelange & Van Dooren, arXiv 1702.04645).
+ *
+ * The method (Algorithm 1 of the paper) works level by level on a weighted
+ * graph G_t: ASSIGN (Sec. 3.1) points every node at its best neighbour,
+ * COMPONENTS (Sec. 3.2) takes the weakly connected components of that
+ * assignment graph as communities, POSITIVE (Sec. 3.3) splits communities
+ * holding nodes of negative local gain by their best bisection, MAXIMAL
+ * (Sec. 3.4) moves nodes -- with their tails -- to their best neighbouring
+ * community, all at once, and AGGREGATE (Sec. 3.5) contracts communities
+ * into the nodes of the next level.  The objective is the weighted
+ * modularity Q_w of Sec. 2.4.
+ *
+ * Graph convention.  The input is an undirected graph given as a symmetric
+ * CSR matrix A: positive int32 weights, columns strictly ascending in every
+ * row, the diagonal A_ii stored once.  k_i = sum_j A_ij (diagonal included),
+ * M2 = sum_i k_i (the m_w of Sec. 2.4 for a symmetric matrix).  M2 must be
+ * below 2^31; every gain is then an exact int64 integer:
+ *   pair(i,j) = M2*A_ij - k_i*k_j            join(i,C) = M2*w(i,C) - k_i*S_C
+ *   stay(i)   = M2*w(i,c_i\i) - k_i*(S_ci - k_i)
+ *   move(B: c->D) = M2*(w(B,D) - w(B,c\B)) - S_B*(S_D - S_c + S_B)
+ *   split(P1,P2)  = S_P1*S_P2 - M2*w(P1,P2)
+ * (S_X = sum of k over X, w(X,Y) = sum of A_uv over u in X, v in Y).  Ties
+ * go to the lowest node id, the lowest community label, the lowest
+ * (first, second) cut node.  Communities carry canonical labels: numbered
+ * 0..n_c-1 in increasing order of their smallest member.
+ *
+ * Memory.  Pointers named *_dev are device pointers (HBM of the current HIP
+ * device), owned by the caller; everything else is host memory.  The handle
+ * owns its device copy of the graph and its work space (allocated with
+ * hipMalloc at creation, released by slm_destroy).
+ *
+ * Streams.  All device work of a handle runs on the stream given at
+ * creation (NULL = the default stream).  Calls that return a device result
+ * are stream-ordered; calls that return host values synchronise the stream.
+ * A handle is used by one thread at a time; distinct handles are
+ * independent.
+ *
+ * Errors.  Every call returns slm_status; slm_last_error() gives a message
+ * for the calling thread's last failure.  SLM_E_INVALID leaves the handle
+ * unchanged.
+ */
+#ifndef SLM_H
+#define SLM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SLM_OK = 0,
+    SLM_E_INVALID = 1,  /* bad argument or CSR (asymmetric, unsorted, weight < 1, ...) */
+    SLM_E_OVERFLOW = 2, /* M2 >= 2^31 or n >= 2^31                                     */
+    SLM_E_NOMEM = 3,    /* device or host allocation failed                            */
+    SLM_E_DEVICE = 4,   /* a HIP call failed                                           */
+    SLM_E_STATE = 5     /* call out of order (e.g. contracting to as many nodes)       */
+} slm_status;
+
+typedef struct slm_graph slm_graph;
+typedef struct slm_result slm_result;
+
+/* Parameters of a run.
+ *   seed       stream of the acceptance draws (Sec. 3.4); a draw is the high
+ *              half of SplitMix64 output number (level<<48 | round<<32 | node)+1
+ *   accept_p   Q32 acceptance threshold: a valid move is accepted iff its
+ *              draw < accept_p (2^31 = probability 1/2, 2^32 = always)
+ *   max_rounds cap on MAXIMAL rounds per level (the loop of Algorithm 1 ends
+ *              earlier when no move is valid)
+ *   max_levels cap on emitted levels, 0 = no cap
+ *   validate   1 = check the CSR (symmetry, sorted unique columns, weights)
+ *              at slm_create */
+typedef struct {
+    uint64_t seed;
+    uint64_t accept_p;
+    int32_t max_rounds;
+    int32_t max_levels;
+    int32_t validate;
+    int32_t reserved;
+} slm_params;
+
+/* Defaults: seed 0, accept_p 2^31, max_rounds 64, max_levels 0, validate 1. */
+void slm_params_default(slm_params *p);
+
+/* Creates a handle holding a device copy of the level-0 graph.
+ *   row_ptr        n+1 offsets, int32 (row_ptr_bytes = 4) or int64 (8)
+ *   col, w         nnz columns and weights
+ *   inputs_on_device  0: the three arrays are host memory; 1: device memory
+ *   validate       1: check symmetry, sorted unique columns, weights >= 1
+ *   hip_stream     hipStream_t for all device work (NULL = default stream)
+ * The inputs are copied; the caller keeps ownership.  Errors: SLM_E_INVALID,
+ * SLM_E_OVERFLOW (M2 or n too large), SLM_E_NOMEM, SLM_E_DEVICE. */
+slm_status slm_create(int64_t n, int64_t nnz, const void *row_ptr, int row_ptr_bytes,
+                      const int32_t *col, const int32_t *w, int inputs_on_device,
+                      int validate, void *hip_stream, slm_graph **out);
+
+void slm_destroy(slm_graph *g);
+
+/* Current level index, its node and entry counts, and M2 (the same at
+ * every level, Sec. 3.5). */
+slm_status slm_level_info(const slm_graph *g, int32_t *level, int64_t *n_t,
+                          int64_t *nnz_t, int64_t *m2);
+
+/* Drops every contracted level: the handle is back at level 0. */
+slm_status slm_reset(slm_graph *g);
+
+/* Copies the current level's CSR to host arrays (row_ptr int64[n_t+1],
+ * col and w int32[nnz_t]); synchronises. */
+slm_status slm_export_level(slm_graph *g, int64_t *row_ptr, int32_t *col, int32_t *w);
+
+/* ASSIGN (Sec. 3.1): a_dev[i] = the neighbour j != i of largest pair(i,j)
+ * (ties to the lowest j) when that pair is positive, else i.
+ * a_dev: n_t entries. */
+slm_status slm_assign(slm_graph *g, int32_t *a_dev);
+
+/* COMPONENTS (Sec. 3.2): canonical labels of the weakly connected
+ * components of {(i, a(i))}; optional cycle flags (1 = on the cycle of its
+ * component).  Writes lab_dev (n_t), on_cycle_dev (n_t bytes, may be NULL)
+ * and the community count (host; synchronises). */
+slm_status slm_components(slm_graph *g, const int32_t *a_dev, int32_t *lab_dev,
+                          uint8_t *on_cycle_dev, int64_t *n_c);
+
+/* POSITIVE (Sec. 3.3): while a community holds a node of negative local
+ * gain g(i) = stay(i), apply its best bisection of the assignment graph --
+ * the self-assignment of one non-cycle node (its subtree splits off) or of
+ * two cycle nodes (the cycle splits in two arcs) -- with the largest split
+ * key, ties to the lowest (first, second) cut node.  Modifies a_dev in
+ * place; *splits (host, may be NULL) = splits applied.  Synchronises. */
+slm_status slm_positive(slm_graph *g, int32_t *a_dev, int64_t *splits);
+
+/* MAXIMAL sweep (Sec. 3.4, first loop of the appendix MAXIMAL): for every
+ * node at once, from the labelling lab_dev (canonical, n_c communities):
+ *   best_c_dev[i] = argmax over neighbouring communities C != c_i of
+ *                   join(i,C) (ties to the lowest C) if that beats stay(i),
+ *                   else c_i
+ *   delta_dev[i]  = join - stay for a move, else 0
+ *   w_own_dev[i]  = w(i, c_i \ i)
+ * No state of the handle changes.  Stream-ordered. */
+slm_status slm_sweep(slm_graph *g, const int32_t *lab_dev, int64_t n_c, int32_t *best_c_dev,
+                     int64_t *delta_dev, int32_t *w_own_dev);
+
+/* One MAXIMAL round followed by POSITIVE (the body of the inner loop of
+ * Algorithm 1) on the assignment a_dev (modified in place).  A node whose
+ * best community differs is valid iff moving its tail -- the node and every
+ * node with a path to it, the whole community for a cycle node -- has
+ * move > 0; a valid node is accepted iff draw(seed, level, round, node) <
+ * accept_p and then points at its best neighbour (largest pair, ties to the
+ * lowest id) inside the target community.  All moves use the state before
+ * the round.  stats (host, 4 entries, may be NULL): candidates, valid,
+ * accepted, splits.  With no valid node nothing changes.  Synchronises. */
+slm_status slm_round(slm_graph *g, const slm_params *p, int32_t level, int32_t round,
+                     int32_t *a_dev, int64_t *stats);
+
+/* One level: ASSIGN, COMPONENTS, POSITIVE, then rounds until none is valid
+ * or max_rounds.  Writes the canonical labels (lab_dev, n_t entries) and
+ * host values n_c, rounds, converged.  Synchronises. */
+slm_status slm_level(slm_graph *g, const slm_params *p, int32_t level, int32_t *lab_dev,
+                     int64_t *n_c, int32_t *rounds, int32_t *converged);
+
+/* Modularity (Sec. 2.4) of a labelling of the current level:
+ * N_Q = M2 * sum_C w(C,C) - sum_C S_C^2 (exact) and Q = N_Q / M2 / M2
+ * (IEEE double, computed on the host).  Synchronises. */
+slm_status slm_modularity(slm_graph *g, const int32_t *lab_dev, int64_t n_c, int64_t *nq,
+                          double *q);
+
+/* AGGREGATE (Sec. 3.5): replaces the current level by its contraction,
+ * A'_CD = sum of A_uv over u in C, v in D (diagonal included), rows sorted
+ * by column.  SLM_E_STATE when n_c == n_t.  Synchronises. */
+slm_status slm_contract(slm_graph *g, const int32_t *lab_dev, int64_t n_c);
+
+/* Full run of Algorithm 1 from level 0 (the handle is reset first): levels
+ * until a level's partition is the identity (not emitted) or max_levels.
+ * The result holds, per emitted level, the labels composed onto the
+ * original nodes, n_c, N_Q, Q, rounds and the converged flag. */
+slm_status slm_run(slm_graph *g, const slm_params *p, slm_result **out);
+
+slm_status slm_result_num_levels(const slm_result *r, int32_t *levels);
+/* labels: n_0 entries owned by the result. */
+slm_status slm_result_level(const slm_result *r, int32_t level, int64_t *n_c,
+                            const int32_t **labels, int64_t *nq, double *q,
+                            int32_t *rounds, int32_t *converged);
+void slm_result_free(slm_result *r);
+
+/* Sweep timing: when enabled, every sweep records HIP events on the
+ * handle's stream around its kernels.  slm_timing_read reports the summed
+ * sweep time (ms), the number of sweeps, the CSR entries they read, and the
+ * algorithmic bytes they moved (8 per entry, 32 per node, 4 per community),
+ * then clears the counters.  Synchronises. */
+slm_status slm_timing_enable(slm_graph *g, int enable);
+slm_status slm_timing_read(slm_graph *g, double *sweep_ms, int64_t *sweeps,
+                           int64_t *entries, int64_t *bytes);
+
+/* Message of the calling thread's last failed call. */
+const char *slm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SLM_H */

@@ -1,0 +1,295 @@
+"""Python binding of libslm.so, the gfx950 implementation of the Synchronised
+Louvain Method (Chiem, Havelange & Van Dooren, arXiv 1702.04645).
+
+Argument marshalling only: every step runs in the HIP kernels behind the C
+ABI declared in include/slm.h.  PyTorch provides device memory (outputs are
+torch CUDA tensors) and the stream (the current torch stream when the graph
+is created).  The library must have been built (``python -m
+paper_1702_04645_amd.build``); importing this module fails loudly when it is
+missing.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libslm.so")
+
+SLM_OK, SLM_E_INVALID, SLM_E_OVERFLOW, SLM_E_NOMEM, SLM_E_DEVICE, SLM_E_STATE = range(6)
+_STATUS = {1: "SLM_E_INVALID", 2: "SLM_E_OVERFLOW", 3: "SLM_E_NOMEM", 4: "SLM_E_DEVICE",
+           5: "SLM_E_STATE"}
+
+
+class SlmError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__("%s: %s" % (_STATUS.get(status, status), msg))
+        self.status = status
+
+
+class Params(C.Structure):
+    """slm_params: seed, accept_p (Q32), max_rounds, max_levels, validate."""
+    _fields_ = [("seed", C.c_uint64), ("accept_p", C.c_uint64), ("max_rounds", C.c_int32),
+                ("max_levels", C.c_int32), ("validate", C.c_int32), ("reserved", C.c_int32)]
+
+
+def params(seed: int = 0, accept_p: int = 1 << 31, max_rounds: int = 64, max_levels: int = 0,
+           validate: int = 1) -> Params:
+    return Params(seed & (2**64 - 1), accept_p, max_rounds, max_levels, validate, 0)
+
+
+_lib = None
+
+
+def lib():
+    """The loaded libslm.so (raises when it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libslm.so is not built; run python -m paper_1702_04645_amd.build")
+    L = C.CDLL(LIB_PATH)
+    P, i32, i64, st = C.c_void_p, C.c_int32, C.c_int64, C.c_int
+    pi32, pi64 = C.POINTER(C.c_int32), C.POINTER(C.c_int64)
+    sigs = {
+        "slm_params_default": (None, [C.POINTER(Params)]),
+        "slm_create": (st, [i64, i64, P, C.c_int, P, P, C.c_int, C.c_int, P, C.POINTER(P)]),
+        "slm_destroy": (None, [P]),
+        "slm_level_info": (st, [P, pi32, pi64, pi64, pi64]),
+        "slm_reset": (st, [P]),
+        "slm_export_level": (st, [P, P, P, P]),
+        "slm_assign": (st, [P, P]),
+        "slm_components": (st, [P, P, P, P, pi64]),
+        "slm_positive": (st, [P, P, pi64]),
+        "slm_sweep": (st, [P, P, i64, P, P, P]),
+        "slm_round": (st, [P, C.POINTER(Params), i32, i32, P, pi64]),
+        "slm_level": (st, [P, C.POINTER(Params), i32, P, pi64, pi32, pi32]),
+        "slm_modularity": (st, [P, P, i64, pi64, C.POINTER(C.c_double)]),
+        "slm_contract": (st, [P, P, i64]),
+        "slm_run": (st, [P, C.POINTER(Params), C.POINTER(P)]),
+        "slm_result_num_levels": (st, [P, pi32]),
+        "slm_result_level": (st, [P, i32, pi64, C.POINTER(C.POINTER(C.c_int32)), pi64,
+                                  C.POINTER(C.c_double), pi32, pi32]),
+        "slm_result_free": (None, [P]),
+        "slm_timing_enable": (st, [P, C.c_int]),
+        "slm_timing_read": (st, [P, C.POINTER(C.c_double), pi64, pi64, pi64]),
+        "slm_last_error": (C.c_char_p, []),
+    }
+    for name, (res, args) in sigs.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = L
+    return L
+
+
+def exported_symbols():
+    return [n for n in lib().__dict__ if n.startswith("slm_")]
+
+
+def _check(status: int):
+    if status != SLM_OK:
+        raise SlmError(status, lib().slm_last_error().decode())
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _dev_i32(n: int):
+    torch = _torch()
+    return torch.empty(max(n, 1), dtype=torch.int32, device="cuda")
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr())
+
+
+@dataclass
+class LevelResult:
+    labels: np.ndarray
+    n_c: int
+    nq: int
+    q: float
+    rounds: int
+    converged: bool
+
+
+class Graph:
+    """A handle on a symmetric integer CSR graph resident in HBM.
+
+    ``row_ptr`` (int32 or int64), ``col`` and ``w`` (int32) are numpy arrays
+    (host) or torch CUDA tensors (device)."""
+
+    def __init__(self, row_ptr, col, w, validate: bool = True, stream=None):
+        torch = _torch()
+        self._h = C.c_void_p()
+        on_dev = isinstance(row_ptr, torch.Tensor) and row_ptr.is_cuda
+        if on_dev:
+            rp, cl, ww = row_ptr.contiguous(), col.contiguous().to(torch.int32), \
+                w.contiguous().to(torch.int32)
+            rp_bytes = rp.element_size()
+            n = rp.numel() - 1
+            nnz = cl.numel()
+            self._keep = (rp, cl, ww)
+            args = (_ptr(rp), _ptr(cl), _ptr(ww))
+        else:
+            rp = np.ascontiguousarray(row_ptr)
+            if rp.dtype not in (np.int32, np.int64):
+                rp = rp.astype(np.int64)
+            cl = np.ascontiguousarray(col, dtype=np.int32)
+            ww = np.ascontiguousarray(w, dtype=np.int32)
+            rp_bytes = rp.dtype.itemsize
+            n = rp.size - 1
+            nnz = cl.size
+            self._keep = (rp, cl, ww)
+            args = (rp.ctypes.data_as(C.c_void_p), cl.ctypes.data_as(C.c_void_p),
+                    ww.ctypes.data_as(C.c_void_p))
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        _check(lib().slm_create(n, nnz, args[0], rp_bytes, args[1], args[2], int(on_dev),
+                                int(validate), C.c_void_p(stream.cuda_stream), C.byref(self._h)))
+        self._keep = None
+        self.n0 = n
+        self.nnz0 = nnz
+
+    def close(self):
+        if self._h:
+            lib().slm_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # -------------------------------------------------------------- level state
+    def level_info(self):
+        lv, n, nnz, m2 = C.c_int32(), C.c_int64(), C.c_int64(), C.c_int64()
+        _check(lib().slm_level_info(self._h, C.byref(lv), C.byref(n), C.byref(nnz), C.byref(m2)))
+        return dict(level=lv.value, n=n.value, nnz=nnz.value, m2=m2.value)
+
+    def reset(self):
+        _check(lib().slm_reset(self._h))
+
+    def export_level(self):
+        info = self.level_info()
+        rp = np.zeros(info["n"] + 1, np.int64)
+        col = np.zeros(max(info["nnz"], 1), np.int32)
+        w = np.zeros(max(info["nnz"], 1), np.int32)
+        _check(lib().slm_export_level(self._h, rp.ctypes.data_as(C.c_void_p),
+                                      col.ctypes.data_as(C.c_void_p),
+                                      w.ctypes.data_as(C.c_void_p)))
+        return rp, col[: info["nnz"]], w[: info["nnz"]]
+
+    # -------------------------------------------------------------- steps
+    def assign(self):
+        n = self.level_info()["n"]
+        a = _dev_i32(n)
+        _check(lib().slm_assign(self._h, _ptr(a)))
+        return a[:n]
+
+    def components(self, a):
+        torch = _torch()
+        n = self.level_info()["n"]
+        a = a.to(torch.int32).contiguous()
+        lab = _dev_i32(n)
+        cyc = torch.empty(max(n, 1), dtype=torch.uint8, device="cuda")
+        nc = C.c_int64()
+        _check(lib().slm_components(self._h, _ptr(a), _ptr(lab), _ptr(cyc), C.byref(nc)))
+        return lab[:n], nc.value, cyc[:n]
+
+    def positive(self, a):
+        torch = _torch()
+        a = a.to(torch.int32).clone()
+        sp = C.c_int64()
+        _check(lib().slm_positive(self._h, _ptr(a), C.byref(sp)))
+        return a, sp.value
+
+    def sweep(self, lab, nc: int):
+        torch = _torch()
+        n = self.level_info()["n"]
+        lab = lab.to(torch.int32).contiguous()
+        best = _dev_i32(n)
+        delta = torch.empty(max(n, 1), dtype=torch.int64, device="cuda")
+        wown = _dev_i32(n)
+        _check(lib().slm_sweep(self._h, _ptr(lab), int(nc), _ptr(best), _ptr(delta), _ptr(wown)))
+        return best[:n], delta[:n], wown[:n]
+
+    def round(self, a, p: Params, level: int, rnd: int):
+        torch = _torch()
+        a = a.to(torch.int32).clone()
+        st = (C.c_int64 * 4)()
+        _check(lib().slm_round(self._h, C.byref(p), level, rnd, _ptr(a), st))
+        return a, dict(candidates=st[0], valid=st[1], accepted=st[2], splits=st[3])
+
+    def level(self, p: Params, level: int):
+        n = self.level_info()["n"]
+        lab = _dev_i32(n)
+        nc, r, cv = C.c_int64(), C.c_int32(), C.c_int32()
+        _check(lib().slm_level(self._h, C.byref(p), level, _ptr(lab), C.byref(nc), C.byref(r),
+                               C.byref(cv)))
+        return lab[:n], nc.value, r.value, bool(cv.value)
+
+    def modularity(self, lab, nc: int):
+        torch = _torch()
+        lab = lab.to(torch.int32).contiguous()
+        nq, q = C.c_int64(), C.c_double()
+        _check(lib().slm_modularity(self._h, _ptr(lab), int(nc), C.byref(nq), C.byref(q)))
+        return nq.value, q.value
+
+    def contract(self, lab, nc: int):
+        torch = _torch()
+        lab = lab.to(torch.int32).contiguous()
+        _check(lib().slm_contract(self._h, _ptr(lab), int(nc)))
+
+    def run(self, p: Params | None = None):
+        if p is None:
+            p = params()
+        res = C.c_void_p()
+        _check(lib().slm_run(self._h, C.byref(p), C.byref(res)))
+        try:
+            L = C.c_int32()
+            _check(lib().slm_result_num_levels(res, C.byref(L)))
+            out = []
+            for l in range(L.value):
+                nc, nq, q = C.c_int64(), C.c_int64(), C.c_double()
+                r, cv = C.c_int32(), C.c_int32()
+                labp = C.POINTER(C.c_int32)()
+                _check(lib().slm_result_level(res, l, C.byref(nc), C.byref(labp), C.byref(nq),
+                                              C.byref(q), C.byref(r), C.byref(cv)))
+                labels = np.ctypeslib.as_array(labp, shape=(self.n0,)).copy() if self.n0 else \
+                    np.zeros(0, np.int32)
+                out.append(LevelResult(labels, nc.value, nq.value, q.value, r.value,
+                                       bool(cv.value)))
+            return out
+        finally:
+            lib().slm_result_free(res)
+
+    # -------------------------------------------------------------- timing
+    def timing(self, enable: bool = True):
+        _check(lib().slm_timing_enable(self._h, int(enable)))
+
+    def timing_read(self):
+        ms, sw, en, by = C.c_double(), C.c_int64(), C.c_int64(), C.c_int64()
+        _check(lib().slm_timing_read(self._h, C.byref(ms), C.byref(sw), C.byref(en), C.byref(by)))
+        return dict(sweep_ms=ms.value, sweeps=sw.value, entries=en.value, bytes=by.value)
+
+
+def run(row_ptr, col, w, seed: int = 0, accept_p: int = 1 << 31, max_rounds: int = 64,
+        max_levels: int = 0):
+    """Full run of Algorithm 1 on the GPU; returns a list of LevelResult."""
+    with Graph(row_ptr, col, w) as g:
+        return g.run(params(seed, accept_p, max_rounds, max_levels))

@@ -1,0 +1,836 @@
+// C ABI of include/slm.h: handles, validation, level state, and the level
+// loop of Algorithm 1 (ASSIGN, COMPONENTS, POSITIVE, MAXIMAL rounds,
+// AGGREGATE) driving the kernels.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "slm.h"
+#include "slm_forest.h"
+
+static thread_local std::string g_err;
+
+struct slm_graph {
+    hipStream_t s = nullptr;
+    int device = 0;
+    i64 n0 = 0, nnz0 = 0, m2 = 0;
+    i64 *rp0 = nullptr;
+    int2 *e0 = nullptr;
+    i64 *rpL[2] = {nullptr, nullptr};
+    int2 *eL[2] = {nullptr, nullptr};
+    int cur = -1;  // -1: level 0 arrays, else rpL[cur] / eL[cur]
+    int level = 0;
+    i64 n = 0, nnz = 0;
+    Bins bins;
+    i64 *hub_span_h = nullptr;
+    Work W;
+    i32 *composed = nullptr;
+    bool timing = false;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    double sweep_ms = 0;
+    i64 sweeps = 0, entries = 0, bytes = 0;
+    std::vector<void *> allocs;
+};
+
+struct slm_result {
+    i64 n0 = 0;
+    std::vector<i64> nc, nq;
+    std::vector<double> q;
+    std::vector<i32> rounds, conv;
+    std::vector<std::vector<i32>> labels;
+};
+
+// ------------------------------------------------------------------ helpers
+template <typename T>
+static T *dalloc(slm_graph *g, i64 count)
+{
+    void *p = nullptr;
+    if (count < 1) count = 1;
+    hipError_t e = hipMalloc(&p, sizeof(T) * (size_t)count);
+    if (e != hipSuccess) throw SlmError{SLM_E_NOMEM, "device allocation failed"};
+    g->allocs.push_back(p);
+    return (T *)p;
+}
+
+static LevelView view(slm_graph *g)
+{
+    LevelView L;
+    L.rp = g->cur < 0 ? g->rp0 : g->rpL[g->cur];
+    L.e = g->cur < 0 ? g->e0 : g->eL[g->cur];
+    L.k = g->W.k;
+    L.diag = g->W.diag;
+    L.n = g->n;
+    L.nnz = g->nnz;
+    L.m2 = g->m2;
+    return L;
+}
+
+static void free_bins(slm_graph *g)
+{
+    Bins &B = g->bins;
+    for (void *p : {(void *)B.hub_tab_off, (void *)B.chunk_hub, (void *)B.chunk_beg,
+                    (void *)B.chunk_off_of_hub})
+        if (p) (void)hipFree(p);
+    B.hub_tab_off = nullptr;
+    B.chunk_hub = nullptr;
+    B.chunk_beg = nullptr;
+    B.chunk_off_of_hub = nullptr;
+    B.nhub = 0;
+    B.nchunk = 0;
+    B.table_total = 0;
+}
+
+static void grow_i32(i32 *&p, i64 &cap, i64 need)
+{
+    if (need <= cap) return;
+    if (p) HIPCHK(hipFree(p));
+    p = nullptr;
+    i64 c = need + need / 2 + 1024;
+    HIPCHK(hipMalloc(&p, sizeof(i32) * c));
+    cap = c;
+}
+
+// Degree bins, hub work lists, strengths and entry rows of the current level.
+static void setup_level(slm_graph *g)
+{
+    hipStream_t s = g->s;
+    Work &W = g->W;
+    Bins &B = g->bins;
+    free_bins(g);
+    const i64 n = g->n;
+    const i64 *rp = g->cur < 0 ? g->rp0 : g->rpL[g->cur];
+    const int2 *e = g->cur < 0 ? g->e0 : g->eL[g->cur];
+    for (int b = 0; b <= NBINS; b++) B.off[b] = 0;
+    if (n > 0) {
+        launch_fill_i64(W.counters, 0, NBINS, s);
+        launch_bin_count(rp, n, W.counters, s);
+        read_scalars(W, W.counters, NBINS, s);
+        for (int b = 0; b < NBINS; b++) B.off[b + 1] = B.off[b] + W.h_scal[b];
+        HIPCHK(hipMemcpyAsync(W.counters, B.off, sizeof(i64) * NBINS, hipMemcpyHostToDevice, s));
+        launch_bin_scatter(rp, n, W.counters, B.nodes, s);
+        const i64 nhub = B.off[BIN_HUB + 1] - B.off[BIN_HUB];
+        B.nhub = (i32)nhub;
+        B.hub_node = B.nodes + B.off[BIN_HUB];
+        if (nhub > 0) {
+            i64 *span_d = nullptr;
+            HIPCHK(hipMalloc(&span_d, sizeof(i64) * 2 * nhub));
+            launch_hub_degrees(rp, B.hub_node, (i32)nhub, span_d, s);
+            std::vector<i64> span(2 * nhub);
+            HIPCHK(hipMemcpyAsync(span.data(), span_d, sizeof(i64) * 2 * nhub,
+                                  hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+            HIPCHK(hipFree(span_d));
+            std::vector<i64> tab_off(nhub + 1, 0);
+            std::vector<i32> chunk_first(nhub + 1, 0);
+            std::vector<i32> chunk_hub;
+            std::vector<i64> chunk_beg;
+            for (i64 h = 0; h < nhub; h++) {
+                const i64 b0 = span[2 * h], b1 = span[2 * h + 1], deg = b1 - b0;
+                i64 t = 1;
+                while (t < 2 * deg) t <<= 1;
+                tab_off[h + 1] = tab_off[h] + t;
+                chunk_first[h] = (i32)chunk_hub.size();
+                for (i64 c = b0; c < b1; c += HUB_CHUNK) {
+                    chunk_hub.push_back((i32)h);
+                    chunk_beg.push_back(c);
+                }
+            }
+            chunk_first[nhub] = (i32)chunk_hub.size();
+            B.nchunk = (i64)chunk_hub.size();
+            B.table_total = tab_off[nhub];
+            HIPCHK(hipMalloc(&B.hub_tab_off, sizeof(i64) * (nhub + 1)));
+            HIPCHK(hipMalloc(&B.chunk_off_of_hub, sizeof(i32) * (nhub + 1)));
+            HIPCHK(hipMalloc(&B.chunk_hub, sizeof(i32) * B.nchunk));
+            HIPCHK(hipMalloc(&B.chunk_beg, sizeof(i64) * B.nchunk));
+            HIPCHK(hipMemcpyAsync(B.hub_tab_off, tab_off.data(), sizeof(i64) * (nhub + 1),
+                                  hipMemcpyHostToDevice, s));
+            HIPCHK(hipMemcpyAsync(B.chunk_off_of_hub, chunk_first.data(), sizeof(i32) * (nhub + 1),
+                                  hipMemcpyHostToDevice, s));
+            HIPCHK(hipMemcpyAsync(B.chunk_hub, chunk_hub.data(), sizeof(i32) * B.nchunk,
+                                  hipMemcpyHostToDevice, s));
+            HIPCHK(hipMemcpyAsync(B.chunk_beg, chunk_beg.data(), sizeof(i64) * B.nchunk,
+                                  hipMemcpyHostToDevice, s));
+            i64 cap_keys = W.hub_tab_cap;
+            grow_i32(W.hub_keys, cap_keys, B.table_total);
+            i64 cap_vals = W.hub_tab_cap;
+            grow_i32(W.hub_vals, cap_vals, B.table_total);
+            W.hub_tab_cap = cap_keys;
+            grow_i32(W.hub_win, W.hub_win_cap, nhub);
+            if (B.nchunk > W.hub_chunk_cap) {
+                if (W.hub_ckey) HIPCHK(hipFree(W.hub_ckey));
+                if (W.hub_cid) HIPCHK(hipFree(W.hub_cid));
+                W.hub_chunk_cap = B.nchunk + 64;
+                HIPCHK(hipMalloc(&W.hub_ckey, sizeof(i64) * W.hub_chunk_cap));
+                HIPCHK(hipMalloc(&W.hub_cid, sizeof(i32) * W.hub_chunk_cap));
+            }
+            HIPCHK(hipStreamSynchronize(s));
+        }
+    }
+    i64 m2 = level_strengths(W, rp, e, B, n, W.k, W.diag, s);
+    if (g->level == 0) g->m2 = m2;
+    LevelView L = view(g);
+    fill_src(L, B, W.src, s);
+}
+
+static void alloc_work(slm_graph *g)
+{
+    Work &W = g->W;
+    const i64 n = g->n0, nnz = g->nnz0;
+    W.n0 = n;
+    W.nnz0 = nnz;
+    int kmax = 2;
+    while (((i64)1 << (kmax - 2)) < n) kmax++;
+    W.kmax = kmax;
+    W.a = dalloc<i32>(g, n);
+    W.lab = dalloc<i32>(g, n);
+    W.comp = dalloc<i32>(g, n);
+    W.best_c = dalloc<i32>(g, n);
+    W.w_own = dalloc<i32>(g, n);
+    W.wc = dalloc<i32>(g, n);
+    W.sigma = dalloc<i32>(g, n);
+    W.k = dalloc<i32>(g, n);
+    W.diag = dalloc<i32>(g, n);
+    W.delta = dalloc<i64>(g, n);
+    W.cyc = dalloc<uint8_t>(g, n);
+    W.act = dalloc<uint8_t>(g, n);
+    W.hasc = dalloc<uint8_t>(g, n);
+    W.exam = dalloc<uint8_t>(g, n);
+    W.exam_next = dalloc<uint8_t>(g, n);
+    W.accept = dalloc<uint8_t>(g, n);
+    W.head = dalloc<uint8_t>(g, n);
+    W.claim = dalloc<i32>(g, n);
+    W.L = dalloc<i32>(g, n);
+    W.pos = dalloc<i32>(g, n);
+    W.cnode = dalloc<i32>(g, n);
+    W.mlist = dalloc<i32>(g, n);
+    W.A0 = dalloc<i32>(g, n);
+    W.A1 = dalloc<i32>(g, n);
+    W.M0 = dalloc<i32>(g, n);
+    W.M1 = dalloc<i32>(g, n);
+    W.J = dalloc<i32>(g, (i64)kmax * (n > 0 ? n : 1));
+    W.D0 = dalloc<i32>(g, n);
+    W.D1 = dalloc<i32>(g, n);
+    W.S0 = dalloc<i64>(g, n);
+    W.S1 = dalloc<i64>(g, n);
+    W.subk = dalloc<i64>(g, n);
+    W.cut = dalloc<i64>(g, n);
+    W.key = dalloc<i64>(g, n);
+    W.bestkey = dalloc<i64>(g, n);
+    W.cbest_key = dalloc<i64>(g, n);
+    W.woff = dalloc<i64>(g, n);
+    W.noff = dalloc<i64>(g, n);
+    W.bestpair = dalloc<u64>(g, n);
+    W.cbest_pair = dalloc<u64>(g, n);
+    W.nca0 = dalloc<i32>(g, n);
+    W.nca1 = dalloc<i32>(g, n);
+    W.wbd = dalloc<i32>(g, n);
+    W.ccnt = dalloc<i32>(g, n);
+    W.cfill = dalloc<i32>(g, n);
+    W.clist = dalloc<i32>(g, n);
+    W.coff = dalloc<i64>(g, n + 1);
+    W.minm = dalloc<i32>(g, n);
+    W.rank = dalloc<i64>(g, n + 1);
+    W.scan_tmp = dalloc<i64>(g, scan_tmp_elems(std::max(n, nnz) + 1) + 16);
+    W.counters = dalloc<i64>(g, 16);
+    W.changed = dalloc<int>(g, 4);
+    W.src = dalloc<i32>(g, nnz);
+    W.rk0 = dalloc<u64>(g, nnz);
+    W.rk1 = dalloc<u64>(g, nnz);
+    W.rv0 = dalloc<i32>(g, nnz);
+    W.rv1 = dalloc<i32>(g, nnz);
+    W.cnt = dalloc<i32>(g, n);
+    W.roff = dalloc<i64>(g, n + 1);
+    W.head_e = dalloc<uint8_t>(g, nnz);
+    W.rank_e = dalloc<i64>(g, nnz + 1);
+    g->bins.nodes = dalloc<i32>(g, n);
+    g->composed = dalloc<i32>(g, n);
+    g->rpL[0] = dalloc<i64>(g, n + 1);
+    g->rpL[1] = dalloc<i64>(g, n + 1);
+    g->eL[0] = dalloc<int2>(g, nnz);
+    g->eL[1] = dalloc<int2>(g, nnz);
+    void *hs = nullptr;
+    HIPCHK(hipHostMalloc(&hs, sizeof(i64) * 64, hipHostMallocDefault));
+    W.h_scal = (i64 *)hs;
+}
+
+static slm_status fail(const SlmError &e)
+{
+    g_err = e.msg;
+    return (slm_status)e.status;
+}
+
+#define API_BEGIN try {
+#define API_END                                                                       \
+    }                                                                                 \
+    catch (const SlmError &e_) { return fail(e_); }                                   \
+    catch (const std::bad_alloc &) { return fail(SlmError{SLM_E_NOMEM, "host allocation failed"}); } \
+    return SLM_OK;
+
+#define REQUIRE(cond, code, msg)                                                      \
+    do {                                                                              \
+        if (!(cond)) throw SlmError{code, msg};                                       \
+    } while (0)
+
+// ------------------------------------------------------------------ validation
+static void validate_host(i64 n, i64 nnz, const std::vector<i64> &rp, const i32 *col,
+                          const i32 *w, i64 *m2_out)
+{
+    REQUIRE(rp[0] == 0 && rp[n] == nnz, SLM_E_INVALID, "row_ptr must start at 0 and end at nnz");
+    i64 m2 = 0;
+    for (i64 i = 0; i < n; i++) {
+        REQUIRE(rp[i + 1] >= rp[i], SLM_E_INVALID, "row_ptr is not monotone");
+        for (i64 e = rp[i]; e < rp[i + 1]; e++) {
+            REQUIRE(col[e] >= 0 && col[e] < n, SLM_E_INVALID, "column out of range");
+            REQUIRE(w[e] >= 1, SLM_E_INVALID, "weights must be positive");
+            if (e > rp[i]) REQUIRE(col[e] > col[e - 1], SLM_E_INVALID,
+                                   "columns must be strictly ascending in every row");
+            m2 += w[e];
+        }
+    }
+    for (i64 i = 0; i < n; i++) {
+        for (i64 e = rp[i]; e < rp[i + 1]; e++) {
+            const i32 j = col[e];
+            const i32 *b = col + rp[j], *en = col + rp[j + 1];
+            const i32 *f = std::lower_bound(b, en, (i32)i);
+            REQUIRE(f != en && *f == (i32)i && w[rp[j] + (f - b)] == w[e], SLM_E_INVALID,
+                    "the matrix is not symmetric");
+        }
+    }
+    *m2_out = m2;
+}
+
+__global__ void k_pack_edges(const i32 *__restrict__ col, const i32 *__restrict__ w, i64 nnz,
+                             int2 *__restrict__ e)
+{
+    for (i64 j = (i64)blockIdx.x * blockDim.x + threadIdx.x; j < nnz;
+         j += (i64)gridDim.x * blockDim.x)
+        e[j] = make_int2(col[j], w[j]);
+}
+
+__global__ void k_widen_rp(const i32 *__restrict__ rp32, i64 n1, i64 *__restrict__ rp)
+{
+    for (i64 j = (i64)blockIdx.x * blockDim.x + threadIdx.x; j < n1;
+         j += (i64)gridDim.x * blockDim.x)
+        rp[j] = rp32[j];
+}
+
+__global__ void k_label_range(const i32 *__restrict__ lab, i64 n, i64 nc, int *__restrict__ bad)
+{
+    for (i64 j = (i64)blockIdx.x * blockDim.x + threadIdx.x; j < n;
+         j += (i64)gridDim.x * blockDim.x)
+        if (lab[j] < 0 || lab[j] >= nc) *bad = 1;
+}
+
+static unsigned small_grid(i64 n)
+{
+    i64 g = (n + 255) / 256;
+    if (g > 8192) g = 8192;
+    if (g < 1) g = 1;
+    return (unsigned)g;
+}
+
+static void check_labels(slm_graph *g, const i32 *lab, i64 nc)
+{
+    REQUIRE(lab != nullptr || g->n == 0, SLM_E_INVALID, "null label array");
+    REQUIRE(nc >= 0 && nc <= g->n, SLM_E_INVALID, "community count out of range");
+    if (g->n == 0) return;
+    HIPCHK(hipMemsetAsync(g->W.changed, 0, sizeof(int), g->s));
+    k_label_range<<<small_grid(g->n), 256, 0, g->s>>>(lab, g->n, nc, g->W.changed);
+    HIPCHK(hipMemcpyAsync(g->W.h_scal, g->W.changed, sizeof(int), hipMemcpyDeviceToHost, g->s));
+    HIPCHK(hipStreamSynchronize(g->s));
+    REQUIRE(*(int *)g->W.h_scal == 0, SLM_E_INVALID, "label out of range");
+}
+
+// ------------------------------------------------------------------ level loop
+static void level_start(slm_graph *g, i64 *nc)
+{
+    Work &W = g->W;
+    LevelView L = view(g);
+    run_assign(L, g->bins, W.a, W.hub_ckey, W.hub_cid, g->s);
+    components(W, W.a, g->n, false, g->s);
+    positive(W, L, g->bins, nc, g->s);
+}
+
+// One MAXIMAL round then POSITIVE; W.lab / *nc must describe W.a.  Returns
+// the valid count.
+static i64 level_round(slm_graph *g, const slm_params *p, int level, int round, i64 *nc,
+                       i64 *stats4)
+{
+    Work &W = g->W;
+    LevelView L = view(g);
+    float ms = 0;
+    i64 st[3] = {0, 0, 0};
+    i64 valid = maximal_moves(W, L, g->bins, *nc, p->seed, level, round, p->accept_p, st, g->s,
+                              g->timing, g->ev0, g->ev1, &ms);
+    if (g->timing) {
+        g->sweep_ms += ms;
+        g->sweeps++;
+        g->entries += g->nnz;
+        g->bytes += 8 * g->nnz + 32 * g->n + 4 * (*nc);
+    }
+    i64 splits = 0;
+    if (valid > 0) {
+        components(W, W.a, g->n, false, g->s);
+        splits = positive(W, L, g->bins, nc, g->s);
+    }
+    if (stats4) {
+        stats4[0] = st[0];
+        stats4[1] = st[1];
+        stats4[2] = st[2];
+        stats4[3] = splits;
+    }
+    return valid;
+}
+
+static void run_level(slm_graph *g, const slm_params *p, int level, i64 *nc, int32_t *rounds,
+                      int32_t *conv)
+{
+    level_start(g, nc);
+    int r = 0;
+    *conv = 0;
+    while (r < p->max_rounds) {
+        i64 valid = level_round(g, p, level, r, nc, nullptr);
+        if (valid == 0) {
+            *conv = 1;
+            break;
+        }
+        r++;
+    }
+    *rounds = r;
+}
+
+static void do_contract(slm_graph *g, const i32 *lab, i64 nc)
+{
+    REQUIRE(nc < g->n, SLM_E_STATE, "contraction needs fewer communities than nodes");
+    Work &W = g->W;
+    LevelView L = view(g);
+    const int dst = g->cur < 0 ? 0 : 1 - g->cur;
+    i64 nnz2 = contract_level(W, L, g->bins, lab, nc, g->rpL[dst], g->eL[dst], g->s);
+    g->cur = dst;
+    g->n = nc;
+    g->nnz = nnz2;
+    g->level++;
+    setup_level(g);
+}
+
+static void do_reset(slm_graph *g)
+{
+    if (g->cur < 0 && g->level == 0) return;
+    g->cur = -1;
+    g->level = 0;
+    g->n = g->n0;
+    g->nnz = g->nnz0;
+    setup_level(g);
+}
+
+// ================================================================== ABI
+extern "C" {
+
+void slm_params_default(slm_params *p)
+{
+    if (!p) return;
+    std::memset(p, 0, sizeof(*p));
+    p->seed = 0;
+    p->accept_p = 1ull << 31;
+    p->max_rounds = 64;
+    p->max_levels = 0;
+    p->validate = 1;
+}
+
+const char *slm_last_error(void)
+{
+    return g_err.c_str();
+}
+
+void slm_destroy(slm_graph *g)
+{
+    if (!g) return;
+    (void)hipStreamSynchronize(g->s);
+    free_bins(g);
+    for (void *p : g->allocs) (void)hipFree(p);
+    Work &W = g->W;
+    for (void *p : {(void *)W.W, (void *)W.hist, (void *)W.hub_keys, (void *)W.hub_vals,
+                    (void *)W.hub_win, (void *)W.hub_ckey, (void *)W.hub_cid})
+        if (p) (void)hipFree(p);
+    if (W.h_scal) (void)hipHostFree(W.h_scal);
+    if (g->ev0) (void)hipEventDestroy(g->ev0);
+    if (g->ev1) (void)hipEventDestroy(g->ev1);
+    delete g;
+}
+
+slm_status slm_create(int64_t n, int64_t nnz, const void *row_ptr, int row_ptr_bytes,
+                      const int32_t *col, const int32_t *w, int inputs_on_device, int validate,
+                      void *hip_stream, slm_graph **out)
+{
+    slm_graph *g = nullptr;
+    try {
+        REQUIRE(out != nullptr, SLM_E_INVALID, "null output handle");
+        *out = nullptr;
+        REQUIRE(n >= 0 && nnz >= 0, SLM_E_INVALID, "negative size");
+        REQUIRE(row_ptr_bytes == 4 || row_ptr_bytes == 8, SLM_E_INVALID, "row_ptr_bytes must be 4 or 8");
+        REQUIRE(row_ptr != nullptr, SLM_E_INVALID, "null row_ptr");
+        REQUIRE(nnz == 0 || (col && w), SLM_E_INVALID, "null col or w");
+        REQUIRE(n < ((i64)1 << 31) - 1, SLM_E_OVERFLOW, "n must be below 2^31 - 1");
+        REQUIRE(nnz < ((i64)1 << 40), SLM_E_OVERFLOW, "too many entries");
+        g = new slm_graph();
+        g->s = (hipStream_t)hip_stream;
+        HIPCHK(hipGetDevice(&g->device));
+        g->n0 = g->n = n;
+        g->nnz0 = g->nnz = nnz;
+        // host copies for validation (or the inputs themselves when on host)
+        std::vector<i64> rp_h;
+        std::vector<i32> col_h, w_h;
+        const i32 *colp = col, *wp = w;
+        i64 m2 = -1;
+        if (!inputs_on_device || validate) {
+            rp_h.resize(n + 1);
+            if (inputs_on_device) {
+                std::vector<char> tmp((size_t)(n + 1) * row_ptr_bytes);
+                HIPCHK(hipMemcpy(tmp.data(), row_ptr, tmp.size(), hipMemcpyDeviceToHost));
+                for (i64 i = 0; i <= n; i++)
+                    rp_h[i] = row_ptr_bytes == 8 ? ((const i64 *)tmp.data())[i]
+                                                 : ((const i32 *)tmp.data())[i];
+                col_h.resize(nnz);
+                w_h.resize(nnz);
+                if (nnz) {
+                    HIPCHK(hipMemcpy(col_h.data(), col, sizeof(i32) * nnz, hipMemcpyDeviceToHost));
+                    HIPCHK(hipMemcpy(w_h.data(), w, sizeof(i32) * nnz, hipMemcpyDeviceToHost));
+                }
+                colp = col_h.data();
+                wp = w_h.data();
+            } else {
+                for (i64 i = 0; i <= n; i++)
+                    rp_h[i] = row_ptr_bytes == 8 ? ((const i64 *)row_ptr)[i]
+                                                 : ((const i32 *)row_ptr)[i];
+            }
+            if (validate) {
+                validate_host(n, nnz, rp_h, colp, wp, &m2);
+                REQUIRE(m2 < ((i64)1 << 31), SLM_E_OVERFLOW, "total weight M2 must be below 2^31");
+            } else {
+                REQUIRE(rp_h[0] == 0 && rp_h[n] == nnz, SLM_E_INVALID, "row_ptr must start at 0 and end at nnz");
+            }
+        }
+        alloc_work(g);
+        g->rp0 = dalloc<i64>(g, n + 1);
+        g->e0 = dalloc<int2>(g, nnz);
+        if (!inputs_on_device) {
+            HIPCHK(hipMemcpyAsync(g->rp0, rp_h.data(), sizeof(i64) * (n + 1), hipMemcpyHostToDevice, g->s));
+            if (nnz) {
+                std::vector<int2> e_h(nnz);
+                for (i64 j = 0; j < nnz; j++) e_h[j] = make_int2(colp[j], wp[j]);
+                HIPCHK(hipMemcpyAsync(g->e0, e_h.data(), sizeof(int2) * nnz, hipMemcpyHostToDevice, g->s));
+                HIPCHK(hipStreamSynchronize(g->s));
+            }
+        } else {
+            if (row_ptr_bytes == 8)
+                HIPCHK(hipMemcpyAsync(g->rp0, row_ptr, sizeof(i64) * (n + 1), hipMemcpyDeviceToDevice, g->s));
+            else
+                k_widen_rp<<<small_grid(n + 1), 256, 0, g->s>>>((const i32 *)row_ptr, n + 1, g->rp0);
+            if (nnz) k_pack_edges<<<small_grid(nnz), 256, 0, g->s>>>(col, w, nnz, g->e0);
+        }
+        HIPCHK(hipEventCreate(&g->ev0));
+        HIPCHK(hipEventCreate(&g->ev1));
+        setup_level(g);
+        REQUIRE(g->m2 < ((i64)1 << 31), SLM_E_OVERFLOW, "total weight M2 must be below 2^31");
+        *out = g;
+        return SLM_OK;
+    } catch (const SlmError &e) {
+        if (g) slm_destroy(g);
+        return fail(e);
+    } catch (const std::bad_alloc &) {
+        if (g) slm_destroy(g);
+        return fail(SlmError{SLM_E_NOMEM, "host allocation failed"});
+    }
+}
+
+slm_status slm_level_info(const slm_graph *g, int32_t *level, int64_t *n_t, int64_t *nnz_t,
+                          int64_t *m2)
+{
+    API_BEGIN
+    REQUIRE(g != nullptr, SLM_E_INVALID, "null handle");
+    if (level) *level = g->level;
+    if (n_t) *n_t = g->n;
+    if (nnz_t) *nnz_t = g->nnz;
+    if (m2) *m2 = g->m2;
+    API_END
+}
+
+slm_status slm_reset(slm_graph *g)
+{
+    API_BEGIN
+    REQUIRE(g != nullptr, SLM_E_INVALID, "null handle");
+    do_reset(g);
+    API_END
+}
+
+slm_status slm_export_level(slm_graph *g, int64_t *row_ptr, int32_t *col, int32_t *w)
+{
+    API_BEGIN
+    REQUIRE(g != nullptr && row_ptr != nullptr, SLM_E_INVALID, "null argument");
+    REQUIRE(g->nnz == 0 || (col && w), SLM_E_INVALID, "null col or w");
+    LevelView L = view(g);
+    HIPCHK(hipMemcpyAsync(row_ptr, L.rp, sizeof(i64) * (g->n + 1), hipMemcpyDeviceToHost, g->s));
+    std::vector<int2> e_h(g->nnz);
+    if (g->nnz)
+        HIPCHK(hipMemcpyAsync(e_h.data(), L.e, sizeof(int2) * g->nnz, hipMemcpyDeviceToHost, g->s));
+    HIPCHK(hipStreamSynchronize(g->s));
+    for (i64 j = 0; j < g->nnz; j++) {
+        col[j] = e_h[j].x;
+        w[j] = e_h[j].y;
+    }
+    API_END
+}
+
+slm_status slm_assign(slm_graph *g, int32_t *a_dev)
+{
+    API_BEGIN
+    REQUIRE(g != nullptr && (a_dev != nullptr || g->n == 0), SLM_E_INVALID, "null argument");
+    if (g->n == 0) return SLM_OK;
+    LevelView L = view(g);
+    run_assign(L, g->bins, a_dev, g->W.hub_ckey, g->W.hub_cid, g->s);
+    API_END
+}
+
+static void load_assignment(slm_graph *g, const i32 *a_dev)
+{
+    HIPCHK(hipMemsetAsync(g->W.changed, 0, sizeof(int), g->s));
+    k_label_range<<<small_grid(g->n), 256, 0, g->s>>>(a_dev, g->n, g->n, g->W.changed);
+    HIPCHK(hipMemcpyAsync(g->W.h_scal, g->W.changed, sizeof(int), hipMemcpyDeviceToHost, g->s));
+    HIPCHK(hipStreamSynchronize(g->s));
+    REQUIRE(*(int *)g->W.h_scal == 0, SLM_E_INVALID, "assignment out of range");
+    HIPCHK(hipMemcpyAsync(g->W.a, a_dev, sizeof(i32) * g->n, hipMemcpyDeviceToDevice, g->s));
+}
+
+slm_status slm_components(slm_graph *g, const int32_t *a_dev, int32_t *lab_dev,
+                          uint8_t *on_cycle_dev, int64_t *n_c)
+{
+    API_BEGIN
+    REQUIRE(g != nullptr, SLM_E_INVALID, "null handle");
+    REQUIRE(g->n == 0 || (a_dev && lab_dev), SLM_E_INVALID, "null argument");
+    if (g->n == 0) {
+        if (n_c) *n_c = 0;
+        return SLM_OK;
+    }
+    load_assignment(g, a_dev);
+    i64 nc = components(g->W, g->W.a, g->n, true, g->s);
+    HIPCHK(hipMemcpyAsync(lab_dev, g->W.lab, sizeof(i32) * g->n, hipMemcpyDeviceToDevice, g->s));
+    if (on_cycle_dev)
+        HIPCHK(hipMemcpyAsync(on_cycle_dev, g->W.cyc, g->n, hipMemcpyDeviceToDevice, g->s));
+    HIPCHK(hipStreamSynchronize(g->s));
+    if (n_c) *n_c = nc;
+    API_END
+}
+
+slm_status slm_positive(slm_graph *g, int32_t *a_dev, int64_t *splits)
+{
+    API_BEGIN
+    REQUIRE(g != nullptr, SLM_E_INVALID, "null handle");
+    REQUIRE(g->n == 0 || a_dev, SLM_E_INVALID, "null argument");
+    if (g->n == 0) {
+        if (splits) *splits = 0;
+        return SLM_OK;
+    }
+    load_assignment(g, a_dev);
+    components(g->W, g->W.a, g->n, false, g->s);
+    i64 nc;
+    LevelView L = view(g);
+    i64 sp = positive(g->W, L, g->bins, &nc, g->s);
+    HIPCHK(hipMemcpyAsync(a_dev, g->W.a, sizeof(i32) * g->n, hipMemcpyDeviceToDevice, g->s));
+    HIPCHK(hipStreamSynchronize(g->s));
+    if (splits) *splits = sp;
+    API_END
+}
+
+slm_status slm_sweep(slm_graph *g, const int32_t *lab_dev, int64_t n_c, int32_t *best_c_dev,
+                     int64_t *delta_dev, int32_t *w_own_dev)
+{
+    API_BEGIN
+    REQUIRE(g != nullptr, SLM_E_INVALID, "null handle");
+    if (g->n == 0) return SLM_OK;
+    REQUIRE(best_c_dev && delta_dev && w_own_dev, SLM_E_INVALID, "null output");
+    check_labels(g, lab_dev, n_c);
+    LevelView L = view(g);
+    community_totals(g->W, L, lab_dev, n_c, g->s);
+    if (g->timing) HIPCHK(hipEventRecord(g->ev0, g->s));
+    run_sweep(L, g->bins, lab_dev, g->W.sigma, best_c_dev, delta_dev, w_own_dev, g->W.hub_keys,
+              g->W.hub_vals, g->W.hub_win, g->s);
+    if (g->timing) {
+        HIPCHK(hipEventRecord(g->ev1, g->s));
+        HIPCHK(hipEventSynchronize(g->ev1));
+        float ms = 0;
+        HIPCHK(hipEventElapsedTime(&ms, g->ev0, g->ev1));
+        g->sweep_ms += ms;
+        g->sweeps++;
+        g->entries += g->nnz;
+        g->bytes += 8 * g->nnz + 32 * g->n + 4 * n_c;
+    }
+    API_END
+}
+
+slm_status slm_round(slm_graph *g, const slm_params *p, int32_t level, int32_t round,
+                     int32_t *a_dev, int64_t *stats)
+{
+    API_BEGIN
+    REQUIRE(g != nullptr && p != nullptr, SLM_E_INVALID, "null argument");
+    REQUIRE(g->n == 0 || a_dev, SLM_E_INVALID, "null assignment");
+    REQUIRE(p->accept_p <= (1ull << 32), SLM_E_INVALID, "accept_p must be at most 2^32");
+    if (g->n == 0) {
+        if (stats) std::memset(stats, 0, sizeof(int64_t) * 4);
+        return SLM_OK;
+    }
+    load_assignment(g, a_dev);
+    i64 nc = components(g->W, g->W.a, g->n, true, g->s);
+    i64 st[4];
+    level_round(g, p, level, round, &nc, st);
+    HIPCHK(hipMemcpyAsync(a_dev, g->W.a, sizeof(i32) * g->n, hipMemcpyDeviceToDevice, g->s));
+    HIPCHK(hipStreamSynchronize(g->s));
+    if (stats) std::memcpy(stats, st, sizeof(st));
+    API_END
+}
+
+slm_status slm_level(slm_graph *g, const slm_params *p, int32_t level, int32_t *lab_dev,
+                     int64_t *n_c, int32_t *rounds, int32_t *converged)
+{
+    API_BEGIN
+    REQUIRE(g != nullptr && p != nullptr, SLM_E_INVALID, "null argument");
+    REQUIRE(g->n == 0 || lab_dev, SLM_E_INVALID, "null labels");
+    REQUIRE(p->accept_p <= (1ull << 32), SLM_E_INVALID, "accept_p must be at most 2^32");
+    if (g->n == 0) {
+        if (n_c) *n_c = 0;
+        if (rounds) *rounds = 0;
+        if (converged) *converged = 1;
+        return SLM_OK;
+    }
+    i64 nc;
+    int32_t r, c;
+    run_level(g, p, level, &nc, &r, &c);
+    HIPCHK(hipMemcpyAsync(lab_dev, g->W.lab, sizeof(i32) * g->n, hipMemcpyDeviceToDevice, g->s));
+    HIPCHK(hipStreamSynchronize(g->s));
+    if (n_c) *n_c = nc;
+    if (rounds) *rounds = r;
+    if (converged) *converged = c;
+    API_END
+}
+
+slm_status slm_modularity(slm_graph *g, const int32_t *lab_dev, int64_t n_c, int64_t *nq,
+                          double *q)
+{
+    API_BEGIN
+    REQUIRE(g != nullptr, SLM_E_INVALID, "null handle");
+    i64 v = 0;
+    if (g->n > 0) {
+        check_labels(g, lab_dev, n_c);
+        v = modularity_num(g->W, view(g), g->bins, lab_dev, n_c, g->s);
+    }
+    if (nq) *nq = v;
+    if (q) *q = g->m2 > 0 ? (double)v / (double)g->m2 / (double)g->m2 : 0.0;
+    API_END
+}
+
+slm_status slm_contract(slm_graph *g, const int32_t *lab_dev, int64_t n_c)
+{
+    API_BEGIN
+    REQUIRE(g != nullptr, SLM_E_INVALID, "null handle");
+    check_labels(g, lab_dev, n_c);
+    do_contract(g, lab_dev, n_c);
+    API_END
+}
+
+slm_status slm_run(slm_graph *g, const slm_params *p, slm_result **out)
+{
+    API_BEGIN
+    REQUIRE(g != nullptr && p != nullptr && out != nullptr, SLM_E_INVALID, "null argument");
+    REQUIRE(p->accept_p <= (1ull << 32), SLM_E_INVALID, "accept_p must be at most 2^32");
+    REQUIRE(p->max_rounds >= 0 && p->max_levels >= 0, SLM_E_INVALID, "negative cap");
+    *out = nullptr;
+    do_reset(g);
+    slm_result *r = new slm_result();
+    r->n0 = g->n0;
+    try {
+        launch_iota_i32(g->composed, g->n0, g->s);
+        int level = 0;
+        while (g->m2 > 0 && g->n > 0) {
+            i64 nc;
+            int32_t rounds, conv;
+            run_level(g, p, level, &nc, &rounds, &conv);
+            if (nc == g->n) break;  // the level partition is the identity
+            compose_labels(g->composed, g->W.lab, g->n0, g->s);
+            i64 nq = modularity_num(g->W, view(g), g->bins, g->W.lab, nc, g->s);
+            std::vector<i32> lab(g->n0);
+            HIPCHK(hipMemcpyAsync(lab.data(), g->composed, sizeof(i32) * g->n0,
+                                  hipMemcpyDeviceToHost, g->s));
+            HIPCHK(hipStreamSynchronize(g->s));
+            r->labels.push_back(std::move(lab));
+            r->nc.push_back(nc);
+            r->nq.push_back(nq);
+            r->q.push_back((double)nq / (double)g->m2 / (double)g->m2);
+            r->rounds.push_back(rounds);
+            r->conv.push_back(conv);
+            level++;
+            if (p->max_levels > 0 && level >= p->max_levels) break;
+            do_contract(g, g->W.lab, nc);
+        }
+    } catch (...) {
+        delete r;
+        throw;
+    }
+    *out = r;
+    API_END
+}
+
+slm_status slm_result_num_levels(const slm_result *r, int32_t *levels)
+{
+    API_BEGIN
+    REQUIRE(r != nullptr && levels != nullptr, SLM_E_INVALID, "null argument");
+    *levels = (int32_t)r->nc.size();
+    API_END
+}
+
+slm_status slm_result_level(const slm_result *r, int32_t level, int64_t *n_c,
+                            const int32_t **labels, int64_t *nq, double *q, int32_t *rounds,
+                            int32_t *converged)
+{
+    API_BEGIN
+    REQUIRE(r != nullptr, SLM_E_INVALID, "null result");
+    REQUIRE(level >= 0 && level < (int32_t)r->nc.size(), SLM_E_INVALID, "level out of range");
+    if (n_c) *n_c = r->nc[level];
+    if (labels) *labels = r->labels[level].data();
+    if (nq) *nq = r->nq[level];
+    if (q) *q = r->q[level];
+    if (rounds) *rounds = r->rounds[level];
+    if (converged) *converged = r->conv[level];
+    API_END
+}
+
+void slm_result_free(slm_result *r)
+{
+    delete r;
+}
+
+slm_status slm_timing_enable(slm_graph *g, int enable)
+{
+    API_BEGIN
+    REQUIRE(g != nullptr, SLM_E_INVALID, "null handle");
+    g->timing = enable != 0;
+    API_END
+}
+
+slm_status slm_timing_read(slm_graph *g, double *sweep_ms, int64_t *sweeps, int64_t *entries,
+                           int64_t *bytes)
+{
+    API_BEGIN
+    REQUIRE(g != nullptr, SLM_E_INVALID, "null handle");
+    HIPCHK(hipStreamSynchronize(g->s));
+    if (sweep_ms) *sweep_ms = g->sweep_ms;
+    if (sweeps) *sweeps = g->sweeps;
+    if (entries) *entries = g->entries;
+    if (bytes) *bytes = g->bytes;
+    g->sweep_ms = 0;
+    g->sweeps = g->entries = g->bytes = 0;
+    API_END
+}
+
+}  // extern "C"

@@ -1,0 +1,209 @@
+// AGGREGATE (Sec. 3.5): the community graph of the next level,
+// A'_CD = sum of A_uv over u in C, v in D.  Rows are first pre-aggregated
+// (one record per distinct (lab_u, lab_v) of a row), the records are sorted
+// by the composite key lab_u << bits | lab_v with an LSD radix sort of 8-bit
+// digits, equal keys are merged by a segmented sum, and the new row offsets
+// come from a histogram of the row part of the keys.
+#include "slm_forest.h"
+
+#define RS_BINS 256
+#define RS_SUB 16
+#define RS_TILE (SLM_BS * RS_SUB)
+
+#define FLAT_LOOP(n)                                                                  \
+    for (i64 j = (i64)blockIdx.x * blockDim.x + threadIdx.x; j < (n);                 \
+         j += (i64)gridDim.x * blockDim.x)
+
+static unsigned flat_grid(i64 n)
+{
+    i64 g = (n + SLM_BS - 1) / SLM_BS;
+    if (g > 16384) g = 16384;
+    if (g < 1) g = 1;
+    return (unsigned)g;
+}
+
+// Records of row u sit at [rp[u], rp[u] + cnt[u]); pack them at roff[u].
+__global__ void k_compact_records(const i32 *__restrict__ src, const i64 *__restrict__ rp,
+                                  const i32 *__restrict__ cnt, const i64 *__restrict__ roff,
+                                  i64 nnz, const u64 *__restrict__ kin, const i32 *__restrict__ vin,
+                                  u64 *__restrict__ kout, i32 *__restrict__ vout)
+{
+    FLAT_LOOP(nnz)
+    {
+        i32 u = src[j];
+        i64 t = j - rp[u];
+        if (t < cnt[u]) {
+            kout[roff[u] + t] = kin[j];
+            vout[roff[u] + t] = vin[j];
+        }
+    }
+}
+
+// ------------------------------------------------------------------ radix sort
+// Tile of RS_TILE items: sub-round r covers items tile + r*256 + tid, so the
+// tile is visited in order and the scatter below is stable.
+__global__ __launch_bounds__(SLM_BS) void k_rs_hist(const u64 *__restrict__ keys, i64 n,
+                                                   int shift, i64 nblk, i64 *__restrict__ hist)
+{
+    __shared__ int cnt[RS_BINS];
+    cnt[threadIdx.x] = 0;
+    __syncthreads();
+    const i64 tile = (i64)blockIdx.x * RS_TILE;
+    for (int r = 0; r < RS_SUB; r++) {
+        i64 idx = tile + (i64)r * SLM_BS + threadIdx.x;
+        if (idx < n) atomicAdd(&cnt[(keys[idx] >> shift) & (RS_BINS - 1)], 1);
+    }
+    __syncthreads();
+    hist[(i64)threadIdx.x * nblk + blockIdx.x] = cnt[threadIdx.x];
+}
+
+__global__ __launch_bounds__(SLM_BS) void k_rs_scatter(const u64 *__restrict__ kin,
+                                                      const i32 *__restrict__ vin, i64 n,
+                                                      int shift, i64 nblk,
+                                                      const i64 *__restrict__ offs,
+                                                      u64 *__restrict__ kout,
+                                                      i32 *__restrict__ vout)
+{
+    __shared__ i64 base[RS_BINS];
+    __shared__ int run[RS_BINS];
+    __shared__ int wcnt[SLM_BS / 64][RS_BINS];
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid / 64;
+    base[tid] = offs[(i64)tid * nblk + blockIdx.x];
+    run[tid] = 0;
+    const u64 lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    const i64 tile = (i64)blockIdx.x * RS_TILE;
+    for (int r = 0; r < RS_SUB; r++) {
+        for (int w = 0; w < SLM_BS / 64; w++) wcnt[w][tid] = 0;
+        __syncthreads();
+        const i64 idx = tile + (i64)r * SLM_BS + tid;
+        const bool ok = idx < n;
+        u64 key = ok ? kin[idx] : 0;
+        i32 val = ok ? vin[idx] : 0;
+        const int d = (int)((key >> shift) & (RS_BINS - 1));
+        u64 peers = __ballot(ok);
+#pragma unroll
+        for (int b = 0; b < 8; b++) {
+            const bool bit = (d >> b) & 1;
+            const u64 m = __ballot(bit);
+            peers &= bit ? m : ~m;
+        }
+        const int rank = __popcll(peers & lt);
+        if (ok && rank == 0) wcnt[wid][d] = __popcll(peers);
+        __syncthreads();
+        if (ok) {
+            int before = run[d];
+            for (int w = 0; w < wid; w++) before += wcnt[w][d];
+            const i64 dst = base[d] + before + rank;
+            kout[dst] = key;
+            vout[dst] = val;
+        }
+        __syncthreads();
+        int add = 0;
+        for (int w = 0; w < SLM_BS / 64; w++) add += wcnt[w][tid];
+        run[tid] += add;
+        __syncthreads();
+    }
+}
+
+// ------------------------------------------------------------------ merge and rows
+__global__ void k_seg_heads(const u64 *__restrict__ keys, i64 n, uint8_t *__restrict__ head)
+{
+    FLAT_LOOP(n) head[j] = (j == 0 || keys[j] != keys[j - 1]) ? 1 : 0;
+}
+
+// Segment s = (number of heads up to j) - 1 gets the weight; heads write keys.
+__global__ void k_seg_sum(const u64 *__restrict__ keys, const i32 *__restrict__ w, i64 n,
+                          const uint8_t *__restrict__ head, const i64 *__restrict__ hpos,
+                          u64 *__restrict__ ukey, i32 *__restrict__ uw)
+{
+    FLAT_LOOP(n)
+    {
+        i64 sidx = hpos[j] + head[j] - 1;
+        if (head[j]) ukey[sidx] = keys[j];
+        atomicAdd(&uw[sidx], w[j]);
+    }
+}
+
+__global__ void k_row_count(const u64 *__restrict__ ukey, i64 u, int bits, i32 *__restrict__ rc)
+{
+    FLAT_LOOP(u) atomicAdd(&rc[(i64)(ukey[j] >> bits)], 1);
+}
+
+__global__ void k_emit_entries(const u64 *__restrict__ ukey, const i32 *__restrict__ uw, i64 u,
+                               int bits, int2 *__restrict__ e_out)
+{
+    const u64 mask = (bits >= 64) ? ~0ull : ((1ull << bits) - 1ull);
+    FLAT_LOOP(u) e_out[j] = make_int2((i32)(ukey[j] & mask), uw[j]);
+}
+
+static int bits_for(i64 nc)
+{
+    int b = 1;
+    while (((i64)1 << b) < nc) b++;
+    return b;
+}
+
+// Sorts (keys, vals) of n items on their low `bits` bits; returns the buffers
+// that hold the result (either the inputs or the alternates).
+static void radix_sort(Work &W, u64 *&k, i32 *&v, u64 *&k2, i32 *&v2, i64 n, int bits,
+                       hipStream_t s)
+{
+    const i64 nblk = (n + RS_TILE - 1) / RS_TILE;
+    const i64 hn = nblk * RS_BINS;
+    if (hn + 1 > W.hist_cap) {
+        if (W.hist) HIPCHK(hipFree(W.hist));
+        W.hist = nullptr;
+        W.hist_cap = hn + 1 + 4096;
+        HIPCHK(hipMalloc(&W.hist, sizeof(i64) * 2 * W.hist_cap));
+    }
+    i64 *hist = W.hist, *offs = W.hist + W.hist_cap;
+    i64 *tmp = W.scan_tmp;  // scan_tmp is sized for n0 + nnz0
+    for (int shift = 0; shift < bits; shift += 8) {
+        k_rs_hist<<<(unsigned)nblk, SLM_BS, 0, s>>>(k, n, shift, nblk, hist);
+        launch_scan_i64(hist, offs, hn, tmp, s);
+        k_rs_scatter<<<(unsigned)nblk, SLM_BS, 0, s>>>(k, v, n, shift, nblk, offs, k2, v2);
+        u64 *tk = k;
+        k = k2;
+        k2 = tk;
+        i32 *tv = v;
+        v = v2;
+        v2 = tv;
+    }
+}
+
+i64 contract_level(Work &W, const LevelView &Lv, const Bins &B, const i32 *lab, i64 nc,
+                   i64 *rp_out, int2 *e_out, hipStream_t s)
+{
+    const i64 n = Lv.n, nnz = Lv.nnz;
+    const int bits = bits_for(nc);
+    launch_fill_i32(W.cnt, 0, n, s);
+    run_contract_rows(Lv, B, lab, bits, W.rk0, W.rv0, W.cnt, s);
+    launch_scan_i32(W.cnt, W.roff, n, W.scan_tmp, s);
+    read_scalars(W, W.roff + n, 1, s);
+    const i64 recs = W.h_scal[0];
+    if (nnz > 0)
+        k_compact_records<<<flat_grid(nnz), SLM_BS, 0, s>>>(W.src, Lv.rp, W.cnt, W.roff, nnz,
+                                                          W.rk0, W.rv0, W.rk1, W.rv1);
+    u64 *k = W.rk1, *k2 = W.rk0;
+    i32 *v = W.rv1, *v2 = W.rv0;
+    if (recs > 0) radix_sort(W, k, v, k2, v2, recs, 2 * bits, s);
+    // merge equal keys: heads -> positions -> sums
+    uint8_t *head = W.head_e;
+    i64 *hpos = W.rank_e;
+    i64 uniq = 0;
+    if (recs > 0) {
+        k_seg_heads<<<flat_grid(recs), SLM_BS, 0, s>>>(k, recs, head);
+        launch_scan_u8(head, hpos, recs, W.scan_tmp, s);
+        read_scalars(W, hpos + recs, 1, s);
+        uniq = W.h_scal[0];
+        launch_fill_i32(v2, 0, uniq, s);
+        k_seg_sum<<<flat_grid(recs), SLM_BS, 0, s>>>(k, v, recs, head, hpos, k2, v2);
+    }
+    // rows of the next level
+    i32 *rc = W.cnt;  // nc <= n
+    launch_fill_i32(rc, 0, nc, s);
+    if (uniq > 0) k_row_count<<<flat_grid(uniq), SLM_BS, 0, s>>>(k2, uniq, bits, rc);
+    launch_scan_i32(rc, rp_out, nc, W.scan_tmp, s);
+    if (uniq > 0) k_emit_entries<<<flat_grid(uniq), SLM_BS, 0, s>>>(k2, v2, uniq, bits, e_out);
+    return uniq;
+}

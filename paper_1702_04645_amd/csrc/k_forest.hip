@@ -1,0 +1,997 @@
+// Kernels on the assignment graph T = {(i, a(i))} (Sec. 3.2-3.4):
+//  - COMPONENTS by pointer doubling: a^(2^K)(i) lies on the cycle of i's
+//    component; the minimum along the doubled path gives the cycle minimum,
+//    a canonical id of the component; canonical labels rank components by
+//    their smallest member.
+//  - Forest view: cycle nodes are roots, every other node's parent is a(i).
+//    Jump tables J_k = parent^(2^k) give depths, roots, lowest common
+//    ancestors, and subtree sums by doubling scatter
+//    S_{k+1}(x) = S_k(x) + sum of S_k(y) over y with parent^(2^k)(y) = x.
+//  - POSITIVE split keys (branch and cycle cuts) and their application.
+//  - MAXIMAL tails: w(B, D) for every candidate through the chain of
+//    candidate ancestors, validity, and the acceptance draw.
+// Arrays indexed by a community id use node-id space ("comp") during
+// POSITIVE and canonical labels elsewhere; kernels take both forms.
+#include "slm_forest.h"
+
+// ------------------------------------------------------------------ helpers
+__device__ __forceinline__ void atomic_max_i64(i64 *p, i64 v)
+{
+    unsigned long long *q = (unsigned long long *)p;
+    unsigned long long old = *q;
+    while ((i64)old < v) {
+        unsigned long long prev = atomicCAS(q, old, (unsigned long long)v);
+        if (prev == old) break;
+        old = prev;
+    }
+}
+
+__device__ __forceinline__ void atomic_min_u64(u64 *p, u64 v)
+{
+    atomicMin((unsigned long long *)p, (unsigned long long)v);
+}
+
+#define NODE_LOOP(n)                                                                  \
+    for (i64 u_ = (i64)blockIdx.x * blockDim.x + threadIdx.x; u_ < (n);               \
+         u_ += (i64)gridDim.x * blockDim.x)
+
+static unsigned node_grid(i64 n)
+{
+    i64 g = (n + SLM_BS - 1) / SLM_BS;
+    if (g > 8192) g = 8192;
+    if (g < 1) g = 1;
+    return (unsigned)g;
+}
+
+// ------------------------------------------------------------------ components
+__global__ void k_comp_init(const i32 *__restrict__ a, i64 n, i32 *__restrict__ A,
+                            i32 *__restrict__ M)
+{
+    NODE_LOOP(n)
+    {
+        i32 u = (i32)u_, x = a[u];
+        A[u] = x;
+        M[u] = u < x ? u : x;
+    }
+}
+
+__global__ void k_comp_step(const i32 *__restrict__ Ai, const i32 *__restrict__ Mi,
+                            i32 *__restrict__ Ao, i32 *__restrict__ Mo, i64 n)
+{
+    NODE_LOOP(n)
+    {
+        i32 x = Ai[u_];
+        Ao[u_] = Ai[x];
+        i32 m1 = Mi[u_], m2 = Mi[x];
+        Mo[u_] = m1 < m2 ? m1 : m2;
+    }
+}
+
+// cmin[u] = the minimum of u's cycle; cyc marks the image of A = cycle nodes.
+__global__ void k_comp_mark(const i32 *__restrict__ A, const i32 *__restrict__ M, i64 n,
+                            i32 *__restrict__ cmin, uint8_t *__restrict__ cyc)
+{
+    NODE_LOOP(n)
+    {
+        i32 z = A[u_];
+        cmin[u_] = M[z];
+        cyc[z] = 1;
+    }
+}
+
+// ------------------------------------------------------------------ canonical labels
+__global__ void k_minmember(const i32 *__restrict__ comp, i64 n, i32 *__restrict__ minm)
+{
+    NODE_LOOP(n) atomicMin(&minm[comp[u_]], (i32)u_);
+}
+
+__global__ void k_head(const i32 *__restrict__ comp, const i32 *__restrict__ minm, i64 n,
+                       uint8_t *__restrict__ head)
+{
+    NODE_LOOP(n) head[u_] = minm[comp[u_]] == (i32)u_;
+}
+
+__global__ void k_label(const i32 *__restrict__ comp, const i32 *__restrict__ minm,
+                        const i64 *__restrict__ rank, i64 n, i32 *__restrict__ lab)
+{
+    NODE_LOOP(n) lab[u_] = (i32)rank[minm[comp[u_]]];
+}
+
+// ------------------------------------------------------------------ cycle positions
+// For cycle nodes of cycles with two or more nodes: distance to the cycle
+// minimum along a (list ranking by doubling); pos = (L - dist) mod L.
+__global__ void k_cyc_len(const i32 *__restrict__ comp, const uint8_t *__restrict__ cyc, i64 n,
+                          i32 *__restrict__ L)
+{
+    NODE_LOOP(n) if (cyc[u_]) atomicAdd(&L[comp[u_]], 1);
+}
+
+__global__ void k_rank_init(const i32 *__restrict__ a, const i32 *__restrict__ comp,
+                            const uint8_t *__restrict__ cyc, const i32 *__restrict__ L, i64 n,
+                            i32 *__restrict__ N, i32 *__restrict__ D)
+{
+    NODE_LOOP(n)
+    {
+        i32 u = (i32)u_;
+        if (!cyc[u] || L[comp[u]] < 2) continue;
+        bool end = comp[u] == u;  // the cycle minimum
+        N[u] = end ? u : a[u];
+        D[u] = end ? 0 : 1;
+    }
+}
+
+__global__ void k_rank_step(const i32 *__restrict__ comp, const uint8_t *__restrict__ cyc,
+                            const i32 *__restrict__ L, i64 n, const i32 *__restrict__ Ni,
+                            const i32 *__restrict__ Di, i32 *__restrict__ No,
+                            i32 *__restrict__ Do, int *__restrict__ changed)
+{
+    NODE_LOOP(n)
+    {
+        i32 u = (i32)u_;
+        if (!cyc[u] || L[comp[u]] < 2) continue;
+        i32 x = Ni[u];
+        No[u] = Ni[x];
+        Do[u] = Di[u] + Di[x];
+        if (Ni[x] != x) *changed = 1;
+    }
+}
+
+__global__ void k_rank_pos(const i32 *__restrict__ comp, const uint8_t *__restrict__ cyc,
+                           const i32 *__restrict__ L, i64 n, const i32 *__restrict__ D,
+                           i32 *__restrict__ pos)
+{
+    NODE_LOOP(n)
+    {
+        i32 u = (i32)u_;
+        if (!cyc[u]) continue;
+        i32 l = L[comp[u]];
+        pos[u] = l < 2 ? 0 : (D[u] == 0 ? 0 : l - D[u]);
+    }
+}
+
+// ------------------------------------------------------------------ forest
+__global__ void k_forest_init(const i32 *__restrict__ a, const uint8_t *__restrict__ cyc,
+                              const i32 *__restrict__ comp, const uint8_t *__restrict__ act,
+                              i64 n, i32 *__restrict__ J0, i32 *__restrict__ D)
+{
+    NODE_LOOP(n)
+    {
+        i32 u = (i32)u_;
+        if (!act[comp[u]]) continue;
+        bool root = cyc[u] != 0;
+        J0[u] = root ? u : a[u];
+        D[u] = root ? 0 : 1;
+    }
+}
+
+__global__ void k_forest_step(const i32 *__restrict__ comp, const uint8_t *__restrict__ act,
+                              i64 n, const i32 *__restrict__ Jk, i32 *__restrict__ Jk1,
+                              const i32 *__restrict__ Di, i32 *__restrict__ Do,
+                              int *__restrict__ changed)
+{
+    NODE_LOOP(n)
+    {
+        i32 u = (i32)u_;
+        if (!act[comp[u]]) continue;
+        i32 x = Jk[u];
+        i32 y = Jk[x];
+        Jk1[u] = y;
+        Do[u] = Di[u] + Di[x];
+        if (y != x) *changed = 1;
+    }
+}
+
+// Subtree sums: S_out = S_in, then S_out[J_k(u)] += S_in[u] for depth >= 2^k.
+__global__ void k_sub_init(const i32 *__restrict__ comp, const uint8_t *__restrict__ act,
+                           i64 n, const i32 *__restrict__ v32, const i64 *__restrict__ v64,
+                           i64 *__restrict__ S)
+{
+    NODE_LOOP(n)
+    {
+        if (!act[comp[u_]]) continue;
+        S[u_] = v32 ? (i64)v32[u_] : v64[u_];
+    }
+}
+
+__global__ void k_sub_copy(const i32 *__restrict__ comp, const uint8_t *__restrict__ act,
+                           i64 n, const i64 *__restrict__ Si, i64 *__restrict__ So)
+{
+    NODE_LOOP(n)
+    {
+        if (!act[comp[u_]]) continue;
+        So[u_] = Si[u_];
+    }
+}
+
+__global__ void k_sub_scatter(const i32 *__restrict__ comp, const uint8_t *__restrict__ act,
+                              i64 n, const i32 *__restrict__ Jk, const i32 *__restrict__ depth,
+                              int step, const i64 *__restrict__ Si, i64 *__restrict__ So)
+{
+    NODE_LOOP(n)
+    {
+        i32 u = (i32)u_;
+        if (!act[comp[u]]) continue;
+        if (depth[u] >= (1 << step)) {
+            i64 v = Si[u];
+            if (v) atomicAdd((unsigned long long *)&So[Jk[u]], (unsigned long long)v);
+        }
+    }
+}
+
+__device__ __forceinline__ i32 lift(i32 u, int d, const i32 *J, i64 n)
+{
+    for (int k = 0; d; k++, d >>= 1)
+        if (d & 1) u = J[(i64)k * n + u];
+    return u;
+}
+
+__device__ __forceinline__ i32 lca(i32 u, i32 v, const i32 *__restrict__ depth,
+                                   const i32 *__restrict__ J, i64 n, int K)
+{
+    int du = depth[u], dv = depth[v];
+    if (du < dv) {
+        i32 t = u;
+        u = v;
+        v = t;
+        int s = du;
+        du = dv;
+        dv = s;
+    }
+    u = lift(u, du - dv, J, n);
+    if (u == v) return u;
+    for (int k = K; k >= 0; k--) {
+        i32 pu = J[(i64)k * n + u], pv = J[(i64)k * n + v];
+        if (pu != pv) {
+            u = pu;
+            v = pv;
+        }
+    }
+    return J[u];
+}
+
+// val[lca(u,v)] -= A_uv for every ordered pair (u,v), u != v, of one tree of
+// an active community (flat pass over CSR entries with their row ids).
+__global__ void k_lca_pass(const i32 *__restrict__ src, const int2 *__restrict__ e, i64 nnz,
+                           const i32 *__restrict__ comp, const uint8_t *__restrict__ act,
+                           const i32 *__restrict__ root, const i32 *__restrict__ depth,
+                           const i32 *__restrict__ J, i64 n, int K, i64 *__restrict__ val)
+{
+    for (i64 j = (i64)blockIdx.x * blockDim.x + threadIdx.x; j < nnz;
+         j += (i64)gridDim.x * blockDim.x) {
+        i32 u = src[j];
+        i32 c = comp[u];
+        if (!act[c]) continue;
+        int2 ed = e[j];
+        i32 v = ed.x;
+        if (v == u || comp[v] != c || root[v] != root[u]) continue;
+        i32 l = lca(u, v, depth, J, n, K);
+        atomicAdd((unsigned long long *)&val[l], (unsigned long long)(-(i64)ed.y));
+    }
+}
+
+// ------------------------------------------------------------------ POSITIVE
+// Per-community accumulators of the communities being examined are reset.
+__global__ void k_pos_reset(const i32 *__restrict__ comp, const uint8_t *__restrict__ exam,
+                            i64 n, i32 *__restrict__ sig, i32 *__restrict__ claim,
+                            uint8_t *__restrict__ act, i64 *__restrict__ bestkey,
+                            u64 *__restrict__ bestpair)
+{
+    NODE_LOOP(n)
+    {
+        i32 c = comp[u_];
+        if (!exam[c]) continue;
+        sig[c] = 0;
+        claim[c] = 0;
+        act[c] = 0;
+        bestkey[c] = INT64_MIN;
+        bestpair[c] = ~0ull;
+    }
+}
+
+__global__ void k_pos_sigma(const i32 *__restrict__ comp, const uint8_t *__restrict__ exam,
+                            const i32 *__restrict__ k, i64 n, i32 *__restrict__ sig)
+{
+    NODE_LOOP(n)
+    {
+        i32 c = comp[u_];
+        if (exam[c] && k[u_]) atomicAdd(&sig[c], k[u_]);
+    }
+}
+
+// g(u) = M2*(wc - A_uu) - k*(S_c - k).  The first node of a community with a
+// negative gain claims it: the community becomes active, is counted, and a
+// cycle of two or more nodes reserves (L+1)(L+2) slots of the cycle
+// matrices and L slots of the cycle node lists.
+__global__ void k_pos_gain(const i32 *__restrict__ comp, const uint8_t *__restrict__ exam,
+                           const i32 *__restrict__ k, const i32 *__restrict__ diag,
+                           const i32 *__restrict__ wc, const i32 *__restrict__ sig,
+                           const i32 *__restrict__ L, i64 m2, i64 n, i32 *__restrict__ claim,
+                           uint8_t *__restrict__ act, i64 *__restrict__ counters,
+                           i64 *__restrict__ woff, i64 *__restrict__ noff,
+                           i32 *__restrict__ mlist)
+{
+    NODE_LOOP(n)
+    {
+        i32 u = (i32)u_;
+        i32 c = comp[u];
+        if (!exam[c]) continue;
+        i64 ku = k[u];
+        i64 g = m2 * (i64)(wc[u] - diag[u]) - ku * ((i64)sig[c] - ku);
+        if (g >= 0) continue;
+        if (atomicExch(&claim[c], 1) != 0) continue;
+        act[c] = 1;
+        atomicAdd((unsigned long long *)&counters[0], 1ull);
+        i32 l = L[c];
+        if (l >= 2) {
+            woff[c] = (i64)atomicAdd((unsigned long long *)&counters[1],
+                                     (unsigned long long)((i64)(l + 1) * (l + 2)));
+            noff[c] = (i64)atomicAdd((unsigned long long *)&counters[3], (unsigned long long)l);
+            i64 idx = (i64)atomicAdd((unsigned long long *)&counters[2], 1ull);
+            mlist[idx] = c;
+        }
+    }
+}
+
+// Branch cut at non-cycle x: one side is the subtree T_x.
+__global__ void k_pos_branch_keys(const i32 *__restrict__ comp, const uint8_t *__restrict__ act,
+                                  const uint8_t *__restrict__ cyc, const i64 *__restrict__ subk,
+                                  const i64 *__restrict__ cut, const i32 *__restrict__ sig,
+                                  i64 m2, i64 n, i64 *__restrict__ key, i64 *__restrict__ bestkey)
+{
+    NODE_LOOP(n)
+    {
+        i32 c = comp[u_];
+        if (!act[c] || cyc[u_]) continue;
+        i64 s = subk[u_];
+        i64 kk = s * ((i64)sig[c] - s) - m2 * cut[u_];
+        key[u_] = kk;
+        atomic_max_i64(&bestkey[c], kk);
+    }
+}
+
+__global__ void k_pos_branch_ties(const i32 *__restrict__ comp, const uint8_t *__restrict__ act,
+                                  const uint8_t *__restrict__ cyc, const i64 *__restrict__ key,
+                                  const i64 *__restrict__ bestkey, i64 n,
+                                  u64 *__restrict__ bestpair)
+{
+    NODE_LOOP(n)
+    {
+        i32 c = comp[u_];
+        if (!act[c] || cyc[u_]) continue;
+        if (key[u_] == bestkey[c]) atomic_min_u64(&bestpair[c], ((u64)u_ << 32) | (u64)u_);
+    }
+}
+
+// Cycle node lists of the active multi-node cycles, by cycle position.
+__global__ void k_pos_cnode(const i32 *__restrict__ comp, const uint8_t *__restrict__ act,
+                            const uint8_t *__restrict__ cyc, const i32 *__restrict__ L,
+                            const i32 *__restrict__ pos, const i64 *__restrict__ noff, i64 n,
+                            i32 *__restrict__ cnode)
+{
+    NODE_LOOP(n)
+    {
+        i32 c = comp[u_];
+        if (!act[c] || !cyc[u_] || L[c] < 2) continue;
+        cnode[noff[c] + pos[u_]] = (i32)u_;
+    }
+}
+
+// W_c[j+1][l+1] += A_uv for entries between the hanging trees at cycle
+// positions j != l of an active multi-node cycle.
+__global__ void k_pos_wmat(const i32 *__restrict__ src, const int2 *__restrict__ e, i64 nnz,
+                           const i32 *__restrict__ comp, const uint8_t *__restrict__ act,
+                           const i32 *__restrict__ L, const i32 *__restrict__ root,
+                           const i32 *__restrict__ pos, const i64 *__restrict__ woff,
+                           i64 *__restrict__ W)
+{
+    for (i64 j = (i64)blockIdx.x * blockDim.x + threadIdx.x; j < nnz;
+         j += (i64)gridDim.x * blockDim.x) {
+        i32 u = src[j];
+        i32 c = comp[u];
+        if (!act[c]) continue;
+        i32 l = L[c];
+        if (l < 2) continue;
+        int2 ed = e[j];
+        i32 v = ed.x;
+        if (comp[v] != c) continue;
+        i32 ru = root[u], rv = root[v];
+        if (ru == rv) continue;
+        i64 idx = woff[c] + (i64)(pos[ru] + 1) * (l + 1) + (pos[rv] + 1);
+        atomicAdd((unsigned long long *)&W[idx], (unsigned long long)(i64)ed.y);
+    }
+}
+
+// One workgroup per active multi-node cycle: 2-D prefix sums of W_c, then
+// every cut pair (c_p, c_q), p < q; the side of positions p+1..q is Y.
+// Block layout: (L+1)^2 matrix entries, then L+1 prefix sums of the
+// hanging-tree totals.
+__global__ __launch_bounds__(SLM_BS) void k_pos_cycle_eval(
+    const i32 *__restrict__ mlist, const i32 *__restrict__ L, const i64 *__restrict__ woff,
+    const i64 *__restrict__ noff, const i32 *__restrict__ cnode, const i64 *__restrict__ subk,
+    const i32 *__restrict__ sig, i64 m2, i64 *__restrict__ W, i64 *__restrict__ bestkey,
+    i64 *__restrict__ cbest_key, u64 *__restrict__ cbest_pair)
+{
+    __shared__ i64 red[32];
+    const i32 c = mlist[blockIdx.x];
+    const int l = L[c];
+    const int l1 = l + 1;
+    i64 *P = W + woff[c];
+    i64 *PH = P + (i64)l1 * l1;
+    const i32 *cn = cnode + noff[c];
+    // rows, then columns: P[i][j] = sum over i' < i, j' < j of W
+    for (int i = threadIdx.x; i < l1; i += blockDim.x)
+        for (int j = 1; j < l1; j++) P[(i64)i * l1 + j] += P[(i64)i * l1 + j - 1];
+    __syncthreads();
+    for (int j = threadIdx.x; j < l1; j += blockDim.x)
+        for (int i = 1; i < l1; i++) P[(i64)i * l1 + j] += P[(i64)(i - 1) * l1 + j];
+    if (threadIdx.x == 0) {
+        PH[0] = 0;
+        for (int j = 0; j < l; j++) PH[j + 1] = PH[j] + subk[cn[j]];
+    }
+    __syncthreads();
+    const i64 sc = sig[c];
+    i64 bk = INT64_MIN;
+    u64 bp = ~0ull;
+    for (i64 t = threadIdx.x; t < (i64)l * l; t += blockDim.x) {
+        int p = (int)(t / l), q = (int)(t % l);
+        if (q <= p) continue;
+        i64 sy = PH[q + 1] - PH[p + 1];
+        i64 rows = P[(i64)(q + 1) * l1 + l] - P[(i64)(p + 1) * l1 + l];
+        i64 blk = P[(i64)(q + 1) * l1 + (q + 1)] - P[(i64)(p + 1) * l1 + (q + 1)] -
+                  P[(i64)(q + 1) * l1 + (p + 1)] + P[(i64)(p + 1) * l1 + (p + 1)];
+        i64 kk = sy * (sc - sy) - m2 * (rows - blk);
+        i32 x = cn[p], y = cn[q];
+        u64 pr = x < y ? (((u64)x << 32) | (u64)y) : (((u64)y << 32) | (u64)x);
+        if (kk > bk || (kk == bk && pr < bp)) {
+            bk = kk;
+            bp = pr;
+        }
+    }
+    // workgroup best: key desc, then first asc, then second asc
+    i32 hi = bk == INT64_MIN ? INT32_MAX : (i32)(bp >> 32);
+    i32 lo = bk == INT64_MIN ? INT32_MAX : (i32)(bp & 0xffffffffu);
+    i64 kb = bk;
+    i32 hb = hi;
+    block_best(kb, hb, red);
+    i64 k2 = (bk == kb && hi == hb) ? 0 : INT64_MIN;
+    i32 lb = (bk == kb && hi == hb) ? lo : INT32_MAX;
+    block_best(k2, lb, red);
+    if (threadIdx.x == 0) {
+        cbest_key[c] = kb;
+        cbest_pair[c] = ((u64)(u32)hb << 32) | (u64)(u32)lb;
+        atomic_max_i64(&bestkey[c], kb);
+    }
+}
+
+__global__ void k_pos_cycle_ties(const i32 *__restrict__ mlist, i64 count,
+                                 const i64 *__restrict__ cbest_key,
+                                 const u64 *__restrict__ cbest_pair,
+                                 const i64 *__restrict__ bestkey, u64 *__restrict__ bestpair)
+{
+    i64 t = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= count) return;
+    i32 c = mlist[t];
+    if (cbest_key[c] == bestkey[c]) atomic_min_u64(&bestpair[c], cbest_pair[c]);
+}
+
+// The chosen cut nodes become self-assigned.
+__global__ void k_pos_apply(const i32 *__restrict__ comp, const uint8_t *__restrict__ act, i64 n,
+                            const u64 *__restrict__ bestpair, i32 *__restrict__ a)
+{
+    NODE_LOOP(n)
+    {
+        i32 c = comp[u_];
+        if (!act[c]) continue;
+        u64 pr = bestpair[c];
+        if (pr == ~0ull) continue;  // no candidate (cannot happen for >= 2 nodes)
+        i32 x = (i32)(pr >> 32), y = (i32)(pr & 0xffffffffu);
+        if ((i32)u_ == x || (i32)u_ == y) a[u_] = (i32)u_;
+    }
+}
+
+// New community ids after the cuts: a branch cut gives T_x the id x; a cycle
+// cut gives the two sides the ids of their new roots.  Cycle flags and
+// cycle lengths follow; both sides are examined in the next round.
+__global__ void k_pos_relabel(i32 *__restrict__ comp, const uint8_t *__restrict__ act, i64 n,
+                              const u64 *__restrict__ bestpair, uint8_t *__restrict__ cyc,
+                              const i32 *__restrict__ depth, const i32 *__restrict__ root,
+                              const i32 *__restrict__ J, const i32 *__restrict__ pos,
+                              i32 *__restrict__ L, uint8_t *__restrict__ exam_next)
+{
+    NODE_LOOP(n)
+    {
+        i32 u = (i32)u_;
+        i32 c = comp[u];
+        if (!act[c]) continue;
+        u64 pr = bestpair[c];
+        if (pr == ~0ull) continue;  // no candidate (cannot happen for >= 2 nodes)
+        i32 x = (i32)(pr >> 32), y = (i32)(pr & 0xffffffffu);
+        i32 nc;
+        if (x == y) {
+            bool in = root[u] == root[x] && depth[u] >= depth[x] &&
+                      lift(u, depth[u] - depth[x], J, n) == x;
+            nc = in ? x : c;
+            if (u == x) {
+                cyc[u] = 1;
+                L[x] = 1;
+            }
+        } else {
+            i32 cp = x, cq = y;
+            int p = pos[x], q = pos[y];
+            if (p > q) {
+                int t = p;
+                p = q;
+                q = t;
+                cp = y;
+                cq = x;
+            }
+            int pr_ = pos[root[u]];
+            bool inY = pr_ > p && pr_ <= q;
+            nc = inY ? cq : cp;
+            if (cyc[u]) cyc[u] = (u == x || u == y);
+            if (u == x || u == y) L[u] = 1;
+        }
+        comp[u] = nc;
+        exam_next[nc] = 1;
+    }
+}
+
+// ------------------------------------------------------------------ MAXIMAL tails
+__global__ void k_sigma(const i32 *__restrict__ lab, const i32 *__restrict__ k, i64 n,
+                        i32 *__restrict__ sig)
+{
+    NODE_LOOP(n) if (k[u_]) atomicAdd(&sig[lab[u_]], k[u_]);
+}
+
+// act[c]: community c holds a non-cycle candidate (its forest is needed);
+// hasc[c]: c holds any candidate; ccnt[c]: its cycle candidates.
+__global__ void k_max_cand(const i32 *__restrict__ lab, const i32 *__restrict__ best_c,
+                           const uint8_t *__restrict__ cyc, i64 n, uint8_t *__restrict__ act,
+                           uint8_t *__restrict__ hasc, i32 *__restrict__ ccnt,
+                           i64 *__restrict__ counters)
+{
+    NODE_LOOP(n)
+    {
+        i32 c = lab[u_];
+        if (best_c[u_] == c) continue;
+        hasc[c] = 1;
+        if (cyc[u_]) atomicAdd(&ccnt[c], 1);
+        else act[c] = 1;
+        atomicAdd((unsigned long long *)&counters[0], 1ull);
+    }
+}
+
+__global__ void k_max_clist(const i32 *__restrict__ lab, const i32 *__restrict__ best_c,
+                            const uint8_t *__restrict__ cyc, i64 n, const i64 *__restrict__ coff,
+                            i32 *__restrict__ cfill, i32 *__restrict__ clist)
+{
+    NODE_LOOP(n)
+    {
+        i32 c = lab[u_];
+        if (best_c[u_] == c || !cyc[u_]) continue;
+        i32 t = atomicAdd(&cfill[c], 1);
+        clist[coff[c] + t] = (i32)u_;
+    }
+}
+
+// Nearest non-cycle candidate ancestor-or-self (first marked ancestor by
+// doubling); -1 when none lies below the cycle.
+__global__ void k_nca_init(const i32 *__restrict__ lab, const uint8_t *__restrict__ act,
+                           const i32 *__restrict__ best_c, const uint8_t *__restrict__ cyc,
+                           const i32 *__restrict__ P, i64 n, i32 *__restrict__ F)
+{
+    NODE_LOOP(n)
+    {
+        i32 u = (i32)u_;
+        i32 c = lab[u];
+        if (!act[c] || cyc[u]) {
+            F[u] = -1;
+            continue;
+        }
+        bool marked = best_c[u] != c;
+        i32 p = P[u];
+        F[u] = marked ? u : (cyc[p] ? -1 : p);
+    }
+}
+
+__global__ void k_nca_step(const i32 *__restrict__ lab, const i32 *__restrict__ best_c, i64 n,
+                           const i32 *__restrict__ Fi, i32 *__restrict__ Fo)
+{
+    NODE_LOOP(n)
+    {
+        i32 f = Fi[u_];
+        if (f < 0 || best_c[f] != lab[f]) Fo[u_] = f;
+        else Fo[u_] = Fi[f];
+    }
+}
+
+// w(B, D) of every candidate: each cross entry (u, v), D = lab v, adds its
+// weight to the candidates whose tail holds u and whose target is D.
+__global__ void k_max_cross(const i32 *__restrict__ src, const int2 *__restrict__ e, i64 nnz,
+                            const i32 *__restrict__ lab, const uint8_t *__restrict__ hasc,
+                            const uint8_t *__restrict__ act, const i32 *__restrict__ nca,
+                            const i32 *__restrict__ P, const i32 *__restrict__ best_c,
+                            const i64 *__restrict__ coff, const i32 *__restrict__ clist,
+                            i32 *__restrict__ wbd)
+{
+    for (i64 j = (i64)blockIdx.x * blockDim.x + threadIdx.x; j < nnz;
+         j += (i64)gridDim.x * blockDim.x) {
+        i32 u = src[j];
+        i32 c = lab[u];
+        if (!hasc[c]) continue;
+        int2 ed = e[j];
+        i32 D = lab[ed.x];
+        if (D == c) continue;
+        if (act[c]) {
+            i32 x = nca[u];
+            // every step climbs strictly; the bound only guards the loop
+            for (int guard = 0; x >= 0 && guard < (1 << 30); guard++) {
+                if (best_c[x] == D) atomicAdd(&wbd[x], ed.y);
+                x = nca[P[x]];
+            }
+        }
+        for (i64 t = coff[c]; t < coff[c + 1]; t++) {
+            i32 z = clist[t];
+            if (best_c[z] == D) atomicAdd(&wbd[z], ed.y);
+        }
+    }
+}
+
+__device__ __forceinline__ u32 accept_draw(u64 seed, int level, int round, i32 node)
+{
+    // SplitMix64 (Steele, Lea & Flood 2014): output number ctr+1 of the stream
+    // seeded with `seed`, ctr = level:16 | round:16 | node:32; high half.
+    u64 ctr = ((u64)(uint16_t)level << 48) | ((u64)(uint16_t)round << 32) | (u64)(u32)node;
+    u64 z = seed + (ctr + 1ull) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z = z ^ (z >> 31);
+    return (u32)(z >> 32);
+}
+
+// move(B: c -> D) > 0 decides validity; valid moves draw.
+__global__ void k_max_valid(const i32 *__restrict__ lab, const i32 *__restrict__ best_c,
+                            const uint8_t *__restrict__ cyc, const i32 *__restrict__ sig,
+                            const i64 *__restrict__ subk, const i64 *__restrict__ cut,
+                            const i32 *__restrict__ wbd, i64 m2, i64 n, u64 seed, int level,
+                            int round, u64 accept_p, uint8_t *__restrict__ accept,
+                            i64 *__restrict__ counters)
+{
+    NODE_LOOP(n)
+    {
+        i32 i = (i32)u_;
+        i32 c = lab[i], D = best_c[i];
+        accept[i] = 0;
+        if (D == c) continue;
+        i64 sb, cb;
+        if (cyc[i]) {
+            sb = sig[c];
+            cb = 0;
+        } else {
+            sb = subk[i];
+            cb = cut[i];
+        }
+        i64 mv = m2 * ((i64)wbd[i] - cb) - sb * ((i64)sig[D] - (i64)sig[c] + sb);
+        if (mv <= 0) continue;
+        atomicAdd((unsigned long long *)&counters[1], 1ull);
+        if ((u64)accept_draw(seed, level, round, i) < accept_p) {
+            accept[i] = 1;
+            atomicAdd((unsigned long long *)&counters[2], 1ull);
+        }
+    }
+}
+
+// ------------------------------------------------------------------ modularity / compose
+__global__ void k_nq_parts(const i32 *__restrict__ wc, i64 n, const i32 *__restrict__ sig,
+                           i64 nc, i64 *__restrict__ acc)
+{
+    __shared__ i64 red[32];
+    i64 a = 0, b = 0;
+    for (i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x; i < n || i < nc;
+         i += (i64)gridDim.x * blockDim.x) {
+        if (i < n) a += wc[i];
+        if (i < nc) b += (i64)sig[i] * (i64)sig[i];
+    }
+    a = block_sum<i64>(a, red);
+    b = block_sum<i64>(b, red);
+    if (threadIdx.x == 0) {
+        atomicAdd((unsigned long long *)&acc[0], (unsigned long long)a);
+        atomicAdd((unsigned long long *)&acc[1], (unsigned long long)b);
+    }
+}
+
+__global__ void k_compose(i32 *__restrict__ composed, const i32 *__restrict__ lab, i64 n0)
+{
+    NODE_LOOP(n0) composed[u_] = lab[composed[u_]];
+}
+
+// ================================================================== host side
+void read_scalars(Work &W, const i64 *dev, int n, hipStream_t s)
+{
+    HIPCHK(hipMemcpyAsync(W.h_scal, dev, sizeof(i64) * n, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+}
+
+static int read_changed(Work &W, hipStream_t s)
+{
+    HIPCHK(hipMemcpyAsync(W.h_scal, W.changed, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return *(int *)W.h_scal;
+}
+
+static int ceil_log2(i64 n)
+{
+    int k = 0;
+    while (((i64)1 << k) < n) k++;
+    return k;
+}
+
+i64 canonical_labels(Work &W, i64 n, hipStream_t s)
+{
+    const unsigned g = node_grid(n);
+    launch_fill_i32(W.minm, INT32_MAX, n, s);
+    k_minmember<<<g, SLM_BS, 0, s>>>(W.comp, n, W.minm);
+    k_head<<<g, SLM_BS, 0, s>>>(W.comp, W.minm, n, W.head);
+    launch_scan_u8(W.head, W.rank, n, W.scan_tmp, s);
+    k_label<<<g, SLM_BS, 0, s>>>(W.comp, W.minm, W.rank, n, W.lab);
+    read_scalars(W, W.rank + n, 1, s);
+    return W.h_scal[0];
+}
+
+i64 components(Work &W, const i32 *a, i64 n, bool want_lab, hipStream_t s)
+{
+    if (n == 0) return 0;
+    const unsigned g = node_grid(n);
+    const int K = ceil_log2(n) + 1;
+    i32 *A = W.A0, *M = W.M0, *A2 = W.A1, *M2 = W.M1;
+    k_comp_init<<<g, SLM_BS, 0, s>>>(a, n, A, M);
+    for (int k = 0; k < K; k++) {
+        k_comp_step<<<g, SLM_BS, 0, s>>>(A, M, A2, M2, n);
+        i32 *t = A;
+        A = A2;
+        A2 = t;
+        t = M;
+        M = M2;
+        M2 = t;
+    }
+    launch_fill_u8(W.cyc, 0, n, s);
+    k_comp_mark<<<g, SLM_BS, 0, s>>>(A, M, n, W.comp, W.cyc);
+    if (!want_lab) return -1;
+    return canonical_labels(W, n, s);
+}
+
+// Forest of the active communities: jump tables J_0..J_K, depth, root.
+static Forest build_forest(Work &W, const i32 *a, const i32 *comp, const uint8_t *act, i64 n,
+                           hipStream_t s)
+{
+    const unsigned g = node_grid(n);
+    k_forest_init<<<g, SLM_BS, 0, s>>>(a, W.cyc, comp, act, n, W.J, W.D0);
+    i32 *Di = W.D0, *Do = W.D1;
+    int k = 0;
+    while (true) {
+        if (k + 1 >= W.kmax) throw SlmError{4, "assignment forest deeper than the jump tables"};
+        HIPCHK(hipMemsetAsync(W.changed, 0, sizeof(int), s));
+        k_forest_step<<<g, SLM_BS, 0, s>>>(comp, act, n, W.J + (i64)k * n, W.J + (i64)(k + 1) * n,
+                                           Di, Do, W.changed);
+        i32 *t = Di;
+        Di = Do;
+        Do = t;
+        if (!read_changed(W, s)) break;
+        k++;
+    }
+    // J_k now maps every node to its root and Di holds exact depths
+    Forest F;
+    F.K = k;
+    F.depth = Di;
+    F.root = W.J + (i64)k * n;
+    return F;
+}
+
+// out = subtree sums of v over the forest (doubling scatter).
+static void subtree_sums(Work &W, const i32 *comp, const uint8_t *act, i64 n, const Forest &F,
+                         const i32 *v32, const i64 *v64, i64 *out, hipStream_t s)
+{
+    const unsigned g = node_grid(n);
+    i64 *Si = W.S0, *So = W.S1;
+    k_sub_init<<<g, SLM_BS, 0, s>>>(comp, act, n, v32, v64, Si);
+    for (int k = 0; k <= F.K; k++) {
+        k_sub_copy<<<g, SLM_BS, 0, s>>>(comp, act, n, Si, So);
+        k_sub_scatter<<<g, SLM_BS, 0, s>>>(comp, act, n, W.J + (i64)k * n, F.depth, k, Si, So);
+        i64 *t = Si;
+        Si = So;
+        So = t;
+    }
+    HIPCHK(hipMemcpyAsync(out, Si, sizeof(i64) * n, hipMemcpyDeviceToDevice, s));
+}
+
+// cut(T_x) = w(T_x, c \ T_x) for every node of the active communities:
+// subtree sums of w(u, c \ u) minus, at every lowest common ancestor, the
+// weight of the tree pairs meeting there.
+static void subtree_cuts(Work &W, const LevelView &Lv, const i32 *comp, const uint8_t *act,
+                         const Forest &F, const i32 *w_other, i64 *cut, hipStream_t s)
+{
+    const i64 n = Lv.n;
+    const unsigned g = node_grid(n);
+    i64 *val = W.key;  // temporary
+    k_sub_init<<<g, SLM_BS, 0, s>>>(comp, act, n, w_other, nullptr, val);
+    if (Lv.nnz > 0)
+        k_lca_pass<<<node_grid(Lv.nnz), SLM_BS, 0, s>>>(W.src, Lv.e, Lv.nnz, comp, act, F.root,
+                                                        F.depth, W.J, n, F.K, val);
+    subtree_sums(W, comp, act, n, F, nullptr, val, cut, s);
+}
+
+// w(u, c \ u) = wc - A_uu for the active nodes (into W.best_c as scratch).
+__global__ void k_w_other(const i32 *__restrict__ comp, const uint8_t *__restrict__ act,
+                          const i32 *__restrict__ wc, const i32 *__restrict__ diag, i64 n,
+                          i32 *__restrict__ out)
+{
+    NODE_LOOP(n)
+    {
+        if (!act[comp[u_]]) continue;
+        out[u_] = wc[u_] - diag[u_];
+    }
+}
+
+i64 positive(Work &W, const LevelView &Lv, const Bins &B, i64 *nc_out, hipStream_t s)
+{
+    const i64 n = Lv.n;
+    if (n == 0) {
+        *nc_out = 0;
+        return 0;
+    }
+    const unsigned g = node_grid(n);
+    // cycle lengths and positions of the multi-node cycles (comp = cycle minimum)
+    launch_fill_i32(W.L, 0, n, s);
+    k_cyc_len<<<g, SLM_BS, 0, s>>>(W.comp, W.cyc, n, W.L);
+    k_rank_init<<<g, SLM_BS, 0, s>>>(W.a, W.comp, W.cyc, W.L, n, W.A0, W.D0);
+    {
+        i32 *Ni = W.A0, *No = W.A1, *Di = W.D0, *Do = W.D1;
+        while (true) {
+            HIPCHK(hipMemsetAsync(W.changed, 0, sizeof(int), s));
+            k_rank_step<<<g, SLM_BS, 0, s>>>(W.comp, W.cyc, W.L, n, Ni, Di, No, Do, W.changed);
+            i32 *t = Ni;
+            Ni = No;
+            No = t;
+            t = Di;
+            Di = Do;
+            Do = t;
+            if (!read_changed(W, s)) break;
+        }
+        k_rank_pos<<<g, SLM_BS, 0, s>>>(W.comp, W.cyc, W.L, n, Di, W.pos);
+    }
+    launch_fill_u8(W.exam, 1, n, s);
+    i64 splits = 0;
+    const i64 entries = Lv.nnz;
+    for (i64 rounds = 0;; rounds++) {
+        // every round adds at least one community, so n rounds bound the loop
+        if (rounds > n) throw SlmError{4, "POSITIVE made no progress"};
+        k_pos_reset<<<g, SLM_BS, 0, s>>>(W.comp, W.exam, n, W.sigma, W.claim, W.act, W.bestkey,
+                                         W.bestpair);
+        k_pos_sigma<<<g, SLM_BS, 0, s>>>(W.comp, W.exam, Lv.k, n, W.sigma);
+        run_own_weight(Lv, B, W.comp, W.exam, W.wc, s);
+        launch_fill_i64(W.counters, 0, 8, s);
+        k_pos_gain<<<g, SLM_BS, 0, s>>>(W.comp, W.exam, Lv.k, Lv.diag, W.wc, W.sigma, W.L, Lv.m2,
+                                        n, W.claim, W.act, W.counters, W.woff, W.noff, W.mlist);
+        read_scalars(W, W.counters, 4, s);
+        const i64 flagged = W.h_scal[0], wtotal = W.h_scal[1], nmulti = W.h_scal[2];
+        if (flagged == 0) break;
+        Forest F = build_forest(W, W.a, W.comp, W.act, n, s);
+        subtree_sums(W, W.comp, W.act, n, F, Lv.k, nullptr, W.subk, s);
+        k_w_other<<<g, SLM_BS, 0, s>>>(W.comp, W.act, W.wc, Lv.diag, n, W.best_c);
+        subtree_cuts(W, Lv, W.comp, W.act, F, W.best_c, W.cut, s);
+        k_pos_branch_keys<<<g, SLM_BS, 0, s>>>(W.comp, W.act, W.cyc, W.subk, W.cut, W.sigma,
+                                               Lv.m2, n, W.key, W.bestkey);
+        if (nmulti > 0) {
+            if (wtotal > W.W_cap) {
+                if (W.W) HIPCHK(hipFree(W.W));
+                W.W = nullptr;
+                i64 cap = wtotal + wtotal / 2 + 1024;
+                HIPCHK(hipMalloc(&W.W, sizeof(i64) * cap));
+                W.W_cap = cap;
+            }
+            launch_fill_i64(W.W, 0, wtotal, s);
+            k_pos_cnode<<<g, SLM_BS, 0, s>>>(W.comp, W.act, W.cyc, W.L, W.pos, W.noff, n, W.cnode);
+            if (entries > 0)
+                k_pos_wmat<<<node_grid(entries), SLM_BS, 0, s>>>(W.src, Lv.e, entries, W.comp,
+                                                                 W.act, W.L, F.root, W.pos,
+                                                                 W.woff, W.W);
+            k_pos_cycle_eval<<<(unsigned)nmulti, SLM_BS, 0, s>>>(
+                W.mlist, W.L, W.woff, W.noff, W.cnode, W.subk, W.sigma, Lv.m2, W.W, W.bestkey,
+                W.cbest_key, W.cbest_pair);
+        }
+        k_pos_branch_ties<<<g, SLM_BS, 0, s>>>(W.comp, W.act, W.cyc, W.key, W.bestkey, n,
+                                               W.bestpair);
+        if (nmulti > 0)
+            k_pos_cycle_ties<<<grid_for(nmulti, SLM_BS), SLM_BS, 0, s>>>(
+                W.mlist, nmulti, W.cbest_key, W.cbest_pair, W.bestkey, W.bestpair);
+        k_pos_apply<<<g, SLM_BS, 0, s>>>(W.comp, W.act, n, W.bestpair, W.a);
+        launch_fill_u8(W.exam_next, 0, n, s);
+        k_pos_relabel<<<g, SLM_BS, 0, s>>>(W.comp, W.act, n, W.bestpair, W.cyc, F.depth, F.root,
+                                           W.J, W.pos, W.L, W.exam_next);
+        uint8_t *t = W.exam;
+        W.exam = W.exam_next;
+        W.exam_next = t;
+        splits += flagged;
+    }
+    *nc_out = canonical_labels(W, n, s);
+    return splits;
+}
+
+void community_totals(Work &W, const LevelView &Lv, const i32 *lab, i64 nc, hipStream_t s)
+{
+    launch_fill_i32(W.sigma, 0, nc, s);
+    if (Lv.n > 0) k_sigma<<<node_grid(Lv.n), SLM_BS, 0, s>>>(lab, Lv.k, Lv.n, W.sigma);
+}
+
+i64 maximal_moves(Work &W, const LevelView &Lv, const Bins &B, i64 nc, u64 seed, int level,
+                  int round, u64 accept_p, i64 *stats, hipStream_t s, bool timing,
+                  hipEvent_t ev0, hipEvent_t ev1, float *sweep_ms)
+{
+    const i64 n = Lv.n;
+    const unsigned g = node_grid(n);
+    community_totals(W, Lv, W.lab, nc, s);
+    if (timing) HIPCHK(hipEventRecord(ev0, s));
+    run_sweep(Lv, B, W.lab, W.sigma, W.best_c, W.delta, W.w_own, W.hub_keys, W.hub_vals,
+              W.hub_win, s);
+    if (timing) HIPCHK(hipEventRecord(ev1, s));
+    // candidates
+    launch_fill_u8(W.act, 0, nc, s);
+    launch_fill_u8(W.hasc, 0, nc, s);
+    launch_fill_i32(W.ccnt, 0, nc, s);
+    launch_fill_i64(W.counters, 0, 8, s);
+    k_max_cand<<<g, SLM_BS, 0, s>>>(W.lab, W.best_c, W.cyc, n, W.act, W.hasc, W.ccnt, W.counters);
+    read_scalars(W, W.counters, 1, s);
+    if (timing) HIPCHK(hipEventElapsedTime(sweep_ms, ev0, ev1));
+    const i64 ncand = W.h_scal[0];
+    stats[0] = ncand;
+    stats[1] = stats[2] = 0;
+    if (ncand == 0) return 0;
+    launch_scan_i32(W.ccnt, W.coff, nc, W.scan_tmp, s);
+    launch_fill_i32(W.cfill, 0, nc, s);
+    k_max_clist<<<g, SLM_BS, 0, s>>>(W.lab, W.best_c, W.cyc, n, W.coff, W.cfill, W.clist);
+    // forest of the communities with non-cycle candidates
+    Forest F = build_forest(W, W.a, W.lab, W.act, n, s);
+    subtree_sums(W, W.lab, W.act, n, F, Lv.k, nullptr, W.subk, s);
+    subtree_cuts(W, Lv, W.lab, W.act, F, W.w_own, W.cut, s);
+    // nearest candidate ancestors
+    k_nca_init<<<g, SLM_BS, 0, s>>>(W.lab, W.act, W.best_c, W.cyc, W.J, n, W.nca0);
+    i32 *Fi = W.nca0, *Fo = W.nca1;
+    for (int k = 0; k <= F.K; k++) {
+        k_nca_step<<<g, SLM_BS, 0, s>>>(W.lab, W.best_c, n, Fi, Fo);
+        i32 *t = Fi;
+        Fi = Fo;
+        Fo = t;
+    }
+    launch_fill_i32(W.wbd, 0, n, s);
+    const i64 entries = Lv.nnz;
+    if (entries > 0)
+        k_max_cross<<<node_grid(entries), SLM_BS, 0, s>>>(W.src, Lv.e, entries, W.lab, W.hasc,
+                                                        W.act, Fi, W.J, W.best_c, W.coff,
+                                                        W.clist, W.wbd);
+    k_max_valid<<<g, SLM_BS, 0, s>>>(W.lab, W.best_c, W.cyc, W.sigma, W.subk, W.cut, W.wbd,
+                                     Lv.m2, n, seed, level, round, accept_p, W.accept,
+                                     W.counters);
+    read_scalars(W, W.counters, 3, s);
+    stats[1] = W.h_scal[1];
+    stats[2] = W.h_scal[2];
+    if (stats[1] == 0) return 0;
+    run_repoint(Lv, B, W.lab, W.best_c, W.accept, W.a, W.hub_ckey, W.hub_cid, s);
+    return stats[1];
+}
+
+i64 modularity_num(Work &W, const LevelView &Lv, const Bins &B, const i32 *lab, i64 nc,
+                   hipStream_t s)
+{
+    community_totals(W, Lv, lab, nc, s);
+    run_own_weight(Lv, B, lab, nullptr, W.wc, s);
+    launch_fill_i64(W.counters, 0, 2, s);
+    i64 m = Lv.n > nc ? Lv.n : nc;
+    k_nq_parts<<<node_grid(m), SLM_BS, 0, s>>>(W.wc, Lv.n, W.sigma, nc, W.counters);
+    read_scalars(W, W.counters, 2, s);
+    return Lv.m2 * W.h_scal[0] - W.h_scal[1];
+}
+
+void compose_labels(i32 *composed, const i32 *lab, i64 n0, hipStream_t s)
+{
+    if (n0 > 0) k_compose<<<node_grid(n0), SLM_BS, 0, s>>>(composed, lab, n0);
+}

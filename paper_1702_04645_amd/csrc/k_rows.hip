@@ -1,0 +1,828 @@
+// Row kernels: every node's CSR row is handled by a group of lanes sized to
+// its degree (the degree bins of slm_impl.h).  Groups of up to 64 lanes live
+// inside one wavefront and keep their per-node community table in LDS; the
+// 4096-entry bin uses a whole 256-lane workgroup per node; hub rows are cut
+// in HUB_CHUNK-entry chunks spread over workgroups with the table in HBM.
+//
+// Kernels here: strengths (Sec. 2.4), ASSIGN (Sec. 3.1), the MAXIMAL sweep
+// and re-pointing (Sec. 3.4), own-community weights, and the per-row
+// pre-aggregation of AGGREGATE (Sec. 3.5).
+#include "slm_forest.h"
+
+// Group shapes per bin: lanes per node G and LDS table slots H (>= 2*deg).
+template <int B> struct BinShape;
+template <> struct BinShape<BIN_ZERO> { static constexpr int G = 1, H = 2; };
+template <> struct BinShape<BIN_8> { static constexpr int G = 8, H = 16; };
+template <> struct BinShape<BIN_32> { static constexpr int G = 32, H = 64; };
+template <> struct BinShape<BIN_128> { static constexpr int G = 64, H = 256; };
+template <> struct BinShape<BIN_512> { static constexpr int G = 64, H = 1024; };
+template <> struct BinShape<BIN_4096> { static constexpr int G = 256, H = 8192; };
+
+template <int G> struct GroupGeom {
+    static constexpr int NG = (G <= 64) ? SLM_BS / G : 1;  // groups per workgroup
+    static constexpr int BSZ = (G <= 64) ? SLM_BS : G;     // workgroup size
+};
+
+template <int H> __device__ __forceinline__ u32 slot_of(i32 c)
+{
+    constexpr int LOG2H = __builtin_ctz(H);
+    return LOG2H == 0 ? 0u : (hash_label(c) >> (32 - LOG2H));
+}
+
+// Orders LDS accesses of the lanes of one group.
+template <int G> __device__ __forceinline__ void group_sync()
+{
+    if constexpr (G <= 64) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    } else {
+        __syncthreads();
+    }
+}
+
+template <int G, typename T> __device__ __forceinline__ T gsum(T v, i64 *red)
+{
+    if constexpr (G == 1) return v;
+    else if constexpr (G <= 64) return group_sum<G, T>(v);
+    else return block_sum<T>(v, red);
+}
+
+template <int G> __device__ __forceinline__ void gbest(i64 &k, i32 &id, i64 *red)
+{
+    if constexpr (G == 1) return;
+    else if constexpr (G <= 64) group_best<G>(k, id);
+    else block_best(k, id, red);
+}
+
+// Exclusive scan of one int per lane over the group; *total = group sum.
+template <int G> __device__ __forceinline__ int gscan(int v, int &total, i64 *red)
+{
+    if constexpr (G == 1) {
+        total = v;
+        return 0;
+    } else if constexpr (G <= 64) {
+        const int gl = threadIdx.x & (G - 1);
+        int inc = v;
+#pragma unroll
+        for (int d = 1; d < G; d <<= 1) {
+            int t = __shfl_up(inc, d, G);
+            if (gl >= d) inc += t;
+        }
+        total = __shfl(inc, G - 1, G);
+        return inc - v;
+    } else {
+        const int lane = threadIdx.x & 63, wid = threadIdx.x / 64, nw = blockDim.x / 64;
+        int inc = v;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            int t = __shfl_up(inc, d, 64);
+            if (lane >= d) inc += t;
+        }
+        __syncthreads();
+        if (lane == 63) red[wid] = inc;
+        __syncthreads();
+        int before = 0, tot = 0;
+        for (int w = 0; w < nw; w++) {
+            if (w < wid) before += (int)red[w];
+            tot += (int)red[w];
+        }
+        __syncthreads();
+        total = tot;
+        return before + inc - v;
+    }
+}
+
+#define GROUP_PROLOGUE(G)                                                            \
+    constexpr int NG = GroupGeom<G>::NG;                                             \
+    const int gl = (int)(threadIdx.x % (G));                                         \
+    const int gi = (int)(threadIdx.x / (G));                                         \
+    const i64 slot = (i64)blockIdx.x * NG + gi;                                      \
+    const bool valid = slot < count;                                                 \
+    const i32 node = valid ? nodes[slot] : 0;
+
+// ------------------------------------------------------------------ strengths
+template <int G>
+__global__ __launch_bounds__(GroupGeom<G>::BSZ) void k_strength(
+    const i64 *__restrict__ rp, const int2 *__restrict__ e, const i32 *__restrict__ nodes,
+    i64 count, i32 *__restrict__ k, i32 *__restrict__ diag, i64 *__restrict__ m2_acc)
+{
+    __shared__ i64 red[32];
+    GROUP_PROLOGUE(G)
+    i64 s = 0, d = 0;
+    if (valid) {
+        for (i64 j = rp[node] + gl; j < rp[node + 1]; j += G) {
+            int2 ed = e[j];
+            s += ed.y;
+            if (ed.x == node) d += ed.y;
+        }
+    }
+    s = gsum<G>(s, red);
+    d = gsum<G>(d, red);
+    i64 contrib = (valid && gl == 0) ? s : 0;
+    if (valid && gl == 0) {
+        k[node] = (i32)s;
+        diag[node] = (i32)d;
+    }
+    contrib = block_sum<i64>(contrib, red);
+    if (threadIdx.x == 0 && contrib) atomicAdd((unsigned long long *)m2_acc, (unsigned long long)contrib);
+}
+
+// ------------------------------------------------------------------ ASSIGN / re-point
+// REPOINT = false: a[i] = argmax_{j != i} pair(i,j) if positive, else i.
+// REPOINT = true : for accepted i, a[i] = argmax_{j: lab j = best_c i} pair(i,j).
+template <int G, bool REPOINT>
+__global__ __launch_bounds__(GroupGeom<G>::BSZ) void k_argmax(
+    LevelView L, const i32 *__restrict__ nodes, i64 count, const i32 *__restrict__ lab,
+    const i32 *__restrict__ best_c, const uint8_t *__restrict__ accept, i32 *__restrict__ a)
+{
+    __shared__ i64 red[32];
+    GROUP_PROLOGUE(G)
+    bool active = valid;
+    if constexpr (REPOINT) active = valid && accept[node];
+    i64 bk = INT64_MIN;
+    i32 bj = INT32_MAX;
+    if (active) {
+        const i64 ki = L.k[node];
+        const i32 D = REPOINT ? best_c[node] : 0;
+        for (i64 j = L.rp[node] + gl; j < L.rp[node + 1]; j += G) {
+            int2 ed = L.e[j];
+            const i32 v = ed.x;
+            if (v == node) continue;
+            if (REPOINT && lab[v] != D) continue;
+            i64 key = L.m2 * (i64)ed.y - ki * (i64)L.k[v];
+            if (better_key(key, v, bk, bj)) {
+                bk = key;
+                bj = v;
+            }
+        }
+    }
+    gbest<G>(bk, bj, red);
+    if (active && gl == 0) {
+        if (REPOINT) a[node] = bj;
+        else a[node] = (bj != INT32_MAX && bk > 0) ? bj : node;
+    }
+}
+
+// ------------------------------------------------------------------ own-community weight
+template <int G>
+__global__ __launch_bounds__(GroupGeom<G>::BSZ) void k_own(
+    LevelView L, const i32 *__restrict__ nodes, i64 count, const i32 *__restrict__ lab,
+    const uint8_t *__restrict__ active, i32 *__restrict__ wc)
+{
+    __shared__ i64 red[32];
+    GROUP_PROLOGUE(G)
+    const i32 ci = valid ? lab[node] : 0;
+    const bool act = valid && (active == nullptr || active[ci]);
+    i64 s = 0;
+    if (act) {
+        for (i64 j = L.rp[node] + gl; j < L.rp[node + 1]; j += G) {
+            int2 ed = L.e[j];
+            if (lab[ed.x] == ci) s += ed.y;
+        }
+    }
+    s = gsum<G>(s, red);
+    if (act && gl == 0) wc[node] = (i32)s;
+}
+
+// ------------------------------------------------------------------ MAXIMAL sweep
+// Per node: w(i,C) for every neighbouring community C in an LDS
+// open-addressing table (own-community weight kept in registers), then the
+// best join(i,C) against stay(i).
+template <int G, int H>
+__global__ __launch_bounds__(GroupGeom<G>::BSZ) void k_sweep_lds(
+    LevelView L, const i32 *__restrict__ nodes, i64 count, const i32 *__restrict__ lab,
+    const i32 *__restrict__ sigma, i32 *__restrict__ best_c, i64 *__restrict__ delta,
+    i32 *__restrict__ w_own)
+{
+    constexpr int NGc = GroupGeom<G>::NG;
+    __shared__ i32 s_key[NGc * H];
+    __shared__ i32 s_val[NGc * H];
+    __shared__ i64 red[32];
+    GROUP_PROLOGUE(G)
+    i32 *keys = s_key + gi * H;
+    i32 *vals = s_val + gi * H;
+    for (int s = gl; s < H; s += G) {
+        keys[s] = -1;
+        vals[s] = 0;
+    }
+    group_sync<G>();
+    const i32 ci = valid ? lab[node] : 0;
+    const i64 ki = valid ? L.k[node] : 0;
+    i64 win = 0;
+    if (valid) {
+        const i64 e1 = L.rp[node + 1];
+        for (i64 j = L.rp[node] + gl; j < e1; j += G) {
+            int2 ed = L.e[j];
+            const i32 v = ed.x;
+            if (v == node) continue;
+            const i32 c = lab[v];
+            if (c == ci) {
+                win += ed.y;
+                continue;
+            }
+            u32 h = slot_of<H>(c);
+            for (int probe = 0; probe < H; probe++) {
+                i32 old = atomicCAS(&keys[h], -1, c);
+                if (old == -1 || old == c) {
+                    atomicAdd(&vals[h], ed.y);
+                    break;
+                }
+                h = (h + 1) & (H - 1);
+            }
+        }
+    }
+    group_sync<G>();
+    i64 bk = INT64_MIN;
+    i32 bc = INT32_MAX;
+    if (valid) {
+        for (int s = gl; s < H; s += G) {
+            const i32 c = keys[s];
+            if (c >= 0) {
+                i64 key = L.m2 * (i64)vals[s] - ki * (i64)sigma[c];
+                if (better_key(key, c, bk, bc)) {
+                    bk = key;
+                    bc = c;
+                }
+            }
+        }
+    }
+    win = gsum<G>(win, red);
+    gbest<G>(bk, bc, red);
+    if (valid && gl == 0) {
+        const i64 stay = L.m2 * win - ki * ((i64)sigma[ci] - ki);
+        if (bc != INT32_MAX && bk > stay) {
+            best_c[node] = bc;
+            delta[node] = bk - stay;
+        } else {
+            best_c[node] = ci;
+            delta[node] = 0;
+        }
+        w_own[node] = (i32)win;
+    }
+}
+
+// ------------------------------------------------------------------ contraction rows
+// Per row u: distinct (lab_u, lab_v) with summed weights (own community and
+// diagonal included), written at rec[rp[u] ..]; cnt[u] = their number.
+template <int G, int H>
+__global__ __launch_bounds__(GroupGeom<G>::BSZ) void k_crows_lds(
+    LevelView L, const i32 *__restrict__ nodes, i64 count, const i32 *__restrict__ lab,
+    int bits, u64 *__restrict__ rec_key, i32 *__restrict__ rec_w, i32 *__restrict__ cnt)
+{
+    constexpr int NGc = GroupGeom<G>::NG;
+    __shared__ i32 s_key[NGc * H];
+    __shared__ i32 s_val[NGc * H];
+    __shared__ i64 red[32];
+    GROUP_PROLOGUE(G)
+    i32 *keys = s_key + gi * H;
+    i32 *vals = s_val + gi * H;
+    for (int s = gl; s < H; s += G) {
+        keys[s] = -1;
+        vals[s] = 0;
+    }
+    group_sync<G>();
+    if (valid) {
+        const i64 e1 = L.rp[node + 1];
+        for (i64 j = L.rp[node] + gl; j < e1; j += G) {
+            int2 ed = L.e[j];
+            const i32 c = lab[ed.x];
+            u32 h = slot_of<H>(c);
+            for (int probe = 0; probe < H; probe++) {
+                i32 old = atomicCAS(&keys[h], -1, c);
+                if (old == -1 || old == c) {
+                    atomicAdd(&vals[h], ed.y);
+                    break;
+                }
+                h = (h + 1) & (H - 1);
+            }
+        }
+    }
+    group_sync<G>();
+    int mine = 0;
+    if (valid)
+        for (int s = gl; s < H; s += G) mine += keys[s] >= 0;
+    int total;
+    int pos = gscan<G>(mine, total, red);
+    if (valid) {
+        const u64 hi = (u64)(u32)lab[node] << bits;
+        const i64 base = L.rp[node];
+        for (int s = gl; s < H; s += G) {
+            const i32 c = keys[s];
+            if (c >= 0) {
+                rec_key[base + pos] = hi | (u64)(u32)c;
+                rec_w[base + pos] = vals[s];
+                pos++;
+            }
+        }
+        if (gl == 0) cnt[node] = total;
+    }
+}
+
+// ------------------------------------------------------------------ hub rows
+// One workgroup per chunk of a hub row.
+__global__ __launch_bounds__(SLM_BS) void k_hub_zero(const i32 *__restrict__ hub_node, i32 nhub,
+                                                    i32 *__restrict__ a, i32 *__restrict__ b)
+{
+    i32 h = blockIdx.x * blockDim.x + threadIdx.x;
+    if (h < nhub) {
+        a[hub_node[h]] = 0;
+        if (b) b[hub_node[h]] = 0;
+    }
+}
+
+__global__ __launch_bounds__(SLM_BS) void k_hub_strength(
+    const i64 *__restrict__ rp, const int2 *__restrict__ e, const i32 *__restrict__ hub_node,
+    const i32 *__restrict__ chunk_hub, const i64 *__restrict__ chunk_beg, i32 *__restrict__ k,
+    i32 *__restrict__ diag, i64 *__restrict__ m2_acc)
+{
+    __shared__ i64 red[32];
+    const i32 h = chunk_hub[blockIdx.x];
+    const i32 node = hub_node[h];
+    const i64 b = chunk_beg[blockIdx.x];
+    i64 end = b + HUB_CHUNK;
+    if (end > rp[node + 1]) end = rp[node + 1];
+    i64 s = 0, d = 0;
+    for (i64 j = b + threadIdx.x; j < end; j += blockDim.x) {
+        int2 ed = e[j];
+        s += ed.y;
+        if (ed.x == node) d += ed.y;
+    }
+    s = block_sum<i64>(s, red);
+    d = block_sum<i64>(d, red);
+    if (threadIdx.x == 0) {
+        atomicAdd(&k[node], (i32)s);
+        if (d) atomicAdd(&diag[node], (i32)d);
+        atomicAdd((unsigned long long *)m2_acc, (unsigned long long)s);
+    }
+}
+
+template <bool REPOINT>
+__global__ __launch_bounds__(SLM_BS) void k_hub_argmax(
+    LevelView L, const i32 *__restrict__ hub_node, const i32 *__restrict__ chunk_hub,
+    const i64 *__restrict__ chunk_beg, const i32 *__restrict__ lab,
+    const i32 *__restrict__ best_c, const uint8_t *__restrict__ accept,
+    i64 *__restrict__ chunk_key, i32 *__restrict__ chunk_id)
+{
+    __shared__ i64 red[32];
+    const i32 h = chunk_hub[blockIdx.x];
+    const i32 node = hub_node[h];
+    bool active = true;
+    if constexpr (REPOINT) active = accept[node] != 0;
+    i64 bk = INT64_MIN;
+    i32 bj = INT32_MAX;
+    if (active) {
+        const i64 b = chunk_beg[blockIdx.x];
+        i64 end = b + HUB_CHUNK;
+        if (end > L.rp[node + 1]) end = L.rp[node + 1];
+        const i64 ki = L.k[node];
+        const i32 D = REPOINT ? best_c[node] : 0;
+        for (i64 j = b + threadIdx.x; j < end; j += blockDim.x) {
+            int2 ed = L.e[j];
+            const i32 v = ed.x;
+            if (v == node) continue;
+            if (REPOINT && lab[v] != D) continue;
+            i64 key = L.m2 * (i64)ed.y - ki * (i64)L.k[v];
+            if (better_key(key, v, bk, bj)) {
+                bk = key;
+                bj = v;
+            }
+        }
+    }
+    block_best(bk, bj, red);
+    if (threadIdx.x == 0) {
+        chunk_key[blockIdx.x] = bk;
+        chunk_id[blockIdx.x] = bj;
+    }
+}
+
+template <bool REPOINT>
+__global__ __launch_bounds__(SLM_BS) void k_hub_argmax_final(
+    const i32 *__restrict__ hub_node, const i32 *__restrict__ chunk_first,
+    const uint8_t *__restrict__ accept, const i64 *__restrict__ chunk_key,
+    const i32 *__restrict__ chunk_id, i32 *__restrict__ a)
+{
+    __shared__ i64 red[32];
+    const i32 h = blockIdx.x;
+    const i32 node = hub_node[h];
+    if (REPOINT && !accept[node]) return;  // uniform over the workgroup
+    i64 bk = INT64_MIN;
+    i32 bj = INT32_MAX;
+    for (i32 c = chunk_first[h] + threadIdx.x; c < chunk_first[h + 1]; c += blockDim.x)
+        if (better_key(chunk_key[c], chunk_id[c], bk, bj)) {
+            bk = chunk_key[c];
+            bj = chunk_id[c];
+        }
+    block_best(bk, bj, red);
+    if (threadIdx.x == 0) {
+        if (REPOINT) a[node] = bj;
+        else a[node] = (bj != INT32_MAX && bk > 0) ? bj : node;
+    }
+}
+
+__global__ __launch_bounds__(SLM_BS) void k_hub_own(
+    LevelView L, const i32 *__restrict__ hub_node, const i32 *__restrict__ chunk_hub,
+    const i64 *__restrict__ chunk_beg, const i32 *__restrict__ lab,
+    const uint8_t *__restrict__ active, i32 *__restrict__ wc)
+{
+    __shared__ i64 red[32];
+    const i32 h = chunk_hub[blockIdx.x];
+    const i32 node = hub_node[h];
+    const i32 ci = lab[node];
+    if (active && !active[ci]) return;  // uniform
+    const i64 b = chunk_beg[blockIdx.x];
+    i64 end = b + HUB_CHUNK;
+    if (end > L.rp[node + 1]) end = L.rp[node + 1];
+    i64 s = 0;
+    for (i64 j = b + threadIdx.x; j < end; j += blockDim.x) {
+        int2 ed = L.e[j];
+        if (lab[ed.x] == ci) s += ed.y;
+    }
+    s = block_sum<i64>(s, red);
+    if (threadIdx.x == 0 && s) atomicAdd(&wc[node], (i32)s);
+}
+
+__global__ __launch_bounds__(SLM_BS) void k_hub_own_zero(const i32 *__restrict__ hub_node,
+                                                        i32 nhub, const i32 *__restrict__ lab,
+                                                        const uint8_t *__restrict__ active,
+                                                        i32 *__restrict__ wc)
+{
+    i32 h = blockIdx.x * blockDim.x + threadIdx.x;
+    if (h < nhub) {
+        i32 node = hub_node[h];
+        if (!active || active[lab[node]]) wc[node] = 0;
+    }
+}
+
+// Hub sweep: chunks insert (community, weight) into the hub's HBM table.
+__global__ __launch_bounds__(SLM_BS) void k_hub_sweep_insert(
+    LevelView L, const i32 *__restrict__ hub_node, const i32 *__restrict__ chunk_hub,
+    const i64 *__restrict__ chunk_beg, const i64 *__restrict__ tab_off,
+    const i32 *__restrict__ lab, i32 *__restrict__ tkey, i32 *__restrict__ tval,
+    i32 *__restrict__ hub_win)
+{
+    __shared__ i64 red[32];
+    const i32 h = chunk_hub[blockIdx.x];
+    const i32 node = hub_node[h];
+    const i32 ci = lab[node];
+    const i64 t0 = tab_off[h];
+    const u32 tmask = (u32)(tab_off[h + 1] - t0 - 1);
+    const int log2t = 32 - __builtin_clz(tmask + 1) - 1;
+    const i64 b = chunk_beg[blockIdx.x];
+    i64 end = b + HUB_CHUNK;
+    if (end > L.rp[node + 1]) end = L.rp[node + 1];
+    i64 win = 0;
+    for (i64 j = b + threadIdx.x; j < end; j += blockDim.x) {
+        int2 ed = L.e[j];
+        const i32 v = ed.x;
+        if (v == node) continue;
+        const i32 c = lab[v];
+        if (c == ci) {
+            win += ed.y;
+            continue;
+        }
+        u32 slot = hash_label(c) >> (32 - log2t);
+        for (u32 probe = 0; probe <= tmask; probe++) {
+            i32 old = atomicCAS(&tkey[t0 + slot], -1, c);
+            if (old == -1 || old == c) {
+                atomicAdd(&tval[t0 + slot], ed.y);
+                break;
+            }
+            slot = (slot + 1) & tmask;
+        }
+    }
+    win = block_sum<i64>(win, red);
+    if (threadIdx.x == 0 && win) atomicAdd(&hub_win[h], (i32)win);
+}
+
+__global__ __launch_bounds__(SLM_BS) void k_hub_sweep_final(
+    LevelView L, const i32 *__restrict__ hub_node, const i64 *__restrict__ tab_off,
+    const i32 *__restrict__ lab, const i32 *__restrict__ sigma, const i32 *__restrict__ tkey,
+    const i32 *__restrict__ tval, const i32 *__restrict__ hub_win, i32 *__restrict__ best_c,
+    i64 *__restrict__ delta, i32 *__restrict__ w_own)
+{
+    __shared__ i64 red[32];
+    const i32 h = blockIdx.x;
+    const i32 node = hub_node[h];
+    const i32 ci = lab[node];
+    const i64 ki = L.k[node];
+    i64 bk = INT64_MIN;
+    i32 bc = INT32_MAX;
+    for (i64 s = tab_off[h] + threadIdx.x; s < tab_off[h + 1]; s += blockDim.x) {
+        const i32 c = tkey[s];
+        if (c >= 0) {
+            i64 key = L.m2 * (i64)tval[s] - ki * (i64)sigma[c];
+            if (better_key(key, c, bk, bc)) {
+                bk = key;
+                bc = c;
+            }
+        }
+    }
+    block_best(bk, bc, red);
+    if (threadIdx.x == 0) {
+        const i64 win = hub_win[h];
+        const i64 stay = L.m2 * win - ki * ((i64)sigma[ci] - ki);
+        if (bc != INT32_MAX && bk > stay) {
+            best_c[node] = bc;
+            delta[node] = bk - stay;
+        } else {
+            best_c[node] = ci;
+            delta[node] = 0;
+        }
+        w_own[node] = (i32)win;
+    }
+}
+
+// Hub contraction rows: one record per entry (merged later by the sort).
+__global__ __launch_bounds__(SLM_BS) void k_hub_crows(
+    LevelView L, const i32 *__restrict__ hub_node, const i32 *__restrict__ chunk_hub,
+    const i64 *__restrict__ chunk_beg, const i32 *__restrict__ lab, int bits,
+    u64 *__restrict__ rec_key, i32 *__restrict__ rec_w, i32 *__restrict__ cnt)
+{
+    const i32 h = chunk_hub[blockIdx.x];
+    const i32 node = hub_node[h];
+    const i64 b = chunk_beg[blockIdx.x];
+    i64 end = b + HUB_CHUNK;
+    if (end > L.rp[node + 1]) end = L.rp[node + 1];
+    const u64 hi = (u64)(u32)lab[node] << bits;
+    for (i64 j = b + threadIdx.x; j < end; j += blockDim.x) {
+        int2 ed = L.e[j];
+        rec_key[j] = hi | (u64)(u32)lab[ed.x];
+        rec_w[j] = ed.y;
+    }
+    if (b == L.rp[node] && threadIdx.x == 0) cnt[node] = (i32)(L.rp[node + 1] - L.rp[node]);
+}
+
+// ------------------------------------------------------------------ bins
+__device__ __forceinline__ int bin_of_degree(i64 d)
+{
+    if (d == 0) return BIN_ZERO;
+    if (d <= 8) return BIN_8;
+    if (d <= 32) return BIN_32;
+    if (d <= 128) return BIN_128;
+    if (d <= 512) return BIN_512;
+    if (d <= 4096) return BIN_4096;
+    return BIN_HUB;
+}
+
+__global__ __launch_bounds__(SLM_BS) void k_bin_count(const i64 *__restrict__ rp, i64 n,
+                                                     i64 *__restrict__ bin_cnt)
+{
+    __shared__ int cnt[NBINS];
+    if (threadIdx.x < NBINS) cnt[threadIdx.x] = 0;
+    __syncthreads();
+    i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) atomicAdd(&cnt[bin_of_degree(rp[i + 1] - rp[i])], 1);
+    __syncthreads();
+    if (threadIdx.x < NBINS && cnt[threadIdx.x])
+        atomicAdd((unsigned long long *)&bin_cnt[threadIdx.x], (unsigned long long)cnt[threadIdx.x]);
+}
+
+// bin_fill[b] starts at the bin's offset; waves reserve runs of consecutive ids.
+__global__ __launch_bounds__(SLM_BS) void k_bin_scatter(const i64 *__restrict__ rp, i64 n,
+                                                       i64 *__restrict__ bin_fill,
+                                                       i32 *__restrict__ bin_nodes)
+{
+    i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+    const int b = i < n ? bin_of_degree(rp[i + 1] - rp[i]) : -1;
+    const int lane = threadIdx.x & 63;
+    for (int bb = 0; bb < NBINS; bb++) {
+        u64 mask = __ballot(b == bb);
+        if (!mask) continue;
+        const int leader = __ffsll((unsigned long long)mask) - 1;
+        i64 base = 0;
+        if (lane == leader)
+            base = (i64)atomicAdd((unsigned long long *)&bin_fill[bb], (unsigned long long)__popcll(mask));
+        base = __shfl(base, leader, 64);
+        if (b == bb) {
+            const u64 below = mask & ((1ull << lane) - 1ull);
+            bin_nodes[base + __popcll(below)] = (i32)i;
+        }
+    }
+}
+
+// span[2h], span[2h+1] = first and one-past-last entry of hub h's row.
+__global__ void k_hub_degrees(const i64 *__restrict__ rp, const i32 *__restrict__ hub_node,
+                              i32 nhub, i64 *__restrict__ span)
+{
+    i32 h = blockIdx.x * blockDim.x + threadIdx.x;
+    if (h < nhub) {
+        span[2 * h] = rp[hub_node[h]];
+        span[2 * h + 1] = rp[hub_node[h] + 1];
+    }
+}
+
+void launch_bin_count(const i64 *rp, i64 n, i64 *bin_cnt, hipStream_t s)
+{
+    if (n > 0) k_bin_count<<<grid_for(n, SLM_BS), SLM_BS, 0, s>>>(rp, n, bin_cnt);
+}
+void launch_bin_scatter(const i64 *rp, i64 n, i64 *bin_fill, i32 *bin_nodes, hipStream_t s)
+{
+    if (n > 0) k_bin_scatter<<<grid_for(n, SLM_BS), SLM_BS, 0, s>>>(rp, n, bin_fill, bin_nodes);
+}
+void launch_hub_degrees(const i64 *rp, const i32 *hub_node, i32 nhub, i64 *deg_out, hipStream_t s)
+{
+    if (nhub > 0) k_hub_degrees<<<grid_for(nhub, SLM_BS), SLM_BS, 0, s>>>(rp, hub_node, nhub, deg_out);
+}
+
+// ------------------------------------------------------------------ dispatch
+template <int B>
+static void bin_launch_geom(const Bins &Bn, i64 &count, const i32 *&nodes, unsigned &grid,
+                            unsigned &block)
+{
+    constexpr int G = BinShape<B>::G;
+    count = Bn.off[B + 1] - Bn.off[B];
+    nodes = Bn.nodes + Bn.off[B];
+    grid = grid_for(count, GroupGeom<G>::NG);
+    block = GroupGeom<G>::BSZ;
+}
+
+#define FOR_LDS_BINS(X) X(BIN_ZERO) X(BIN_8) X(BIN_32) X(BIN_128) X(BIN_512) X(BIN_4096)
+
+void run_strength_binned(const i64 *rp, const int2 *e, const Bins &Bn, i32 *k, i32 *diag,
+                         i64 *m2_acc, hipStream_t s)
+{
+#define X(B)                                                                          \
+    {                                                                                 \
+        i64 cnt;                                                                      \
+        const i32 *nd;                                                                \
+        unsigned gr, bl;                                                              \
+        bin_launch_geom<B>(Bn, cnt, nd, gr, bl);                                      \
+        if (cnt > 0)                                                                  \
+            k_strength<BinShape<B>::G><<<gr, bl, 0, s>>>(rp, e, nd, cnt, k, diag, m2_acc); \
+    }
+    FOR_LDS_BINS(X)
+#undef X
+    if (Bn.nhub > 0) {
+        k_hub_zero<<<grid_for(Bn.nhub, SLM_BS), SLM_BS, 0, s>>>(Bn.hub_node, Bn.nhub, k, diag);
+        k_hub_strength<<<(unsigned)Bn.nchunk, SLM_BS, 0, s>>>(rp, e, Bn.hub_node, Bn.chunk_hub,
+                                                             Bn.chunk_beg, k, diag, m2_acc);
+    }
+}
+
+void run_assign(const LevelView &L, const Bins &Bn, i32 *a, i64 *hub_key, i32 *hub_id,
+                hipStream_t s)
+{
+#define X(B)                                                                          \
+    {                                                                                 \
+        i64 cnt;                                                                      \
+        const i32 *nd;                                                                \
+        unsigned gr, bl;                                                              \
+        bin_launch_geom<B>(Bn, cnt, nd, gr, bl);                                      \
+        if (cnt > 0)                                                                  \
+            k_argmax<BinShape<B>::G, false><<<gr, bl, 0, s>>>(L, nd, cnt, nullptr, nullptr, \
+                                                              nullptr, a);            \
+    }
+    FOR_LDS_BINS(X)
+#undef X
+    if (Bn.nhub > 0) {
+        k_hub_argmax<false><<<(unsigned)Bn.nchunk, SLM_BS, 0, s>>>(
+            L, Bn.hub_node, Bn.chunk_hub, Bn.chunk_beg, nullptr, nullptr, nullptr, hub_key, hub_id);
+        k_hub_argmax_final<false><<<(unsigned)Bn.nhub, SLM_BS, 0, s>>>(
+            Bn.hub_node, Bn.chunk_off_of_hub, nullptr, hub_key, hub_id, a);
+    }
+}
+
+void run_repoint(const LevelView &L, const Bins &Bn, const i32 *lab, const i32 *best_c,
+                 const uint8_t *accept, i32 *a, i64 *hub_key, i32 *hub_id, hipStream_t s)
+{
+#define X(B)                                                                          \
+    {                                                                                 \
+        i64 cnt;                                                                      \
+        const i32 *nd;                                                                \
+        unsigned gr, bl;                                                              \
+        bin_launch_geom<B>(Bn, cnt, nd, gr, bl);                                      \
+        if (cnt > 0 && B != BIN_ZERO)                                                 \
+            k_argmax<BinShape<B>::G, true><<<gr, bl, 0, s>>>(L, nd, cnt, lab, best_c, accept, a); \
+    }
+    FOR_LDS_BINS(X)
+#undef X
+    if (Bn.nhub > 0) {
+        k_hub_argmax<true><<<(unsigned)Bn.nchunk, SLM_BS, 0, s>>>(
+            L, Bn.hub_node, Bn.chunk_hub, Bn.chunk_beg, lab, best_c, accept, hub_key, hub_id);
+        k_hub_argmax_final<true><<<(unsigned)Bn.nhub, SLM_BS, 0, s>>>(
+            Bn.hub_node, Bn.chunk_off_of_hub, accept, hub_key, hub_id, a);
+    }
+}
+
+void run_own_weight(const LevelView &L, const Bins &Bn, const i32 *lab, const uint8_t *active,
+                    i32 *wc, hipStream_t s)
+{
+#define X(B)                                                                          \
+    {                                                                                 \
+        i64 cnt;                                                                      \
+        const i32 *nd;                                                                \
+        unsigned gr, bl;                                                              \
+        bin_launch_geom<B>(Bn, cnt, nd, gr, bl);                                      \
+        if (cnt > 0) k_own<BinShape<B>::G><<<gr, bl, 0, s>>>(L, nd, cnt, lab, active, wc); \
+    }
+    FOR_LDS_BINS(X)
+#undef X
+    if (Bn.nhub > 0) {
+        k_hub_own_zero<<<grid_for(Bn.nhub, SLM_BS), SLM_BS, 0, s>>>(Bn.hub_node, Bn.nhub, lab,
+                                                                   active, wc);
+        k_hub_own<<<(unsigned)Bn.nchunk, SLM_BS, 0, s>>>(L, Bn.hub_node, Bn.chunk_hub,
+                                                        Bn.chunk_beg, lab, active, wc);
+    }
+}
+
+void run_sweep(const LevelView &L, const Bins &Bn, const i32 *lab, const i32 *sigma,
+               i32 *best_c, i64 *delta, i32 *w_own, i32 *hub_keys, i32 *hub_vals,
+               i32 *hub_win, hipStream_t s)
+{
+#define X(B)                                                                          \
+    {                                                                                 \
+        i64 cnt;                                                                      \
+        const i32 *nd;                                                                \
+        unsigned gr, bl;                                                              \
+        bin_launch_geom<B>(Bn, cnt, nd, gr, bl);                                      \
+        if (cnt > 0)                                                                  \
+            k_sweep_lds<BinShape<B>::G, BinShape<B>::H><<<gr, bl, 0, s>>>(            \
+                L, nd, cnt, lab, sigma, best_c, delta, w_own);                        \
+    }
+    FOR_LDS_BINS(X)
+#undef X
+    if (Bn.nhub > 0) {
+        launch_fill_i32(hub_keys, -1, Bn.table_total, s);
+        launch_fill_i32(hub_vals, 0, Bn.table_total, s);
+        launch_fill_i32(hub_win, 0, Bn.nhub, s);
+        k_hub_sweep_insert<<<(unsigned)Bn.nchunk, SLM_BS, 0, s>>>(
+            L, Bn.hub_node, Bn.chunk_hub, Bn.chunk_beg, Bn.hub_tab_off, lab, hub_keys, hub_vals,
+            hub_win);
+        k_hub_sweep_final<<<(unsigned)Bn.nhub, SLM_BS, 0, s>>>(L, Bn.hub_node, Bn.hub_tab_off, lab,
+                                                              sigma, hub_keys, hub_vals, hub_win,
+                                                              best_c, delta, w_own);
+    }
+}
+
+void run_contract_rows(const LevelView &L, const Bins &Bn, const i32 *lab, int lab_bits,
+                       u64 *rec_key, i32 *rec_w, i32 *cnt, hipStream_t s)
+{
+#define X(B)                                                                          \
+    {                                                                                 \
+        i64 c_;                                                                       \
+        const i32 *nd;                                                                \
+        unsigned gr, bl;                                                              \
+        bin_launch_geom<B>(Bn, c_, nd, gr, bl);                                       \
+        if (c_ > 0)                                                                   \
+            k_crows_lds<BinShape<B>::G, BinShape<B>::H><<<gr, bl, 0, s>>>(            \
+                L, nd, c_, lab, lab_bits, rec_key, rec_w, cnt);                       \
+    }
+    FOR_LDS_BINS(X)
+#undef X
+    if (Bn.nhub > 0)
+        k_hub_crows<<<(unsigned)Bn.nchunk, SLM_BS, 0, s>>>(L, Bn.hub_node, Bn.chunk_hub,
+                                                          Bn.chunk_beg, lab, lab_bits, rec_key,
+                                                          rec_w, cnt);
+}
+
+// ------------------------------------------------------------------ row ids of the entries
+template <int G>
+__global__ __launch_bounds__(GroupGeom<G>::BSZ) void k_src(const i64 *__restrict__ rp,
+                                                          const i32 *__restrict__ nodes,
+                                                          i64 count, i32 *__restrict__ src)
+{
+    GROUP_PROLOGUE(G)
+    if (valid)
+        for (i64 j = rp[node] + gl; j < rp[node + 1]; j += G) src[j] = node;
+}
+
+__global__ __launch_bounds__(SLM_BS) void k_hub_src(const i64 *__restrict__ rp,
+                                                   const i32 *__restrict__ hub_node,
+                                                   const i32 *__restrict__ chunk_hub,
+                                                   const i64 *__restrict__ chunk_beg,
+                                                   i32 *__restrict__ src)
+{
+    const i32 node = hub_node[chunk_hub[blockIdx.x]];
+    const i64 b = chunk_beg[blockIdx.x];
+    i64 end = b + HUB_CHUNK;
+    if (end > rp[node + 1]) end = rp[node + 1];
+    for (i64 j = b + threadIdx.x; j < end; j += blockDim.x) src[j] = node;
+}
+
+void fill_src(const LevelView &L, const Bins &Bn, i32 *src, hipStream_t s)
+{
+#define X(B)                                                                          \
+    {                                                                                 \
+        i64 cnt;                                                                      \
+        const i32 *nd;                                                                \
+        unsigned gr, bl;                                                              \
+        bin_launch_geom<B>(Bn, cnt, nd, gr, bl);                                      \
+        if (cnt > 0 && B != BIN_ZERO) k_src<BinShape<B>::G><<<gr, bl, 0, s>>>(L.rp, nd, cnt, src); \
+    }
+    FOR_LDS_BINS(X)
+#undef X
+    if (Bn.nhub > 0)
+        k_hub_src<<<(unsigned)Bn.nchunk, SLM_BS, 0, s>>>(L.rp, Bn.hub_node, Bn.chunk_hub,
+                                                        Bn.chunk_beg, src);
+}
+
+i64 level_strengths(Work &W, const i64 *rp, const int2 *e, const Bins &B, i64 n, i32 *k,
+                    i32 *diag, hipStream_t s)
+{
+    (void)n;
+    launch_fill_i64(W.counters, 0, 1, s);
+    run_strength_binned(rp, e, B, k, diag, W.counters, s);
+    read_scalars(W, W.counters, 1, s);
+    return W.h_scal[0];
+}

@@ -1,0 +1,109 @@
+// Work space of a handle and the host-side steps built on the forest
+// kernels (components, POSITIVE, MAXIMAL resolution) and on the contraction
+// kernels.
+#pragma once
+
+#include "slm_impl.h"
+
+struct Work {
+    i64 n0 = 0, nnz0 = 0;
+    int kmax = 0;  // number of jump tables held
+
+    // per node (n0 entries)
+    i32 *a = nullptr, *lab = nullptr, *comp = nullptr, *best_c = nullptr, *w_own = nullptr;
+    i32 *wc = nullptr, *sigma = nullptr, *k = nullptr, *diag = nullptr;
+    i64 *delta = nullptr;
+    uint8_t *cyc = nullptr, *act = nullptr, *hasc = nullptr, *exam = nullptr,
+            *exam_next = nullptr, *accept = nullptr, *head = nullptr;
+    i32 *claim = nullptr, *L = nullptr, *pos = nullptr, *cnode = nullptr, *mlist = nullptr;
+    i32 *A0 = nullptr, *A1 = nullptr, *M0 = nullptr, *M1 = nullptr;
+    i32 *J = nullptr;  // kmax tables of n0
+    i32 *D0 = nullptr, *D1 = nullptr;
+    i64 *S0 = nullptr, *S1 = nullptr, *subk = nullptr, *cut = nullptr, *key = nullptr;
+    i64 *bestkey = nullptr, *cbest_key = nullptr, *woff = nullptr, *noff = nullptr;
+    u64 *bestpair = nullptr, *cbest_pair = nullptr;
+    i32 *nca0 = nullptr, *nca1 = nullptr, *wbd = nullptr;
+    i32 *ccnt = nullptr, *cfill = nullptr, *clist = nullptr;
+    i64 *coff = nullptr;
+    i32 *minm = nullptr;
+    i64 *rank = nullptr;    // n0 + 1
+    i64 *scan_tmp = nullptr;
+    i64 *W = nullptr;       // cycle matrices (grown on demand)
+    i64 W_cap = 0;
+
+    i64 *counters = nullptr;  // device, 8 entries
+    int *changed = nullptr;   // device flag
+    i64 *h_scal = nullptr;    // pinned host, 16 entries
+
+    // per entry (nnz0)
+    i32 *src = nullptr;  // row of every CSR entry
+    u64 *rk0 = nullptr, *rk1 = nullptr;
+    i32 *rv0 = nullptr, *rv1 = nullptr;
+    i32 *cnt = nullptr;   // n0
+    i64 *roff = nullptr;  // n0 + 1
+    i64 *hist = nullptr;  // radix histograms
+    i64 hist_cap = 0;
+    uint8_t *head_e = nullptr; // nnz0 segment heads
+    i64 *rank_e = nullptr;     // nnz0 + 1
+
+    // hub work space
+    i32 *hub_keys = nullptr, *hub_vals = nullptr, *hub_win = nullptr;
+    i64 hub_tab_cap = 0;
+    i64 hub_win_cap = 0;
+    i64 *hub_ckey = nullptr;
+    i32 *hub_cid = nullptr;
+    i64 hub_chunk_cap = 0;
+};
+
+struct Forest {
+    int K = 0;            // highest jump table index in use
+    i32 *depth = nullptr;
+    i32 *root = nullptr;
+};
+
+// Reads n device int64 values into W.h_scal (synchronises the stream).
+void read_scalars(Work &W, const i64 *dev, int n, hipStream_t s);
+
+// COMPONENTS (Sec. 3.2) of the assignment a: W.comp = cycle minimum of every
+// node's component, W.cyc = cycle flags; with want_lab also the canonical
+// labels W.lab.  Returns n_c (only when want_lab, else -1).
+i64 components(Work &W, const i32 *a, i64 n, bool want_lab, hipStream_t s);
+
+// Canonical labels of the node-id community ids in W.comp; returns n_c.
+i64 canonical_labels(Work &W, i64 n, hipStream_t s);
+
+// POSITIVE (Sec. 3.3) on W.a (modified).  Expects W.comp / W.cyc from
+// components(); leaves W.lab canonical.  Returns splits; *nc = n_c.
+i64 positive(Work &W, const LevelView &Lv, const Bins &B, i64 *nc, hipStream_t s);
+
+// One MAXIMAL round (Sec. 3.4) on W.a with the canonical labels W.lab (n_c
+// communities): sweep, tails, validity, draws, re-pointing.  Returns the
+// number of valid moves (0: nothing changed); stats[0..2] = candidates,
+// valid, accepted.
+i64 maximal_moves(Work &W, const LevelView &Lv, const Bins &B, i64 nc, u64 seed, int level,
+                  int round, u64 accept_p, i64 *stats, hipStream_t s, bool timing,
+                  hipEvent_t ev0, hipEvent_t ev1, float *sweep_ms);
+
+// Community totals S_C (canonical labels).
+void community_totals(Work &W, const LevelView &Lv, const i32 *lab, i64 nc, hipStream_t s);
+
+// Modularity numerator N_Q of the labelling lab (Sec. 2.4).
+i64 modularity_num(Work &W, const LevelView &Lv, const Bins &B, const i32 *lab, i64 nc,
+                   hipStream_t s);
+
+// composed[v] = lab[composed[v]]
+void compose_labels(i32 *composed, const i32 *lab, i64 n0, hipStream_t s);
+
+// Row ids of every CSR entry.
+void fill_src(const LevelView &Lv, const Bins &B, i32 *src, hipStream_t s);
+
+// AGGREGATE (Sec. 3.5): contraction of the level into rp_out / e_out
+// (n_c rows); returns the entry count.
+i64 contract_level(Work &W, const LevelView &Lv, const Bins &B, const i32 *lab, i64 nc,
+                   i64 *rp_out, int2 *e_out, hipStream_t s);
+
+// Strengths and diagonal of the level; returns M2.
+i64 level_strengths(Work &W, const i64 *rp, const int2 *e, const Bins &B, i64 n, i32 *k,
+                    i32 *diag, hipStream_t s);
+void run_strength_binned(const i64 *rp, const int2 *e, const Bins &Bn, i32 *k, i32 *diag,
+                         i64 *m2_acc, hipStream_t s);

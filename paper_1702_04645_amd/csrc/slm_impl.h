@@ -1,0 +1,186 @@
+// Internal declarations of the gfx950 implementation of the Synchronised
+// Louvain Method.  Device helpers, the level view handed to kernels, and the
+// host-side launchers each kernel file provides.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+typedef int64_t i64;
+typedef int32_t i32;
+typedef uint32_t u32;
+typedef uint64_t u64;
+
+#define SLM_WAVE 64
+#define SLM_BS 256
+
+// ---------------------------------------------------------------- errors
+struct SlmError {
+    int status;
+    std::string msg;
+};
+#define HIPCHK(call)                                                                  \
+    do {                                                                              \
+        hipError_t e_ = (call);                                                       \
+        if (e_ != hipSuccess)                                                         \
+            throw SlmError{4, std::string(#call) + ": " + hipGetErrorString(e_)};     \
+    } while (0)
+
+// ---------------------------------------------------------------- degree bins
+// A node is handled by a group of lanes sized to its degree.  Bins 1..5 keep
+// the per-node community table in LDS; bin 6 ("hub") rows are split in
+// chunks of HUB_CHUNK entries spread over many workgroups, with the table in
+// HBM.  Bin 0 holds isolated nodes.
+enum { BIN_ZERO = 0, BIN_8, BIN_32, BIN_128, BIN_512, BIN_4096, BIN_HUB, NBINS };
+static const i64 kBinMaxDeg[NBINS] = {0, 8, 32, 128, 512, 4096, INT64_MAX};
+#define HUB_CHUNK 4096
+
+struct Bins {
+    i32 *nodes = nullptr;      // device: node ids grouped by bin
+    i64 off[NBINS + 1] = {0};  // host: bin b = nodes[off[b] .. off[b+1])
+    // hub rows: work items (hub index, first entry) and per-hub tables
+    i32 nhub = 0;
+    i64 nchunk = 0;
+    i64 table_total = 0;       // sum of the hubs' table sizes
+    i32 *hub_node = nullptr;   // device [nhub]
+    i64 *hub_tab_off = nullptr;// device [nhub+1] offsets into the HBM tables
+    i32 *chunk_hub = nullptr;  // device [nchunk] hub index of each chunk
+    i64 *chunk_beg = nullptr;  // device [nchunk] first entry of each chunk
+    i32 *chunk_off_of_hub = nullptr; // device [nhub+1] first chunk of each hub
+};
+
+// Read-only view of one level's graph as the kernels see it.
+struct LevelView {
+    const i64 *rp;   // n+1 offsets
+    const int2 *e;   // nnz entries: x = column, y = weight
+    const i32 *k;    // strengths
+    const i32 *diag; // A_ii (0 if absent)
+    i64 n;
+    i64 nnz;
+    i64 m2;
+};
+
+// ---------------------------------------------------------------- device helpers
+__device__ __forceinline__ bool better_key(i64 k1, i32 id1, i64 k2, i32 id2)
+{
+    return k1 > k2 || (k1 == k2 && id1 < id2);
+}
+
+__device__ __forceinline__ u32 hash_label(i32 c)
+{
+    return (u32)c * 0x9E3779B1u;
+}
+
+// Sum over a group of G lanes (G a power of two, at most 64).
+template <int G, typename T>
+__device__ __forceinline__ T group_sum(T v)
+{
+#pragma unroll
+    for (int off = G / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, G);
+    return v;
+}
+
+// Best (key desc, id asc) over a group of G lanes (G <= 64).
+template <int G>
+__device__ __forceinline__ void group_best(i64 &key, i32 &id)
+{
+#pragma unroll
+    for (int off = G / 2; off > 0; off >>= 1) {
+        i64 ok = __shfl_xor(key, off, G);
+        i32 oi = __shfl_xor(id, off, G);
+        if (better_key(ok, oi, key, id)) {
+            key = ok;
+            id = oi;
+        }
+    }
+}
+
+// Workgroup-wide best (key desc, id asc); every thread gets the result.
+// scratch: at least 2 * (blockDim/64) slots of i64.
+__device__ __forceinline__ void block_best(i64 &key, i32 &id, i64 *scratch)
+{
+    group_best<64>(key, id);
+    const int wid = threadIdx.x / 64, nw = blockDim.x / 64;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) {
+        scratch[2 * wid] = key;
+        scratch[2 * wid + 1] = id;
+    }
+    __syncthreads();
+    key = scratch[0];
+    id = (i32)scratch[1];
+    for (int w = 1; w < nw; w++) {
+        i64 k2 = scratch[2 * w];
+        i32 i2 = (i32)scratch[2 * w + 1];
+        if (better_key(k2, i2, key, id)) {
+            key = k2;
+            id = i2;
+        }
+    }
+    __syncthreads();
+}
+
+template <typename T>
+__device__ __forceinline__ T block_sum(T v, i64 *scratch)
+{
+    v = group_sum<64>(v);
+    const int wid = threadIdx.x / 64, nw = blockDim.x / 64;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) scratch[wid] = (i64)v;
+    __syncthreads();
+    T s = 0;
+    for (int w = 0; w < nw; w++) s += (T)scratch[w];
+    __syncthreads();
+    return s;
+}
+
+static inline unsigned grid_for(i64 items, int per_block)
+{
+    i64 g = (items + per_block - 1) / per_block;
+    if (g < 1) g = 1;
+    return (unsigned)g;
+}
+
+// ---------------------------------------------------------------- utilities (k_util.hip)
+void launch_fill_i32(i32 *p, i32 v, i64 n, hipStream_t s);
+void launch_fill_i64(i64 *p, i64 v, i64 n, hipStream_t s);
+void launch_fill_u8(uint8_t *p, uint8_t v, i64 n, hipStream_t s);
+void launch_iota_i32(i32 *p, i64 n, hipStream_t s);
+// out[0..n] = exclusive prefix sums of in[0..n-1], out[n] = total.
+// tmp: at least scan_tmp_elems(n) i64.
+i64 scan_tmp_elems(i64 n);
+void launch_scan_i32(const i32 *in, i64 *out, i64 n, i64 *tmp, hipStream_t s);
+void launch_scan_i64(const i64 *in, i64 *out, i64 n, i64 *tmp, hipStream_t s);
+void launch_scan_u8(const uint8_t *in, i64 *out, i64 n, i64 *tmp, hipStream_t s);
+
+// ---------------------------------------------------------------- level setup (k_rows.hip)
+void launch_bin_count(const i64 *rp, i64 n, i64 *bin_cnt, hipStream_t s);
+void launch_bin_scatter(const i64 *rp, i64 n, i64 *bin_fill, i32 *bin_nodes, hipStream_t s);
+// span_out[2h], span_out[2h+1] = entry range of hub h's row.
+void launch_hub_degrees(const i64 *rp, const i32 *hub_node, i32 nhub, i64 *span_out,
+                        hipStream_t s);
+
+// ---------------------------------------------------------------- row kernels (k_rows.hip)
+// ASSIGN (Sec. 3.1): a[i] = best neighbour or i.
+void run_assign(const LevelView &L, const Bins &B, i32 *a, i64 *hub_key, i32 *hub_id,
+                hipStream_t s);
+// MAXIMAL sweep (Sec. 3.4): best_c, delta, w_own from labels and totals.
+void run_sweep(const LevelView &L, const Bins &B, const i32 *lab, const i32 *sigma,
+               i32 *best_c, i64 *delta, i32 *w_own, i32 *hub_keys, i32 *hub_vals,
+               i32 *hub_win, hipStream_t s);
+// wc[i] = sum of A_ij over j with lab[j] == lab[i] (diagonal included); only
+// for nodes with active[lab[i]] != 0 when active is given.
+void run_own_weight(const LevelView &L, const Bins &B, const i32 *lab, const uint8_t *active,
+                    i32 *wc, hipStream_t s);
+// Re-pointing (Sec. 3.4): for nodes with accept[i], a[i] = argmax over
+// neighbours j with lab[j] == best_c[i] of pair(i,j), ties to the lowest j.
+void run_repoint(const LevelView &L, const Bins &B, const i32 *lab, const i32 *best_c,
+                 const uint8_t *accept, i32 *a, i64 *hub_key, i32 *hub_id, hipStream_t s);
+// Contraction records of every row: distinct (lab_u, lab_v) pairs with summed
+// weights, written at rec_key/rec_w[rp[u] ..]; cnt[u] = their number.
+void run_contract_rows(const LevelView &L, const Bins &B, const i32 *lab, int lab_bits,
+                       u64 *rec_key, i32 *rec_w, i32 *cnt, hipStream_t s);
+

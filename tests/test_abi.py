@@ -1,0 +1,55 @@
+"""Host-side checks of the C-ABI library: it loads, exports every entry
+point include/slm.h declares, and rejects bad arguments before touching a
+device."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared():
+    src = open(os.path.join(ROOT, "include", "slm.h")).read()
+    return sorted(set(re.findall(r"\b(slm_[a-z_]+)\s*\(", src)))
+
+
+def test_header_declares_the_boundary():
+    names = declared()
+    for must in ("slm_create", "slm_sweep", "slm_contract", "slm_run", "slm_destroy"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    import paper_1702_04645_amd as slm
+    lib = slm.lib()
+    for name in declared():
+        assert hasattr(lib, name), name
+
+
+def test_invalid_arguments_are_rejected_without_a_device():
+    import paper_1702_04645_amd as slm
+    lib = slm.lib()
+    h = C.c_void_p()
+    rp = np.zeros(3, np.int64)
+    # bad row_ptr width
+    st = lib.slm_create(2, 0, rp.ctypes.data_as(C.c_void_p), 3, None, None, 0, 1, None,
+                        C.byref(h))
+    assert st == slm.SLM_E_INVALID and b"row_ptr" in lib.slm_last_error()
+    # negative size
+    st = lib.slm_create(-1, 0, rp.ctypes.data_as(C.c_void_p), 8, None, None, 0, 1, None,
+                        C.byref(h))
+    assert st == slm.SLM_E_INVALID
+    # n too large
+    st = lib.slm_create(1 << 31, 0, rp.ctypes.data_as(C.c_void_p), 8, None, None, 0, 1, None,
+                        C.byref(h))
+    assert st == slm.SLM_E_OVERFLOW
+    # missing entries
+    st = lib.slm_create(2, 2, rp.ctypes.data_as(C.c_void_p), 8, None, None, 0, 1, None,
+                        C.byref(h))
+    assert st == slm.SLM_E_INVALID
+    p = slm.Params()
+    lib.slm_params_default(C.byref(p))
+    assert p.accept_p == 1 << 31 and p.max_rounds == 64 and p.validate == 1
