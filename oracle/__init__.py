@@ -50,6 +50,7 @@ def _load():
         "or_positive": (i64, [i64, P, P, P, P, i64, P]),
         "or_sweep": (None, [i64, P, P, P, P, i64, P, i64, P, P, P]),
         "or_maximal_round": (i64, [i64, P, P, P, P, i64, P, u64, i32, i32, u64, P]),
+        "or_maximal_round_ex": (i64, [i64, P, P, P, P, i64, P, u64, i32, i32, u64, P, P]),
         "or_modularity_num": (i64, [i64, P, P, P, P, i64, P, i64]),
         "or_modularity": (C.c_double, [i64, i64]),
         "or_contract": (i64, [i64, P, P, P, P, i64, P, P, P]),
@@ -140,15 +141,20 @@ def sweep(g: Graph, lab: np.ndarray, nc: int):
 
 
 def maximal_round(g: Graph, a: np.ndarray, seed: int, level: int, rnd: int,
-                  accept_p: int = DEFAULT_ACCEPT):
+                  accept_p: int = DEFAULT_ACCEPT, with_repointed: bool = False):
     """One MAXIMAL round followed by POSITIVE on a copy of ``a``.
-    Returns (new assignment, valid count, stats dict)."""
+    Returns (new assignment, valid count, stats dict); with_repointed adds the
+    assignment after the re-pointing, before POSITIVE."""
     a = np.array(a, dtype=np.int32, copy=True)
+    rep = np.array(a, dtype=np.int32, copy=True)
     st = np.zeros(4, np.int64)
-    valid = int(_load().or_maximal_round(*g._g(), g.m2, _p(a), seed & (2**64 - 1), level,
-                                         rnd, accept_p, _p(st)))
-    return a, valid, dict(candidates=int(st[0]), valid=int(st[1]), accepted=int(st[2]),
-                          splits=int(st[3]))
+    valid = int(_load().or_maximal_round_ex(*g._g(), g.m2, _p(a), seed & (2**64 - 1), level,
+                                            rnd, accept_p, _p(st), _p(rep)))
+    stats = dict(candidates=int(st[0]), valid=int(st[1]), accepted=int(st[2]),
+                 splits=int(st[3]))
+    if with_repointed:
+        return a, valid, stats, rep
+    return a, valid, stats
 
 
 def modularity_num(g: Graph, lab: np.ndarray, nc: int) -> int:

@@ -684,10 +684,26 @@ static void free_forest(forest *F)
  * applied together; the communities then are the components of the new
  * assignment graph, and POSITIVE runs on them.
  * stats (optional, 4 entries): candidates, valid, accepted, splits. */
+int64_t or_maximal_round_ex(int64_t n, const int64_t *rp, const int32_t *col,
+                            const int32_t *w, const int64_t *k, int64_t m2,
+                            int32_t *a, uint64_t seed, int32_t level, int32_t round,
+                            uint64_t accept_p, int64_t *stats, int32_t *a_repointed);
+
 int64_t or_maximal_round(int64_t n, const int64_t *rp, const int32_t *col,
                          const int32_t *w, const int64_t *k, int64_t m2,
                          int32_t *a, uint64_t seed, int32_t level, int32_t round,
                          uint64_t accept_p, int64_t *stats)
+{
+    return or_maximal_round_ex(n, rp, col, w, k, m2, a, seed, level, round, accept_p, stats,
+                               NULL);
+}
+
+/* As or_maximal_round; a_repointed (optional) receives the assignment after
+ * the re-pointing and before POSITIVE (unchanged when no move is valid). */
+int64_t or_maximal_round_ex(int64_t n, const int64_t *rp, const int32_t *col,
+                            const int32_t *w, const int64_t *k, int64_t m2,
+                            int32_t *a, uint64_t seed, int32_t level, int32_t round,
+                            uint64_t accept_p, int64_t *stats, int32_t *a_repointed)
 {
     int32_t *lab = xmalloc((size_t)n * sizeof(int32_t));
     int64_t nc = or_components(n, a, lab, NULL);
@@ -760,7 +776,10 @@ int64_t or_maximal_round(int64_t n, const int64_t *rp, const int32_t *col,
         }
         memcpy(a, a_new, (size_t)n * sizeof(int32_t));
         free(a_new);
+        if (a_repointed) memcpy(a_repointed, a, (size_t)n * sizeof(int32_t));
         splits = or_positive(n, rp, col, w, k, m2, a);
+    } else if (a_repointed) {
+        memcpy(a_repointed, a, (size_t)n * sizeof(int32_t));
     }
     if (stats) {
         stats[0] = n_cand;

@@ -231,6 +231,30 @@ static void alloc_work(slm_graph *g)
     W.cfill = dalloc<i32>(g, n);
     W.clist = dalloc<i32>(g, n);
     W.coff = dalloc<i64>(g, n + 1);
+    W.fidx = dalloc<i32>(g, n);
+    W.flist = dalloc<i32>(g, n);
+    W.fcnt = dalloc<i32>(g, n);
+    W.flen = dalloc<i32>(g, n);
+    W.mem = dalloc<i32>(g, n);
+    W.ptmp = dalloc<i32>(g, n);
+    W.pord = dalloc<i32>(g, n);
+    W.pchl = dalloc<i32>(g, 2 * n);
+    W.plvl = dalloc<i32>(g, 2 * n + 1);
+    W.part = dalloc<i32>(g, n);
+    W.win = dalloc<i32>(g, n);
+    W.psub = dalloc<i32>(g, n);
+    W.pcut = dalloc<i32>(g, n);
+    W.pdep = dalloc<i32>(g, n);
+    W.proot = dalloc<i32>(g, n);
+    W.chs = dalloc<i32>(g, n);
+    W.chc = dalloc<i32>(g, n);
+    W.mem_off = dalloc<i64>(g, n + 1);
+    W.pdp = dalloc<i64>(g, 2 * n + 1);
+    W.woff_f = dalloc<i64>(g, n + 1);
+    W.noff_f = dalloc<i64>(g, n + 1);
+    W.wsz = dalloc<i64>(g, n);
+    W.nsz = dalloc<i64>(g, n);
+    W.pstk = dalloc<int4>(g, n);
     W.minm = dalloc<i32>(g, n);
     W.rank = dalloc<i64>(g, n + 1);
     W.scan_tmp = dalloc<i64>(g, scan_tmp_elems(std::max(n, nnz) + 1) + 16);

@@ -80,10 +80,6 @@ __global__ void k_comp_mark(const i32 *__restrict__ A, const i32 *__restrict__ M
 }
 
 // ------------------------------------------------------------------ canonical labels
-__global__ void k_minmember(const i32 *__restrict__ comp, i64 n, i32 *__restrict__ minm)
-{
-    NODE_LOOP(n) atomicMin(&minm[comp[u_]], (i32)u_);
-}
 
 __global__ void k_head(const i32 *__restrict__ comp, const i32 *__restrict__ minm, i64 n,
                        uint8_t *__restrict__ head)
@@ -95,58 +91,6 @@ __global__ void k_label(const i32 *__restrict__ comp, const i32 *__restrict__ mi
                         const i64 *__restrict__ rank, i64 n, i32 *__restrict__ lab)
 {
     NODE_LOOP(n) lab[u_] = (i32)rank[minm[comp[u_]]];
-}
-
-// ------------------------------------------------------------------ cycle positions
-// For cycle nodes of cycles with two or more nodes: distance to the cycle
-// minimum along a (list ranking by doubling); pos = (L - dist) mod L.
-__global__ void k_cyc_len(const i32 *__restrict__ comp, const uint8_t *__restrict__ cyc, i64 n,
-                          i32 *__restrict__ L)
-{
-    NODE_LOOP(n) if (cyc[u_]) atomicAdd(&L[comp[u_]], 1);
-}
-
-__global__ void k_rank_init(const i32 *__restrict__ a, const i32 *__restrict__ comp,
-                            const uint8_t *__restrict__ cyc, const i32 *__restrict__ L, i64 n,
-                            i32 *__restrict__ N, i32 *__restrict__ D)
-{
-    NODE_LOOP(n)
-    {
-        i32 u = (i32)u_;
-        if (!cyc[u] || L[comp[u]] < 2) continue;
-        bool end = comp[u] == u;  // the cycle minimum
-        N[u] = end ? u : a[u];
-        D[u] = end ? 0 : 1;
-    }
-}
-
-__global__ void k_rank_step(const i32 *__restrict__ comp, const uint8_t *__restrict__ cyc,
-                            const i32 *__restrict__ L, i64 n, const i32 *__restrict__ Ni,
-                            const i32 *__restrict__ Di, i32 *__restrict__ No,
-                            i32 *__restrict__ Do, int *__restrict__ changed)
-{
-    NODE_LOOP(n)
-    {
-        i32 u = (i32)u_;
-        if (!cyc[u] || L[comp[u]] < 2) continue;
-        i32 x = Ni[u];
-        No[u] = Ni[x];
-        Do[u] = Di[u] + Di[x];
-        if (Ni[x] != x) *changed = 1;
-    }
-}
-
-__global__ void k_rank_pos(const i32 *__restrict__ comp, const uint8_t *__restrict__ cyc,
-                           const i32 *__restrict__ L, i64 n, const i32 *__restrict__ D,
-                           i32 *__restrict__ pos)
-{
-    NODE_LOOP(n)
-    {
-        i32 u = (i32)u_;
-        if (!cyc[u]) continue;
-        i32 l = L[comp[u]];
-        pos[u] = l < 2 ? 0 : (D[u] == 0 ? 0 : l - D[u]);
-    }
 }
 
 // ------------------------------------------------------------------ forest
@@ -269,279 +213,124 @@ __global__ void k_lca_pass(const i32 *__restrict__ src, const int2 *__restrict__
     }
 }
 
-// ------------------------------------------------------------------ POSITIVE
-// Per-community accumulators of the communities being examined are reset.
-__global__ void k_pos_reset(const i32 *__restrict__ comp, const uint8_t *__restrict__ exam,
-                            i64 n, i32 *__restrict__ sig, i32 *__restrict__ claim,
-                            uint8_t *__restrict__ act, i64 *__restrict__ bestkey,
-                            u64 *__restrict__ bestpair)
+// ------------------------------------------------------------------ block-aggregated totals
+// out[key[i]] (op)= val[i] for i < n, with an LDS hash per workgroup so that
+// a community spread over many nodes costs one global atomic per workgroup.
+#define AGG_BS 1024
+#define AGG_ITEMS 4
+#define AGG_SLOTS 8192
+template <bool MIN>
+__global__ __launch_bounds__(AGG_BS) void k_agg(const i32 *__restrict__ key,
+                                               const i32 *__restrict__ val, i64 n,
+                                               i32 *__restrict__ out)
+{
+    __shared__ i32 hk[AGG_SLOTS];
+    __shared__ i32 hv[AGG_SLOTS];
+    for (int i = threadIdx.x; i < AGG_SLOTS; i += AGG_BS) {
+        hk[i] = -1;
+        hv[i] = MIN ? INT32_MAX : 0;
+    }
+    __syncthreads();
+    const i64 base = (i64)blockIdx.x * AGG_BS * AGG_ITEMS;
+    for (int r = 0; r < AGG_ITEMS; r++) {
+        const i64 i = base + (i64)r * AGG_BS + threadIdx.x;
+        if (i >= n) continue;
+        const i32 c = key[i];
+        const i32 v = MIN ? (i32)i : val[i];
+        if (!MIN && v == 0) continue;
+        u32 h = hash_label(c) >> (32 - 13);
+        for (int probe = 0; probe < AGG_SLOTS; probe++) {
+            i32 old = atomicCAS(&hk[h], -1, c);
+            if (old == -1 || old == c) {
+                if (MIN) atomicMin(&hv[h], v);
+                else atomicAdd(&hv[h], v);
+                break;
+            }
+            h = (h + 1) & (AGG_SLOTS - 1);
+        }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < AGG_SLOTS; i += AGG_BS) {
+        const i32 c = hk[i];
+        if (c < 0) continue;
+        if (MIN) atomicMin(&out[c], hv[i]);
+        else atomicAdd(&out[c], hv[i]);
+    }
+}
+
+static void agg_add(const i32 *key, const i32 *val, i64 n, i32 *out, hipStream_t s)
+{
+    if (n > 0)
+        k_agg<false><<<grid_for(n, AGG_BS * AGG_ITEMS), AGG_BS, 0, s>>>(key, val, n, out);
+}
+
+static void agg_min_index(const i32 *key, i64 n, i32 *out, hipStream_t s)
+{
+    if (n > 0)
+        k_agg<true><<<grid_for(n, AGG_BS * AGG_ITEMS), AGG_BS, 0, s>>>(key, nullptr, n, out);
+}
+
+// ------------------------------------------------------------------ POSITIVE set-up
+// g(u) = M2*(wc - A_uu) - k*(S_c - k) < 0 flags community c; the first such
+// node numbers it.
+__global__ void k_pos_flag(const i32 *__restrict__ comp, const i32 *__restrict__ k,
+                           const i32 *__restrict__ diag, const i32 *__restrict__ wc,
+                           const i32 *__restrict__ sig, i64 m2, i64 n,
+                           i32 *__restrict__ fidx, i32 *__restrict__ flist,
+                           i64 *__restrict__ counters)
 {
     NODE_LOOP(n)
     {
         i32 c = comp[u_];
-        if (!exam[c]) continue;
-        sig[c] = 0;
-        claim[c] = 0;
-        act[c] = 0;
-        bestkey[c] = INT64_MIN;
-        bestpair[c] = ~0ull;
-    }
-}
-
-__global__ void k_pos_sigma(const i32 *__restrict__ comp, const uint8_t *__restrict__ exam,
-                            const i32 *__restrict__ k, i64 n, i32 *__restrict__ sig)
-{
-    NODE_LOOP(n)
-    {
-        i32 c = comp[u_];
-        if (exam[c] && k[u_]) atomicAdd(&sig[c], k[u_]);
-    }
-}
-
-// g(u) = M2*(wc - A_uu) - k*(S_c - k).  The first node of a community with a
-// negative gain claims it: the community becomes active, is counted, and a
-// cycle of two or more nodes reserves (L+1)(L+2) slots of the cycle
-// matrices and L slots of the cycle node lists.
-__global__ void k_pos_gain(const i32 *__restrict__ comp, const uint8_t *__restrict__ exam,
-                           const i32 *__restrict__ k, const i32 *__restrict__ diag,
-                           const i32 *__restrict__ wc, const i32 *__restrict__ sig,
-                           const i32 *__restrict__ L, i64 m2, i64 n, i32 *__restrict__ claim,
-                           uint8_t *__restrict__ act, i64 *__restrict__ counters,
-                           i64 *__restrict__ woff, i64 *__restrict__ noff,
-                           i32 *__restrict__ mlist)
-{
-    NODE_LOOP(n)
-    {
-        i32 u = (i32)u_;
-        i32 c = comp[u];
-        if (!exam[c]) continue;
-        i64 ku = k[u];
-        i64 g = m2 * (i64)(wc[u] - diag[u]) - ku * ((i64)sig[c] - ku);
+        i64 ku = k[u_];
+        i64 g = m2 * (i64)(wc[u_] - diag[u_]) - ku * ((i64)sig[c] - ku);
         if (g >= 0) continue;
-        if (atomicExch(&claim[c], 1) != 0) continue;
-        act[c] = 1;
-        atomicAdd((unsigned long long *)&counters[0], 1ull);
-        i32 l = L[c];
-        if (l >= 2) {
-            woff[c] = (i64)atomicAdd((unsigned long long *)&counters[1],
-                                     (unsigned long long)((i64)(l + 1) * (l + 2)));
-            noff[c] = (i64)atomicAdd((unsigned long long *)&counters[3], (unsigned long long)l);
-            i64 idx = (i64)atomicAdd((unsigned long long *)&counters[2], 1ull);
-            mlist[idx] = c;
+        if (atomicCAS(&fidx[c], -1, -2) == -1) {
+            i32 f = (i32)atomicAdd((unsigned long long *)&counters[0], 1ull);
+            flist[f] = c;
+            fidx[c] = f;
         }
     }
 }
 
-// Branch cut at non-cycle x: one side is the subtree T_x.
-__global__ void k_pos_branch_keys(const i32 *__restrict__ comp, const uint8_t *__restrict__ act,
-                                  const uint8_t *__restrict__ cyc, const i64 *__restrict__ subk,
-                                  const i64 *__restrict__ cut, const i32 *__restrict__ sig,
-                                  i64 m2, i64 n, i64 *__restrict__ key, i64 *__restrict__ bestkey)
+// Member and cycle-node counts of the flagged communities.
+__global__ void k_pos_count(const i32 *__restrict__ comp, const uint8_t *__restrict__ cyc,
+                            const i32 *__restrict__ fidx, i64 n, i32 *__restrict__ fcnt,
+                            i32 *__restrict__ flen)
 {
     NODE_LOOP(n)
     {
-        i32 c = comp[u_];
-        if (!act[c] || cyc[u_]) continue;
-        i64 s = subk[u_];
-        i64 kk = s * ((i64)sig[c] - s) - m2 * cut[u_];
-        key[u_] = kk;
-        atomic_max_i64(&bestkey[c], kk);
+        i32 f = fidx[comp[u_]];
+        if (f < 0) continue;
+        atomicAdd(&fcnt[f], 1);
+        if (cyc[u_]) atomicAdd(&flen[f], 1);
     }
 }
 
-__global__ void k_pos_branch_ties(const i32 *__restrict__ comp, const uint8_t *__restrict__ act,
-                                  const uint8_t *__restrict__ cyc, const i64 *__restrict__ key,
-                                  const i64 *__restrict__ bestkey, i64 n,
-                                  u64 *__restrict__ bestpair)
+__global__ void k_pos_sizes(const i32 *__restrict__ flen, i64 nflag, i64 *__restrict__ wsz,
+                            i64 *__restrict__ nsz)
+{
+    i64 f = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= nflag) return;
+    i64 l = flen[f];
+    wsz[f] = l >= 2 ? l * l : 0;
+    nsz[f] = l >= 2 ? l : 0;
+}
+
+__global__ void k_pos_scatter(const i32 *__restrict__ comp, const i32 *__restrict__ fidx, i64 n,
+                              const i64 *__restrict__ mem_off, i32 *__restrict__ fill,
+                              i32 *__restrict__ mem)
 {
     NODE_LOOP(n)
     {
-        i32 c = comp[u_];
-        if (!act[c] || cyc[u_]) continue;
-        if (key[u_] == bestkey[c]) atomic_min_u64(&bestpair[c], ((u64)u_ << 32) | (u64)u_);
-    }
-}
-
-// Cycle node lists of the active multi-node cycles, by cycle position.
-__global__ void k_pos_cnode(const i32 *__restrict__ comp, const uint8_t *__restrict__ act,
-                            const uint8_t *__restrict__ cyc, const i32 *__restrict__ L,
-                            const i32 *__restrict__ pos, const i64 *__restrict__ noff, i64 n,
-                            i32 *__restrict__ cnode)
-{
-    NODE_LOOP(n)
-    {
-        i32 c = comp[u_];
-        if (!act[c] || !cyc[u_] || L[c] < 2) continue;
-        cnode[noff[c] + pos[u_]] = (i32)u_;
-    }
-}
-
-// W_c[j+1][l+1] += A_uv for entries between the hanging trees at cycle
-// positions j != l of an active multi-node cycle.
-__global__ void k_pos_wmat(const i32 *__restrict__ src, const int2 *__restrict__ e, i64 nnz,
-                           const i32 *__restrict__ comp, const uint8_t *__restrict__ act,
-                           const i32 *__restrict__ L, const i32 *__restrict__ root,
-                           const i32 *__restrict__ pos, const i64 *__restrict__ woff,
-                           i64 *__restrict__ W)
-{
-    for (i64 j = (i64)blockIdx.x * blockDim.x + threadIdx.x; j < nnz;
-         j += (i64)gridDim.x * blockDim.x) {
-        i32 u = src[j];
-        i32 c = comp[u];
-        if (!act[c]) continue;
-        i32 l = L[c];
-        if (l < 2) continue;
-        int2 ed = e[j];
-        i32 v = ed.x;
-        if (comp[v] != c) continue;
-        i32 ru = root[u], rv = root[v];
-        if (ru == rv) continue;
-        i64 idx = woff[c] + (i64)(pos[ru] + 1) * (l + 1) + (pos[rv] + 1);
-        atomicAdd((unsigned long long *)&W[idx], (unsigned long long)(i64)ed.y);
-    }
-}
-
-// One workgroup per active multi-node cycle: 2-D prefix sums of W_c, then
-// every cut pair (c_p, c_q), p < q; the side of positions p+1..q is Y.
-// Block layout: (L+1)^2 matrix entries, then L+1 prefix sums of the
-// hanging-tree totals.
-__global__ __launch_bounds__(SLM_BS) void k_pos_cycle_eval(
-    const i32 *__restrict__ mlist, const i32 *__restrict__ L, const i64 *__restrict__ woff,
-    const i64 *__restrict__ noff, const i32 *__restrict__ cnode, const i64 *__restrict__ subk,
-    const i32 *__restrict__ sig, i64 m2, i64 *__restrict__ W, i64 *__restrict__ bestkey,
-    i64 *__restrict__ cbest_key, u64 *__restrict__ cbest_pair)
-{
-    __shared__ i64 red[32];
-    const i32 c = mlist[blockIdx.x];
-    const int l = L[c];
-    const int l1 = l + 1;
-    i64 *P = W + woff[c];
-    i64 *PH = P + (i64)l1 * l1;
-    const i32 *cn = cnode + noff[c];
-    // rows, then columns: P[i][j] = sum over i' < i, j' < j of W
-    for (int i = threadIdx.x; i < l1; i += blockDim.x)
-        for (int j = 1; j < l1; j++) P[(i64)i * l1 + j] += P[(i64)i * l1 + j - 1];
-    __syncthreads();
-    for (int j = threadIdx.x; j < l1; j += blockDim.x)
-        for (int i = 1; i < l1; i++) P[(i64)i * l1 + j] += P[(i64)(i - 1) * l1 + j];
-    if (threadIdx.x == 0) {
-        PH[0] = 0;
-        for (int j = 0; j < l; j++) PH[j + 1] = PH[j] + subk[cn[j]];
-    }
-    __syncthreads();
-    const i64 sc = sig[c];
-    i64 bk = INT64_MIN;
-    u64 bp = ~0ull;
-    for (i64 t = threadIdx.x; t < (i64)l * l; t += blockDim.x) {
-        int p = (int)(t / l), q = (int)(t % l);
-        if (q <= p) continue;
-        i64 sy = PH[q + 1] - PH[p + 1];
-        i64 rows = P[(i64)(q + 1) * l1 + l] - P[(i64)(p + 1) * l1 + l];
-        i64 blk = P[(i64)(q + 1) * l1 + (q + 1)] - P[(i64)(p + 1) * l1 + (q + 1)] -
-                  P[(i64)(q + 1) * l1 + (p + 1)] + P[(i64)(p + 1) * l1 + (p + 1)];
-        i64 kk = sy * (sc - sy) - m2 * (rows - blk);
-        i32 x = cn[p], y = cn[q];
-        u64 pr = x < y ? (((u64)x << 32) | (u64)y) : (((u64)y << 32) | (u64)x);
-        if (kk > bk || (kk == bk && pr < bp)) {
-            bk = kk;
-            bp = pr;
-        }
-    }
-    // workgroup best: key desc, then first asc, then second asc
-    i32 hi = bk == INT64_MIN ? INT32_MAX : (i32)(bp >> 32);
-    i32 lo = bk == INT64_MIN ? INT32_MAX : (i32)(bp & 0xffffffffu);
-    i64 kb = bk;
-    i32 hb = hi;
-    block_best(kb, hb, red);
-    i64 k2 = (bk == kb && hi == hb) ? 0 : INT64_MIN;
-    i32 lb = (bk == kb && hi == hb) ? lo : INT32_MAX;
-    block_best(k2, lb, red);
-    if (threadIdx.x == 0) {
-        cbest_key[c] = kb;
-        cbest_pair[c] = ((u64)(u32)hb << 32) | (u64)(u32)lb;
-        atomic_max_i64(&bestkey[c], kb);
-    }
-}
-
-__global__ void k_pos_cycle_ties(const i32 *__restrict__ mlist, i64 count,
-                                 const i64 *__restrict__ cbest_key,
-                                 const u64 *__restrict__ cbest_pair,
-                                 const i64 *__restrict__ bestkey, u64 *__restrict__ bestpair)
-{
-    i64 t = (i64)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= count) return;
-    i32 c = mlist[t];
-    if (cbest_key[c] == bestkey[c]) atomic_min_u64(&bestpair[c], cbest_pair[c]);
-}
-
-// The chosen cut nodes become self-assigned.
-__global__ void k_pos_apply(const i32 *__restrict__ comp, const uint8_t *__restrict__ act, i64 n,
-                            const u64 *__restrict__ bestpair, i32 *__restrict__ a)
-{
-    NODE_LOOP(n)
-    {
-        i32 c = comp[u_];
-        if (!act[c]) continue;
-        u64 pr = bestpair[c];
-        if (pr == ~0ull) continue;  // no candidate (cannot happen for >= 2 nodes)
-        i32 x = (i32)(pr >> 32), y = (i32)(pr & 0xffffffffu);
-        if ((i32)u_ == x || (i32)u_ == y) a[u_] = (i32)u_;
-    }
-}
-
-// New community ids after the cuts: a branch cut gives T_x the id x; a cycle
-// cut gives the two sides the ids of their new roots.  Cycle flags and
-// cycle lengths follow; both sides are examined in the next round.
-__global__ void k_pos_relabel(i32 *__restrict__ comp, const uint8_t *__restrict__ act, i64 n,
-                              const u64 *__restrict__ bestpair, uint8_t *__restrict__ cyc,
-                              const i32 *__restrict__ depth, const i32 *__restrict__ root,
-                              const i32 *__restrict__ J, const i32 *__restrict__ pos,
-                              i32 *__restrict__ L, uint8_t *__restrict__ exam_next)
-{
-    NODE_LOOP(n)
-    {
-        i32 u = (i32)u_;
-        i32 c = comp[u];
-        if (!act[c]) continue;
-        u64 pr = bestpair[c];
-        if (pr == ~0ull) continue;  // no candidate (cannot happen for >= 2 nodes)
-        i32 x = (i32)(pr >> 32), y = (i32)(pr & 0xffffffffu);
-        i32 nc;
-        if (x == y) {
-            bool in = root[u] == root[x] && depth[u] >= depth[x] &&
-                      lift(u, depth[u] - depth[x], J, n) == x;
-            nc = in ? x : c;
-            if (u == x) {
-                cyc[u] = 1;
-                L[x] = 1;
-            }
-        } else {
-            i32 cp = x, cq = y;
-            int p = pos[x], q = pos[y];
-            if (p > q) {
-                int t = p;
-                p = q;
-                q = t;
-                cp = y;
-                cq = x;
-            }
-            int pr_ = pos[root[u]];
-            bool inY = pr_ > p && pr_ <= q;
-            nc = inY ? cq : cp;
-            if (cyc[u]) cyc[u] = (u == x || u == y);
-            if (u == x || u == y) L[u] = 1;
-        }
-        comp[u] = nc;
-        exam_next[nc] = 1;
+        i32 f = fidx[comp[u_]];
+        if (f < 0) continue;
+        i32 t = atomicAdd(&fill[f], 1);
+        mem[mem_off[f] + t] = (i32)u_;
     }
 }
 
 // ------------------------------------------------------------------ MAXIMAL tails
-__global__ void k_sigma(const i32 *__restrict__ lab, const i32 *__restrict__ k, i64 n,
-                        i32 *__restrict__ sig)
-{
-    NODE_LOOP(n) if (k[u_]) atomicAdd(&sig[lab[u_]], k[u_]);
-}
 
 // act[c]: community c holds a non-cycle candidate (its forest is needed);
 // hasc[c]: c holds any candidate; ccnt[c]: its cycle candidates.
@@ -550,6 +339,8 @@ __global__ void k_max_cand(const i32 *__restrict__ lab, const i32 *__restrict__ 
                            uint8_t *__restrict__ hasc, i32 *__restrict__ ccnt,
                            i64 *__restrict__ counters)
 {
+    __shared__ i64 red[32];
+    i64 cnt = 0;
     NODE_LOOP(n)
     {
         i32 c = lab[u_];
@@ -557,8 +348,10 @@ __global__ void k_max_cand(const i32 *__restrict__ lab, const i32 *__restrict__ 
         hasc[c] = 1;
         if (cyc[u_]) atomicAdd(&ccnt[c], 1);
         else act[c] = 1;
-        atomicAdd((unsigned long long *)&counters[0], 1ull);
+        cnt++;
     }
+    cnt = block_sum<i64>(cnt, red);
+    if (threadIdx.x == 0 && cnt) atomicAdd((unsigned long long *)&counters[0], (unsigned long long)cnt);
 }
 
 __global__ void k_max_clist(const i32 *__restrict__ lab, const i32 *__restrict__ best_c,
@@ -657,6 +450,8 @@ __global__ void k_max_valid(const i32 *__restrict__ lab, const i32 *__restrict__
                             int round, u64 accept_p, uint8_t *__restrict__ accept,
                             i64 *__restrict__ counters)
 {
+    __shared__ i64 red[32];
+    i64 nv = 0, na = 0;
     NODE_LOOP(n)
     {
         i32 i = (i32)u_;
@@ -673,11 +468,17 @@ __global__ void k_max_valid(const i32 *__restrict__ lab, const i32 *__restrict__
         }
         i64 mv = m2 * ((i64)wbd[i] - cb) - sb * ((i64)sig[D] - (i64)sig[c] + sb);
         if (mv <= 0) continue;
-        atomicAdd((unsigned long long *)&counters[1], 1ull);
+        nv++;
         if ((u64)accept_draw(seed, level, round, i) < accept_p) {
             accept[i] = 1;
-            atomicAdd((unsigned long long *)&counters[2], 1ull);
+            na++;
         }
+    }
+    nv = block_sum<i64>(nv, red);
+    na = block_sum<i64>(na, red);
+    if (threadIdx.x == 0) {
+        if (nv) atomicAdd((unsigned long long *)&counters[1], (unsigned long long)nv);
+        if (na) atomicAdd((unsigned long long *)&counters[2], (unsigned long long)na);
     }
 }
 
@@ -730,7 +531,7 @@ i64 canonical_labels(Work &W, i64 n, hipStream_t s)
 {
     const unsigned g = node_grid(n);
     launch_fill_i32(W.minm, INT32_MAX, n, s);
-    k_minmember<<<g, SLM_BS, 0, s>>>(W.comp, n, W.minm);
+    agg_min_index(W.comp, n, W.minm, s);
     k_head<<<g, SLM_BS, 0, s>>>(W.comp, W.minm, n, W.head);
     launch_scan_u8(W.head, W.rank, n, W.scan_tmp, s);
     k_label<<<g, SLM_BS, 0, s>>>(W.comp, W.minm, W.rank, n, W.lab);
@@ -820,17 +621,6 @@ static void subtree_cuts(Work &W, const LevelView &Lv, const i32 *comp, const ui
     subtree_sums(W, comp, act, n, F, nullptr, val, cut, s);
 }
 
-// w(u, c \ u) = wc - A_uu for the active nodes (into W.best_c as scratch).
-__global__ void k_w_other(const i32 *__restrict__ comp, const uint8_t *__restrict__ act,
-                          const i32 *__restrict__ wc, const i32 *__restrict__ diag, i64 n,
-                          i32 *__restrict__ out)
-{
-    NODE_LOOP(n)
-    {
-        if (!act[comp[u_]]) continue;
-        out[u_] = wc[u_] - diag[u_];
-    }
-}
 
 i64 positive(Work &W, const LevelView &Lv, const Bins &B, i64 *nc_out, hipStream_t s)
 {
@@ -840,78 +630,71 @@ i64 positive(Work &W, const LevelView &Lv, const Bins &B, i64 *nc_out, hipStream
         return 0;
     }
     const unsigned g = node_grid(n);
-    // cycle lengths and positions of the multi-node cycles (comp = cycle minimum)
-    launch_fill_i32(W.L, 0, n, s);
-    k_cyc_len<<<g, SLM_BS, 0, s>>>(W.comp, W.cyc, n, W.L);
-    k_rank_init<<<g, SLM_BS, 0, s>>>(W.a, W.comp, W.cyc, W.L, n, W.A0, W.D0);
-    {
-        i32 *Ni = W.A0, *No = W.A1, *Di = W.D0, *Do = W.D1;
-        while (true) {
-            HIPCHK(hipMemsetAsync(W.changed, 0, sizeof(int), s));
-            k_rank_step<<<g, SLM_BS, 0, s>>>(W.comp, W.cyc, W.L, n, Ni, Di, No, Do, W.changed);
-            i32 *t = Ni;
-            Ni = No;
-            No = t;
-            t = Di;
-            Di = Do;
-            Do = t;
-            if (!read_changed(W, s)) break;
-        }
-        k_rank_pos<<<g, SLM_BS, 0, s>>>(W.comp, W.cyc, W.L, n, Di, W.pos);
-    }
-    launch_fill_u8(W.exam, 1, n, s);
+    // communities (ids = cycle minima) holding a node of negative local gain
+    launch_fill_i32(W.sigma, 0, n, s);
+    agg_add(W.comp, Lv.k, n, W.sigma, s);
+    run_own_weight(Lv, B, W.comp, nullptr, W.wc, s);
+    launch_fill_i32(W.fidx, -1, n, s);
+    launch_fill_i64(W.counters, 0, 8, s);
+    k_pos_flag<<<g, SLM_BS, 0, s>>>(W.comp, Lv.k, Lv.diag, W.wc, W.sigma, Lv.m2, n, W.fidx,
+                                    W.flist, W.counters);
+    read_scalars(W, W.counters, 1, s);
+    const i64 nflag = W.h_scal[0];
     i64 splits = 0;
-    const i64 entries = Lv.nnz;
-    for (i64 rounds = 0;; rounds++) {
-        // every round adds at least one community, so n rounds bound the loop
-        if (rounds > n) throw SlmError{4, "POSITIVE made no progress"};
-        k_pos_reset<<<g, SLM_BS, 0, s>>>(W.comp, W.exam, n, W.sigma, W.claim, W.act, W.bestkey,
-                                         W.bestpair);
-        k_pos_sigma<<<g, SLM_BS, 0, s>>>(W.comp, W.exam, Lv.k, n, W.sigma);
-        run_own_weight(Lv, B, W.comp, W.exam, W.wc, s);
-        launch_fill_i64(W.counters, 0, 8, s);
-        k_pos_gain<<<g, SLM_BS, 0, s>>>(W.comp, W.exam, Lv.k, Lv.diag, W.wc, W.sigma, W.L, Lv.m2,
-                                        n, W.claim, W.act, W.counters, W.woff, W.noff, W.mlist);
-        read_scalars(W, W.counters, 4, s);
-        const i64 flagged = W.h_scal[0], wtotal = W.h_scal[1], nmulti = W.h_scal[2];
-        if (flagged == 0) break;
-        Forest F = build_forest(W, W.a, W.comp, W.act, n, s);
-        subtree_sums(W, W.comp, W.act, n, F, Lv.k, nullptr, W.subk, s);
-        k_w_other<<<g, SLM_BS, 0, s>>>(W.comp, W.act, W.wc, Lv.diag, n, W.best_c);
-        subtree_cuts(W, Lv, W.comp, W.act, F, W.best_c, W.cut, s);
-        k_pos_branch_keys<<<g, SLM_BS, 0, s>>>(W.comp, W.act, W.cyc, W.subk, W.cut, W.sigma,
-                                               Lv.m2, n, W.key, W.bestkey);
-        if (nmulti > 0) {
-            if (wtotal > W.W_cap) {
-                if (W.W) HIPCHK(hipFree(W.W));
-                W.W = nullptr;
-                i64 cap = wtotal + wtotal / 2 + 1024;
-                HIPCHK(hipMalloc(&W.W, sizeof(i64) * cap));
-                W.W_cap = cap;
-            }
-            launch_fill_i64(W.W, 0, wtotal, s);
-            k_pos_cnode<<<g, SLM_BS, 0, s>>>(W.comp, W.act, W.cyc, W.L, W.pos, W.noff, n, W.cnode);
-            if (entries > 0)
-                k_pos_wmat<<<node_grid(entries), SLM_BS, 0, s>>>(W.src, Lv.e, entries, W.comp,
-                                                                 W.act, W.L, F.root, W.pos,
-                                                                 W.woff, W.W);
-            k_pos_cycle_eval<<<(unsigned)nmulti, SLM_BS, 0, s>>>(
-                W.mlist, W.L, W.woff, W.noff, W.cnode, W.subk, W.sigma, Lv.m2, W.W, W.bestkey,
-                W.cbest_key, W.cbest_pair);
+    if (nflag > 0) {
+        // members of every flagged community, contiguous
+        launch_fill_i32(W.fcnt, 0, nflag, s);
+        launch_fill_i32(W.flen, 0, nflag, s);
+        k_pos_count<<<g, SLM_BS, 0, s>>>(W.comp, W.cyc, W.fidx, n, W.fcnt, W.flen);
+        launch_scan_i32(W.fcnt, W.mem_off, nflag, W.scan_tmp, s);
+        launch_fill_i32(W.fcnt, 0, nflag, s);
+        k_pos_scatter<<<g, SLM_BS, 0, s>>>(W.comp, W.fidx, n, W.mem_off, W.fcnt, W.mem);
+        k_pos_sizes<<<grid_for(nflag, SLM_BS), SLM_BS, 0, s>>>(W.flen, nflag, W.wsz, W.nsz);
+        launch_scan_i64(W.wsz, W.woff_f, nflag, W.scan_tmp, s);
+        launch_scan_i64(W.nsz, W.noff_f, nflag, W.scan_tmp, s);
+        read_scalars(W, W.woff_f + nflag, 1, s);
+        const i64 wtotal = W.h_scal[0];
+        if (wtotal > W.W_cap) {
+            if (W.W) HIPCHK(hipFree(W.W));
+            W.W = nullptr;
+            i64 cap = wtotal + wtotal / 2 + 1024;
+            HIPCHK(hipMalloc(&W.W, sizeof(i64) * cap));
+            W.W_cap = cap;
         }
-        k_pos_branch_ties<<<g, SLM_BS, 0, s>>>(W.comp, W.act, W.cyc, W.key, W.bestkey, n,
-                                               W.bestpair);
-        if (nmulti > 0)
-            k_pos_cycle_ties<<<grid_for(nmulti, SLM_BS), SLM_BS, 0, s>>>(
-                W.mlist, nmulti, W.cbest_key, W.cbest_pair, W.bestkey, W.bestpair);
-        k_pos_apply<<<g, SLM_BS, 0, s>>>(W.comp, W.act, n, W.bestpair, W.a);
-        launch_fill_u8(W.exam_next, 0, n, s);
-        k_pos_relabel<<<g, SLM_BS, 0, s>>>(W.comp, W.act, n, W.bestpair, W.cyc, F.depth, F.root,
-                                           W.J, W.pos, W.L, W.exam_next);
-        uint8_t *t = W.exam;
-        W.exam = W.exam_next;
-        W.exam_next = t;
-        splits += flagged;
+        HIPCHK(hipMemcpyAsync(W.part, W.comp, sizeof(i32) * n, hipMemcpyDeviceToDevice, s));
+        launch_fill_i64(W.counters, 0, 1, s);
+        PosArgs A;
+        A.G = Lv;
+        A.a = W.a;
+        A.cyc = W.cyc;
+        A.flist = W.flist;
+        A.mem_off = W.mem_off;
+        A.mem = W.mem;
+        A.tmp = W.ptmp;
+        A.ord = W.pord;
+        A.chl = W.pchl;
+        A.dpre = W.pdp;
+        A.lvl = W.plvl;
+        A.stk = W.pstk;
+        A.part = W.part;
+        A.win = W.win;
+        A.subk = W.psub;
+        A.cut = W.pcut;
+        A.dep = W.pdep;
+        A.root = W.proot;
+        A.chs = W.chs;
+        A.chc = W.chc;
+        A.cpos = W.pos;
+        A.lcyc = W.flen;
+        A.woff = W.woff_f;
+        A.W = W.W;
+        A.noff = W.noff_f;
+        A.cn = W.cnode;
+        A.splits = W.counters;
+        launch_positive_wg(A, nflag, s);
+        read_scalars(W, W.counters, 1, s);
+        splits = W.h_scal[0];
+        HIPCHK(hipMemcpyAsync(W.comp, W.part, sizeof(i32) * n, hipMemcpyDeviceToDevice, s));
     }
     *nc_out = canonical_labels(W, n, s);
     return splits;
@@ -920,7 +703,7 @@ i64 positive(Work &W, const LevelView &Lv, const Bins &B, i64 *nc_out, hipStream
 void community_totals(Work &W, const LevelView &Lv, const i32 *lab, i64 nc, hipStream_t s)
 {
     launch_fill_i32(W.sigma, 0, nc, s);
-    if (Lv.n > 0) k_sigma<<<node_grid(Lv.n), SLM_BS, 0, s>>>(lab, Lv.k, Lv.n, W.sigma);
+    agg_add(lab, Lv.k, Lv.n, W.sigma, s);
 }
 
 i64 maximal_moves(Work &W, const LevelView &Lv, const Bins &B, i64 nc, u64 seed, int level,

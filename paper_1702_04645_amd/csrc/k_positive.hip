@@ -1,0 +1,621 @@
+// POSITIVE (Sec. 3.3) with one workgroup per community that holds a node of
+// negative local gain.  A community never interacts with another one during
+// POSITIVE, so each workgroup runs the whole split sequence of its community
+// (the while loop of the appendix POSITIVE) without leaving the kernel.
+//
+// The workgroup keeps, for every node u of the part P being split:
+//   win(u)  = w(u, P \ u)                      -> g(u) = M2*win - k(S_P - k)
+//   subk(u) = S over the subtree of u          (forest view: cycle nodes are
+//   cut(u)  = w(T_u, P \ T_u)                   roots, parents are a(u))
+// A branch cut at x (x non-cycle) removes T_x from P.  Instead of rebuilding
+// P' = P \ T_x, the state is updated in place:
+//   - S along the ancestors of x drops by subk(x);
+//   - every entry (v, u) with v in T_x, u in P' lowers win(u) and win(v), the
+//     cut of the nodes on the paths u -> lca and parent(x) -> lca (the pair
+//     is no longer inside the part), and the cut of the nodes on v -> x
+//     (inside T_x the pair now leaves the part);
+//   - for a cycle of two or more nodes, the weight between the hanging trees.
+// T_x keeps its subtree sums; its new root is x.  A cycle cut (self-assigning
+// two cycle nodes) rebuilds both sides from scratch.  Keys:
+//   branch x:      subk(x)(S_P - subk(x)) - M2 cut(x)
+//   cycle (cp,cq): S_Y(S_P - S_Y) - M2 w(X, Y), Y = hanging trees at cycle
+//                  positions p+1..q
+// ties to the lowest (first, second) cut node; the best cut is applied even
+// when its key is not positive, until no node of the part has g < 0.
+#include "slm_forest.h"
+
+#define PW_BS 512
+#define PW_NW (PW_BS / 64)
+
+enum { ST_INIT = 1 };
+
+struct PwShared {
+    i64 red[2 * PW_NW + 2];
+    i64 sig;       // S_P
+    i64 bkey;      // best key
+    u64 bpair;     // best (first, second)
+    int neg;
+    int sp;        // stack size
+    int s, e, pid, flags;
+    int tail, head, lev_end;
+    int L;         // cycle length of the part
+    int chl_top;   // next free slot of the children arena
+};
+
+__device__ __forceinline__ i64 wg_sum(i64 v, PwShared &S)
+{
+    v = group_sum<64>(v);
+    const int wid = threadIdx.x / 64;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) S.red[wid] = v;
+    __syncthreads();
+    i64 t = 0;
+    for (int w = 0; w < PW_NW; w++) t += S.red[w];
+    __syncthreads();
+    return t;
+}
+
+// Best (key desc, pair asc) over the workgroup.
+__device__ __forceinline__ void wg_best(i64 &key, u64 &pair, PwShared &S)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        i64 ok = __shfl_xor(key, off, 64);
+        u64 op = __shfl_xor(pair, off, 64);
+        if (ok > key || (ok == key && op < pair)) {
+            key = ok;
+            pair = op;
+        }
+    }
+    const int wid = threadIdx.x / 64;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) {
+        S.red[2 * wid] = key;
+        S.red[2 * wid + 1] = (i64)pair;
+    }
+    __syncthreads();
+    key = S.red[0];
+    pair = (u64)S.red[1];
+    for (int w = 1; w < PW_NW; w++) {
+        i64 k2 = S.red[2 * w];
+        u64 p2 = (u64)S.red[2 * w + 1];
+        if (k2 > key || (k2 == key && p2 < pair)) {
+            key = k2;
+            pair = p2;
+        }
+    }
+    __syncthreads();
+}
+
+// Exclusive scan of one value per thread over the workgroup; *total = sum.
+__device__ __forceinline__ i64 wg_scan(i64 v, i64 &total, PwShared &S)
+{
+    const int lane = threadIdx.x & 63, wid = threadIdx.x / 64;
+    i64 inc = v;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        i64 t = __shfl_up(inc, d, 64);
+        if (lane >= d) inc += t;
+    }
+    __syncthreads();
+    if (lane == 63) S.red[wid] = inc;
+    __syncthreads();
+    i64 before = 0, tot = 0;
+    for (int w = 0; w < PW_NW; w++) {
+        if (w < wid) before += S.red[w];
+        tot += S.red[w];
+    }
+    __syncthreads();
+    total = tot;
+    return before + inc - v;
+}
+
+// Adds val into dst[idx] with one atomic per run of equal idx inside the
+// wave.  idx must be non-decreasing over the in-range lanes of the wave, so
+// equal keys form one run; lanes out of range pass in_range = false, lanes
+// filtered out keep their key and pass val = 0.
+__device__ __forceinline__ void wave_run_add(bool in_range, i32 idx, i64 val, i32 *dst)
+{
+    const int lane = threadIdx.x & 63;
+    i32 key = in_range ? idx : -1;
+    i64 v = in_range ? val : 0;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        i64 t = __shfl_up(v, d, 64);
+        i32 k2 = __shfl_up(key, d, 64);
+        if (lane >= d && k2 == key) v += t;
+    }
+    i32 nxt = __shfl_down(key, 1, 64);
+    bool last = (lane == 63) || nxt != key;
+    if (in_range && last && v != 0) atomicAdd(&dst[idx], (i32)v);
+}
+
+__device__ __forceinline__ i32 parent_of(i32 u, const i32 *a, const uint8_t *cyc)
+{
+    return cyc[u] ? u : a[u];
+}
+
+// Flattened walk over the CSR entries of nodes list[0..cnt): degree prefix
+// into dp[0..cnt], then entry t of the list belongs to list[upper(dp, t)-1].
+__device__ __forceinline__ i64 wg_degree_prefix(const i32 *list, int cnt, const i64 *rp, i64 *dp,
+                                                PwShared &S)
+{
+    i64 carry = 0;
+    for (int b = 0; b < cnt; b += PW_BS) {
+        int i = b + threadIdx.x;
+        i64 d = i < cnt ? rp[list[i] + 1] - rp[list[i]] : 0;
+        i64 tot;
+        i64 ex = wg_scan(d, tot, S);
+        if (i < cnt) dp[i] = carry + ex;
+        carry += tot;
+    }
+    if (threadIdx.x == 0) dp[cnt] = carry;
+    __syncthreads();
+    return carry;
+}
+
+__device__ __forceinline__ int find_slot(const i64 *dp, int cnt, i64 t)
+{
+    int lo = 0, hi = cnt;  // dp[lo] <= t < dp[hi]
+    while (hi - lo > 1) {
+        int mid = (lo + hi) >> 1;
+        if (dp[mid] <= t) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// Stable partition of r[0..m): members with keep(u) first; others after.
+// Uses out as temporary; returns the number kept.
+template <class Keep>
+__device__ int wg_partition(i32 *r, int m, i32 *out, Keep keep, PwShared &S)
+{
+    i64 carry_k = 0, carry_o = 0;
+    // count kept first
+    i64 nk = 0;
+    for (int b = 0; b < m; b += PW_BS) {
+        int i = b + threadIdx.x;
+        nk += (i < m && keep(r[i])) ? 1 : 0;
+    }
+    nk = wg_sum(nk, S);
+    for (int b = 0; b < m; b += PW_BS) {
+        int i = b + threadIdx.x;
+        bool ok = i < m;
+        i32 u = ok ? r[i] : 0;
+        bool k = ok && keep(u);
+        i64 tk, to;
+        i64 ek = wg_scan(k ? 1 : 0, tk, S);
+        i64 eo = wg_scan((ok && !k) ? 1 : 0, to, S);
+        if (k) out[carry_k + ek] = u;
+        else if (ok) out[nk + carry_o + eo] = u;
+        carry_k += tk;
+        carry_o += to;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < m; i += PW_BS) r[i] = out[i];
+    __syncthreads();
+    return (int)nk;
+}
+
+__global__ __launch_bounds__(PW_BS) void k_positive_wg(PosArgs A)
+{
+    __shared__ PwShared S;
+    const int f = blockIdx.x;
+    const i64 base = A.mem_off[f];
+    const int m0 = (int)(A.mem_off[f + 1] - base);
+    i32 *M = A.mem + base;
+    i32 *TMP = A.tmp + base;
+    i32 *ORD = A.ord + base;
+    i32 *CHL = A.chl + 2 * base;  // arena of 2*m0 slots: every part built from
+                                  // scratch takes fresh slots, so the children
+                                  // lists of parts waiting on the stack survive
+    i64 *DP = A.dpre + base + f;
+    int4 *STK = A.stk + base;
+    const int Lc0 = A.lcyc[f];
+    i64 *Wm = Lc0 >= 2 ? A.W + A.woff[f] : nullptr;  // (L x L) weights between hanging trees
+    i32 *CN = A.cn + A.noff[f];
+    const LevelView &G = A.G;
+    const i64 m2 = G.m2;
+    i32 *a = A.a;
+    uint8_t *cyc = A.cyc;
+
+    if (threadIdx.x == 0) {
+        STK[0] = make_int4(0, m0, A.flist[f], ST_INIT);
+        S.sp = 1;
+        S.chl_top = 0;
+    }
+    __syncthreads();
+    while (true) {
+        __syncthreads();
+        if (S.sp == 0) break;
+        if (threadIdx.x == 0) {
+            int4 t = STK[--S.sp];
+            S.s = t.x;
+            S.e = t.y;
+            S.pid = t.z;
+            S.flags = t.w;
+        }
+        __syncthreads();
+        const int s = S.s, pid = S.pid;
+        if (S.e - s <= 1) continue;
+        // -------------------------------------------------- (re)build a part
+        if (S.flags & ST_INIT) {
+            const int m = S.e - s;
+            i32 *P = M + s;
+            i64 sg = 0, nl = 0;
+            for (int i = threadIdx.x; i < m; i += PW_BS) {
+                i32 u = P[i];
+                A.part[u] = pid;
+                A.win[u] = 0;
+                A.chc[u] = 0;
+                A.subk[u] = G.k[u];
+                sg += G.k[u];
+                nl += cyc[u] ? 1 : 0;
+            }
+            sg = wg_sum(sg, S);
+            nl = wg_sum(nl, S);
+            if (threadIdx.x == 0) {
+                S.sig = sg;
+                S.L = (int)nl;
+            }
+            // children lists (contiguous per parent), positions absolute in CHL
+            for (int i = threadIdx.x; i < m; i += PW_BS) {
+                i32 u = P[i];
+                if (!cyc[u]) atomicAdd(&A.chc[a[u]], 1);
+            }
+            __syncthreads();
+            {
+                const int arena = S.chl_top;
+                i64 carry = 0;
+                for (int b = 0; b < m; b += PW_BS) {
+                    int i = b + threadIdx.x;
+                    i64 c = i < m ? A.chc[P[i]] : 0;
+                    i64 tot;
+                    i64 ex = wg_scan(c, tot, S);
+                    if (i < m) A.chs[P[i]] = (i32)(arena + carry + ex);
+                    carry += tot;
+                }
+                __syncthreads();
+                if (threadIdx.x == 0) S.chl_top = arena + m;
+            }
+            for (int i = threadIdx.x; i < m; i += PW_BS) A.chc[P[i]] = 0;
+            __syncthreads();
+            for (int i = threadIdx.x; i < m; i += PW_BS) {
+                i32 u = P[i];
+                if (!cyc[u]) {
+                    i32 p = a[u];
+                    int slot = atomicAdd(&A.chc[p], 1);
+                    CHL[A.chs[p] + slot] = u;
+                }
+            }
+            __syncthreads();
+            // level order from the cycle nodes (children of a node stay contiguous)
+            if (threadIdx.x == 0) S.tail = 0;
+            __syncthreads();
+            for (int i = threadIdx.x; i < m; i += PW_BS) {
+                i32 u = P[i];
+                if (cyc[u]) {
+                    int q = atomicAdd(&S.tail, 1);
+                    ORD[q] = u;
+                    A.dep[u] = 0;
+                    A.root[u] = u;
+                }
+            }
+            __syncthreads();
+            // cycle positions along a, from the smallest cycle node
+            if (S.L >= 2 && threadIdx.x == 0) {
+                i32 z = INT32_MAX;
+                for (int q = 0; q < S.L; q++) z = min(z, ORD[q]);
+                i32 y = z;
+                for (int j = 0; j < S.L; j++) {
+                    CN[j] = y;
+                    A.cpos[y] = j;
+                    y = a[y];
+                }
+            }
+            int lev_b = 0;
+            if (threadIdx.x == 0) {
+                S.head = 0;
+                S.lev_end = S.tail;
+            }
+            __syncthreads();
+            int nlev = 0;
+            while (true) {
+                const int lb = S.head, le = S.lev_end;
+                if (lb == le) break;
+                if (threadIdx.x == 0) A.lvl[base + f + nlev] = lb;
+                nlev++;
+                for (int i = lb + threadIdx.x; i < le; i += PW_BS) {
+                    i32 u = ORD[i];
+                    int c = A.chc[u];
+                    if (c) {
+                        int q = atomicAdd(&S.tail, c);
+                        int cs = A.chs[u];
+                        for (int j = 0; j < c; j++) {
+                            i32 ch = CHL[cs + j];
+                            ORD[q + j] = ch;
+                            A.dep[ch] = A.dep[u] + 1;
+                            A.root[ch] = A.root[u];
+                        }
+                    }
+                }
+                __syncthreads();
+                if (threadIdx.x == 0) {
+                    S.head = le;
+                    S.lev_end = S.tail;
+                }
+                __syncthreads();
+            }
+            if (threadIdx.x == 0) A.lvl[base + f + nlev] = m;
+            (void)lev_b;
+            // win, and the intra-part entries between different hanging trees
+            const int L = S.L;
+            if (L >= 2)
+                for (int i = threadIdx.x; i < L * L; i += PW_BS) Wm[i] = 0;
+            const i64 tot = wg_degree_prefix(P, m, G.rp, DP, S);
+            for (i64 b = 0; b < tot; b += PW_BS) {
+                const i64 t = b + threadIdx.x;
+                i32 u = 0;
+                i64 val = 0;
+                if (t < tot) {
+                    int slot = find_slot(DP, m, t);
+                    u = P[slot];
+                    int2 ed = G.e[G.rp[u] + (t - DP[slot])];
+                    i32 v = ed.x;
+                    if (v != u && A.part[v] == pid) {
+                        val = ed.y;
+                        if (L >= 2 && A.root[u] != A.root[v])
+                            atomicAdd((unsigned long long *)&Wm[A.cpos[A.root[u]] * L +
+                                                                 A.cpos[A.root[v]]],
+                                      (unsigned long long)(i64)ed.y);
+                    }
+                }
+                wave_run_add(t < tot, u, val, A.win);
+            }
+            __syncthreads();
+            // cut(u) = subtree sum of win minus, at every lowest common ancestor
+            // inside one tree, the weight of the pairs meeting there
+            for (int i = threadIdx.x; i < m; i += PW_BS) A.cut[P[i]] = A.win[P[i]];
+            __syncthreads();
+            for (i64 b = 0; b < tot; b += PW_BS) {
+                const i64 t = b + threadIdx.x;
+                if (t < tot) {
+                    int slot = find_slot(DP, m, t);
+                    i32 u = P[slot];
+                    int2 ed = G.e[G.rp[u] + (t - DP[slot])];
+                    i32 v = ed.x;
+                    if (v != u && A.part[v] == pid && A.root[u] == A.root[v]) {
+                        i32 x = u, y = v;
+                        while (A.dep[x] > A.dep[y]) x = a[x];
+                        while (A.dep[y] > A.dep[x]) y = a[y];
+                        while (x != y) {
+                            x = a[x];
+                            y = a[y];
+                        }
+                        if (!cyc[x]) atomicSub(&A.cut[x], ed.y);
+                    }
+                }
+            }
+            __syncthreads();
+            // subtree sums, deepest level first (siblings are contiguous)
+            for (int l = nlev - 1; l >= 1; l--) {
+                const int lb = A.lvl[base + f + l], le = A.lvl[base + f + l + 1];
+                for (int b = lb; b < le; b += PW_BS) {
+                    const int i = b + threadIdx.x;
+                    bool on = i < le;
+                    i32 u = on ? ORD[i] : 0;
+                    i32 p = on ? a[u] : 0;
+                    bool toroot = on && cyc[p];
+                    wave_run_add(on, p, (on && (L >= 2 || !toroot)) ? A.subk[u] : 0, A.subk);
+                    wave_run_add(on, p, (on && !toroot) ? A.cut[u] : 0, A.cut);
+                }
+                __syncthreads();
+            }
+        } else {
+            const int m = S.e - s;
+            i64 sg = 0;
+            for (int i = threadIdx.x; i < m; i += PW_BS) sg += G.k[M[s + i]];
+            sg = wg_sum(sg, S);
+            if (threadIdx.x == 0) {
+                S.sig = sg;
+                S.L = 1;
+            }
+            __syncthreads();
+        }
+        // -------------------------------------------------- split loop
+        while (true) {
+            const int m = S.e - s;
+            i32 *P = M + s;
+            const i64 sig = S.sig;
+            const int L = S.L;
+            if (m <= 1) break;
+            i64 bk = INT64_MIN;
+            u64 bp = ~0ull;
+            int neg = 0;
+            for (int i = threadIdx.x; i < m; i += PW_BS) {
+                i32 u = P[i];
+                const i64 ku = G.k[u];
+                if (m2 * (i64)A.win[u] - ku * (sig - ku) < 0) neg = 1;
+                if (!cyc[u]) {
+                    const i64 sx = A.subk[u];
+                    const i64 key = sx * (sig - sx) - m2 * (i64)A.cut[u];
+                    const u64 pr = ((u64)(u32)u << 32) | (u64)(u32)u;
+                    if (key > bk || (key == bk && pr < bp)) {
+                        bk = key;
+                        bp = pr;
+                    }
+                }
+            }
+            // cycle cuts: pairs p < q of cycle positions
+            if (L >= 2) {
+                for (int t = threadIdx.x; t < L * L; t += PW_BS) {
+                    const int p = t / L, q = t % L;
+                    if (q <= p) continue;
+                    i64 sy = 0, wxy = 0;
+                    for (int j = p + 1; j <= q; j++) {
+                        sy += A.subk[CN[j]];
+                        for (int l = 0; l < L; l++)
+                            if (l <= p || l > q) wxy += Wm[j * L + l];
+                    }
+                    const i64 key = sy * (sig - sy) - m2 * wxy;
+                    const i32 x = CN[p], y = CN[q];
+                    const u64 pr = x < y ? (((u64)(u32)x << 32) | (u64)(u32)y)
+                                         : (((u64)(u32)y << 32) | (u64)(u32)x);
+                    if (key > bk || (key == bk && pr < bp)) {
+                        bk = key;
+                        bp = pr;
+                    }
+                }
+            }
+            neg = (int)wg_sum(neg, S);
+            wg_best(bk, bp, S);
+            if (!neg || bp == ~0ull) break;
+            const i32 x = (i32)(bp >> 32), y = (i32)(bp & 0xffffffffu);
+            if (threadIdx.x == 0) atomicAdd((unsigned long long *)A.splits, 1ull);
+            if (x != y) {
+                // ---------------- cycle cut: rebuild both sides
+                int p = A.cpos[x], q = A.cpos[y];
+                i32 cp = x, cq = y;
+                if (p > q) {
+                    int tt = p;
+                    p = q;
+                    q = tt;
+                    cp = y;
+                    cq = x;
+                }
+                __syncthreads();
+                for (int j = threadIdx.x; j < L; j += PW_BS) cyc[CN[j]] = 0;
+                __syncthreads();
+                if (threadIdx.x == 0) {
+                    cyc[x] = 1;
+                    cyc[y] = 1;
+                    a[x] = x;
+                    a[y] = y;
+                }
+                const int pp = p, qq = q;
+                auto inX = [&](i32 u) {
+                    const int pr = A.cpos[A.root[u]];
+                    return !(pr > pp && pr <= qq);
+                };
+                const int nx = wg_partition(P, m, ORD, inX, S);
+                // both sides take their ids now: a one-node side is never
+                // rebuilt, and the other side must not count it as a member
+                for (int i = threadIdx.x; i < m; i += PW_BS) A.part[P[i]] = i < nx ? cp : cq;
+                __syncthreads();
+                if (threadIdx.x == 0) {
+                    STK[S.sp++] = make_int4(s, s + nx, cp, ST_INIT);
+                    STK[S.sp++] = make_int4(s + nx, S.e, cq, ST_INIT);
+                }
+                __syncthreads();
+                break;
+            }
+            // ---------------- branch cut at x: T_x leaves the part
+            const i32 px = a[x];
+            const i32 rx = A.root[x];
+            const i64 sx = A.subk[x];
+            __syncthreads();
+            // T_x in level order: TMP[0..t)
+            if (threadIdx.x == 0) {
+                TMP[0] = x;
+                S.head = 0;
+                S.tail = 1;
+                S.lev_end = 1;
+                A.part[x] = x;
+            }
+            __syncthreads();
+            while (true) {
+                const int lb = S.head, le = S.lev_end;
+                if (lb == le) break;
+                for (int i = lb + threadIdx.x; i < le; i += PW_BS) {
+                    i32 u = TMP[i];
+                    int c = A.chc[u];
+                    int cs = A.chs[u];
+                    for (int j = 0; j < c; j++) {
+                        i32 ch = CHL[cs + j];
+                        if (A.part[ch] != pid) continue;
+                        int q = atomicAdd(&S.tail, 1);
+                        TMP[q] = ch;
+                        A.part[ch] = x;
+                    }
+                }
+                __syncthreads();
+                if (threadIdx.x == 0) {
+                    S.head = le;
+                    S.lev_end = S.tail;
+                }
+                __syncthreads();
+            }
+            const int tcount = S.tail;
+            for (int i = threadIdx.x; i < tcount; i += PW_BS) A.root[TMP[i]] = x;
+            if (threadIdx.x == 0) {
+                // ancestors of x lose S_{T_x}
+                i32 yv = px;
+                while (true) {
+                    A.subk[yv] -= (i32)sx;
+                    if (cyc[yv]) break;
+                    yv = a[yv];
+                }
+                a[x] = x;
+                cyc[x] = 1;
+            }
+            __syncthreads();
+            // entries between T_x and the rest of the part
+            const i64 tot = wg_degree_prefix(TMP, tcount, G.rp, DP, S);
+            for (i64 b = 0; b < tot; b += PW_BS) {
+                const i64 t = b + threadIdx.x;
+                i32 v = 0;
+                i64 val = 0;
+                if (t < tot) {
+                    int slot = find_slot(DP, tcount, t);
+                    v = TMP[slot];
+                    int2 ed = G.e[G.rp[v] + (t - DP[slot])];
+                    i32 u = ed.x;
+                    if (A.part[u] == pid) {
+                        val = ed.y;
+                        const i32 A_ = ed.y;
+                        atomicSub(&A.win[u], A_);
+                        // paths u -> lca and px -> lca in the part before the cut
+                        i32 p1 = u, p2 = px;
+                        while (A.dep[p1] > A.dep[p2]) {
+                            atomicSub(&A.cut[p1], A_);
+                            p1 = a[p1];
+                        }
+                        while (A.dep[p2] > A.dep[p1]) {
+                            atomicSub(&A.cut[p2], A_);
+                            p2 = a[p2];
+                        }
+                        while (p1 != p2) {
+                            atomicSub(&A.cut[p1], A_);
+                            atomicSub(&A.cut[p2], A_);
+                            if (cyc[p1] && cyc[p2]) break;
+                            p1 = a[p1];
+                            p2 = a[p2];
+                        }
+                        // path v -> x inside T_x
+                        for (i32 q = v; q != x; q = a[q]) atomicSub(&A.cut[q], A_);
+                        if (L >= 2 && A.root[u] != rx) {
+                            const int j = A.cpos[rx], l = A.cpos[A.root[u]];
+                            atomicAdd((unsigned long long *)&Wm[j * L + l], (unsigned long long)(-(i64)A_));
+                            atomicAdd((unsigned long long *)&Wm[l * L + j], (unsigned long long)(-(i64)A_));
+                        }
+                    }
+                }
+                wave_run_add(t < tot, v, -val, A.win);
+            }
+            __syncthreads();
+            // the part keeps its members first, T_x goes to the end of the range
+            const int keep = wg_partition(P, m, ORD, [&](i32 u) { return A.part[u] == pid; }, S);
+            if (threadIdx.x == 0) {
+                STK[S.sp++] = make_int4(s + keep, S.e, x, 0);
+                S.e = s + keep;
+                S.sig = sig - sx;
+            }
+            __syncthreads();
+        }
+    }
+}
+
+void launch_positive_wg(const PosArgs &A, i64 nflag, hipStream_t s)
+{
+    if (nflag > 0) k_positive_wg<<<(unsigned)nflag, PW_BS, 0, s>>>(A);
+}

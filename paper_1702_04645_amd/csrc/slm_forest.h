@@ -16,6 +16,14 @@ struct Work {
     uint8_t *cyc = nullptr, *act = nullptr, *hasc = nullptr, *exam = nullptr,
             *exam_next = nullptr, *accept = nullptr, *head = nullptr;
     i32 *claim = nullptr, *L = nullptr, *pos = nullptr, *cnode = nullptr, *mlist = nullptr;
+    // POSITIVE work space
+    i32 *fidx = nullptr, *flist = nullptr, *fcnt = nullptr, *flen = nullptr, *mem = nullptr;
+    i32 *ptmp = nullptr, *pord = nullptr, *pchl = nullptr, *plvl = nullptr;
+    i32 *part = nullptr, *win = nullptr, *psub = nullptr, *pcut = nullptr, *pdep = nullptr,
+        *proot = nullptr, *chs = nullptr, *chc = nullptr;
+    i64 *mem_off = nullptr, *pdp = nullptr, *woff_f = nullptr, *noff_f = nullptr;
+    i64 *wsz = nullptr, *nsz = nullptr;
+    int4 *pstk = nullptr;
     i32 *A0 = nullptr, *A1 = nullptr, *M0 = nullptr, *M1 = nullptr;
     i32 *J = nullptr;  // kmax tables of n0
     i32 *D0 = nullptr, *D1 = nullptr;
@@ -54,6 +62,29 @@ struct Work {
     i32 *hub_cid = nullptr;
     i64 hub_chunk_cap = 0;
 };
+
+// Arguments of the workgroup-per-community POSITIVE kernel.
+struct PosArgs {
+    LevelView G;
+    i32 *a;              // assignment (updated)
+    uint8_t *cyc;        // cycle flags (updated)
+    const i32 *flist;    // community id of every flagged community
+    const i64 *mem_off;  // members of flagged community f: mem[mem_off[f] .. mem_off[f+1])
+    i32 *mem;
+    i32 *tmp, *ord;      // per-community scratch (n entries)
+    i32 *chl;            // children arena (2n entries)
+    i64 *dpre;           // degree prefixes (n + nflag entries)
+    i32 *lvl;            // level starts (n + nflag entries)
+    int4 *stk;           // part stack (n entries)
+    i32 *part, *win, *subk, *cut, *dep, *root, *chs, *chc, *cpos;  // per node
+    const i32 *lcyc;     // cycle length of every flagged community
+    const i64 *woff;     // cycle weight matrix offsets (L*L entries when L >= 2)
+    i64 *W;
+    const i64 *noff;     // cycle node list offsets
+    i32 *cn;
+    i64 *splits;
+};
+void launch_positive_wg(const PosArgs &A, i64 nflag, hipStream_t s);
 
 struct Forest {
     int K = 0;            // highest jump table index in use
