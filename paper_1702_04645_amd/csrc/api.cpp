@@ -72,8 +72,11 @@ static void free_bins(slm_graph *g)
 {
     Bins &B = g->bins;
     for (void *p : {(void *)B.hub_tab_off, (void *)B.chunk_hub, (void *)B.chunk_beg,
-                    (void *)B.chunk_off_of_hub})
+                    (void *)B.chunk_off_of_hub, (void *)B.tile_hub, (void *)B.tile_off_of_hub})
         if (p) (void)hipFree(p);
+    B.tile_hub = nullptr;
+    B.tile_off_of_hub = nullptr;
+    B.ntile = 0;
     B.hub_tab_off = nullptr;
     B.chunk_hub = nullptr;
     B.chunk_beg = nullptr;
@@ -127,11 +130,15 @@ static void setup_level(slm_graph *g)
             std::vector<i32> chunk_first(nhub + 1, 0);
             std::vector<i32> chunk_hub;
             std::vector<i64> chunk_beg;
+            std::vector<i32> tile_first(nhub + 1, 0);
+            std::vector<i32> tile_hub;
             for (i64 h = 0; h < nhub; h++) {
                 const i64 b0 = span[2 * h], b1 = span[2 * h + 1], deg = b1 - b0;
-                i64 t = 1;
+                i64 t = HUB_TILE;
                 while (t < 2 * deg) t <<= 1;
                 tab_off[h + 1] = tab_off[h] + t;
+                tile_first[h] = (i32)tile_hub.size();
+                for (i64 q = 0; q < t / HUB_TILE; q++) tile_hub.push_back((i32)h);
                 chunk_first[h] = (i32)chunk_hub.size();
                 for (i64 c = b0; c < b1; c += HUB_CHUNK) {
                     chunk_hub.push_back((i32)h);
@@ -139,6 +146,21 @@ static void setup_level(slm_graph *g)
                 }
             }
             chunk_first[nhub] = (i32)chunk_hub.size();
+            tile_first[nhub] = (i32)tile_hub.size();
+            B.ntile = (i64)tile_hub.size();
+            HIPCHK(hipMalloc(&B.tile_hub, sizeof(i32) * B.ntile));
+            HIPCHK(hipMalloc(&B.tile_off_of_hub, sizeof(i32) * (nhub + 1)));
+            HIPCHK(hipMemcpyAsync(B.tile_hub, tile_hub.data(), sizeof(i32) * B.ntile,
+                                  hipMemcpyHostToDevice, s));
+            HIPCHK(hipMemcpyAsync(B.tile_off_of_hub, tile_first.data(), sizeof(i32) * (nhub + 1),
+                                  hipMemcpyHostToDevice, s));
+            if (B.ntile > W.hub_tile_cap) {
+                if (W.hub_tkey) HIPCHK(hipFree(W.hub_tkey));
+                if (W.hub_tid) HIPCHK(hipFree(W.hub_tid));
+                W.hub_tile_cap = B.ntile + 64;
+                HIPCHK(hipMalloc(&W.hub_tkey, sizeof(i64) * W.hub_tile_cap));
+                HIPCHK(hipMalloc(&W.hub_tid, sizeof(i32) * W.hub_tile_cap));
+            }
             B.nchunk = (i64)chunk_hub.size();
             B.table_total = tab_off[nhub];
             HIPCHK(hipMalloc(&B.hub_tab_off, sizeof(i64) * (nhub + 1)));
@@ -255,6 +277,12 @@ static void alloc_work(slm_graph *g)
     W.wsz = dalloc<i64>(g, n);
     W.nsz = dalloc<i64>(g, n);
     W.pstk = dalloc<int4>(g, n);
+    W.mpos = dalloc<i32>(g, n);
+    W.xk = dalloc<i32>(g, n);
+    W.xw = dalloc<i32>(g, n);
+    W.xs = dalloc<i32>(g, n);
+    W.xc = dalloc<i32>(g, n);
+    W.xf = dalloc<uint8_t>(g, n);
     W.minm = dalloc<i32>(g, n);
     W.rank = dalloc<i64>(g, n + 1);
     W.scan_tmp = dalloc<i64>(g, scan_tmp_elems(std::max(n, nnz) + 1) + 16);
@@ -477,7 +505,8 @@ void slm_destroy(slm_graph *g)
     for (void *p : g->allocs) (void)hipFree(p);
     Work &W = g->W;
     for (void *p : {(void *)W.W, (void *)W.hist, (void *)W.hub_keys, (void *)W.hub_vals,
-                    (void *)W.hub_win, (void *)W.hub_ckey, (void *)W.hub_cid})
+                    (void *)W.hub_win, (void *)W.hub_ckey, (void *)W.hub_cid,
+                    (void *)W.hub_tkey, (void *)W.hub_tid})
         if (p) (void)hipFree(p);
     if (W.h_scal) (void)hipHostFree(W.h_scal);
     if (g->ev0) (void)hipEventDestroy(g->ev0);
@@ -680,7 +709,7 @@ slm_status slm_sweep(slm_graph *g, const int32_t *lab_dev, int64_t n_c, int32_t 
     community_totals(g->W, L, lab_dev, n_c, g->s);
     if (g->timing) HIPCHK(hipEventRecord(g->ev0, g->s));
     run_sweep(L, g->bins, lab_dev, g->W.sigma, best_c_dev, delta_dev, w_own_dev, g->W.hub_keys,
-              g->W.hub_vals, g->W.hub_win, g->s);
+              g->W.hub_vals, g->W.hub_win, g->W.hub_tkey, g->W.hub_tid, g->s);
     if (g->timing) {
         HIPCHK(hipEventRecord(g->ev1, g->s));
         HIPCHK(hipEventSynchronize(g->ev1));

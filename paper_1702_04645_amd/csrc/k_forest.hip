@@ -691,9 +691,21 @@ i64 positive(Work &W, const LevelView &Lv, const Bins &B, i64 *nc_out, hipStream
         A.noff = W.noff_f;
         A.cn = W.cnode;
         A.splits = W.counters;
+        A.mpos = W.mpos;
+        A.xk = W.xk;
+        A.xw = W.xw;
+        A.xs = W.xs;
+        A.xc = W.xc;
+        A.xf = W.xf;
+        HIPCHK(hipMemsetAsync(W.changed, 0, sizeof(int), s));
+        A.err = W.changed;
         launch_positive_wg(A, nflag, s);
         read_scalars(W, W.counters, 1, s);
         splits = W.h_scal[0];
+        HIPCHK(hipMemcpyAsync(W.h_scal + 8, W.changed, sizeof(int), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        const int perr = *(int *)(W.h_scal + 8);
+        if (perr) throw SlmError{4, "POSITIVE loop bound tripped (code " + std::to_string(perr) + ")"};
         HIPCHK(hipMemcpyAsync(W.comp, W.part, sizeof(i32) * n, hipMemcpyDeviceToDevice, s));
     }
     *nc_out = canonical_labels(W, n, s);
@@ -715,7 +727,7 @@ i64 maximal_moves(Work &W, const LevelView &Lv, const Bins &B, i64 nc, u64 seed,
     community_totals(W, Lv, W.lab, nc, s);
     if (timing) HIPCHK(hipEventRecord(ev0, s));
     run_sweep(Lv, B, W.lab, W.sigma, W.best_c, W.delta, W.w_own, W.hub_keys, W.hub_vals,
-              W.hub_win, s);
+              W.hub_win, W.hub_tkey, W.hub_tid, s);
     if (timing) HIPCHK(hipEventRecord(ev1, s));
     // candidates
     launch_fill_u8(W.act, 0, nc, s);

@@ -40,6 +40,7 @@ struct PwShared {
     int tail, head, lev_end;
     int L;         // cycle length of the part
     int chl_top;   // next free slot of the children arena
+    int iters;     // loop guard (workgroup-uniform loops)
 };
 
 __device__ __forceinline__ i64 wg_sum(i64 v, PwShared &S)
@@ -130,9 +131,12 @@ __device__ __forceinline__ void wave_run_add(bool in_range, i32 idx, i64 val, i3
     if (in_range && last && v != 0) atomicAdd(&dst[idx], (i32)v);
 }
 
-__device__ __forceinline__ i32 parent_of(i32 u, const i32 *a, const uint8_t *cyc)
+// Every loop of the kernel is bounded by the part size; a bound that trips
+// (which a consistent state never does) records an error code and ends the
+// workgroup's work instead of spinning.
+__device__ __forceinline__ void report(int *err, int code)
 {
-    return cyc[u] ? u : a[u];
+    atomicCAS(err, 0, code);
 }
 
 // Flattened walk over the CSR entries of nodes list[0..cnt): degree prefix
@@ -223,11 +227,17 @@ __global__ __launch_bounds__(PW_BS) void k_positive_wg(PosArgs A)
         STK[0] = make_int4(0, m0, A.flist[f], ST_INIT);
         S.sp = 1;
         S.chl_top = 0;
+        S.iters = 0;
     }
     __syncthreads();
     while (true) {
         __syncthreads();
         if (S.sp == 0) break;
+        // every pass pops one part; parts and splits are fewer than 2*m0
+        if (S.iters > 4 * m0 + 8) {
+            if (threadIdx.x == 0) report(A.err, 5);
+            break;
+        }
         if (threadIdx.x == 0) {
             int4 t = STK[--S.sp];
             S.s = t.x;
@@ -386,13 +396,16 @@ __global__ __launch_bounds__(PW_BS) void k_positive_wg(PosArgs A)
                     i32 v = ed.x;
                     if (v != u && A.part[v] == pid && A.root[u] == A.root[v]) {
                         i32 x = u, y = v;
-                        while (A.dep[x] > A.dep[y]) x = a[x];
-                        while (A.dep[y] > A.dep[x]) y = a[y];
-                        while (x != y) {
+                        int guard = 0;
+                        // a walk takes at most 2 (m - 1) steps
+                        while (A.dep[x] > A.dep[y] && guard++ < 2 * m) x = a[x];
+                        while (A.dep[y] > A.dep[x] && guard++ < 2 * m) y = a[y];
+                        while (x != y && guard++ < 2 * m) {
                             x = a[x];
                             y = a[y];
                         }
-                        if (!cyc[x]) atomicSub(&A.cut[x], ed.y);
+                        if (guard >= 2 * m) report(A.err, 1);
+                        else if (!cyc[x]) atomicSub(&A.cut[x], ed.y);
                     }
                 }
             }
@@ -424,6 +437,13 @@ __global__ __launch_bounds__(PW_BS) void k_positive_wg(PosArgs A)
         }
         // -------------------------------------------------- split loop
         while (true) {
+            __syncthreads();
+            if (threadIdx.x == 0) S.iters++;
+            __syncthreads();
+            if (S.iters > 4 * m0 + 8) {
+                if (threadIdx.x == 0) report(A.err, 6);
+                break;
+            }
             const int m = S.e - s;
             i32 *P = M + s;
             const i64 sig = S.sig;
@@ -550,7 +570,11 @@ __global__ __launch_bounds__(PW_BS) void k_positive_wg(PosArgs A)
             if (threadIdx.x == 0) {
                 // ancestors of x lose S_{T_x}
                 i32 yv = px;
-                while (true) {
+                for (int guard = 0;; guard++) {
+                    if (guard >= m) {
+                        report(A.err, 4);
+                        break;
+                    }
                     A.subk[yv] -= (i32)sx;
                     if (cyc[yv]) break;
                     yv = a[yv];
@@ -576,23 +600,28 @@ __global__ __launch_bounds__(PW_BS) void k_positive_wg(PosArgs A)
                         atomicSub(&A.win[u], A_);
                         // paths u -> lca and px -> lca in the part before the cut
                         i32 p1 = u, p2 = px;
-                        while (A.dep[p1] > A.dep[p2]) {
+                        int guard = 0;
+                        while (A.dep[p1] > A.dep[p2] && guard++ < 2 * m) {
                             atomicSub(&A.cut[p1], A_);
                             p1 = a[p1];
                         }
-                        while (A.dep[p2] > A.dep[p1]) {
+                        while (A.dep[p2] > A.dep[p1] && guard++ < 2 * m) {
                             atomicSub(&A.cut[p2], A_);
                             p2 = a[p2];
                         }
-                        while (p1 != p2) {
+                        while (p1 != p2 && guard++ < 2 * m) {
                             atomicSub(&A.cut[p1], A_);
                             atomicSub(&A.cut[p2], A_);
                             if (cyc[p1] && cyc[p2]) break;
                             p1 = a[p1];
                             p2 = a[p2];
                         }
+                        if (guard >= 2 * m) report(A.err, 2);
                         // path v -> x inside T_x
-                        for (i32 q = v; q != x; q = a[q]) atomicSub(&A.cut[q], A_);
+                        guard = 0;
+                        for (i32 q = v; q != x && guard < m; q = a[q], guard++)
+                            atomicSub(&A.cut[q], A_);
+                        if (guard >= m) report(A.err, 3);
                         if (L >= 2 && A.root[u] != rx) {
                             const int j = A.cpos[rx], l = A.cpos[A.root[u]];
                             atomicAdd((unsigned long long *)&Wm[j * L + l], (unsigned long long)(-(i64)A_));

@@ -1,7 +1,7 @@
 // Row kernels: every node's CSR row is handled by a group of lanes sized to
 // its degree (the degree bins of slm_impl.h).  Groups of up to 64 lanes live
 // inside one wavefront and keep their per-node community table in LDS; the
-// 4096-entry bin uses a whole 256-lane workgroup per node; hub rows are cut
+// 2048- and 4096-entry bins use a whole workgroup per node; hub rows are cut
 // in HUB_CHUNK-entry chunks spread over workgroups with the table in HBM.
 //
 // Kernels here: strengths (Sec. 2.4), ASSIGN (Sec. 3.1), the MAXIMAL sweep
@@ -16,7 +16,8 @@ template <> struct BinShape<BIN_8> { static constexpr int G = 8, H = 16; };
 template <> struct BinShape<BIN_32> { static constexpr int G = 32, H = 64; };
 template <> struct BinShape<BIN_128> { static constexpr int G = 64, H = 256; };
 template <> struct BinShape<BIN_512> { static constexpr int G = 64, H = 1024; };
-template <> struct BinShape<BIN_4096> { static constexpr int G = 256, H = 8192; };
+template <> struct BinShape<BIN_2048> { static constexpr int G = 256, H = 4096; };
+template <> struct BinShape<BIN_4096> { static constexpr int G = 512, H = 8192; };
 
 template <int G> struct GroupGeom {
     static constexpr int NG = (G <= 64) ? SLM_BS / G : 1;  // groups per workgroup
@@ -183,83 +184,6 @@ __global__ __launch_bounds__(GroupGeom<G>::BSZ) void k_own(
     }
     s = gsum<G>(s, red);
     if (act && gl == 0) wc[node] = (i32)s;
-}
-
-// ------------------------------------------------------------------ MAXIMAL sweep
-// Per node: w(i,C) for every neighbouring community C in an LDS
-// open-addressing table (own-community weight kept in registers), then the
-// best join(i,C) against stay(i).
-template <int G, int H>
-__global__ __launch_bounds__(GroupGeom<G>::BSZ) void k_sweep_lds(
-    LevelView L, const i32 *__restrict__ nodes, i64 count, const i32 *__restrict__ lab,
-    const i32 *__restrict__ sigma, i32 *__restrict__ best_c, i64 *__restrict__ delta,
-    i32 *__restrict__ w_own)
-{
-    constexpr int NGc = GroupGeom<G>::NG;
-    __shared__ i32 s_key[NGc * H];
-    __shared__ i32 s_val[NGc * H];
-    __shared__ i64 red[32];
-    GROUP_PROLOGUE(G)
-    i32 *keys = s_key + gi * H;
-    i32 *vals = s_val + gi * H;
-    for (int s = gl; s < H; s += G) {
-        keys[s] = -1;
-        vals[s] = 0;
-    }
-    group_sync<G>();
-    const i32 ci = valid ? lab[node] : 0;
-    const i64 ki = valid ? L.k[node] : 0;
-    i64 win = 0;
-    if (valid) {
-        const i64 e1 = L.rp[node + 1];
-        for (i64 j = L.rp[node] + gl; j < e1; j += G) {
-            int2 ed = L.e[j];
-            const i32 v = ed.x;
-            if (v == node) continue;
-            const i32 c = lab[v];
-            if (c == ci) {
-                win += ed.y;
-                continue;
-            }
-            u32 h = slot_of<H>(c);
-            for (int probe = 0; probe < H; probe++) {
-                i32 old = atomicCAS(&keys[h], -1, c);
-                if (old == -1 || old == c) {
-                    atomicAdd(&vals[h], ed.y);
-                    break;
-                }
-                h = (h + 1) & (H - 1);
-            }
-        }
-    }
-    group_sync<G>();
-    i64 bk = INT64_MIN;
-    i32 bc = INT32_MAX;
-    if (valid) {
-        for (int s = gl; s < H; s += G) {
-            const i32 c = keys[s];
-            if (c >= 0) {
-                i64 key = L.m2 * (i64)vals[s] - ki * (i64)sigma[c];
-                if (better_key(key, c, bk, bc)) {
-                    bk = key;
-                    bc = c;
-                }
-            }
-        }
-    }
-    win = gsum<G>(win, red);
-    gbest<G>(bk, bc, red);
-    if (valid && gl == 0) {
-        const i64 stay = L.m2 * win - ki * ((i64)sigma[ci] - ki);
-        if (bc != INT32_MAX && bk > stay) {
-            best_c[node] = bc;
-            delta[node] = bk - stay;
-        } else {
-            best_c[node] = ci;
-            delta[node] = 0;
-        }
-        w_own[node] = (i32)win;
-    }
 }
 
 // ------------------------------------------------------------------ contraction rows
@@ -454,85 +378,6 @@ __global__ __launch_bounds__(SLM_BS) void k_hub_own_zero(const i32 *__restrict__
     }
 }
 
-// Hub sweep: chunks insert (community, weight) into the hub's HBM table.
-__global__ __launch_bounds__(SLM_BS) void k_hub_sweep_insert(
-    LevelView L, const i32 *__restrict__ hub_node, const i32 *__restrict__ chunk_hub,
-    const i64 *__restrict__ chunk_beg, const i64 *__restrict__ tab_off,
-    const i32 *__restrict__ lab, i32 *__restrict__ tkey, i32 *__restrict__ tval,
-    i32 *__restrict__ hub_win)
-{
-    __shared__ i64 red[32];
-    const i32 h = chunk_hub[blockIdx.x];
-    const i32 node = hub_node[h];
-    const i32 ci = lab[node];
-    const i64 t0 = tab_off[h];
-    const u32 tmask = (u32)(tab_off[h + 1] - t0 - 1);
-    const int log2t = 32 - __builtin_clz(tmask + 1) - 1;
-    const i64 b = chunk_beg[blockIdx.x];
-    i64 end = b + HUB_CHUNK;
-    if (end > L.rp[node + 1]) end = L.rp[node + 1];
-    i64 win = 0;
-    for (i64 j = b + threadIdx.x; j < end; j += blockDim.x) {
-        int2 ed = L.e[j];
-        const i32 v = ed.x;
-        if (v == node) continue;
-        const i32 c = lab[v];
-        if (c == ci) {
-            win += ed.y;
-            continue;
-        }
-        u32 slot = hash_label(c) >> (32 - log2t);
-        for (u32 probe = 0; probe <= tmask; probe++) {
-            i32 old = atomicCAS(&tkey[t0 + slot], -1, c);
-            if (old == -1 || old == c) {
-                atomicAdd(&tval[t0 + slot], ed.y);
-                break;
-            }
-            slot = (slot + 1) & tmask;
-        }
-    }
-    win = block_sum<i64>(win, red);
-    if (threadIdx.x == 0 && win) atomicAdd(&hub_win[h], (i32)win);
-}
-
-__global__ __launch_bounds__(SLM_BS) void k_hub_sweep_final(
-    LevelView L, const i32 *__restrict__ hub_node, const i64 *__restrict__ tab_off,
-    const i32 *__restrict__ lab, const i32 *__restrict__ sigma, const i32 *__restrict__ tkey,
-    const i32 *__restrict__ tval, const i32 *__restrict__ hub_win, i32 *__restrict__ best_c,
-    i64 *__restrict__ delta, i32 *__restrict__ w_own)
-{
-    __shared__ i64 red[32];
-    const i32 h = blockIdx.x;
-    const i32 node = hub_node[h];
-    const i32 ci = lab[node];
-    const i64 ki = L.k[node];
-    i64 bk = INT64_MIN;
-    i32 bc = INT32_MAX;
-    for (i64 s = tab_off[h] + threadIdx.x; s < tab_off[h + 1]; s += blockDim.x) {
-        const i32 c = tkey[s];
-        if (c >= 0) {
-            i64 key = L.m2 * (i64)tval[s] - ki * (i64)sigma[c];
-            if (better_key(key, c, bk, bc)) {
-                bk = key;
-                bc = c;
-            }
-        }
-    }
-    block_best(bk, bc, red);
-    if (threadIdx.x == 0) {
-        const i64 win = hub_win[h];
-        const i64 stay = L.m2 * win - ki * ((i64)sigma[ci] - ki);
-        if (bc != INT32_MAX && bk > stay) {
-            best_c[node] = bc;
-            delta[node] = bk - stay;
-        } else {
-            best_c[node] = ci;
-            delta[node] = 0;
-        }
-        w_own[node] = (i32)win;
-    }
-}
-
 // Hub contraction rows: one record per entry (merged later by the sort).
 __global__ __launch_bounds__(SLM_BS) void k_hub_crows(
     LevelView L, const i32 *__restrict__ hub_node, const i32 *__restrict__ chunk_hub,
@@ -561,6 +406,7 @@ __device__ __forceinline__ int bin_of_degree(i64 d)
     if (d <= 32) return BIN_32;
     if (d <= 128) return BIN_128;
     if (d <= 512) return BIN_512;
+    if (d <= 2048) return BIN_2048;
     if (d <= 4096) return BIN_4096;
     return BIN_HUB;
 }
@@ -637,7 +483,7 @@ static void bin_launch_geom(const Bins &Bn, i64 &count, const i32 *&nodes, unsig
     block = GroupGeom<G>::BSZ;
 }
 
-#define FOR_LDS_BINS(X) X(BIN_ZERO) X(BIN_8) X(BIN_32) X(BIN_128) X(BIN_512) X(BIN_4096)
+#define FOR_LDS_BINS(X) X(BIN_ZERO) X(BIN_8) X(BIN_32) X(BIN_128) X(BIN_512) X(BIN_2048) X(BIN_4096)
 
 void run_strength_binned(const i64 *rp, const int2 *e, const Bins &Bn, i32 *k, i32 *diag,
                          i64 *m2_acc, hipStream_t s)
@@ -723,35 +569,6 @@ void run_own_weight(const LevelView &L, const Bins &Bn, const i32 *lab, const ui
                                                                    active, wc);
         k_hub_own<<<(unsigned)Bn.nchunk, SLM_BS, 0, s>>>(L, Bn.hub_node, Bn.chunk_hub,
                                                         Bn.chunk_beg, lab, active, wc);
-    }
-}
-
-void run_sweep(const LevelView &L, const Bins &Bn, const i32 *lab, const i32 *sigma,
-               i32 *best_c, i64 *delta, i32 *w_own, i32 *hub_keys, i32 *hub_vals,
-               i32 *hub_win, hipStream_t s)
-{
-#define X(B)                                                                          \
-    {                                                                                 \
-        i64 cnt;                                                                      \
-        const i32 *nd;                                                                \
-        unsigned gr, bl;                                                              \
-        bin_launch_geom<B>(Bn, cnt, nd, gr, bl);                                      \
-        if (cnt > 0)                                                                  \
-            k_sweep_lds<BinShape<B>::G, BinShape<B>::H><<<gr, bl, 0, s>>>(            \
-                L, nd, cnt, lab, sigma, best_c, delta, w_own);                        \
-    }
-    FOR_LDS_BINS(X)
-#undef X
-    if (Bn.nhub > 0) {
-        launch_fill_i32(hub_keys, -1, Bn.table_total, s);
-        launch_fill_i32(hub_vals, 0, Bn.table_total, s);
-        launch_fill_i32(hub_win, 0, Bn.nhub, s);
-        k_hub_sweep_insert<<<(unsigned)Bn.nchunk, SLM_BS, 0, s>>>(
-            L, Bn.hub_node, Bn.chunk_hub, Bn.chunk_beg, Bn.hub_tab_off, lab, hub_keys, hub_vals,
-            hub_win);
-        k_hub_sweep_final<<<(unsigned)Bn.nhub, SLM_BS, 0, s>>>(L, Bn.hub_node, Bn.hub_tab_off, lab,
-                                                              sigma, hub_keys, hub_vals, hub_win,
-                                                              best_c, delta, w_own);
     }
 }
 

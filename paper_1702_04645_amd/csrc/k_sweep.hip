@@ -1,0 +1,414 @@
+// The synchronous move sweep of MAXIMAL (Sec. 3.4): for every node i at once,
+// w(i,C) for each neighbouring community C, join(i,C) = M2 w(i,C) - k_i S_C,
+// the best C != c_i (key desc, label asc), and a move when it beats
+// stay(i) = M2 w(i, c_i \ i) - k_i (S_ci - k_i).
+//
+// Rows are handled by lane groups sized to their degree:
+//   deg <= 8       8-lane group, one entry per lane; equal labels are found
+//                  by shuffles inside the group (no LDS);
+//   deg <= 512     32- or 64-lane groups with an LDS open-addressing table
+//                  and a list of the occupied slots, so reading and clearing
+//                  the table costs the number of distinct labels; groups loop
+//                  over the nodes of their bin;
+//   deg <= 4096    one 256- or 512-lane workgroup per node, same table;
+//   larger (hubs)  rows cut in HUB_CHUNK-entry chunks; a workgroup totals its
+//                  chunk in LDS and adds the distinct labels to the hub's HBM
+//                  table; table tiles are then scanned in parallel.
+// The own community's weight never enters a table: it is summed in
+// registers.  Entries are int2 (column, weight), read once, coalesced per
+// group.
+#include "slm_forest.h"
+
+template <int H> __device__ __forceinline__ u32 sw_slot(i32 c)
+{
+    constexpr int LOG2H = __builtin_ctz(H);
+    return hash_label(c) >> (32 - LOG2H);
+}
+
+template <int G> __device__ __forceinline__ void sw_sync()
+{
+    if constexpr (G <= 64) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    } else {
+        __syncthreads();
+    }
+}
+
+__device__ __forceinline__ void write_move(const LevelView &L, i32 node, i32 ci, i64 ki, i64 win,
+                                           i64 bk, i32 bc, const i32 *__restrict__ sigma,
+                                           i32 *__restrict__ best_c, i64 *__restrict__ delta,
+                                           i32 *__restrict__ w_own)
+{
+    const i64 stay = L.m2 * win - ki * ((i64)sigma[ci] - ki);
+    if (bc != INT32_MAX && bk > stay) {
+        best_c[node] = bc;
+        delta[node] = bk - stay;
+    } else {
+        best_c[node] = ci;
+        delta[node] = 0;
+    }
+    w_own[node] = (i32)win;
+}
+
+// ------------------------------------------------------------------ isolated nodes
+__global__ __launch_bounds__(SLM_BS) void k_sweep_zero(const i32 *__restrict__ nodes, i64 count,
+                                                      const i32 *__restrict__ lab,
+                                                      i32 *__restrict__ best_c,
+                                                      i64 *__restrict__ delta,
+                                                      i32 *__restrict__ w_own)
+{
+    for (i64 t = (i64)blockIdx.x * blockDim.x + threadIdx.x; t < count;
+         t += (i64)gridDim.x * blockDim.x) {
+        const i32 u = nodes[t];
+        best_c[u] = lab[u];
+        delta[u] = 0;
+        w_own[u] = 0;
+    }
+}
+
+// ------------------------------------------------------------------ tiny rows
+template <int G>
+__global__ __launch_bounds__(SLM_BS) void k_sweep_tiny(LevelView L, const i32 *__restrict__ nodes,
+                                                      i64 count, const i32 *__restrict__ lab,
+                                                      const i32 *__restrict__ sigma,
+                                                      i32 *__restrict__ best_c,
+                                                      i64 *__restrict__ delta,
+                                                      i32 *__restrict__ w_own)
+{
+    constexpr int NG = SLM_BS / G;
+    const int gl = threadIdx.x % G;
+    const i64 slot = (i64)blockIdx.x * NG + threadIdx.x / G;
+    const bool valid = slot < count;
+    const i32 node = valid ? nodes[slot] : 0;
+    i32 ci = 0;
+    i64 ki = 0;
+    i32 c = -1;
+    i64 wv = 0, win = 0;
+    if (valid) {
+        ci = lab[node];
+        ki = L.k[node];
+        const i64 e0 = L.rp[node], deg = L.rp[node + 1] - e0;
+        if (gl < deg) {
+            const int2 ed = L.e[e0 + gl];
+            if (ed.x != node) {
+                const i32 cv = lab[ed.x];
+                if (cv == ci) win = ed.y;
+                else {
+                    c = cv;
+                    wv = ed.y;
+                }
+            }
+        }
+    }
+    // total weight of this lane's label over the group; the first lane of a
+    // label evaluates it
+    i64 tot = 0;
+    bool first = true;
+#pragma unroll
+    for (int j = 0; j < G; j++) {
+        const i32 cj = __shfl(c, j, G);
+        const i64 wj = __shfl(wv, j, G);
+        if (cj == c) {
+            tot += wj;
+            if (j < gl) first = false;
+        }
+    }
+    i64 bk = INT64_MIN;
+    i32 bc = INT32_MAX;
+    if (c >= 0 && first) {
+        bk = L.m2 * tot - ki * (i64)sigma[c];
+        bc = c;
+    }
+    win = group_sum<G, i64>(win);
+    group_best<G>(bk, bc);
+    if (valid && gl == 0) write_move(L, node, ci, ki, win, bk, bc, sigma, best_c, delta, w_own);
+}
+
+// ------------------------------------------------------------------ LDS table with slot list
+// One table per group; the groups of a workgroup loop over the nodes of the
+// bin.  G lanes per node (G <= 64: the group lives in one wavefront; G > 64:
+// the whole workgroup), H slots (H >= 2 * max degree), U = max degree / G
+// entries per lane: a lane issues all its entry loads, then all its label
+// gathers, before touching the table, so the memory latency of a row is paid
+// about once.
+template <int H>
+__device__ __forceinline__ void table_insert(i32 *keys, i32 *vals, i32 *list, i32 *cnt, i32 c,
+                                             i32 w)
+{
+    u32 h = sw_slot<H>(c);
+    for (int probe = 0; probe < H; probe++) {
+        const i32 old = atomicCAS(&keys[h], -1, c);
+        if (old == -1) {
+            atomicAdd(&vals[h], w);
+            list[atomicAdd(cnt, 1)] = (i32)h;
+            return;
+        }
+        if (old == c) {
+            atomicAdd(&vals[h], w);
+            return;
+        }
+        h = (h + 1) & (H - 1);
+    }
+}
+
+template <int G, int H, int U>
+__global__ __launch_bounds__(G <= 64 ? SLM_BS : G) void k_sweep_hash(
+    LevelView L, const i32 *__restrict__ nodes, i64 count, const i32 *__restrict__ lab,
+    const i32 *__restrict__ sigma, i32 *__restrict__ best_c, i64 *__restrict__ delta,
+    i32 *__restrict__ w_own)
+{
+    constexpr int NG = G <= 64 ? SLM_BS / G : 1;
+    constexpr int BSZ = G <= 64 ? SLM_BS : G;
+    constexpr int LIST = H / 2;
+    __shared__ i32 s_key[NG * H];
+    __shared__ i32 s_val[NG * H];
+    __shared__ i32 s_list[NG * LIST];
+    __shared__ i32 s_cnt[NG];
+    __shared__ i64 red[32];
+    const int gl = threadIdx.x % G, gi = threadIdx.x / G;
+    i32 *keys = s_key + gi * H;
+    i32 *vals = s_val + gi * H;
+    i32 *list = s_list + gi * LIST;
+    for (int i = threadIdx.x; i < NG * H; i += BSZ) {
+        s_key[i] = -1;
+        s_val[i] = 0;
+    }
+    if (threadIdx.x < NG) s_cnt[threadIdx.x] = 0;
+    __syncthreads();
+    for (i64 slot = (i64)blockIdx.x * NG + gi; slot < count; slot += (i64)gridDim.x * NG) {
+        const i32 node = nodes[slot];
+        const i32 ci = lab[node];
+        const i64 ki = L.k[node];
+        const i64 e0 = L.rp[node];
+        const int deg = (int)(L.rp[node + 1] - e0);
+        int2 ed[U];
+        i32 c[U];
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            const int j = gl + u * G;
+            ed[u] = j < deg ? L.e[e0 + j] : make_int2(-1, 0);
+        }
+#pragma unroll
+        for (int u = 0; u < U; u++) c[u] = (ed[u].x >= 0 && ed[u].x != node) ? lab[ed[u].x] : -1;
+        i64 win = 0;
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            if (c[u] < 0) continue;
+            if (c[u] == ci) win += ed[u].y;
+            else table_insert<H>(keys, vals, list, &s_cnt[gi], c[u], ed[u].y);
+        }
+        sw_sync<G>();
+        const int nd = s_cnt[gi];
+        i64 bk = INT64_MIN;
+        i32 bc = INT32_MAX;
+        for (int i = gl; i < nd; i += G) {
+            const i32 h = list[i];
+            const i32 cc = keys[h];
+            const i64 key = L.m2 * (i64)vals[h] - ki * (i64)sigma[cc];
+            if (better_key(key, cc, bk, bc)) {
+                bk = key;
+                bc = cc;
+            }
+            keys[h] = -1;
+            vals[h] = 0;
+        }
+        if constexpr (G <= 64) {
+            win = group_sum<G, i64>(win);
+            group_best<G>(bk, bc);
+        } else {
+            win = block_sum<i64>(win, red);
+            block_best(bk, bc, red);
+        }
+        if (gl == 0) {
+            write_move(L, node, ci, ki, win, bk, bc, sigma, best_c, delta, w_own);
+            s_cnt[gi] = 0;
+        }
+        sw_sync<G>();
+    }
+}
+
+// ------------------------------------------------------------------ hub rows
+// Chunk totals in LDS, then the distinct labels go to the hub's HBM table.
+#define HUB_H 8192
+#define HUB_BS 512
+__global__ __launch_bounds__(HUB_BS) void k_sweep_hub_chunk(
+    LevelView L, const i32 *__restrict__ hub_node, const i32 *__restrict__ chunk_hub,
+    const i64 *__restrict__ chunk_beg, const i64 *__restrict__ tab_off,
+    const i32 *__restrict__ lab, i32 *__restrict__ tkey, i32 *__restrict__ tval,
+    i32 *__restrict__ hub_win)
+{
+    __shared__ i32 keys[HUB_H];
+    __shared__ i32 vals[HUB_H];
+    __shared__ i32 list[HUB_CHUNK];
+    __shared__ int cnt;
+    __shared__ i64 red[32];
+    for (int i = threadIdx.x; i < HUB_H; i += HUB_BS) {
+        keys[i] = -1;
+        vals[i] = 0;
+    }
+    if (threadIdx.x == 0) cnt = 0;
+    __syncthreads();
+    const i32 h = chunk_hub[blockIdx.x];
+    const i32 node = hub_node[h];
+    const i32 ci = lab[node];
+    const i64 b = chunk_beg[blockIdx.x];
+    i64 end = b + HUB_CHUNK;
+    if (end > L.rp[node + 1]) end = L.rp[node + 1];
+    constexpr int U = HUB_CHUNK / HUB_BS;
+    int2 ed[U];
+    i32 c[U];
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+        const i64 j = b + threadIdx.x + (i64)u * HUB_BS;
+        ed[u] = j < end ? L.e[j] : make_int2(-1, 0);
+    }
+#pragma unroll
+    for (int u = 0; u < U; u++) c[u] = (ed[u].x >= 0 && ed[u].x != node) ? lab[ed[u].x] : -1;
+    i64 win = 0;
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+        if (c[u] < 0) continue;
+        if (c[u] == ci) win += ed[u].y;
+        else table_insert<HUB_H>(keys, vals, list, &cnt, c[u], ed[u].y);
+    }
+    __syncthreads();
+    const i64 t0 = tab_off[h];
+    const u32 tmask = (u32)(tab_off[h + 1] - t0 - 1);
+    const int log2t = 31 - __builtin_clz(tmask + 1);
+    for (int i = threadIdx.x; i < cnt; i += HUB_BS) {
+        const i32 s = list[i];
+        const i32 c = keys[s];
+        const i32 v = vals[s];
+        u32 slot = hash_label(c) >> (32 - log2t);
+        for (u32 probe = 0; probe <= tmask; probe++) {
+            const i32 old = atomicCAS(&tkey[t0 + slot], -1, c);
+            if (old == -1 || old == c) {
+                atomicAdd(&tval[t0 + slot], v);
+                break;
+            }
+            slot = (slot + 1) & tmask;
+        }
+    }
+    win = block_sum<i64>(win, red);
+    if (threadIdx.x == 0 && win) atomicAdd(&hub_win[h], (i32)win);
+}
+
+// Best entry of one HUB_TILE-slot tile of a hub table.
+__global__ __launch_bounds__(SLM_BS) void k_sweep_hub_tile(
+    LevelView L, const i32 *__restrict__ hub_node, const i32 *__restrict__ tile_hub,
+    const i64 *__restrict__ tab_off, const i32 *__restrict__ tile_first,
+    const i32 *__restrict__ sigma, const i32 *__restrict__ tkey, const i32 *__restrict__ tval,
+    i64 *__restrict__ tile_key, i32 *__restrict__ tile_id)
+{
+    __shared__ i64 red[32];
+    const i32 h = tile_hub[blockIdx.x];
+    const i64 ki = L.k[hub_node[h]];
+    const i64 base = tab_off[h] + (i64)(blockIdx.x - tile_first[h]) * HUB_TILE;
+    i64 bk = INT64_MIN;
+    i32 bc = INT32_MAX;
+    for (int i = threadIdx.x; i < HUB_TILE; i += SLM_BS) {
+        const i32 c = tkey[base + i];
+        if (c >= 0) {
+            const i64 key = L.m2 * (i64)tval[base + i] - ki * (i64)sigma[c];
+            if (better_key(key, c, bk, bc)) {
+                bk = key;
+                bc = c;
+            }
+        }
+    }
+    block_best(bk, bc, red);
+    if (threadIdx.x == 0) {
+        tile_key[blockIdx.x] = bk;
+        tile_id[blockIdx.x] = bc;
+    }
+}
+
+__global__ __launch_bounds__(64) void k_sweep_hub_final(
+    LevelView L, const i32 *__restrict__ hub_node, const i32 *__restrict__ tile_first,
+    const i32 *__restrict__ lab, const i32 *__restrict__ sigma, const i64 *__restrict__ tile_key,
+    const i32 *__restrict__ tile_id, const i32 *__restrict__ hub_win, i32 *__restrict__ best_c,
+    i64 *__restrict__ delta, i32 *__restrict__ w_own)
+{
+    const i32 h = blockIdx.x;
+    i64 bk = INT64_MIN;
+    i32 bc = INT32_MAX;
+    for (i32 t = tile_first[h] + threadIdx.x; t < tile_first[h + 1]; t += 64)
+        if (better_key(tile_key[t], tile_id[t], bk, bc)) {
+            bk = tile_key[t];
+            bc = tile_id[t];
+        }
+    group_best<64>(bk, bc);
+    if (threadIdx.x == 0) {
+        const i32 node = hub_node[h];
+        write_move(L, node, lab[node], L.k[node], hub_win[h], bk, bc, sigma, best_c, delta, w_own);
+    }
+}
+
+// ------------------------------------------------------------------ dispatch
+static unsigned persistent_grid(i64 count, int per_block, int max_blocks)
+{
+    i64 g = (count + per_block - 1) / per_block;
+    if (g > max_blocks) g = max_blocks;
+    if (g < 1) g = 1;
+    return (unsigned)g;
+}
+
+void run_sweep(const LevelView &L, const Bins &Bn, const i32 *lab, const i32 *sigma,
+               i32 *best_c, i64 *delta, i32 *w_own, i32 *hub_keys, i32 *hub_vals,
+               i32 *hub_win, i64 *hub_tile_key, i32 *hub_tile_id, hipStream_t s)
+{
+    const i32 *nodes;
+    i64 cnt;
+    cnt = Bn.off[BIN_ZERO + 1] - Bn.off[BIN_ZERO];
+    nodes = Bn.nodes + Bn.off[BIN_ZERO];
+    if (cnt > 0)
+        k_sweep_zero<<<persistent_grid(cnt, SLM_BS, 2048), SLM_BS, 0, s>>>(nodes, cnt, lab, best_c,
+                                                                          delta, w_own);
+    cnt = Bn.off[BIN_8 + 1] - Bn.off[BIN_8];
+    nodes = Bn.nodes + Bn.off[BIN_8];
+    if (cnt > 0)
+        k_sweep_tiny<8><<<grid_for(cnt, SLM_BS / 8), SLM_BS, 0, s>>>(L, nodes, cnt, lab, sigma,
+                                                                   best_c, delta, w_own);
+    cnt = Bn.off[BIN_32 + 1] - Bn.off[BIN_32];
+    nodes = Bn.nodes + Bn.off[BIN_32];
+    if (cnt > 0)
+        k_sweep_hash<32, 64, 1><<<persistent_grid(cnt, SLM_BS / 32, 8192), SLM_BS, 0, s>>>(
+            L, nodes, cnt, lab, sigma, best_c, delta, w_own);
+    cnt = Bn.off[BIN_128 + 1] - Bn.off[BIN_128];
+    nodes = Bn.nodes + Bn.off[BIN_128];
+    if (cnt > 0)
+        k_sweep_hash<64, 256, 2><<<persistent_grid(cnt, SLM_BS / 64, 8192), SLM_BS, 0, s>>>(
+            L, nodes, cnt, lab, sigma, best_c, delta, w_own);
+    cnt = Bn.off[BIN_512 + 1] - Bn.off[BIN_512];
+    nodes = Bn.nodes + Bn.off[BIN_512];
+    if (cnt > 0)
+        k_sweep_hash<64, 1024, 8><<<persistent_grid(cnt, SLM_BS / 64, 4096), SLM_BS, 0, s>>>(
+            L, nodes, cnt, lab, sigma, best_c, delta, w_own);
+    cnt = Bn.off[BIN_2048 + 1] - Bn.off[BIN_2048];
+    nodes = Bn.nodes + Bn.off[BIN_2048];
+    if (cnt > 0)
+        k_sweep_hash<256, 4096, 8><<<persistent_grid(cnt, 1, 4096), 256, 0, s>>>(
+            L, nodes, cnt, lab, sigma, best_c, delta, w_own);
+    cnt = Bn.off[BIN_4096 + 1] - Bn.off[BIN_4096];
+    nodes = Bn.nodes + Bn.off[BIN_4096];
+    if (cnt > 0)
+        k_sweep_hash<512, 8192, 8><<<persistent_grid(cnt, 1, 2048), 512, 0, s>>>(
+            L, nodes, cnt, lab, sigma, best_c, delta, w_own);
+    if (Bn.nhub > 0) {
+        launch_fill_i32(hub_keys, -1, Bn.table_total, s);
+        launch_fill_i32(hub_vals, 0, Bn.table_total, s);
+        launch_fill_i32(hub_win, 0, Bn.nhub, s);
+        k_sweep_hub_chunk<<<(unsigned)Bn.nchunk, HUB_BS, 0, s>>>(
+            L, Bn.hub_node, Bn.chunk_hub, Bn.chunk_beg, Bn.hub_tab_off, lab, hub_keys, hub_vals,
+            hub_win);
+        k_sweep_hub_tile<<<(unsigned)Bn.ntile, SLM_BS, 0, s>>>(L, Bn.hub_node, Bn.tile_hub,
+                                                              Bn.hub_tab_off, Bn.tile_off_of_hub,
+                                                              sigma, hub_keys, hub_vals,
+                                                              hub_tile_key, hub_tile_id);
+        k_sweep_hub_final<<<(unsigned)Bn.nhub, 64, 0, s>>>(L, Bn.hub_node, Bn.tile_off_of_hub, lab,
+                                                          sigma, hub_tile_key, hub_tile_id,
+                                                          hub_win, best_c, delta, w_own);
+    }
+}

@@ -24,6 +24,8 @@ struct Work {
     i64 *mem_off = nullptr, *pdp = nullptr, *woff_f = nullptr, *noff_f = nullptr;
     i64 *wsz = nullptr, *nsz = nullptr;
     int4 *pstk = nullptr;
+    i32 *mpos = nullptr, *xk = nullptr, *xw = nullptr, *xs = nullptr, *xc = nullptr;
+    uint8_t *xf = nullptr;
     i32 *A0 = nullptr, *A1 = nullptr, *M0 = nullptr, *M1 = nullptr;
     i32 *J = nullptr;  // kmax tables of n0
     i32 *D0 = nullptr, *D1 = nullptr;
@@ -61,6 +63,9 @@ struct Work {
     i64 *hub_ckey = nullptr;
     i32 *hub_cid = nullptr;
     i64 hub_chunk_cap = 0;
+    i64 *hub_tkey = nullptr;   // per table tile
+    i32 *hub_tid = nullptr;
+    i64 hub_tile_cap = 0;
 };
 
 // Arguments of the workgroup-per-community POSITIVE kernel.
@@ -77,12 +82,16 @@ struct PosArgs {
     i32 *lvl;            // level starts (n + nflag entries)
     int4 *stk;           // part stack (n entries)
     i32 *part, *win, *subk, *cut, *dep, *root, *chs, *chc, *cpos;  // per node
+    i32 *mpos;                  // per node: index of the node in the member arrays
+    i32 *xk, *xw, *xs, *xc;     // per member (member order): k, win, subtree k, cut
+    uint8_t *xf;                // per member: cycle flag
     const i32 *lcyc;     // cycle length of every flagged community
     const i64 *woff;     // cycle weight matrix offsets (L*L entries when L >= 2)
     i64 *W;
     const i64 *noff;     // cycle node list offsets
     i32 *cn;
     i64 *splits;
+    int *err;            // 0, or the first tripped loop bound
 };
 void launch_positive_wg(const PosArgs &A, i64 nflag, hipStream_t s);
 

@@ -30,13 +30,14 @@ struct SlmError {
     } while (0)
 
 // ---------------------------------------------------------------- degree bins
-// A node is handled by a group of lanes sized to its degree.  Bins 1..5 keep
-// the per-node community table in LDS; bin 6 ("hub") rows are split in
+// A node is handled by a group of lanes sized to its degree.  Bins 1..6 keep
+// the per-node community table in LDS; bin 7 ("hub") rows are split in
 // chunks of HUB_CHUNK entries spread over many workgroups, with the table in
 // HBM.  Bin 0 holds isolated nodes.
-enum { BIN_ZERO = 0, BIN_8, BIN_32, BIN_128, BIN_512, BIN_4096, BIN_HUB, NBINS };
-static const i64 kBinMaxDeg[NBINS] = {0, 8, 32, 128, 512, 4096, INT64_MAX};
+enum { BIN_ZERO = 0, BIN_8, BIN_32, BIN_128, BIN_512, BIN_2048, BIN_4096, BIN_HUB, NBINS };
+static const i64 kBinMaxDeg[NBINS] = {0, 8, 32, 128, 512, 2048, 4096, INT64_MAX};
 #define HUB_CHUNK 4096
+#define HUB_TILE 8192  // slots of a hub table finalized by one workgroup
 
 struct Bins {
     i32 *nodes = nullptr;      // device: node ids grouped by bin
@@ -50,6 +51,9 @@ struct Bins {
     i32 *chunk_hub = nullptr;  // device [nchunk] hub index of each chunk
     i64 *chunk_beg = nullptr;  // device [nchunk] first entry of each chunk
     i32 *chunk_off_of_hub = nullptr; // device [nhub+1] first chunk of each hub
+    i64 ntile = 0;             // table tiles (HUB_TILE slots each)
+    i32 *tile_hub = nullptr;   // device [ntile] hub index of each tile
+    i32 *tile_off_of_hub = nullptr; // device [nhub+1] first tile of each hub
 };
 
 // Read-only view of one level's graph as the kernels see it.
@@ -168,9 +172,10 @@ void launch_hub_degrees(const i64 *rp, const i32 *hub_node, i32 nhub, i64 *span_
 void run_assign(const LevelView &L, const Bins &B, i32 *a, i64 *hub_key, i32 *hub_id,
                 hipStream_t s);
 // MAXIMAL sweep (Sec. 3.4): best_c, delta, w_own from labels and totals.
+// hub_tile_key / hub_tile_id: one slot per table tile.
 void run_sweep(const LevelView &L, const Bins &B, const i32 *lab, const i32 *sigma,
                i32 *best_c, i64 *delta, i32 *w_own, i32 *hub_keys, i32 *hub_vals,
-               i32 *hub_win, hipStream_t s);
+               i32 *hub_win, i64 *hub_tile_key, i32 *hub_tile_id, hipStream_t s);
 // wc[i] = sum of A_ij over j with lab[j] == lab[i] (diagonal included); only
 // for nodes with active[lab[i]] != 0 when active is given.
 void run_own_weight(const LevelView &L, const Bins &B, const i32 *lab, const uint8_t *active,
