@@ -30,7 +30,7 @@ import numpy as np
 
 __all__ = [
     "rng", "csr_from_pairs", "sbm", "rmat", "lfr_style", "sbm_batch_sizes",
-    "sbm_batch_graph", "cliques", "path", "star", "random_sparse", "CONFIG_SEEDS",
+    "sbm_batch_graph", "sbm_batch", "batch_member_seed", "cliques", "path", "star", "random_sparse", "CONFIG_SEEDS",
     "config_graph",
 ]
 
@@ -68,13 +68,12 @@ def csr_from_pairs(n: int, u: np.ndarray, v: np.ndarray, wt: np.ndarray | None =
         head[0] = True
         np.not_equal(key[1:], key[:-1], out=head[1:])
         starts = np.flatnonzero(head)
-        ukey = key[starts]
         uw = np.add.reduceat(ww, starts)
+        sel = order[starts]
+        rows, cols = uu[sel], vv[sel]
     else:
-        ukey = key
         uw = ww
-    rows = ukey // n
-    cols = ukey - rows * n
+        rows, cols = uu, vv
     counts = np.bincount(rows, minlength=n) if n else np.zeros(0, np.int64)
     row_ptr = np.zeros(n + 1, dtype=np.int64)
     np.cumsum(counts, out=row_ptr[1:])
@@ -266,6 +265,23 @@ def sbm_batch_graph(n: int, block: int, p_in: float, mean_ext_deg: float, seed: 
     ``mean_ext_deg`` (unused when the graph is a single block)."""
     p_out = 0.0 if n <= block else min(1.0, mean_ext_deg / float(n - block))
     return sbm(n, block, p_in, p_out, seed)
+
+
+def batch_member_seed(seed: int, index: int) -> int:
+    """Seed of member ``index`` of a batch drawn from ``seed``."""
+    return int(np.random.SeedSequence([seed & (2**63 - 1), index]).generate_state(1, np.uint64)[0])
+
+
+def sbm_batch(count: int, n_lo: int, n_hi: int, seed: int, p_in: float = 0.2,
+              mean_ext_deg: float = 2.0, indices=None):
+    """Members of a batch of planted-partition graphs: node counts
+    log-uniform in [n_lo, n_hi], block sizes uniform in 16..256, p_in, and
+    p_out for the given mean external degree.  ``indices`` picks members
+    (default: all); a member depends only on (seed, index)."""
+    ns, bs = sbm_batch_sizes(count, n_lo, n_hi, seed)
+    idx = range(count) if indices is None else indices
+    return [sbm_batch_graph(int(ns[i]), int(bs[i]), p_in, mean_ext_deg,
+                            batch_member_seed(seed, i)) for i in idx]
 
 
 def config_graph(name: str, seed: int | None = None):

@@ -183,6 +183,43 @@ slm_status slm_result_level(const slm_result *r, int32_t level, int64_t *n_c,
                             int32_t *rounds, int32_t *converged);
 void slm_result_free(slm_result *r);
 
+/* ---------------------------------------------------------------- batches
+ * Many independent graphs in one handle: they are held as one disjoint union
+ * and every kernel launch of a level serves all of them.  Each graph keeps
+ * its own M2 (every key of its nodes uses it), its own seed, level and local
+ * node numbers for the draws, and leaves the union when its level partition
+ * is the identity or it has emitted max_levels levels; its result is
+ * therefore the one slm_run gives for that graph alone with the same seed.
+ * The batched run is an extension of the method for throughput; the paper
+ * runs one graph at a time. */
+
+/* A host-memory CSR (same convention as slm_create; row_ptr is int64). */
+typedef struct {
+    int64_t n, nnz;
+    const int64_t *row_ptr;
+    const int32_t *col;
+    const int32_t *w;
+} slm_graph_desc;
+
+/* Creates a batch handle from count >= 1 host graphs (copied; the caller
+ * keeps ownership).  Each graph's M2 must be below 2^31 and the batch must
+ * hold fewer than 2^31 - 1 nodes.  validate as in slm_create.  On a batch
+ * handle slm_assign, slm_components, slm_positive, slm_sweep, slm_round and
+ * slm_level act on the level-0 union (slm_round and slm_level draw with
+ * the given seed and level for every graph); slm_run, slm_modularity and
+ * slm_contract return SLM_E_STATE. */
+slm_status slm_batch_create(int32_t count, const slm_graph_desc *graphs, int validate,
+                            void *hip_stream, slm_graph **out);
+
+/* Number of graphs of a batch handle (0 for a plain handle). */
+slm_status slm_batch_size(const slm_graph *g, int32_t *count);
+
+/* Full runs of Algorithm 1 for every graph of the batch.  seeds: one per
+ * graph (host), or NULL for p->seed everywhere.  outs: host array of
+ * count result pointers, each freed with slm_result_free.  Synchronises. */
+slm_status slm_batch_run(slm_graph *g, const slm_params *p, const uint64_t *seeds,
+                         slm_result **outs);
+
 /* Sweep timing: when enabled, every sweep records HIP events on the
  * handle's stream around its kernels.  slm_timing_read reports the summed
  * sweep time (ms), the number of sweeps, the CSR entries they read, and the

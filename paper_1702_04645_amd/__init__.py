@@ -77,6 +77,9 @@ def lib():
         "slm_timing_enable": (st, [P, C.c_int]),
         "slm_timing_read": (st, [P, C.POINTER(C.c_double), pi64, pi64, pi64]),
         "slm_last_error": (C.c_char_p, []),
+        "slm_batch_create": (st, [i32, P, C.c_int, P, C.POINTER(P)]),
+        "slm_batch_size": (st, [P, pi32]),
+        "slm_batch_run": (st, [P, C.POINTER(Params), P, P]),
     }
     for name, (res, args) in sigs.items():
         f = getattr(L, name)
@@ -260,23 +263,7 @@ class Graph:
             p = params()
         res = C.c_void_p()
         _check(lib().slm_run(self._h, C.byref(p), C.byref(res)))
-        try:
-            L = C.c_int32()
-            _check(lib().slm_result_num_levels(res, C.byref(L)))
-            out = []
-            for l in range(L.value):
-                nc, nq, q = C.c_int64(), C.c_int64(), C.c_double()
-                r, cv = C.c_int32(), C.c_int32()
-                labp = C.POINTER(C.c_int32)()
-                _check(lib().slm_result_level(res, l, C.byref(nc), C.byref(labp), C.byref(nq),
-                                              C.byref(q), C.byref(r), C.byref(cv)))
-                labels = np.ctypeslib.as_array(labp, shape=(self.n0,)).copy() if self.n0 else \
-                    np.zeros(0, np.int32)
-                out.append(LevelResult(labels, nc.value, nq.value, q.value, r.value,
-                                       bool(cv.value)))
-            return out
-        finally:
-            lib().slm_result_free(res)
+        return _take_result(res, self.n0)
 
     # -------------------------------------------------------------- timing
     def timing(self, enable: bool = True):
@@ -286,6 +273,78 @@ class Graph:
         ms, sw, en, by = C.c_double(), C.c_int64(), C.c_int64(), C.c_int64()
         _check(lib().slm_timing_read(self._h, C.byref(ms), C.byref(sw), C.byref(en), C.byref(by)))
         return dict(sweep_ms=ms.value, sweeps=sw.value, entries=en.value, bytes=by.value)
+
+
+def _take_result(res, n0: int):
+    """Copies an slm_result into a list of LevelResult and frees it."""
+    try:
+        L = C.c_int32()
+        _check(lib().slm_result_num_levels(res, C.byref(L)))
+        out = []
+        for l in range(L.value):
+            nc, nq, q = C.c_int64(), C.c_int64(), C.c_double()
+            r, cv = C.c_int32(), C.c_int32()
+            labp = C.POINTER(C.c_int32)()
+            _check(lib().slm_result_level(res, l, C.byref(nc), C.byref(labp), C.byref(nq),
+                                          C.byref(q), C.byref(r), C.byref(cv)))
+            labels = np.ctypeslib.as_array(labp, shape=(n0,)).copy() if n0 else \
+                np.zeros(0, np.int32)
+            out.append(LevelResult(labels, nc.value, nq.value, q.value, r.value, bool(cv.value)))
+        return out
+    finally:
+        lib().slm_result_free(res)
+
+
+class _Desc(C.Structure):
+    _fields_ = [("n", C.c_int64), ("nnz", C.c_int64), ("row_ptr", C.c_void_p),
+                ("col", C.c_void_p), ("w", C.c_void_p)]
+
+
+class Batch(Graph):
+    """Many independent graphs (a list of host CSR triples) in one handle,
+    run together as one disjoint union.  The single-step methods inherited
+    from Graph act on the level-0 union."""
+
+    def __init__(self, graphs, validate: bool = True, stream=None):
+        torch = _torch()
+        self._h = C.c_void_p()
+        keep = []
+        descs = (_Desc * len(graphs))()
+        for i, (rp, col, w) in enumerate(graphs):
+            rp = np.ascontiguousarray(rp, dtype=np.int64)
+            cl = np.ascontiguousarray(col, dtype=np.int32)
+            ww = np.ascontiguousarray(w, dtype=np.int32)
+            keep.append((rp, cl, ww))
+            descs[i] = _Desc(rp.size - 1, cl.size, rp.ctypes.data, cl.ctypes.data, ww.ctypes.data)
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        _check(lib().slm_batch_create(len(graphs), descs, int(validate),
+                                      C.c_void_p(stream.cuda_stream), C.byref(self._h)))
+        self.sizes = [k[0].size - 1 for k in keep]
+        self.n0 = int(sum(self.sizes))
+        self.nnz0 = int(sum(k[1].size for k in keep))
+
+    def __len__(self):
+        return len(self.sizes)
+
+    def run(self, p: Params | None = None, seeds=None):
+        """Full runs of every graph; returns one list of LevelResult per graph."""
+        if p is None:
+            p = params()
+        G = len(self.sizes)
+        sd = None
+        if seeds is not None:
+            sd = np.ascontiguousarray([int(x) & (2**64 - 1) for x in seeds], dtype=np.uint64)
+            assert sd.size == G
+        outs = (C.c_void_p * G)()
+        _check(lib().slm_batch_run(self._h, C.byref(p),
+                                   sd.ctypes.data_as(C.c_void_p) if sd is not None else None,
+                                   outs))
+        res = []
+        for i in range(G):
+            res.append(_take_result(C.c_void_p(outs[i]), self.sizes[i]))
+        return res
 
 
 def run(row_ptr, col, w, seed: int = 0, accept_p: int = 1 << 31, max_rounds: int = 64,

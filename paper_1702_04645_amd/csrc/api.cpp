@@ -33,6 +33,21 @@ struct slm_graph {
     double sweep_ms = 0;
     i64 sweeps = 0, entries = 0, bytes = 0;
     std::vector<void *> allocs;
+
+    // A batch handle holds G independent graphs as one disjoint union (G = 0
+    // for a plain graph).  Graph g owns the original nodes [base0[g],
+    // base0[g+1]) and, at the current level, the nodes [base[g], base[g+1]).
+    int G = 0;
+    std::vector<i64> base0, m2g, base;
+    i32 *gid0 = nullptr;                // per original node: graph
+    i32 *gidL[3] = {nullptr, nullptr, nullptr};  // per node: graph ([2] = level 0)
+    i32 *m2nL[3] = {nullptr, nullptr, nullptr};  // per node: M2 of its graph
+    i64 *d_gbase = nullptr, *d_first = nullptr, *d_gcb = nullptr, *d_accI = nullptr,
+        *d_accS = nullptr, *d_shift = nullptr, *d_gvalid = nullptr, *d_m2g = nullptr;
+    u64 *d_gseed = nullptr;
+    i32 *d_glev = nullptr;
+    uint8_t *d_flag = nullptr;
+    i32 *lab2 = nullptr;
 };
 
 struct slm_result {
@@ -65,6 +80,19 @@ static LevelView view(slm_graph *g)
     L.n = g->n;
     L.nnz = g->nnz;
     L.m2 = g->m2;
+    L.m2n = nullptr;
+    L.gid = nullptr;
+    L.gbase = nullptr;
+    L.gseed = nullptr;
+    L.glev = nullptr;
+    if (g->G > 0) {
+        const int c = g->cur < 0 ? 2 : g->cur;
+        L.m2n = g->m2nL[c];
+        L.gid = g->gidL[c];
+        L.gbase = g->d_gbase;
+        L.gseed = g->d_gseed;
+        L.glev = g->d_glev;
+    }
     return L;
 }
 
@@ -409,14 +437,14 @@ static void level_start(slm_graph *g, i64 *nc)
 // One MAXIMAL round then POSITIVE; W.lab / *nc must describe W.a.  Returns
 // the valid count.
 static i64 level_round(slm_graph *g, const slm_params *p, int level, int round, i64 *nc,
-                       i64 *stats4)
+                       i64 *stats4, unsigned long long *gvalid = nullptr)
 {
     Work &W = g->W;
     LevelView L = view(g);
     float ms = 0;
     i64 st[3] = {0, 0, 0};
     i64 valid = maximal_moves(W, L, g->bins, *nc, p->seed, level, round, p->accept_p, st, g->s,
-                              g->timing, g->ev0, g->ev1, &ms);
+                              g->timing, g->ev0, g->ev1, &ms, gvalid);
     if (g->timing) {
         g->sweep_ms += ms;
         g->sweeps++;
@@ -468,13 +496,224 @@ static void do_contract(slm_graph *g, const i32 *lab, i64 nc)
     setup_level(g);
 }
 
+static void batch_upload_base(slm_graph *g)
+{
+    HIPCHK(hipMemcpyAsync(g->d_gbase, g->base.data(), sizeof(i64) * (g->G + 1),
+                          hipMemcpyHostToDevice, g->s));
+    HIPCHK(hipStreamSynchronize(g->s));  // g->base may change right after
+}
+
 static void do_reset(slm_graph *g)
 {
+    if (g->G > 0 && g->base != g->base0) {
+        g->base = g->base0;
+        batch_upload_base(g);
+    }
     if (g->cur < 0 && g->level == 0) return;
     g->cur = -1;
     g->level = 0;
     g->n = g->n0;
     g->nnz = g->nnz0;
+    setup_level(g);
+}
+
+// Draw parameters of the single-step calls on a batch: every graph uses the
+// caller's seed and level, as a run of that graph alone would.
+static void batch_set_draws(slm_graph *g, u64 seed, int level)
+{
+    if (g->G == 0) return;
+    std::vector<u64> sd(g->G, seed);
+    std::vector<i32> lv(g->G, level);
+    HIPCHK(hipMemcpyAsync(g->d_gseed, sd.data(), sizeof(u64) * g->G, hipMemcpyHostToDevice, g->s));
+    HIPCHK(hipMemcpyAsync(g->d_glev, lv.data(), sizeof(i32) * g->G, hipMemcpyHostToDevice, g->s));
+    HIPCHK(hipStreamSynchronize(g->s));
+}
+
+// ------------------------------------------------------------------ batches
+static void alloc_batch(slm_graph *g)
+{
+    const int G = g->G;
+    const i64 n = g->n0;
+    for (int c = 0; c < 3; c++) {
+        g->gidL[c] = dalloc<i32>(g, n);
+        g->m2nL[c] = dalloc<i32>(g, n);
+    }
+    g->gid0 = g->gidL[2];
+    g->lab2 = dalloc<i32>(g, n);
+    g->d_gbase = dalloc<i64>(g, G + 1);
+    g->d_gcb = dalloc<i64>(g, G + 1);
+    g->d_first = dalloc<i64>(g, G);
+    g->d_accI = dalloc<i64>(g, G);
+    g->d_accS = dalloc<i64>(g, G);
+    g->d_shift = dalloc<i64>(g, G);
+    g->d_gvalid = dalloc<i64>(g, G);
+    g->d_m2g = dalloc<i64>(g, G);
+    g->d_gseed = dalloc<u64>(g, G);
+    g->d_glev = dalloc<i32>(g, G);
+    g->d_flag = dalloc<uint8_t>(g, G);
+    i64 maxn = 0;
+    for (int i = 0; i < G; i++) maxn = std::max(maxn, g->base0[i + 1] - g->base0[i]);
+    HIPCHK(hipMemcpyAsync(g->d_gbase, g->base0.data(), sizeof(i64) * (G + 1),
+                          hipMemcpyHostToDevice, g->s));
+    HIPCHK(hipMemcpyAsync(g->d_m2g, g->m2g.data(), sizeof(i64) * G, hipMemcpyHostToDevice, g->s));
+    batch_meta(g->d_gbase, G, g->d_m2g, maxn, g->gidL[2], g->m2nL[2], g->s);
+    HIPCHK(hipStreamSynchronize(g->s));
+}
+
+template <typename T>
+static void to_host(std::vector<T> &h, const T *d, i64 count, hipStream_t s)
+{
+    h.resize((size_t)count);
+    if (count > 0)
+        HIPCHK(hipMemcpyAsync(h.data(), d, sizeof(T) * count, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+}
+
+// All graphs of a batch through Algorithm 1 at once.  Graph g draws with
+// seeds[g]; its levels, rounds and labels are those of a run on its own:
+// its keys use its own M2, its draws its own seed, level and local node
+// numbers, and a graph whose round finds no valid move is left unchanged
+// by the rounds the others still need.  A graph leaves the union when its
+// level partition is the identity or it has emitted max_levels levels.
+static void batch_run(slm_graph *g, const slm_params *p, const u64 *seeds,
+                      std::vector<slm_result *> &res)
+{
+    const int G = g->G;
+    Work &W = g->W;
+    hipStream_t s = g->s;
+    do_reset(g);
+    {
+        std::vector<u64> sd(G);
+        for (int i = 0; i < G; i++) sd[i] = seeds ? seeds[i] : p->seed;
+        HIPCHK(hipMemcpyAsync(g->d_gseed, sd.data(), sizeof(u64) * G, hipMemcpyHostToDevice, s));
+        launch_fill_i32(g->d_glev, 0, G, s);
+        HIPCHK(hipStreamSynchronize(s));
+    }
+    launch_iota_i32(g->composed, g->n0, s);
+    std::vector<char> alive(G);
+    std::vector<int> emitted(G, 0);
+    for (int i = 0; i < G; i++) {
+        alive[i] = g->base0[i + 1] > g->base0[i];
+        res[i]->n0 = g->base0[i + 1] - g->base0[i];
+    }
+    std::vector<i64> hv, first, accI, accS;
+    std::vector<i32> comp_h;
+    int level = 0;
+    while (g->n > 0) {
+        i64 nc;
+        level_start(g, &nc);
+        std::vector<i32> rounds(G, -1), conv(G, 0);
+        int r = 0;
+        while (r < p->max_rounds) {
+            launch_fill_i64(g->d_gvalid, 0, G, s);
+            const i64 valid = level_round(g, p, level, r, &nc, nullptr,
+                                          (unsigned long long *)g->d_gvalid);
+            to_host(hv, g->d_gvalid, G, s);
+            for (int i = 0; i < G; i++)
+                if (alive[i] && rounds[i] < 0 && hv[i] == 0) {
+                    rounds[i] = r;
+                    conv[i] = 1;
+                }
+            if (valid == 0) break;
+            r++;
+        }
+        for (int i = 0; i < G; i++)
+            if (alive[i] && rounds[i] < 0) rounds[i] = r;
+        // community range of every graph: its first node holds its first label
+        batch_first_labels(W.lab, g->d_gbase, G, g->d_first, s);
+        to_host(first, g->d_first, G, s);
+        std::vector<i64> gcb(G + 1);
+        gcb[G] = nc;
+        for (int i = G - 1; i >= 0; i--) gcb[i] = first[i] >= 0 ? first[i] : gcb[i + 1];
+        std::vector<uint8_t> emit(G, 0);
+        std::vector<char> leave(G, 0);
+        bool any_emit = false;
+        for (int i = 0; i < G; i++) {
+            if (!alive[i]) continue;
+            const i64 nci = gcb[i + 1] - gcb[i], ni = g->base[i + 1] - g->base[i];
+            if (nci == ni) {
+                leave[i] = 1;  // the identity: not emitted
+                continue;
+            }
+            emit[i] = 1;
+            any_emit = true;
+        }
+        if (any_emit) {
+            HIPCHK(hipMemcpyAsync(g->d_flag, emit.data(), G, hipMemcpyHostToDevice, s));
+            HIPCHK(hipMemcpyAsync(g->d_gcb, gcb.data(), sizeof(i64) * (G + 1),
+                                  hipMemcpyHostToDevice, s));
+            batch_compose(g->composed, W.lab, g->gid0, g->d_flag, g->n0, s);
+            modularity_graphs(W, view(g), g->bins, W.lab, nc, G, g->d_gcb, g->d_accI,
+                              g->d_accS, s);
+            to_host(accI, g->d_accI, G, s);
+            to_host(accS, g->d_accS, G, s);
+            to_host(comp_h, g->composed, g->n0, s);
+            for (int i = 0; i < G; i++) {
+                if (!emit[i]) continue;
+                slm_result *R = res[i];
+                const i64 b0 = g->base0[i], n0i = g->base0[i + 1] - b0;
+                std::vector<i32> lab(n0i);
+                for (i64 v = 0; v < n0i; v++) lab[v] = (i32)(comp_h[b0 + v] - gcb[i]);
+                const i64 m2 = g->m2g[i];
+                const i64 nq = m2 * accI[i] - accS[i];
+                R->labels.push_back(std::move(lab));
+                R->nc.push_back(gcb[i + 1] - gcb[i]);
+                R->nq.push_back(nq);
+                R->q.push_back((double)nq / (double)m2 / (double)m2);
+                R->rounds.push_back(rounds[i]);
+                R->conv.push_back(conv[i]);
+                emitted[i]++;
+                if (p->max_levels > 0 && emitted[i] >= p->max_levels) leave[i] = 1;
+            }
+        }
+        // the graphs that stay form the next level's union
+        std::vector<i64> shift(G, -1), nbase(G + 1, 0);
+        i64 gone = 0, nc2 = 0;
+        bool any = false;
+        for (int i = 0; i < G; i++) {
+            nbase[i] = nc2;
+            if (!alive[i]) continue;
+            const i64 nci = gcb[i + 1] - gcb[i];
+            if (leave[i]) {
+                alive[i] = 0;
+                gone += nci;
+                continue;
+            }
+            shift[i] = gone;
+            nc2 += nci;
+            any = true;
+        }
+        nbase[G] = nc2;
+        if (!any) break;
+        level++;
+        HIPCHK(hipMemcpyAsync(g->d_shift, shift.data(), sizeof(i64) * G, hipMemcpyHostToDevice, s));
+        const int dst = g->cur < 0 ? 0 : 1 - g->cur;
+        const int src = g->cur < 0 ? 2 : g->cur;
+        batch_relabel(W.lab, g->gidL[src], g->m2nL[src], g->d_shift, g->n, g->lab2,
+                      g->gidL[dst], g->m2nL[dst], s);
+        // composed labels of the graphs that stay become next-level node ids
+        batch_compose_shift(g->composed, g->gid0, g->d_shift, g->n0, s);
+        do_contract(g, g->lab2, nc2);
+        g->base = nbase;
+        batch_upload_base(g);
+        launch_fill_i32(g->d_glev, level, G, s);
+    }
+    HIPCHK(hipStreamSynchronize(s));
+}
+
+// Device copy of a host CSR (entries already packed) and the level-0 state.
+static void init_from_host(slm_graph *g, const i64 *rp_h, const int2 *e_h)
+{
+    alloc_work(g);
+    if (g->G > 0) alloc_batch(g);
+    g->rp0 = dalloc<i64>(g, g->n0 + 1);
+    g->e0 = dalloc<int2>(g, g->nnz0);
+    HIPCHK(hipMemcpyAsync(g->rp0, rp_h, sizeof(i64) * (g->n0 + 1), hipMemcpyHostToDevice, g->s));
+    if (g->nnz0)
+        HIPCHK(hipMemcpyAsync(g->e0, e_h, sizeof(int2) * g->nnz0, hipMemcpyHostToDevice, g->s));
+    HIPCHK(hipStreamSynchronize(g->s));
+    HIPCHK(hipEventCreate(&g->ev0));
+    HIPCHK(hipEventCreate(&g->ev1));
     setup_level(g);
 }
 
@@ -735,6 +974,7 @@ slm_status slm_round(slm_graph *g, const slm_params *p, int32_t level, int32_t r
         return SLM_OK;
     }
     load_assignment(g, a_dev);
+    batch_set_draws(g, p->seed, level);
     i64 nc = components(g->W, g->W.a, g->n, true, g->s);
     i64 st[4];
     level_round(g, p, level, round, &nc, st);
@@ -759,6 +999,7 @@ slm_status slm_level(slm_graph *g, const slm_params *p, int32_t level, int32_t *
     }
     i64 nc;
     int32_t r, c;
+    batch_set_draws(g, p->seed, level);
     run_level(g, p, level, &nc, &r, &c);
     HIPCHK(hipMemcpyAsync(lab_dev, g->W.lab, sizeof(i32) * g->n, hipMemcpyDeviceToDevice, g->s));
     HIPCHK(hipStreamSynchronize(g->s));
@@ -773,6 +1014,7 @@ slm_status slm_modularity(slm_graph *g, const int32_t *lab_dev, int64_t n_c, int
 {
     API_BEGIN
     REQUIRE(g != nullptr, SLM_E_INVALID, "null handle");
+    REQUIRE(g->G == 0, SLM_E_STATE, "a batch reports modularity per graph through slm_batch_run");
     i64 v = 0;
     if (g->n > 0) {
         check_labels(g, lab_dev, n_c);
@@ -787,6 +1029,7 @@ slm_status slm_contract(slm_graph *g, const int32_t *lab_dev, int64_t n_c)
 {
     API_BEGIN
     REQUIRE(g != nullptr, SLM_E_INVALID, "null handle");
+    REQUIRE(g->G == 0, SLM_E_STATE, "a batch contracts inside slm_batch_run");
     check_labels(g, lab_dev, n_c);
     do_contract(g, lab_dev, n_c);
     API_END
@@ -798,6 +1041,7 @@ slm_status slm_run(slm_graph *g, const slm_params *p, slm_result **out)
     REQUIRE(g != nullptr && p != nullptr && out != nullptr, SLM_E_INVALID, "null argument");
     REQUIRE(p->accept_p <= (1ull << 32), SLM_E_INVALID, "accept_p must be at most 2^32");
     REQUIRE(p->max_rounds >= 0 && p->max_levels >= 0, SLM_E_INVALID, "negative cap");
+    REQUIRE(g->G == 0, SLM_E_STATE, "a batch handle runs with slm_batch_run");
     *out = nullptr;
     do_reset(g);
     slm_result *r = new slm_result();
@@ -883,6 +1127,98 @@ slm_status slm_timing_read(slm_graph *g, double *sweep_ms, int64_t *sweeps, int6
     if (bytes) *bytes = g->bytes;
     g->sweep_ms = 0;
     g->sweeps = g->entries = g->bytes = 0;
+    API_END
+}
+
+slm_status slm_batch_create(int32_t count, const slm_graph_desc *graphs, int validate,
+                            void *hip_stream, slm_graph **out)
+{
+    slm_graph *g = nullptr;
+    try {
+        REQUIRE(out != nullptr, SLM_E_INVALID, "null output handle");
+        *out = nullptr;
+        REQUIRE(count >= 1 && graphs != nullptr, SLM_E_INVALID, "a batch needs at least one graph");
+        std::vector<i64> base0(count + 1, 0), ebase(count + 1, 0), m2g(count, 0);
+        for (int i = 0; i < count; i++) {
+            const slm_graph_desc &d = graphs[i];
+            REQUIRE(d.n >= 0 && d.nnz >= 0, SLM_E_INVALID, "negative size");
+            REQUIRE(d.row_ptr != nullptr, SLM_E_INVALID, "null row_ptr");
+            REQUIRE(d.nnz == 0 || (d.col && d.w), SLM_E_INVALID, "null col or w");
+            base0[i + 1] = base0[i] + d.n;
+            ebase[i + 1] = ebase[i] + d.nnz;
+        }
+        const i64 N = base0[count], NNZ = ebase[count];
+        REQUIRE(N < ((i64)1 << 31) - 1, SLM_E_OVERFLOW, "the batch must hold fewer than 2^31 - 1 nodes");
+        REQUIRE(NNZ < ((i64)1 << 40), SLM_E_OVERFLOW, "too many entries");
+        std::vector<i64> rp_h(N + 1);
+        std::vector<int2> e_h(NNZ);
+        for (int i = 0; i < count; i++) {
+            const slm_graph_desc &d = graphs[i];
+            std::vector<i64> rp(d.row_ptr, d.row_ptr + d.n + 1);
+            i64 m2 = 0;
+            if (validate) {
+                validate_host(d.n, d.nnz, rp, d.col, d.w, &m2);
+            } else {
+                REQUIRE(rp[0] == 0 && rp[d.n] == d.nnz, SLM_E_INVALID,
+                        "row_ptr must start at 0 and end at nnz");
+                for (i64 j = 0; j < d.nnz; j++) m2 += d.w[j];
+            }
+            REQUIRE(m2 < ((i64)1 << 31), SLM_E_OVERFLOW, "total weight M2 must be below 2^31");
+            m2g[i] = m2;
+            for (i64 v = 0; v < d.n; v++) rp_h[base0[i] + v] = ebase[i] + rp[v];
+            const i32 off = (i32)base0[i];
+            for (i64 j = 0; j < d.nnz; j++)
+                e_h[ebase[i] + j] = make_int2(d.col[j] + off, d.w[j]);
+        }
+        rp_h[N] = NNZ;
+        g = new slm_graph();
+        g->s = (hipStream_t)hip_stream;
+        HIPCHK(hipGetDevice(&g->device));
+        g->n0 = g->n = N;
+        g->nnz0 = g->nnz = NNZ;
+        g->G = count;
+        g->base0 = base0;
+        g->base = base0;
+        g->m2g = m2g;
+        init_from_host(g, rp_h.data(), e_h.data());
+        batch_set_draws(g, 0, 0);
+        *out = g;
+        return SLM_OK;
+    } catch (const SlmError &e) {
+        if (g) slm_destroy(g);
+        return fail(e);
+    } catch (const std::bad_alloc &) {
+        if (g) slm_destroy(g);
+        return fail(SlmError{SLM_E_NOMEM, "host allocation failed"});
+    }
+}
+
+slm_status slm_batch_size(const slm_graph *g, int32_t *count)
+{
+    API_BEGIN
+    REQUIRE(g != nullptr && count != nullptr, SLM_E_INVALID, "null argument");
+    *count = g->G;
+    API_END
+}
+
+slm_status slm_batch_run(slm_graph *g, const slm_params *p, const uint64_t *seeds,
+                         slm_result **outs)
+{
+    API_BEGIN
+    REQUIRE(g != nullptr && p != nullptr && outs != nullptr, SLM_E_INVALID, "null argument");
+    REQUIRE(g->G > 0, SLM_E_STATE, "not a batch handle (use slm_run)");
+    REQUIRE(p->accept_p <= (1ull << 32), SLM_E_INVALID, "accept_p must be at most 2^32");
+    REQUIRE(p->max_rounds >= 0 && p->max_levels >= 0, SLM_E_INVALID, "negative cap");
+    for (int i = 0; i < g->G; i++) outs[i] = nullptr;
+    std::vector<slm_result *> res(g->G, nullptr);
+    try {
+        for (int i = 0; i < g->G; i++) res[i] = new slm_result();
+        batch_run(g, p, seeds, res);
+    } catch (...) {
+        for (slm_result *r : res) delete r;
+        throw;
+    }
+    for (int i = 0; i < g->G; i++) outs[i] = res[i];
     API_END
 }
 

@@ -275,15 +275,16 @@ static void agg_min_index(const i32 *key, i64 n, i32 *out, hipStream_t s)
 // node numbers it.
 __global__ void k_pos_flag(const i32 *__restrict__ comp, const i32 *__restrict__ k,
                            const i32 *__restrict__ diag, const i32 *__restrict__ wc,
-                           const i32 *__restrict__ sig, i64 m2, i64 n,
-                           i32 *__restrict__ fidx, i32 *__restrict__ flist,
+                           const i32 *__restrict__ sig, const i32 *__restrict__ m2n, i64 m2,
+                           i64 n, i32 *__restrict__ fidx, i32 *__restrict__ flist,
                            i64 *__restrict__ counters)
 {
     NODE_LOOP(n)
     {
         i32 c = comp[u_];
         i64 ku = k[u_];
-        i64 g = m2 * (i64)(wc[u_] - diag[u_]) - ku * ((i64)sig[c] - ku);
+        const i64 m2u = m2n ? (i64)m2n[u_] : m2;
+        i64 g = m2u * (i64)(wc[u_] - diag[u_]) - ku * ((i64)sig[c] - ku);
         if (g >= 0) continue;
         if (atomicCAS(&fidx[c], -1, -2) == -1) {
             i32 f = (i32)atomicAdd((unsigned long long *)&counters[0], 1ull);
@@ -442,37 +443,59 @@ __device__ __forceinline__ u32 accept_draw(u64 seed, int level, int round, i32 n
     return (u32)(z >> 32);
 }
 
-// move(B: c -> D) > 0 decides validity; valid moves draw.
-__global__ void k_max_valid(const i32 *__restrict__ lab, const i32 *__restrict__ best_c,
-                            const uint8_t *__restrict__ cyc, const i32 *__restrict__ sig,
-                            const i64 *__restrict__ subk, const i64 *__restrict__ cut,
-                            const i32 *__restrict__ wbd, i64 m2, i64 n, u64 seed, int level,
-                            int round, u64 accept_p, uint8_t *__restrict__ accept,
-                            i64 *__restrict__ counters)
+// move(B: c -> D) > 0 decides validity; valid moves draw.  In a batch the
+// key uses the node's own graph total, the draw its graph's seed, level and
+// local node number, and gvalid[g] counts the valid moves of graph g.
+__global__ void k_max_valid(LevelView L, const i32 *__restrict__ lab,
+                            const i32 *__restrict__ best_c, const uint8_t *__restrict__ cyc,
+                            const i32 *__restrict__ sig, const i64 *__restrict__ subk,
+                            const i64 *__restrict__ cut, const i32 *__restrict__ wbd, u64 seed,
+                            int level, int round, u64 accept_p, uint8_t *__restrict__ accept,
+                            i64 *__restrict__ counters, unsigned long long *__restrict__ gvalid)
 {
     __shared__ i64 red[32];
+    const i64 n = L.n;
     i64 nv = 0, na = 0;
-    NODE_LOOP(n)
-    {
-        i32 i = (i32)u_;
-        i32 c = lab[i], D = best_c[i];
-        accept[i] = 0;
-        if (D == c) continue;
-        i64 sb, cb;
-        if (cyc[i]) {
-            sb = sig[c];
-            cb = 0;
-        } else {
-            sb = subk[i];
-            cb = cut[i];
+    // every lane of a wavefront runs the same iterations (seg_add_sorted)
+    for (i64 b = (i64)blockIdx.x * blockDim.x; b < n; b += (i64)gridDim.x * blockDim.x) {
+        const i64 u = b + threadIdx.x;
+        bool ok = false;
+        i32 g = -1;
+        if (u < n) {
+            const i32 i = (i32)u;
+            g = L.gid ? L.gid[i] : 0;
+            const i32 c = lab[i], D = best_c[i];
+            accept[i] = 0;
+            if (D != c) {
+                i64 sb, cb;
+                if (cyc[i]) {
+                    sb = sig[c];
+                    cb = 0;
+                } else {
+                    sb = subk[i];
+                    cb = cut[i];
+                }
+                const i64 mv = node_m2(L, i) * ((i64)wbd[i] - cb) -
+                               sb * ((i64)sig[D] - (i64)sig[c] + sb);
+                if (mv > 0) {
+                    ok = true;
+                    nv++;
+                    u64 sd = seed;
+                    int lv = level;
+                    i32 loc = i;
+                    if (L.gid) {
+                        sd = L.gseed[g];
+                        lv = L.glev[g];
+                        loc = (i32)(u - L.gbase[g]);
+                    }
+                    if ((u64)accept_draw(sd, lv, round, loc) < accept_p) {
+                        accept[i] = 1;
+                        na++;
+                    }
+                }
+            }
         }
-        i64 mv = m2 * ((i64)wbd[i] - cb) - sb * ((i64)sig[D] - (i64)sig[c] + sb);
-        if (mv <= 0) continue;
-        nv++;
-        if ((u64)accept_draw(seed, level, round, i) < accept_p) {
-            accept[i] = 1;
-            na++;
-        }
+        if (gvalid) seg_add_sorted(gvalid, g, ok ? 1 : 0);
     }
     nv = block_sum<i64>(nv, red);
     na = block_sum<i64>(na, red);
@@ -636,7 +659,7 @@ i64 positive(Work &W, const LevelView &Lv, const Bins &B, i64 *nc_out, hipStream
     run_own_weight(Lv, B, W.comp, nullptr, W.wc, s);
     launch_fill_i32(W.fidx, -1, n, s);
     launch_fill_i64(W.counters, 0, 8, s);
-    k_pos_flag<<<g, SLM_BS, 0, s>>>(W.comp, Lv.k, Lv.diag, W.wc, W.sigma, Lv.m2, n, W.fidx,
+    k_pos_flag<<<g, SLM_BS, 0, s>>>(W.comp, Lv.k, Lv.diag, W.wc, W.sigma, Lv.m2n, Lv.m2, n, W.fidx,
                                     W.flist, W.counters);
     read_scalars(W, W.counters, 1, s);
     const i64 nflag = W.h_scal[0];
@@ -720,7 +743,7 @@ void community_totals(Work &W, const LevelView &Lv, const i32 *lab, i64 nc, hipS
 
 i64 maximal_moves(Work &W, const LevelView &Lv, const Bins &B, i64 nc, u64 seed, int level,
                   int round, u64 accept_p, i64 *stats, hipStream_t s, bool timing,
-                  hipEvent_t ev0, hipEvent_t ev1, float *sweep_ms)
+                  hipEvent_t ev0, hipEvent_t ev1, float *sweep_ms, unsigned long long *gvalid)
 {
     const i64 n = Lv.n;
     const unsigned g = node_grid(n);
@@ -763,9 +786,9 @@ i64 maximal_moves(Work &W, const LevelView &Lv, const Bins &B, i64 nc, u64 seed,
         k_max_cross<<<node_grid(entries), SLM_BS, 0, s>>>(W.src, Lv.e, entries, W.lab, W.hasc,
                                                         W.act, Fi, W.J, W.best_c, W.coff,
                                                         W.clist, W.wbd);
-    k_max_valid<<<g, SLM_BS, 0, s>>>(W.lab, W.best_c, W.cyc, W.sigma, W.subk, W.cut, W.wbd,
-                                     Lv.m2, n, seed, level, round, accept_p, W.accept,
-                                     W.counters);
+    k_max_valid<<<g, SLM_BS, 0, s>>>(Lv, W.lab, W.best_c, W.cyc, W.sigma, W.subk, W.cut, W.wbd,
+                                     seed, level, round, accept_p, W.accept, W.counters,
+                                     gvalid);
     read_scalars(W, W.counters, 3, s);
     stats[1] = W.h_scal[1];
     stats[2] = W.h_scal[2];
@@ -784,6 +807,47 @@ i64 modularity_num(Work &W, const LevelView &Lv, const Bins &B, const i32 *lab, 
     k_nq_parts<<<node_grid(m), SLM_BS, 0, s>>>(W.wc, Lv.n, W.sigma, nc, W.counters);
     read_scalars(W, W.counters, 2, s);
     return Lv.m2 * W.h_scal[0] - W.h_scal[1];
+}
+
+// Per-graph parts of N_Q in a batch.  Nodes and labels of one graph are
+// contiguous, so the keys of consecutive lanes are sorted (seg_add_sorted).
+__global__ void k_nq_graph(const i32 *__restrict__ wc, const i32 *__restrict__ gid, i64 n,
+                           const i32 *__restrict__ sig, i64 nc, const i64 *__restrict__ gcb,
+                           int G, unsigned long long *__restrict__ accI,
+                           unsigned long long *__restrict__ accS)
+{
+    const i64 m = n > nc ? n : nc;
+    for (i64 b = (i64)blockIdx.x * blockDim.x; b < m; b += (i64)gridDim.x * blockDim.x) {
+        const i64 u = b + threadIdx.x;
+        seg_add_sorted(accI, u < n ? gid[u] : -1, u < n ? (i64)wc[u] : 0);
+        i32 g = -1;
+        i64 sq = 0;
+        if (u < nc) {
+            int lo = 0, hi = G - 1;  // last g with gcb[g] <= u
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (gcb[mid] <= u) lo = mid;
+                else hi = mid - 1;
+            }
+            g = lo;
+            sq = (i64)sig[u] * (i64)sig[u];
+        }
+        seg_add_sorted(accS, g, sq);
+    }
+}
+
+void modularity_graphs(Work &W, const LevelView &Lv, const Bins &B, const i32 *lab, i64 nc,
+                       int G, const i64 *gcb, i64 *accI, i64 *accS, hipStream_t s)
+{
+    community_totals(W, Lv, lab, nc, s);
+    run_own_weight(Lv, B, lab, nullptr, W.wc, s);
+    launch_fill_i64(accI, 0, G, s);
+    launch_fill_i64(accS, 0, G, s);
+    const i64 m = Lv.n > nc ? Lv.n : nc;
+    if (m > 0)
+        k_nq_graph<<<node_grid(m), SLM_BS, 0, s>>>(W.wc, Lv.gid, Lv.n, W.sigma, nc, gcb, G,
+                                                   (unsigned long long *)accI,
+                                                   (unsigned long long *)accS);
 }
 
 void compose_labels(i32 *composed, const i32 *lab, i64 n0, hipStream_t s)

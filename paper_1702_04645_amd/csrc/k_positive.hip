@@ -219,7 +219,7 @@ __global__ __launch_bounds__(PW_BS) void k_positive_wg(PosArgs A)
     i64 *Wm = Lc0 >= 2 ? A.W + A.woff[f] : nullptr;  // (L x L) weights between hanging trees
     i32 *CN = A.cn + A.noff[f];
     const LevelView &G = A.G;
-    const i64 m2 = G.m2;
+    const i64 m2 = node_m2(G, M[0]);  // every member belongs to one graph
     i32 *a = A.a;
     uint8_t *cyc = A.cyc;
 

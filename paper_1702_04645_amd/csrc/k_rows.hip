@@ -145,13 +145,14 @@ __global__ __launch_bounds__(GroupGeom<G>::BSZ) void k_argmax(
     i32 bj = INT32_MAX;
     if (active) {
         const i64 ki = L.k[node];
+        const i64 m2 = node_m2(L, node);
         const i32 D = REPOINT ? best_c[node] : 0;
         for (i64 j = L.rp[node] + gl; j < L.rp[node + 1]; j += G) {
             int2 ed = L.e[j];
             const i32 v = ed.x;
             if (v == node) continue;
             if (REPOINT && lab[v] != D) continue;
-            i64 key = L.m2 * (i64)ed.y - ki * (i64)L.k[v];
+            i64 key = m2 * (i64)ed.y - ki * (i64)L.k[v];
             if (better_key(key, v, bk, bj)) {
                 bk = key;
                 bj = v;
@@ -205,8 +206,10 @@ __global__ __launch_bounds__(GroupGeom<G>::BSZ) void k_crows_lds(
         keys[s] = -1;
         vals[s] = 0;
     }
+    // rows labelled -1 belong to graphs leaving a batch: no records
+    const bool keep = valid && lab[node] >= 0;
     group_sync<G>();
-    if (valid) {
+    if (keep) {
         const i64 e1 = L.rp[node + 1];
         for (i64 j = L.rp[node] + gl; j < e1; j += G) {
             int2 ed = L.e[j];
@@ -224,11 +227,11 @@ __global__ __launch_bounds__(GroupGeom<G>::BSZ) void k_crows_lds(
     }
     group_sync<G>();
     int mine = 0;
-    if (valid)
+    if (keep)
         for (int s = gl; s < H; s += G) mine += keys[s] >= 0;
     int total;
     int pos = gscan<G>(mine, total, red);
-    if (valid) {
+    if (keep) {
         const u64 hi = (u64)(u32)lab[node] << bits;
         const i64 base = L.rp[node];
         for (int s = gl; s < H; s += G) {
@@ -300,13 +303,14 @@ __global__ __launch_bounds__(SLM_BS) void k_hub_argmax(
         i64 end = b + HUB_CHUNK;
         if (end > L.rp[node + 1]) end = L.rp[node + 1];
         const i64 ki = L.k[node];
+        const i64 m2 = node_m2(L, node);
         const i32 D = REPOINT ? best_c[node] : 0;
         for (i64 j = b + threadIdx.x; j < end; j += blockDim.x) {
             int2 ed = L.e[j];
             const i32 v = ed.x;
             if (v == node) continue;
             if (REPOINT && lab[v] != D) continue;
-            i64 key = L.m2 * (i64)ed.y - ki * (i64)L.k[v];
+            i64 key = m2 * (i64)ed.y - ki * (i64)L.k[v];
             if (better_key(key, v, bk, bj)) {
                 bk = key;
                 bj = v;
@@ -389,6 +393,7 @@ __global__ __launch_bounds__(SLM_BS) void k_hub_crows(
     const i64 b = chunk_beg[blockIdx.x];
     i64 end = b + HUB_CHUNK;
     if (end > L.rp[node + 1]) end = L.rp[node + 1];
+    if (lab[node] < 0) return;  // the hub's graph leaves a batch: no records
     const u64 hi = (u64)(u32)lab[node] << bits;
     for (i64 j = b + threadIdx.x; j < end; j += blockDim.x) {
         int2 ed = L.e[j];

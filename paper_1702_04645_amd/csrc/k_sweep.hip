@@ -41,7 +41,7 @@ __device__ __forceinline__ void write_move(const LevelView &L, i32 node, i32 ci,
                                            i32 *__restrict__ best_c, i64 *__restrict__ delta,
                                            i32 *__restrict__ w_own)
 {
-    const i64 stay = L.m2 * win - ki * ((i64)sigma[ci] - ki);
+    const i64 stay = node_m2(L, node) * win - ki * ((i64)sigma[ci] - ki);
     if (bc != INT32_MAX && bk > stay) {
         best_c[node] = bc;
         delta[node] = bk - stay;
@@ -118,7 +118,7 @@ __global__ __launch_bounds__(SLM_BS) void k_sweep_tiny(LevelView L, const i32 *_
     i64 bk = INT64_MIN;
     i32 bc = INT32_MAX;
     if (c >= 0 && first) {
-        bk = L.m2 * tot - ki * (i64)sigma[c];
+        bk = node_m2(L, node) * tot - ki * (i64)sigma[c];
         bc = c;
     }
     win = group_sum<G, i64>(win);
@@ -181,6 +181,7 @@ __global__ __launch_bounds__(G <= 64 ? SLM_BS : G) void k_sweep_hash(
         const i32 node = nodes[slot];
         const i32 ci = lab[node];
         const i64 ki = L.k[node];
+        const i64 m2 = node_m2(L, node);
         const i64 e0 = L.rp[node];
         const int deg = (int)(L.rp[node + 1] - e0);
         int2 ed[U];
@@ -206,7 +207,7 @@ __global__ __launch_bounds__(G <= 64 ? SLM_BS : G) void k_sweep_hash(
         for (int i = gl; i < nd; i += G) {
             const i32 h = list[i];
             const i32 cc = keys[h];
-            const i64 key = L.m2 * (i64)vals[h] - ki * (i64)sigma[cc];
+            const i64 key = m2 * (i64)vals[h] - ki * (i64)sigma[cc];
             if (better_key(key, cc, bk, bc)) {
                 bk = key;
                 bc = cc;
@@ -305,13 +306,14 @@ __global__ __launch_bounds__(SLM_BS) void k_sweep_hub_tile(
     __shared__ i64 red[32];
     const i32 h = tile_hub[blockIdx.x];
     const i64 ki = L.k[hub_node[h]];
+    const i64 m2 = node_m2(L, hub_node[h]);
     const i64 base = tab_off[h] + (i64)(blockIdx.x - tile_first[h]) * HUB_TILE;
     i64 bk = INT64_MIN;
     i32 bc = INT32_MAX;
     for (int i = threadIdx.x; i < HUB_TILE; i += SLM_BS) {
         const i32 c = tkey[base + i];
         if (c >= 0) {
-            const i64 key = L.m2 * (i64)tval[base + i] - ki * (i64)sigma[c];
+            const i64 key = m2 * (i64)tval[base + i] - ki * (i64)sigma[c];
             if (better_key(key, c, bk, bc)) {
                 bk = key;
                 bc = c;

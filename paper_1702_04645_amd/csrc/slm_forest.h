@@ -122,7 +122,8 @@ i64 positive(Work &W, const LevelView &Lv, const Bins &B, i64 *nc, hipStream_t s
 // valid, accepted.
 i64 maximal_moves(Work &W, const LevelView &Lv, const Bins &B, i64 nc, u64 seed, int level,
                   int round, u64 accept_p, i64 *stats, hipStream_t s, bool timing,
-                  hipEvent_t ev0, hipEvent_t ev1, float *sweep_ms);
+                  hipEvent_t ev0, hipEvent_t ev1, float *sweep_ms,
+                  unsigned long long *gvalid = nullptr);
 
 // Community totals S_C (canonical labels).
 void community_totals(Work &W, const LevelView &Lv, const i32 *lab, i64 nc, hipStream_t s);
@@ -130,6 +131,11 @@ void community_totals(Work &W, const LevelView &Lv, const i32 *lab, i64 nc, hipS
 // Modularity numerator N_Q of the labelling lab (Sec. 2.4).
 i64 modularity_num(Work &W, const LevelView &Lv, const Bins &B, const i32 *lab, i64 nc,
                    hipStream_t s);
+// Per-graph modularity parts of a batch: accI[g] = sum of w(C,C) and
+// accS[g] = sum of S_C^2 over the communities of graph g, where graph g owns
+// the labels [gcb[g], gcb[g+1]).  accI and accS (G entries) are overwritten.
+void modularity_graphs(Work &W, const LevelView &Lv, const Bins &B, const i32 *lab, i64 nc,
+                       int G, const i64 *gcb, i64 *accI, i64 *accS, hipStream_t s);
 
 // composed[v] = lab[composed[v]]
 void compose_labels(i32 *composed, const i32 *lab, i64 n0, hipStream_t s);
@@ -147,3 +153,14 @@ i64 level_strengths(Work &W, const i64 *rp, const int2 *e, const Bins &B, i64 n,
                     i32 *diag, hipStream_t s);
 void run_strength_binned(const i64 *rp, const int2 *e, const Bins &Bn, i32 *k, i32 *diag,
                          i64 *m2_acc, hipStream_t s);
+
+// ---------------------------------------------------------------- batches
+void batch_first_labels(const i32 *lab, const i64 *gbase, int G, i64 *first, hipStream_t s);
+void batch_compose(i32 *composed, const i32 *lab, const i32 *gid0, const uint8_t *flag, i64 n0,
+                   hipStream_t s);
+void batch_compose_shift(i32 *composed, const i32 *gid0, const i64 *shift, i64 n0,
+                         hipStream_t s);
+void batch_relabel(const i32 *lab, const i32 *gid, const i32 *m2n, const i64 *shift, i64 n,
+                   i32 *lab2, i32 *gid2, i32 *m2n2, hipStream_t s);
+void batch_meta(const i64 *gbase, int G, const i64 *m2g, i64 max_nodes, i32 *gid, i32 *m2n,
+                hipStream_t s);

@@ -65,7 +65,42 @@ struct LevelView {
     i64 n;
     i64 nnz;
     i64 m2;
+    // A batch is the disjoint union of independent graphs.  Every key of a
+    // node then uses the total weight of its own graph, and the acceptance
+    // draw uses its graph's seed, level and local node number.  All null for
+    // a single graph (m2 above applies to every node).
+    const i32 *m2n;   // per node: M2 of its graph
+    const i32 *gid;   // per node: graph index
+    const i64 *gbase; // per graph: first node at this level
+    const u64 *gseed; // per graph: seed
+    const i32 *glev;  // per graph: level index
 };
+
+__device__ __forceinline__ i64 node_m2(const LevelView &L, i64 i)
+{
+    return L.m2n ? (i64)L.m2n[i] : L.m2;
+}
+
+// Adds v to acc[key] for every lane of the wavefront, where the keys are
+// non-decreasing across lanes (nodes of one graph are contiguous): a
+// segmented reduction leaves one atomic per distinct key.  Only trailing
+// lanes (past the end of the range) may pass key < 0; a lane inside the range
+// that adds nothing passes its own key with v = 0.  Every lane of the
+// wavefront must call it.
+__device__ __forceinline__ void seg_add_sorted(unsigned long long *acc, i32 key, i64 v)
+{
+    const int lane = threadIdx.x & 63;
+    i64 x = key >= 0 ? v : 0;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const i64 y = __shfl_up(x, d, 64);
+        const i32 ky = __shfl_up(key, d, 64);
+        if (lane >= d && ky == key) x += y;
+    }
+    const i32 kn = __shfl_down(key, 1, 64);
+    const bool last = lane == 63 || kn != key;
+    if (last && key >= 0 && x != 0) atomicAdd(&acc[key], (unsigned long long)x);
+}
 
 // ---------------------------------------------------------------- device helpers
 __device__ __forceinline__ bool better_key(i64 k1, i32 id1, i64 k2, i32 id2)

@@ -53,3 +53,34 @@ def test_invalid_arguments_are_rejected_without_a_device():
     p = slm.Params()
     lib.slm_params_default(C.byref(p))
     assert p.accept_p == 1 << 31 and p.max_rounds == 64 and p.validate == 1
+
+
+def test_batch_arguments_are_rejected_without_a_device():
+    import paper_1702_04645_amd as slm
+    lib = slm.lib()
+    h = C.c_void_p()
+    # no graphs
+    assert lib.slm_batch_create(0, None, 1, None, C.byref(h)) == slm.SLM_E_INVALID
+
+    def descs(*graphs):
+        arr = (slm._Desc * len(graphs))()
+        for i, (rp, col, w) in enumerate(graphs):
+            arr[i] = slm._Desc(rp.size - 1, col.size, rp.ctypes.data, col.ctypes.data,
+                               w.ctypes.data)
+        return arr
+
+    ok = (np.array([0, 1, 2], np.int64), np.array([1, 0], np.int32), np.array([1, 1], np.int32))
+    # an asymmetric member
+    bad = (np.array([0, 1, 1], np.int64), np.array([1], np.int32), np.array([1], np.int32))
+    d = descs(ok, bad)
+    assert lib.slm_batch_create(2, d, 1, None, C.byref(h)) == slm.SLM_E_INVALID
+    assert b"symmetric" in lib.slm_last_error()
+    # a member whose total weight reaches 2^31
+    big = (np.array([0, 1, 2], np.int64), np.array([1, 0], np.int32),
+           np.array([2**30, 2**30], np.int32))
+    d = descs(ok, big)
+    assert lib.slm_batch_create(2, d, 1, None, C.byref(h)) == slm.SLM_E_OVERFLOW
+    # row_ptr not ending at nnz (validation off still checks it)
+    short = (np.array([0, 1, 1], np.int64), np.array([1, 0], np.int32), np.array([1, 1], np.int32))
+    d = descs(short)
+    assert lib.slm_batch_create(1, d, 0, None, C.byref(h)) == slm.SLM_E_INVALID
