@@ -69,6 +69,138 @@ def cpu_baseline(rp, col, w, budget_s: float):
                        % (reps, el))
 
 
+def _gen_member(args):
+    import graphgen as gg
+    seed, i, count = args
+    return gg.sbm_batch(count, 64, 65536, seed, indices=[i])[0]
+
+
+def batch_members(count: int, seed: int, procs: int):
+    """The batch family: planted-partition graphs with log-uniform node counts
+    in [64, 65536], block sizes 16..256, p_in 0.2, mean external degree 2.
+    Generated in a process pool (before the GPU is touched)."""
+    import multiprocessing as mp
+    work = [(seed, i, count) for i in range(count)]
+    if procs <= 1:
+        return [_gen_member(a) for a in work]
+    with mp.get_context("fork").Pool(procs) as pool:
+        return pool.map(_gen_member, work, chunksize=4)
+
+
+def _oracle_member(args):
+    import oracle
+    rp, col, w, seed = args
+    t = time.perf_counter()
+    oracle.run(rp, col, w, seed=seed)
+    return time.perf_counter() - t
+
+
+def batch_bench(args):
+    """Graphs per second of the batch family: all members in one batched run,
+    against the plain path (one handle and one run per graph) on a sample,
+    and the oracle (one process per host core) on a sample."""
+    import graphgen as gg
+    count = args.batch_count
+    seed = gg.CONFIG_SEEDS["batch2048"]
+    procs = max(1, min(16, os.cpu_count() or 1))
+    t = time.time()
+    members = batch_members(count, seed, procs)
+    seeds = [gg.batch_member_seed(args.seed, i) for i in range(count)]
+    n_tot = sum(m[0].size - 1 for m in members)
+    nnz_tot = sum(m[1].size for m in members)
+    log("batch: %d graphs, %d nodes, %d entries, generated in %.1fs"
+        % (count, n_tot, nnz_tot, time.time() - t))
+    stride = max(1, count // args.plain_sample)
+    sample = list(range(0, count, stride))
+    cpu = None
+    if not args.no_cpu:
+        import multiprocessing as mp
+        osample = sample[: max(1, min(len(sample), 4 * procs))]
+        t = time.perf_counter()
+        with mp.get_context("fork").Pool(procs) as pool:
+            times = pool.map(_oracle_member, [(*members[i], seeds[i]) for i in osample])
+        el = time.perf_counter() - t
+        cpu = dict(value=len(osample) / el, unit="graphs/s", cores=procs, kind="oracle",
+                   sample="%d members (every %d-th), one oracle process per core, %.1f s"
+                          % (len(osample), stride, el),
+                   oracle_seconds_per_graph=sum(times) / len(times))
+        log("oracle: %.2f graphs/s on %d cores" % (cpu["value"], procs))
+
+    import torch
+    import paper_1702_04645_amd as slm
+    p = slm.params()
+    t = time.perf_counter()
+    b = slm.Batch(members, validate=False)
+    t_create = time.perf_counter() - t
+    for i in range(args.warmup):
+        b.run(p, seeds=seeds)
+    b.timing(True)
+    b.timing_read()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for i in range(args.steps):
+        res = b.run(p, seeds=seeds)
+        log("batched step %d done" % i)
+    torch.cuda.synchronize()
+    t_batch = (time.perf_counter() - t) / max(args.steps, 1)
+    tm = b.timing_read()
+    b.close()
+    del b
+    levels = sum(len(r) for r in res)
+    # plain path on the sample: one handle per graph, created outside the timing
+    handles = [slm.Graph(*members[i], validate=False) for i in sample]
+    for h, i in zip(handles, sample):
+        h.run(slm.params(seed=seeds[i]))  # warm-up
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for h, i in zip(handles, sample):
+        h.run(slm.params(seed=seeds[i]))
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t
+    for h in handles:
+        h.close()
+    # the same sample as one batch
+    sb = slm.Batch([members[i] for i in sample], validate=False)
+    sb.run(p, seeds=[seeds[i] for i in sample])
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    sb.run(p, seeds=[seeds[i] for i in sample])
+    torch.cuda.synchronize()
+    t_sample_batch = time.perf_counter() - t
+    sb.close()
+    sweep_s = tm["sweep_ms"] / 1e3
+    achieved = tm["bytes"] / sweep_s / 1e9 if sweep_s > 0 else 0.0
+    out = {
+        "metric": "graphs/s batched vs plain",
+        "value": round(count / t_batch, 2),
+        "unit": "graphs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(t_batch * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int64",
+        "data": "synthetic",
+        "config": dict(workload="batch2048", graphs=count, nodes=n_tot, entries=nnz_tot,
+                       n_range=[64, 65536], block=[16, 256], p_in=0.2, mean_ext_deg=2,
+                       seed=seed, emitted_levels=levels),
+        "plain_graphs_per_s": round(len(sample) / t_plain, 2),
+        "sample_batched_graphs_per_s": round(len(sample) / t_sample_batch, 2),
+        "plain_sample": "%d members (every %d-th)" % (len(sample), stride),
+        "create_s": round(t_create, 3),
+        "sweep_gteps": round(tm["entries"] / sweep_s / 1e9, 3) if sweep_s > 0 else 0.0,
+        "sweeps_timed": tm["sweeps"],
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": None},
+    }
+    if cpu:
+        out["cpu_baseline"] = cpu
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -78,12 +210,16 @@ def main():
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--batch-count", type=int, default=2048)
+    ap.add_argument("--plain-sample", type=int, default=128)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
     rank = int(os.environ.get("RANK", "0"))
+    if args.workload == "batch2048":
+        return batch_bench(args)
 
     import torch
     import paper_1702_04645_amd as slm

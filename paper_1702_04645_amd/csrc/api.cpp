@@ -305,12 +305,7 @@ static void alloc_work(slm_graph *g)
     W.wsz = dalloc<i64>(g, n);
     W.nsz = dalloc<i64>(g, n);
     W.pstk = dalloc<int4>(g, n);
-    W.mpos = dalloc<i32>(g, n);
-    W.xk = dalloc<i32>(g, n);
-    W.xw = dalloc<i32>(g, n);
-    W.xs = dalloc<i32>(g, n);
-    W.xc = dalloc<i32>(g, n);
-    W.xf = dalloc<uint8_t>(g, n);
+    W.stamp = dalloc<i32>(g, n);
     W.minm = dalloc<i32>(g, n);
     W.rank = dalloc<i64>(g, n + 1);
     W.scan_tmp = dalloc<i64>(g, scan_tmp_elems(std::max(n, nnz) + 1) + 16);

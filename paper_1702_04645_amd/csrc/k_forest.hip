@@ -714,12 +714,7 @@ i64 positive(Work &W, const LevelView &Lv, const Bins &B, i64 *nc_out, hipStream
         A.noff = W.noff_f;
         A.cn = W.cnode;
         A.splits = W.counters;
-        A.mpos = W.mpos;
-        A.xk = W.xk;
-        A.xw = W.xw;
-        A.xs = W.xs;
-        A.xc = W.xc;
-        A.xf = W.xf;
+        A.stamp = W.stamp;
         HIPCHK(hipMemsetAsync(W.changed, 0, sizeof(int), s));
         A.err = W.changed;
         launch_positive_wg(A, nflag, s);

@@ -22,12 +22,35 @@
 //                  positions p+1..q
 // ties to the lowest (first, second) cut node; the best cut is applied even
 // when its key is not positive, until no node of the part has g < 0.
+//
+// Split search.  A full scan of the part keeps, per lane, its PW_TOP best
+// branch keys and its lowest gain as a candidate set; every other node is
+// summarised by value buckets (by subtree strength for keys, by strength k
+// for gains).  Between scans, a cut changes the key or gain of a node in two
+// ways only: through S_P, which drops by D for everyone (a key falls by at
+// least its bucket's floor times D, a gain rises by at least that much), and
+// through the nodes whose own terms the cut updates (ancestors of x, nodes on
+// the corrected cut paths, neighbours of T_x), which join the candidate set.
+// The candidates are evaluated exactly at every split; when the bucket
+// bounds cannot rule out a better key (ties included) or a negative gain
+// outside the set, the part is scanned again.  The answer is therefore
+// always the one a full scan would give.  T_x stays in the range (marked by
+// its id) until the part is finished; it is then gathered from its root into
+// a range of its own.
 #include "slm_forest.h"
 
 #define PW_BS 512
 #define PW_NW (PW_BS / 64)
 
-enum { ST_INIT = 1 };
+// Stack entries (s, e, part id, flags): ST_INIT rebuilds the part from its
+// member range; ST_GATHER is a subtree cut off a part: its members are
+// collected from its root when it is popped, into a range assigned when the
+// part it left is finished (e holds its size until then, s = -1).
+enum { ST_INIT = 1, ST_GATHER = 2 };
+
+#define PW_CAND 4096  // candidate set of the split search
+#define PW_TOP 4      // branch-key candidates kept per lane by a full scan
+#define PW_NB 33      // value buckets: 0 for v <= 0, else 1 + floor(log2 v)
 
 struct PwShared {
     i64 red[2 * PW_NW + 2];
@@ -41,7 +64,80 @@ struct PwShared {
     int L;         // cycle length of the part
     int chl_top;   // next free slot of the children arena
     int iters;     // loop guard (workgroup-uniform loops)
+    int sp0;       // stack size when the current part started
+    // split search: the nodes of the candidate set are evaluated exactly at
+    // every split; every other node of the part is bounded by the bucket of
+    // its value at the last full scan (see pw_thr / pw_lb)
+    int need_scan, epoch, ncand, cand_over;
+    i64 sig_scan;  // S_P at the last full scan
+    u64 kmax[PW_NB];  // per bucket of subtree strength: max branch key (order-mapped)
+    u64 kpair[PW_NB]; // per bucket: lowest cut pair among its nodes whose key is that max
+    u64 gmin[PW_NB];  // per bucket of strength: min local gain (order-mapped)
+    i32 cand[PW_CAND];
 };
+
+__device__ __forceinline__ u64 ord_map(i64 v) { return (u64)v ^ (1ull << 63); }
+__device__ __forceinline__ i64 ord_unmap(u64 v) { return (i64)(v ^ (1ull << 63)); }
+__device__ __forceinline__ int pw_bucket(i64 v) { return v <= 0 ? 0 : 64 - __clzll((u64)v); }
+__device__ __forceinline__ i64 pw_floor(int b) { return b ? ((i64)1 << (b - 1)) : 0; }
+
+// Upper bound on the branch key of every node outside the candidate set.
+// Such a node kept its subtree strength and cut since the last scan, so its
+// key fell by (strength) * D, D = the drop of S_P since then; a node of
+// bucket b has strength >= pw_floor(b).  Only a node whose key was its
+// bucket's maximum can reach the bound, so *tpair = the lowest cut pair of
+// those nodes over the buckets that reach it (ties go to the lowest pair).
+__device__ __forceinline__ i64 pw_thr(const PwShared &S, i64 D, u64 *tpair)
+{
+    i64 t = INT64_MIN;
+    u64 tp = ~0ull;
+    for (int b = 0; b < PW_NB; b++) {
+        if (S.kmax[b] == 0) continue;
+        const i64 v = ord_unmap(S.kmax[b]) - pw_floor(b) * D;
+        if (v > t) {
+            t = v;
+            tp = S.kpair[b];
+        } else if (v == t) {
+            tp = min(tp, (u64)S.kpair[b]);
+        }
+    }
+    *tpair = tp;
+    return t;
+}
+
+// Lower bound on the local gain g = M2 w_in - k (S_P - k) of every node
+// outside the candidate set: it rose by k * D.
+__device__ __forceinline__ i64 pw_lb(const PwShared &S, i64 D)
+{
+    i64 t = INT64_MAX;
+    for (int b = 0; b < PW_NB; b++)
+        if (S.gmin[b] != ~0ull) t = min(t, ord_unmap(S.gmin[b]) + pw_floor(b) * D);
+    return t;
+}
+
+// Adds v to the candidate set once per scan epoch.
+__device__ __forceinline__ void pw_add_cand(PwShared &S, i32 *stamp, i32 v)
+{
+    if (atomicExch(&stamp[v], S.epoch) == S.epoch) return;
+    const int i = atomicAdd(&S.ncand, 1);
+    if (i < PW_CAND) S.cand[i] = v;
+    else S.cand_over = 1;
+}
+
+// Ranges for the subtrees cut off the finished part: consecutive from off.
+__device__ __forceinline__ void pw_assign(int4 *STK, int from, int to, int off)
+{
+    for (int k = from; k < to; k++) {
+        int4 t = STK[k];
+        if ((t.w & ST_GATHER) && t.x < 0) {
+            const int sz = t.y;
+            t.x = off;
+            t.y = off + sz;
+            off += sz;
+            STK[k] = t;
+        }
+    }
+}
 
 __device__ __forceinline__ i64 wg_sum(i64 v, PwShared &S)
 {
@@ -223,18 +319,23 @@ __global__ __launch_bounds__(PW_BS) void k_positive_wg(PosArgs A)
     i32 *a = A.a;
     uint8_t *cyc = A.cyc;
 
+    i32 *stamp = A.stamp;
+    // iterations: at most one pass per part and, per split, one full scan
+    // and one split step; parts and splits are fewer than 2*m0
+    const int iter_cap = 6 * m0 + 16;
+
     if (threadIdx.x == 0) {
         STK[0] = make_int4(0, m0, A.flist[f], ST_INIT);
         S.sp = 1;
         S.chl_top = 0;
         S.iters = 0;
+        S.epoch = 0;
     }
     __syncthreads();
     while (true) {
         __syncthreads();
         if (S.sp == 0) break;
-        // every pass pops one part; parts and splits are fewer than 2*m0
-        if (S.iters > 4 * m0 + 8) {
+        if (S.iters > iter_cap) {
             if (threadIdx.x == 0) report(A.err, 5);
             break;
         }
@@ -244,8 +345,15 @@ __global__ __launch_bounds__(PW_BS) void k_positive_wg(PosArgs A)
             S.e = t.y;
             S.pid = t.z;
             S.flags = t.w;
+            S.sp0 = S.sp;
+            S.need_scan = 1;
+            S.iters++;
         }
         __syncthreads();
+        if (S.s < 0 || S.e < S.s || S.e > m0) {  // a range outside the community
+            if (threadIdx.x == 0) report(A.err, 9);
+            break;
+        }
         const int s = S.s, pid = S.pid;
         if (S.e - s <= 1) continue;
         // -------------------------------------------------- (re)build a part
@@ -256,6 +364,7 @@ __global__ __launch_bounds__(PW_BS) void k_positive_wg(PosArgs A)
             for (int i = threadIdx.x; i < m; i += PW_BS) {
                 i32 u = P[i];
                 A.part[u] = pid;
+                stamp[u] = -1;
                 A.win[u] = 0;
                 A.chc[u] = 0;
                 A.subk[u] = G.k[u];
@@ -425,9 +534,44 @@ __global__ __launch_bounds__(PW_BS) void k_positive_wg(PosArgs A)
                 __syncthreads();
             }
         } else {
+            // ST_GATHER: T_x, cut off an earlier part, is the subtree of its
+            // root x over the children lists, restricted to the nodes that
+            // still carry its id; its range holds exactly its members.
             const int m = S.e - s;
+            i32 *P = M + s;
+            if (threadIdx.x == 0) {
+                P[0] = pid;
+                S.head = 0;
+                S.tail = 1;
+                S.lev_end = 1;
+            }
+            __syncthreads();
+            for (int lv = 0; lv <= m; lv++) {
+                const int lb = S.head, le = S.lev_end;
+                if (lb == le) break;
+                for (int i = lb + threadIdx.x; i < le; i += PW_BS) {
+                    const i32 u = P[i];
+                    const int c = A.chc[u], cs = A.chs[u];
+                    for (int j = 0; j < c; j++) {
+                        const i32 ch = CHL[cs + j];
+                        if (A.part[ch] != pid) continue;
+                        const int q = atomicAdd(&S.tail, 1);
+                        if (q < m) P[q] = ch;
+                    }
+                }
+                __syncthreads();
+                if (threadIdx.x == 0) {
+                    S.head = le;
+                    S.lev_end = min(S.tail, m);
+                }
+                __syncthreads();
+            }
+            if (S.tail != m) {
+                if (threadIdx.x == 0) report(A.err, 8);
+                break;
+            }
             i64 sg = 0;
-            for (int i = threadIdx.x; i < m; i += PW_BS) sg += G.k[M[s + i]];
+            for (int i = threadIdx.x; i < m; i += PW_BS) sg += G.k[P[i]];
             sg = wg_sum(sg, S);
             if (threadIdx.x == 0) {
                 S.sig = sg;
@@ -440,31 +584,165 @@ __global__ __launch_bounds__(PW_BS) void k_positive_wg(PosArgs A)
             __syncthreads();
             if (threadIdx.x == 0) S.iters++;
             __syncthreads();
-            if (S.iters > 4 * m0 + 8) {
+            if (S.iters > iter_cap) {
                 if (threadIdx.x == 0) report(A.err, 6);
                 break;
             }
-            const int m = S.e - s;
+            int m = S.e - s;
             i32 *P = M + s;
             const i64 sig = S.sig;
             const int L = S.L;
             if (m <= 1) break;
+            const bool scanned = S.need_scan != 0;
+            __syncthreads();
             i64 bk = INT64_MIN;
             u64 bp = ~0ull;
             int neg = 0;
-            for (int i = threadIdx.x; i < m; i += PW_BS) {
-                i32 u = P[i];
-                const i64 ku = G.k[u];
-                if (m2 * (i64)A.win[u] - ku * (sig - ku) < 0) neg = 1;
-                if (!cyc[u]) {
-                    const i64 sx = A.subk[u];
-                    const i64 key = sx * (sig - sx) - m2 * (i64)A.cut[u];
-                    const u64 pr = ((u64)(u32)u << 32) | (u64)(u32)u;
-                    if (key > bk || (key == bk && pr < bp)) {
-                        bk = key;
-                        bp = pr;
+            if (scanned) {
+                // ---- full scan of the range; nodes that left the part are
+                // skipped.  Every lane keeps its best branch key and its
+                // lowest gain as candidates; all other nodes go to the
+                // buckets that bound them until the next scan.
+                for (int b = threadIdx.x; b < PW_NB; b += PW_BS) {
+                    S.kmax[b] = 0;
+                    S.kpair[b] = ~0ull;
+                    S.gmin[b] = ~0ull;
+                }
+                if (threadIdx.x == 0) {
+                    S.epoch++;
+                    S.ncand = 0;
+                    S.cand_over = 0;
+                    S.sig_scan = sig;
+                    S.need_scan = 0;
+                }
+                __syncthreads();
+                // per lane: the PW_TOP best (key desc, pair asc) branch keys,
+                // sorted; a node pushed out goes to its bucket
+                i64 tk[PW_TOP], ts[PW_TOP];
+                u64 tp[PW_TOP];
+#pragma unroll
+                for (int q = 0; q < PW_TOP; q++) {
+                    tk[q] = INT64_MIN;
+                    tp[q] = ~0ull;
+                    ts[q] = 0;
+                }
+                i32 gu = -1;
+                i64 gm = INT64_MAX, gk = 0, live = 0;
+                constexpr int SU = 8;
+                for (int i0 = threadIdx.x; i0 < m; i0 += PW_BS * SU) {
+                    i32 uu[SU], pp[SU], ww[SU], sxv[SU], cxv[SU], kk[SU];
+                    uint8_t cy[SU];
+#pragma unroll
+                    for (int j = 0; j < SU; j++) {
+                        const int i = i0 + j * PW_BS;
+                        uu[j] = i < m ? P[i] : -1;
+                    }
+#pragma unroll
+                    for (int j = 0; j < SU; j++) {
+                        pp[j] = -1;
+                        kk[j] = ww[j] = sxv[j] = cxv[j] = 0;
+                        cy[j] = 1;
+                        if (uu[j] >= 0) {
+                            const i32 u = uu[j];
+                            pp[j] = A.part[u];
+                            kk[j] = G.k[u];
+                            ww[j] = A.win[u];
+                            cy[j] = cyc[u];
+                            sxv[j] = A.subk[u];
+                            cxv[j] = A.cut[u];
+                        }
+                    }
+#pragma unroll
+                    for (int j = 0; j < SU; j++) {
+                        if (uu[j] < 0 || pp[j] != pid) continue;
+                        const i32 u = uu[j];
+                        live++;
+                        const i64 ku = kk[j];
+                        const i64 g = m2 * (i64)ww[j] - ku * (sig - ku);
+                        if (g < gm) {
+                            if (gu >= 0) atomicMin((unsigned long long *)&S.gmin[pw_bucket(gk)], (unsigned long long)ord_map(gm));
+                            gm = g;
+                            gu = u;
+                            gk = ku;
+                        } else {
+                            atomicMin((unsigned long long *)&S.gmin[pw_bucket(ku)], (unsigned long long)ord_map(g));
+                        }
+                        if (!cy[j]) {
+                            i64 ck = sxv[j] * (sig - sxv[j]) - m2 * (i64)cxv[j];
+                            u64 cp = ((u64)(u32)u << 32) | (u64)(u32)u;
+                            i64 cs = sxv[j];
+                            // insert into the sorted top list; what falls off
+                            // the end goes to its bucket
+#pragma unroll
+                            for (int q = 0; q < PW_TOP; q++) {
+                                if (ck > tk[q] || (ck == tk[q] && cp < tp[q])) {
+                                    const i64 k2 = tk[q], s2 = ts[q];
+                                    const u64 p2 = tp[q];
+                                    tk[q] = ck;
+                                    tp[q] = cp;
+                                    ts[q] = cs;
+                                    ck = k2;
+                                    cp = p2;
+                                    cs = s2;
+                                }
+                            }
+                            if (cp != ~0ull)
+                                atomicMax((unsigned long long *)&S.kmax[pw_bucket(cs)], (unsigned long long)ord_map(ck));
+                        }
                     }
                 }
+                bk = tk[0];
+                bp = tp[0];
+                neg = gm < 0 ? 1 : 0;
+                __syncthreads();
+                // lowest pair among the bucket nodes that hold their bucket's
+                // maximum key (the lane bests are candidates, not bucket nodes)
+                for (int i = threadIdx.x; i < m; i += PW_BS) {
+                    const i32 u = P[i];
+                    bool top = false;
+#pragma unroll
+                    for (int q = 0; q < PW_TOP; q++) top |= tp[q] == (((u64)(u32)u << 32) | (u64)(u32)u);
+                    if (top || A.part[u] != pid || cyc[u]) continue;
+                    const i64 sx = A.subk[u];
+                    const int b = pw_bucket(sx);
+                    const i64 key = sx * (sig - sx) - m2 * (i64)A.cut[u];
+                    if (ord_map(key) == S.kmax[b])
+                        atomicMin((unsigned long long *)&S.kpair[b],
+                                  (unsigned long long)(((u64)(u32)u << 32) | (u64)(u32)u));
+                }
+                __syncthreads();
+#pragma unroll
+                for (int q = 0; q < PW_TOP; q++)
+                    if (tp[q] != ~0ull) pw_add_cand(S, stamp, (i32)(tp[q] >> 32));
+                if (gu >= 0) pw_add_cand(S, stamp, gu);
+                live = wg_sum(live, S);
+                if (m > 2 * live + PW_BS) {  // most of the range has left: compact
+                    const int kept =
+                        wg_partition(P, m, ORD, [&](i32 u) { return A.part[u] == pid; }, S);
+                    if (threadIdx.x == 0) S.e = s + kept;
+                    __syncthreads();
+                    m = kept;
+                }
+            } else {
+                // ---- the candidate set, exactly
+                const int nc = min(S.ncand, PW_CAND);
+                i64 gm = INT64_MAX;
+                for (int i = threadIdx.x; i < nc; i += PW_BS) {
+                    const i32 u = S.cand[i];
+                    if (A.part[u] != pid) continue;
+                    const i64 ku = G.k[u];
+                    gm = min(gm, m2 * (i64)A.win[u] - ku * (sig - ku));
+                    if (!cyc[u]) {
+                        const i64 sx = A.subk[u];
+                        const i64 key = sx * (sig - sx) - m2 * (i64)A.cut[u];
+                        const u64 pr = ((u64)(u32)u << 32) | (u64)(u32)u;
+                        if (key > bk || (key == bk && pr < bp)) {
+                            bk = key;
+                            bp = pr;
+                        }
+                    }
+                }
+                neg = gm < 0 ? 1 : 0;
             }
             // cycle cuts: pairs p < q of cycle positions
             if (L >= 2) {
@@ -489,6 +767,22 @@ __global__ __launch_bounds__(PW_BS) void k_positive_wg(PosArgs A)
             }
             neg = (int)wg_sum(neg, S);
             wg_best(bk, bp, S);
+            if (!scanned) {
+                // the set decides only if no node outside it can change the
+                // answer; otherwise scan the whole part
+                const i64 D = S.sig_scan - sig;
+                u64 tpair;
+                const i64 thr = pw_thr(S, D, &tpair), lb = pw_lb(S, D);
+                bool sure = true;
+                if (!neg && lb < 0) sure = false;
+                if (neg && bp != ~0ull && !(bk > thr || (bk == thr && bp < tpair))) sure = false;
+                if (neg && bp == ~0ull && thr != INT64_MIN) sure = false;
+                if (!sure) {
+                    __syncthreads();
+                    if (threadIdx.x == 0) S.need_scan = 1;
+                    continue;
+                }
+            }
             if (!neg || bp == ~0ull) break;
             const i32 x = (i32)(bp >> 32), y = (i32)(bp & 0xffffffffu);
             if (threadIdx.x == 0) atomicAdd((unsigned long long *)A.splits, 1ull);
@@ -517,14 +811,21 @@ __global__ __launch_bounds__(PW_BS) void k_positive_wg(PosArgs A)
                     const int pr = A.cpos[A.root[u]];
                     return !(pr > pp && pr <= qq);
                 };
-                const int nx = wg_partition(P, m, ORD, inX, S);
+                // the members still in the part first, then the two sides
+                const int live =
+                    wg_partition(P, m, ORD, [&](i32 u) { return A.part[u] == pid; }, S);
+                const int nx = wg_partition(P, live, ORD, inX, S);
                 // both sides take their ids now: a one-node side is never
                 // rebuilt, and the other side must not count it as a member
-                for (int i = threadIdx.x; i < m; i += PW_BS) A.part[P[i]] = i < nx ? cp : cq;
+                for (int i = threadIdx.x; i < live; i += PW_BS) A.part[P[i]] = i < nx ? cp : cq;
                 __syncthreads();
                 if (threadIdx.x == 0) {
-                    STK[S.sp++] = make_int4(s, s + nx, cp, ST_INIT);
-                    STK[S.sp++] = make_int4(s + nx, S.e, cq, ST_INIT);
+                    pw_assign(STK, S.sp0, S.sp, s + live);
+                    if (S.sp + 2 > m0) report(A.err, 10);
+                    else {
+                        STK[S.sp++] = make_int4(s, s + nx, cp, ST_INIT);
+                        STK[S.sp++] = make_int4(s + nx, s + live, cq, ST_INIT);
+                    }
                 }
                 __syncthreads();
                 break;
@@ -576,6 +877,7 @@ __global__ __launch_bounds__(PW_BS) void k_positive_wg(PosArgs A)
                         break;
                     }
                     A.subk[yv] -= (i32)sx;
+                    pw_add_cand(S, stamp, yv);
                     if (cyc[yv]) break;
                     yv = a[yv];
                 }
@@ -598,20 +900,25 @@ __global__ __launch_bounds__(PW_BS) void k_positive_wg(PosArgs A)
                         val = ed.y;
                         const i32 A_ = ed.y;
                         atomicSub(&A.win[u], A_);
+                        pw_add_cand(S, stamp, u);
                         // paths u -> lca and px -> lca in the part before the cut
                         i32 p1 = u, p2 = px;
                         int guard = 0;
                         while (A.dep[p1] > A.dep[p2] && guard++ < 2 * m) {
                             atomicSub(&A.cut[p1], A_);
+                            pw_add_cand(S, stamp, p1);
                             p1 = a[p1];
                         }
                         while (A.dep[p2] > A.dep[p1] && guard++ < 2 * m) {
                             atomicSub(&A.cut[p2], A_);
+                            pw_add_cand(S, stamp, p2);
                             p2 = a[p2];
                         }
                         while (p1 != p2 && guard++ < 2 * m) {
                             atomicSub(&A.cut[p1], A_);
                             atomicSub(&A.cut[p2], A_);
+                            pw_add_cand(S, stamp, p1);
+                            pw_add_cand(S, stamp, p2);
                             if (cyc[p1] && cyc[p2]) break;
                             p1 = a[p1];
                             p2 = a[p2];
@@ -632,17 +939,24 @@ __global__ __launch_bounds__(PW_BS) void k_positive_wg(PosArgs A)
                 wave_run_add(t < tot, v, -val, A.win);
             }
             __syncthreads();
-            // the part keeps its members first, T_x goes to the end of the range
-            const int keep = wg_partition(P, m, ORD, [&](i32 u) { return A.part[u] == pid; }, S);
+            // T_x stays in the range, marked by its id, and waits on the stack
+            // for a range of its own (a single node needs none)
             if (threadIdx.x == 0) {
-                STK[S.sp++] = make_int4(s + keep, S.e, x, 0);
-                S.e = s + keep;
+                if (tcount > 1) {
+                    if (S.sp >= m0) report(A.err, 10);
+                    else STK[S.sp++] = make_int4(-1, tcount, x, ST_GATHER);
+                }
                 S.sig = sig - sx;
+                if (S.cand_over) S.need_scan = 1;
             }
             __syncthreads();
         }
+        // the subtrees cut off this part take their ranges inside it
+        if (threadIdx.x == 0) pw_assign(STK, S.sp0, S.sp, s);
+        __syncthreads();
     }
 }
+
 
 void launch_positive_wg(const PosArgs &A, i64 nflag, hipStream_t s)
 {

@@ -24,8 +24,7 @@ struct Work {
     i64 *mem_off = nullptr, *pdp = nullptr, *woff_f = nullptr, *noff_f = nullptr;
     i64 *wsz = nullptr, *nsz = nullptr;
     int4 *pstk = nullptr;
-    i32 *mpos = nullptr, *xk = nullptr, *xw = nullptr, *xs = nullptr, *xc = nullptr;
-    uint8_t *xf = nullptr;
+    i32 *stamp = nullptr;  // POSITIVE: candidate-set epoch of every node
     i32 *A0 = nullptr, *A1 = nullptr, *M0 = nullptr, *M1 = nullptr;
     i32 *J = nullptr;  // kmax tables of n0
     i32 *D0 = nullptr, *D1 = nullptr;
@@ -82,9 +81,7 @@ struct PosArgs {
     i32 *lvl;            // level starts (n + nflag entries)
     int4 *stk;           // part stack (n entries)
     i32 *part, *win, *subk, *cut, *dep, *root, *chs, *chc, *cpos;  // per node
-    i32 *mpos;                  // per node: index of the node in the member arrays
-    i32 *xk, *xw, *xs, *xc;     // per member (member order): k, win, subtree k, cut
-    uint8_t *xf;                // per member: cycle flag
+    i32 *stamp;          // per node: scan epoch in which it joined the candidate set
     const i32 *lcyc;     // cycle length of every flagged community
     const i64 *woff;     // cycle weight matrix offsets (L*L entries when L >= 2)
     i64 *W;
