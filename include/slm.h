@@ -220,6 +220,59 @@ slm_status slm_batch_size(const slm_graph *g, int32_t *count);
 slm_status slm_batch_run(slm_graph *g, const slm_params *p, const uint64_t *seeds,
                          slm_result **outs);
 
+/* ---------------------------------------------------------------- serving
+ * A server runs requests as they arrive.  Each lane is a union engine (the
+ * batched run above) with its own HIP stream and host thread; at every level
+ * boundary it admits queued requests in order while they fit its free
+ * capacity, runs one level for all resident graphs in the same launches, and
+ * hands finished graphs to their tickets.  A graph keeps its CSR and labels
+ * in HBM for its whole run.  Each result is the one slm_run gives for that
+ * graph alone with the request's seed, whatever else is resident.  With two
+ * lanes, graphs above large_nodes nodes use the second lane, so long runs of
+ * large graphs overlap on the device with the stream of small ones.  The
+ * serving loop is an extension for throughput and latency; the paper runs
+ * one graph at a time. */
+typedef struct slm_server slm_server;
+
+typedef struct {
+    int64_t node_capacity;   /* nodes resident at once per lane (0: 2^22)       */
+    int64_t entry_capacity;  /* CSR entries resident at once per lane (0: 2^26) */
+    int32_t max_members;     /* graphs resident at once per lane (0: 4096)      */
+    int32_t lanes;           /* 1 or 2                                          */
+    int64_t large_nodes;     /* with 2 lanes: graphs with more nodes use lane 1 */
+    int32_t validate;        /* check every submitted CSR                       */
+    int32_t reserved;
+    slm_params params;       /* accept_p, max_rounds, max_levels of every run   */
+} slm_server_cfg;
+
+/* Creates the lanes (each reserves HBM for its capacities at once; the sum is
+ * reported by slm_server_stats) on the current device.  The streams are
+ * created with the default priority. */
+slm_status slm_server_create(const slm_server_cfg *cfg, slm_server **out);
+
+/* Queues a host CSR (copied; the caller keeps ownership) with its draw seed.
+ * SLM_E_NOMEM when it can never fit its lane; SLM_E_INVALID /
+ * SLM_E_OVERFLOW as for slm_create.  *ticket identifies the result. */
+slm_status slm_server_submit(slm_server *sv, const slm_graph_desc *g, uint64_t seed,
+                             uint64_t *ticket);
+
+/* The result of a ticket (then owned by the caller, freed with
+ * slm_result_free), or *out = NULL while it runs.  A ticket is delivered
+ * once; an unknown or delivered ticket gives SLM_E_INVALID.  SLM_E_DEVICE
+ * when its lane failed (message in slm_last_error). */
+slm_status slm_server_poll(slm_server *sv, uint64_t ticket, slm_result **out);
+
+/* As slm_server_poll, but blocks until the result is there. */
+slm_status slm_server_wait(slm_server *sv, uint64_t ticket, slm_result **out);
+
+/* Requests submitted and completed so far, and the HBM bytes the lanes hold. */
+slm_status slm_server_stats(slm_server *sv, int64_t *submitted, int64_t *completed,
+                            int64_t *reserved_bytes);
+
+/* Stops admitting, lets resident graphs finish, drops queued ones and frees
+ * everything, undelivered results included. */
+void slm_server_destroy(slm_server *sv);
+
 /* Sweep timing: when enabled, every sweep records HIP events on the
  * handle's stream around its kernels.  slm_timing_read reports the summed
  * sweep time (ms), the number of sweeps, the CSR entries they read, and the

@@ -80,6 +80,12 @@ def lib():
         "slm_batch_create": (st, [i32, P, C.c_int, P, C.POINTER(P)]),
         "slm_batch_size": (st, [P, pi32]),
         "slm_batch_run": (st, [P, C.POINTER(Params), P, P]),
+        "slm_server_create": (st, [P, C.POINTER(P)]),
+        "slm_server_submit": (st, [P, P, C.c_uint64, C.POINTER(C.c_uint64)]),
+        "slm_server_poll": (st, [P, C.c_uint64, C.POINTER(P)]),
+        "slm_server_wait": (st, [P, C.c_uint64, C.POINTER(P)]),
+        "slm_server_stats": (st, [P, pi64, pi64, pi64]),
+        "slm_server_destroy": (None, [P]),
     }
     for name, (res, args) in sigs.items():
         f = getattr(L, name)
@@ -345,6 +351,72 @@ class Batch(Graph):
         for i in range(G):
             res.append(_take_result(C.c_void_p(outs[i]), self.sizes[i]))
         return res
+
+
+class _ServerCfg(C.Structure):
+    _fields_ = [("node_capacity", C.c_int64), ("entry_capacity", C.c_int64),
+                ("max_members", C.c_int32), ("lanes", C.c_int32), ("large_nodes", C.c_int64),
+                ("validate", C.c_int32), ("reserved", C.c_int32), ("params", Params)]
+
+
+class Server:
+    """Serving loop of the library: requests run as they arrive, admitted at
+    level boundaries while they fit a lane's capacity; one or two lanes
+    (graphs above ``large_nodes`` nodes take the second)."""
+
+    def __init__(self, node_capacity: int = 0, entry_capacity: int = 0, max_members: int = 0,
+                 lanes: int = 1, large_nodes: int = 1 << 62, validate: bool = True,
+                 p: Params | None = None):
+        self._h = C.c_void_p()
+        cfg = _ServerCfg(node_capacity, entry_capacity, max_members, lanes, large_nodes,
+                         int(validate), 0, p if p is not None else params())
+        _check(lib().slm_server_create(C.byref(cfg), C.byref(self._h)))
+        self._n0 = {}
+
+    def submit(self, row_ptr, col, w, seed: int = 0) -> int:
+        rp = np.ascontiguousarray(row_ptr, dtype=np.int64)
+        cl = np.ascontiguousarray(col, dtype=np.int32)
+        ww = np.ascontiguousarray(w, dtype=np.int32)
+        d = _Desc(rp.size - 1, cl.size, rp.ctypes.data, cl.ctypes.data, ww.ctypes.data)
+        t = C.c_uint64()
+        _check(lib().slm_server_submit(self._h, C.byref(d), seed & (2**64 - 1), C.byref(t)))
+        self._n0[t.value] = rp.size - 1
+        return t.value
+
+    def poll(self, ticket: int):
+        """The levels of a finished request (once), else None."""
+        res = C.c_void_p()
+        _check(lib().slm_server_poll(self._h, ticket, C.byref(res)))
+        if not res.value:
+            return None
+        return _take_result(res, self._n0.pop(ticket))
+
+    def wait(self, ticket: int):
+        res = C.c_void_p()
+        _check(lib().slm_server_wait(self._h, ticket, C.byref(res)))
+        return _take_result(res, self._n0.pop(ticket))
+
+    def stats(self):
+        a, b, c = C.c_int64(), C.c_int64(), C.c_int64()
+        _check(lib().slm_server_stats(self._h, C.byref(a), C.byref(b), C.byref(c)))
+        return dict(submitted=a.value, completed=b.value, reserved_bytes=c.value)
+
+    def close(self):
+        if self._h:
+            lib().slm_server_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
 
 
 def run(row_ptr, col, w, seed: int = 0, accept_p: int = 1 << 31, max_rounds: int = 64,

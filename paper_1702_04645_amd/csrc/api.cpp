@@ -4,6 +4,12 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <condition_variable>
+#include <deque>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
+#include <unordered_set>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -12,6 +18,27 @@
 #include "slm_forest.h"
 
 static thread_local std::string g_err;
+
+struct slm_result {
+    i64 n0 = 0;
+    std::vector<i64> nc, nq;
+    std::vector<double> q;
+    std::vector<i32> rounds, conv;
+    std::vector<std::vector<i32>> labels;
+};
+
+// One graph of a union.
+struct Member {
+    u64 ticket = 0;           // batch index, or server ticket
+    i64 n0 = 0, nnz0 = 0, m2 = 0;
+    u64 seed = 0;
+    int level = 0;            // index of its next level
+    std::vector<i32> comp;    // original node -> its node at the current level
+    slm_result *res = nullptr;
+    // a server member keeps its CSR until it joins the union
+    std::vector<i64> rp;
+    std::vector<i32> col, w;
+};
 
 struct slm_graph {
     hipStream_t s = nullptr;
@@ -33,29 +60,26 @@ struct slm_graph {
     double sweep_ms = 0;
     i64 sweeps = 0, entries = 0, bytes = 0;
     std::vector<void *> allocs;
+    i64 reserved = 0;  // device bytes held by allocs
 
-    // A batch handle holds G independent graphs as one disjoint union (G = 0
-    // for a plain graph).  Graph g owns the original nodes [base0[g],
-    // base0[g+1]) and, at the current level, the nodes [base[g], base[g+1]).
-    int G = 0;
-    std::vector<i64> base0, m2g, base;
-    i32 *gid0 = nullptr;                // per original node: graph
-    i32 *gidL[3] = {nullptr, nullptr, nullptr};  // per node: graph ([2] = level 0)
+    // A union handle (a batch, or a lane of a server) holds G independent
+    // graphs ("members") as one disjoint union; G = 0 for a plain graph.
+    // The member at position q owns the nodes [base[q], base[q+1]) of the
+    // current level.  Members leave when they finish and, in a server, join
+    // at level boundaries; positions are renumbered in order.
+    bool is_union = false;
+    int G = 0, P_cap = 0;
+    std::vector<Member> mem;
+    std::vector<i64> base;
+    std::vector<Member> mem0;  // a batch's members at level 0 (for every run)
+    std::vector<i64> base0;
+    i32 *gidL[3] = {nullptr, nullptr, nullptr};  // per node: position ([2] = level 0)
     i32 *m2nL[3] = {nullptr, nullptr, nullptr};  // per node: M2 of its graph
     i64 *d_gbase = nullptr, *d_first = nullptr, *d_gcb = nullptr, *d_accI = nullptr,
-        *d_accS = nullptr, *d_shift = nullptr, *d_gvalid = nullptr, *d_m2g = nullptr;
+        *d_accS = nullptr, *d_shift = nullptr, *d_gvalid = nullptr, *d_m2p = nullptr;
     u64 *d_gseed = nullptr;
-    i32 *d_glev = nullptr;
-    uint8_t *d_flag = nullptr;
+    i32 *d_glev = nullptr, *d_newpos = nullptr;
     i32 *lab2 = nullptr;
-};
-
-struct slm_result {
-    i64 n0 = 0;
-    std::vector<i64> nc, nq;
-    std::vector<double> q;
-    std::vector<i32> rounds, conv;
-    std::vector<std::vector<i32>> labels;
 };
 
 // ------------------------------------------------------------------ helpers
@@ -67,6 +91,7 @@ static T *dalloc(slm_graph *g, i64 count)
     hipError_t e = hipMalloc(&p, sizeof(T) * (size_t)count);
     if (e != hipSuccess) throw SlmError{SLM_E_NOMEM, "device allocation failed"};
     g->allocs.push_back(p);
+    g->reserved += (i64)(sizeof(T) * (size_t)count);
     return (T *)p;
 }
 
@@ -85,7 +110,7 @@ static LevelView view(slm_graph *g)
     L.gbase = nullptr;
     L.gseed = nullptr;
     L.glev = nullptr;
-    if (g->G > 0) {
+    if (g->is_union) {
         const int c = g->cur < 0 ? 2 : g->cur;
         L.m2n = g->m2nL[c];
         L.gid = g->gidL[c];
@@ -477,7 +502,8 @@ static void run_level(slm_graph *g, const slm_params *p, int level, i64 *nc, int
     *rounds = r;
 }
 
-static void do_contract(slm_graph *g, const i32 *lab, i64 nc)
+// AGGREGATE into the other level buffer; the caller runs setup_level.
+static void contract_only(slm_graph *g, const i32 *lab, i64 nc)
 {
     REQUIRE(nc < g->n, SLM_E_STATE, "contraction needs fewer communities than nodes");
     Work &W = g->W;
@@ -488,21 +514,43 @@ static void do_contract(slm_graph *g, const i32 *lab, i64 nc)
     g->n = nc;
     g->nnz = nnz2;
     g->level++;
+}
+
+static void do_contract(slm_graph *g, const i32 *lab, i64 nc)
+{
+    contract_only(g, lab, nc);
     setup_level(g);
 }
 
-static void batch_upload_base(slm_graph *g)
+// Per-position device arrays of a union from the host members.
+static void union_upload(slm_graph *g)
 {
-    HIPCHK(hipMemcpyAsync(g->d_gbase, g->base.data(), sizeof(i64) * (g->G + 1),
-                          hipMemcpyHostToDevice, g->s));
-    HIPCHK(hipStreamSynchronize(g->s));  // g->base may change right after
+    const int G = g->G;
+    std::vector<u64> sd(G);
+    std::vector<i32> lv(G);
+    std::vector<i64> m2(G);
+    for (int q = 0; q < G; q++) {
+        sd[q] = g->mem[q].seed;
+        lv[q] = g->mem[q].level;
+        m2[q] = g->mem[q].m2;
+    }
+    hipStream_t s = g->s;
+    HIPCHK(hipMemcpyAsync(g->d_gbase, g->base.data(), sizeof(i64) * (G + 1), hipMemcpyHostToDevice, s));
+    if (G > 0) {
+        HIPCHK(hipMemcpyAsync(g->d_gseed, sd.data(), sizeof(u64) * G, hipMemcpyHostToDevice, s));
+        HIPCHK(hipMemcpyAsync(g->d_glev, lv.data(), sizeof(i32) * G, hipMemcpyHostToDevice, s));
+        HIPCHK(hipMemcpyAsync(g->d_m2p, m2.data(), sizeof(i64) * G, hipMemcpyHostToDevice, s));
+    }
+    HIPCHK(hipStreamSynchronize(s));  // the host vectors may change right after
 }
 
 static void do_reset(slm_graph *g)
 {
-    if (g->G > 0 && g->base != g->base0) {
+    if (g->is_union && !g->mem0.empty()) {
+        g->mem = g->mem0;
         g->base = g->base0;
-        batch_upload_base(g);
+        g->G = (int)g->mem.size();
+        union_upload(g);
     }
     if (g->cur < 0 && g->level == 0) return;
     g->cur = -1;
@@ -516,43 +564,44 @@ static void do_reset(slm_graph *g)
 // caller's seed and level, as a run of that graph alone would.
 static void batch_set_draws(slm_graph *g, u64 seed, int level)
 {
-    if (g->G == 0) return;
-    std::vector<u64> sd(g->G, seed);
-    std::vector<i32> lv(g->G, level);
-    HIPCHK(hipMemcpyAsync(g->d_gseed, sd.data(), sizeof(u64) * g->G, hipMemcpyHostToDevice, g->s));
-    HIPCHK(hipMemcpyAsync(g->d_glev, lv.data(), sizeof(i32) * g->G, hipMemcpyHostToDevice, g->s));
-    HIPCHK(hipStreamSynchronize(g->s));
+    if (!g->is_union || g->G == 0) return;
+    for (Member &m : g->mem) {
+        m.seed = seed;
+        m.level = level;
+    }
+    union_upload(g);
 }
 
-// ------------------------------------------------------------------ batches
-static void alloc_batch(slm_graph *g)
+// ------------------------------------------------------------------ unions
+static void alloc_union(slm_graph *g, int P_cap)
 {
-    const int G = g->G;
     const i64 n = g->n0;
+    g->is_union = true;
+    g->P_cap = P_cap;
     for (int c = 0; c < 3; c++) {
         g->gidL[c] = dalloc<i32>(g, n);
         g->m2nL[c] = dalloc<i32>(g, n);
     }
-    g->gid0 = g->gidL[2];
     g->lab2 = dalloc<i32>(g, n);
-    g->d_gbase = dalloc<i64>(g, G + 1);
-    g->d_gcb = dalloc<i64>(g, G + 1);
-    g->d_first = dalloc<i64>(g, G);
-    g->d_accI = dalloc<i64>(g, G);
-    g->d_accS = dalloc<i64>(g, G);
-    g->d_shift = dalloc<i64>(g, G);
-    g->d_gvalid = dalloc<i64>(g, G);
-    g->d_m2g = dalloc<i64>(g, G);
-    g->d_gseed = dalloc<u64>(g, G);
-    g->d_glev = dalloc<i32>(g, G);
-    g->d_flag = dalloc<uint8_t>(g, G);
+    g->d_gbase = dalloc<i64>(g, P_cap + 1);
+    g->d_gcb = dalloc<i64>(g, P_cap + 1);
+    g->d_first = dalloc<i64>(g, P_cap);
+    g->d_accI = dalloc<i64>(g, P_cap);
+    g->d_accS = dalloc<i64>(g, P_cap);
+    g->d_shift = dalloc<i64>(g, P_cap);
+    g->d_gvalid = dalloc<i64>(g, P_cap);
+    g->d_m2p = dalloc<i64>(g, P_cap);
+    g->d_gseed = dalloc<u64>(g, P_cap);
+    g->d_glev = dalloc<i32>(g, P_cap);
+    g->d_newpos = dalloc<i32>(g, P_cap);
+}
+
+// Per-node position and M2 of the members at positions [p0, G).
+static void union_meta(slm_graph *g, int p0, i32 *gid, i32 *m2n)
+{
     i64 maxn = 0;
-    for (int i = 0; i < G; i++) maxn = std::max(maxn, g->base0[i + 1] - g->base0[i]);
-    HIPCHK(hipMemcpyAsync(g->d_gbase, g->base0.data(), sizeof(i64) * (G + 1),
-                          hipMemcpyHostToDevice, g->s));
-    HIPCHK(hipMemcpyAsync(g->d_m2g, g->m2g.data(), sizeof(i64) * G, hipMemcpyHostToDevice, g->s));
-    batch_meta(g->d_gbase, G, g->d_m2g, maxn, g->gidL[2], g->m2nL[2], g->s);
-    HIPCHK(hipStreamSynchronize(g->s));
+    for (int q = p0; q < g->G; q++) maxn = std::max(maxn, g->base[q + 1] - g->base[q]);
+    batch_meta(g->d_gbase, p0, g->G - p0, g->d_m2p, maxn, gid, m2n, g->s);
 }
 
 template <typename T>
@@ -564,143 +613,187 @@ static void to_host(std::vector<T> &h, const T *d, i64 count, hipStream_t s)
     HIPCHK(hipStreamSynchronize(s));
 }
 
-// All graphs of a batch through Algorithm 1 at once.  Graph g draws with
-// seeds[g]; its levels, rounds and labels are those of a run on its own:
-// its keys use its own M2, its draws its own seed, level and local node
-// numbers, and a graph whose round finds no valid move is left unchanged
-// by the rounds the others still need.  A graph leaves the union when its
-// level partition is the identity or it has emitted max_levels levels.
-static void batch_run(slm_graph *g, const slm_params *p, const u64 *seeds,
-                      std::vector<slm_result *> &res)
+// Appends members (with their level-0 CSRs) after the nodes of the current
+// level buffer; the caller runs setup_level.  Capacity is checked by the
+// caller.
+static void union_append(slm_graph *g, std::vector<Member> &add)
+{
+    if (add.empty()) return;
+    hipStream_t s = g->s;
+    if (g->cur < 0) g->cur = 0;  // a server union lives in the level buffers
+    i64 n_add = 0, e_add = 0;
+    for (const Member &m : add) {
+        n_add += m.n0;
+        e_add += m.nnz0;
+    }
+    std::vector<i64> rp_h(n_add + 1);
+    std::vector<int2> e_h(e_add);
+    i64 nb = g->n, eb = g->nnz, vi = 0, ej = 0;
+    const int p0 = g->G;
+    for (Member &m : add) {
+        for (i64 v = 0; v < m.n0; v++) rp_h[vi + v] = eb + ej + m.rp[v];
+        const i32 off = (i32)(nb + vi);
+        for (i64 j = 0; j < m.nnz0; j++) e_h[ej + j] = make_int2(m.col[j] + off, m.w[j]);
+        g->base.push_back(nb + vi + m.n0);
+        vi += m.n0;
+        ej += m.nnz0;
+        m.rp.clear();
+        m.rp.shrink_to_fit();
+        m.col.clear();
+        m.col.shrink_to_fit();
+        m.w.clear();
+        m.w.shrink_to_fit();
+        g->mem.push_back(std::move(m));
+    }
+    rp_h[n_add] = eb + e_add;
+    add.clear();
+    i64 *rp = g->rpL[g->cur];
+    int2 *e = g->eL[g->cur];
+    HIPCHK(hipMemcpyAsync(rp + nb, rp_h.data(), sizeof(i64) * (n_add + 1), hipMemcpyHostToDevice, s));
+    if (e_add)
+        HIPCHK(hipMemcpyAsync(e + eb, e_h.data(), sizeof(int2) * e_add, hipMemcpyHostToDevice, s));
+    g->G = (int)g->mem.size();
+    g->n = nb + n_add;
+    g->nnz = eb + e_add;
+    union_upload(g);  // also waits for the copies above
+    union_meta(g, p0, g->gidL[g->cur], g->m2nL[g->cur]);
+}
+
+// One level of Algorithm 1 for every member of the union, all in the same
+// launches.  Member q draws with its own seed and level; its keys use its own
+// M2.  A member whose round finds no valid move is unchanged by the rounds
+// the others still need, so its rounds and convergence are its own.  At the
+// end every member reads its community range from its first node, emits its
+// level (labels composed onto its original nodes, n_c, N_Q, Q, rounds,
+// converged), and leaves when the partition is the identity or max_levels is
+// reached; the others are contracted together (setup_level is left to the
+// caller, which may append members first).  Leaving members go to `done`.
+static void union_level(slm_graph *g, const slm_params *p, std::vector<Member> &done)
 {
     const int G = g->G;
     Work &W = g->W;
     hipStream_t s = g->s;
-    do_reset(g);
-    {
-        std::vector<u64> sd(G);
-        for (int i = 0; i < G; i++) sd[i] = seeds ? seeds[i] : p->seed;
-        HIPCHK(hipMemcpyAsync(g->d_gseed, sd.data(), sizeof(u64) * G, hipMemcpyHostToDevice, s));
-        launch_fill_i32(g->d_glev, 0, G, s);
-        HIPCHK(hipStreamSynchronize(s));
-    }
-    launch_iota_i32(g->composed, g->n0, s);
-    std::vector<char> alive(G);
-    std::vector<int> emitted(G, 0);
-    for (int i = 0; i < G; i++) {
-        alive[i] = g->base0[i + 1] > g->base0[i];
-        res[i]->n0 = g->base0[i + 1] - g->base0[i];
-    }
+    i64 nc;
+    level_start(g, &nc);
+    std::vector<i32> rounds(G, -1), conv(G, 0);
     std::vector<i64> hv, first, accI, accS;
-    std::vector<i32> comp_h;
-    int level = 0;
-    while (g->n > 0) {
-        i64 nc;
-        level_start(g, &nc);
-        std::vector<i32> rounds(G, -1), conv(G, 0);
-        int r = 0;
-        while (r < p->max_rounds) {
-            launch_fill_i64(g->d_gvalid, 0, G, s);
-            const i64 valid = level_round(g, p, level, r, &nc, nullptr,
-                                          (unsigned long long *)g->d_gvalid);
-            to_host(hv, g->d_gvalid, G, s);
-            for (int i = 0; i < G; i++)
-                if (alive[i] && rounds[i] < 0 && hv[i] == 0) {
-                    rounds[i] = r;
-                    conv[i] = 1;
-                }
-            if (valid == 0) break;
-            r++;
-        }
-        for (int i = 0; i < G; i++)
-            if (alive[i] && rounds[i] < 0) rounds[i] = r;
-        // community range of every graph: its first node holds its first label
-        batch_first_labels(W.lab, g->d_gbase, G, g->d_first, s);
-        to_host(first, g->d_first, G, s);
-        std::vector<i64> gcb(G + 1);
-        gcb[G] = nc;
-        for (int i = G - 1; i >= 0; i--) gcb[i] = first[i] >= 0 ? first[i] : gcb[i + 1];
-        std::vector<uint8_t> emit(G, 0);
-        std::vector<char> leave(G, 0);
-        bool any_emit = false;
-        for (int i = 0; i < G; i++) {
-            if (!alive[i]) continue;
-            const i64 nci = gcb[i + 1] - gcb[i], ni = g->base[i + 1] - g->base[i];
-            if (nci == ni) {
-                leave[i] = 1;  // the identity: not emitted
-                continue;
+    int r = 0;
+    while (r < p->max_rounds) {
+        launch_fill_i64(g->d_gvalid, 0, G, s);
+        const i64 valid = level_round(g, p, 0, r, &nc, nullptr, (unsigned long long *)g->d_gvalid);
+        to_host(hv, g->d_gvalid, G, s);
+        for (int q = 0; q < G; q++)
+            if (rounds[q] < 0 && hv[q] == 0) {
+                rounds[q] = r;
+                conv[q] = 1;
             }
-            emit[i] = 1;
-            any_emit = true;
-        }
-        if (any_emit) {
-            HIPCHK(hipMemcpyAsync(g->d_flag, emit.data(), G, hipMemcpyHostToDevice, s));
-            HIPCHK(hipMemcpyAsync(g->d_gcb, gcb.data(), sizeof(i64) * (G + 1),
-                                  hipMemcpyHostToDevice, s));
-            batch_compose(g->composed, W.lab, g->gid0, g->d_flag, g->n0, s);
-            modularity_graphs(W, view(g), g->bins, W.lab, nc, G, g->d_gcb, g->d_accI,
-                              g->d_accS, s);
-            to_host(accI, g->d_accI, G, s);
-            to_host(accS, g->d_accS, G, s);
-            to_host(comp_h, g->composed, g->n0, s);
-            for (int i = 0; i < G; i++) {
-                if (!emit[i]) continue;
-                slm_result *R = res[i];
-                const i64 b0 = g->base0[i], n0i = g->base0[i + 1] - b0;
-                std::vector<i32> lab(n0i);
-                for (i64 v = 0; v < n0i; v++) lab[v] = (i32)(comp_h[b0 + v] - gcb[i]);
-                const i64 m2 = g->m2g[i];
-                const i64 nq = m2 * accI[i] - accS[i];
-                R->labels.push_back(std::move(lab));
-                R->nc.push_back(gcb[i + 1] - gcb[i]);
-                R->nq.push_back(nq);
-                R->q.push_back((double)nq / (double)m2 / (double)m2);
-                R->rounds.push_back(rounds[i]);
-                R->conv.push_back(conv[i]);
-                emitted[i]++;
-                if (p->max_levels > 0 && emitted[i] >= p->max_levels) leave[i] = 1;
-            }
-        }
-        // the graphs that stay form the next level's union
-        std::vector<i64> shift(G, -1), nbase(G + 1, 0);
-        i64 gone = 0, nc2 = 0;
-        bool any = false;
-        for (int i = 0; i < G; i++) {
-            nbase[i] = nc2;
-            if (!alive[i]) continue;
-            const i64 nci = gcb[i + 1] - gcb[i];
-            if (leave[i]) {
-                alive[i] = 0;
-                gone += nci;
-                continue;
-            }
-            shift[i] = gone;
-            nc2 += nci;
-            any = true;
-        }
-        nbase[G] = nc2;
-        if (!any) break;
-        level++;
-        HIPCHK(hipMemcpyAsync(g->d_shift, shift.data(), sizeof(i64) * G, hipMemcpyHostToDevice, s));
-        const int dst = g->cur < 0 ? 0 : 1 - g->cur;
-        const int src = g->cur < 0 ? 2 : g->cur;
-        batch_relabel(W.lab, g->gidL[src], g->m2nL[src], g->d_shift, g->n, g->lab2,
-                      g->gidL[dst], g->m2nL[dst], s);
-        // composed labels of the graphs that stay become next-level node ids
-        batch_compose_shift(g->composed, g->gid0, g->d_shift, g->n0, s);
-        do_contract(g, g->lab2, nc2);
-        g->base = nbase;
-        batch_upload_base(g);
-        launch_fill_i32(g->d_glev, level, G, s);
+        if (valid == 0) break;
+        r++;
     }
-    HIPCHK(hipStreamSynchronize(s));
+    for (int q = 0; q < G; q++)
+        if (rounds[q] < 0) rounds[q] = r;
+    batch_first_labels(W.lab, g->d_gbase, G, g->d_first, s);
+    to_host(first, g->d_first, G, s);
+    std::vector<i64> gcb(G + 1);
+    gcb[G] = nc;
+    for (int q = G - 1; q >= 0; q--) gcb[q] = first[q] >= 0 ? first[q] : gcb[q + 1];
+    std::vector<char> emit(G, 0), leave(G, 0);
+    bool any_emit = false;
+    for (int q = 0; q < G; q++) {
+        if (gcb[q + 1] - gcb[q] == g->base[q + 1] - g->base[q]) leave[q] = 1;  // identity
+        else emit[q] = any_emit = true;
+    }
+    if (any_emit) {
+        HIPCHK(hipMemcpyAsync(g->d_gcb, gcb.data(), sizeof(i64) * (G + 1), hipMemcpyHostToDevice, s));
+        modularity_graphs(W, view(g), g->bins, W.lab, nc, G, g->d_gcb, g->d_accI, g->d_accS, s);
+        to_host(accI, g->d_accI, G, s);
+        to_host(accS, g->d_accS, G, s);
+        std::vector<i32> lab_h;
+        to_host(lab_h, W.lab, g->n, s);
+        for (int q = 0; q < G; q++) {
+            if (!emit[q]) continue;
+            Member &m = g->mem[q];
+            const i32 *lq = lab_h.data() + g->base[q];
+            const i32 c0 = (i32)gcb[q];
+            for (i64 v = 0; v < m.n0; v++) m.comp[v] = lq[m.comp[v]] - c0;
+            const i64 nq = m.m2 * accI[q] - accS[q];
+            slm_result *R = m.res;
+            R->labels.push_back(m.comp);
+            R->nc.push_back(gcb[q + 1] - gcb[q]);
+            R->nq.push_back(nq);
+            R->q.push_back((double)nq / (double)m.m2 / (double)m.m2);
+            R->rounds.push_back(rounds[q]);
+            R->conv.push_back(conv[q]);
+            m.level++;
+            if (p->max_levels > 0 && (int)R->nc.size() >= p->max_levels) leave[q] = 1;
+        }
+    }
+    // the members that stay form the next level's union, in order
+    std::vector<i64> shift(G, -1), nbase(1, 0);
+    std::vector<i32> newpos(G, -1);
+    std::vector<Member> stay;
+    i64 gone = 0, nc2 = 0;
+    for (int q = 0; q < G; q++) {
+        const i64 ncq = gcb[q + 1] - gcb[q];
+        if (leave[q]) {
+            gone += ncq;
+            done.push_back(std::move(g->mem[q]));
+            continue;
+        }
+        shift[q] = gone;
+        newpos[q] = (i32)stay.size();
+        nc2 += ncq;
+        nbase.push_back(nc2);
+        stay.push_back(std::move(g->mem[q]));
+    }
+    g->level++;
+    if (stay.empty()) {
+        g->mem.clear();
+        g->base.assign(1, 0);
+        g->G = 0;
+        g->n = g->nnz = 0;
+        return;
+    }
+    HIPCHK(hipMemcpyAsync(g->d_shift, shift.data(), sizeof(i64) * G, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(g->d_newpos, newpos.data(), sizeof(i32) * G, hipMemcpyHostToDevice, s));
+    const int dst = g->cur < 0 ? 0 : 1 - g->cur;
+    const int src = g->cur < 0 ? 2 : g->cur;
+    batch_relabel(W.lab, g->gidL[src], g->m2nL[src], g->d_shift, g->d_newpos, g->n, g->lab2,
+                  g->gidL[dst], g->m2nL[dst], s);
+    contract_only(g, g->lab2, nc2);
+    g->mem = std::move(stay);
+    g->base = std::move(nbase);
+    g->G = (int)g->mem.size();
+    union_upload(g);
+}
+
+// All members of a batch through Algorithm 1; results by batch index.
+static void batch_run(slm_graph *g, const slm_params *p, const u64 *seeds,
+                      std::vector<slm_result *> &res)
+{
+    do_reset(g);
+    for (int q = 0; q < g->G; q++) {
+        Member &m = g->mem[q];
+        m.seed = seeds ? seeds[m.ticket] : p->seed;
+        m.level = 0;
+        m.res = res[m.ticket];
+        m.res->n0 = m.n0;
+        m.comp.resize(m.n0);
+        for (i64 v = 0; v < m.n0; v++) m.comp[v] = (i32)v;
+    }
+    union_upload(g);
+    std::vector<Member> done;
+    while (g->G > 0 && g->n > 0) {
+        union_level(g, p, done);
+        if (g->G > 0) setup_level(g);
+    }
+    HIPCHK(hipStreamSynchronize(g->s));
 }
 
 // Device copy of a host CSR (entries already packed) and the level-0 state.
 static void init_from_host(slm_graph *g, const i64 *rp_h, const int2 *e_h)
 {
     alloc_work(g);
-    if (g->G > 0) alloc_batch(g);
     g->rp0 = dalloc<i64>(g, g->n0 + 1);
     g->e0 = dalloc<int2>(g, g->nnz0);
     HIPCHK(hipMemcpyAsync(g->rp0, rp_h, sizeof(i64) * (g->n0 + 1), hipMemcpyHostToDevice, g->s));
@@ -1009,7 +1102,7 @@ slm_status slm_modularity(slm_graph *g, const int32_t *lab_dev, int64_t n_c, int
 {
     API_BEGIN
     REQUIRE(g != nullptr, SLM_E_INVALID, "null handle");
-    REQUIRE(g->G == 0, SLM_E_STATE, "a batch reports modularity per graph through slm_batch_run");
+    REQUIRE(!g->is_union, SLM_E_STATE, "a batch reports modularity per graph through slm_batch_run");
     i64 v = 0;
     if (g->n > 0) {
         check_labels(g, lab_dev, n_c);
@@ -1024,7 +1117,7 @@ slm_status slm_contract(slm_graph *g, const int32_t *lab_dev, int64_t n_c)
 {
     API_BEGIN
     REQUIRE(g != nullptr, SLM_E_INVALID, "null handle");
-    REQUIRE(g->G == 0, SLM_E_STATE, "a batch contracts inside slm_batch_run");
+    REQUIRE(!g->is_union, SLM_E_STATE, "a batch contracts inside slm_batch_run");
     check_labels(g, lab_dev, n_c);
     do_contract(g, lab_dev, n_c);
     API_END
@@ -1036,7 +1129,7 @@ slm_status slm_run(slm_graph *g, const slm_params *p, slm_result **out)
     REQUIRE(g != nullptr && p != nullptr && out != nullptr, SLM_E_INVALID, "null argument");
     REQUIRE(p->accept_p <= (1ull << 32), SLM_E_INVALID, "accept_p must be at most 2^32");
     REQUIRE(p->max_rounds >= 0 && p->max_levels >= 0, SLM_E_INVALID, "negative cap");
-    REQUIRE(g->G == 0, SLM_E_STATE, "a batch handle runs with slm_batch_run");
+    REQUIRE(!g->is_union, SLM_E_STATE, "a batch handle runs with slm_batch_run");
     *out = nullptr;
     do_reset(g);
     slm_result *r = new slm_result();
@@ -1171,12 +1264,23 @@ slm_status slm_batch_create(int32_t count, const slm_graph_desc *graphs, int val
         HIPCHK(hipGetDevice(&g->device));
         g->n0 = g->n = N;
         g->nnz0 = g->nnz = NNZ;
-        g->G = count;
+        g->mem0.resize(count);
+        for (int i = 0; i < count; i++) {
+            Member &m = g->mem0[i];
+            m.ticket = (u64)i;
+            m.n0 = graphs[i].n;
+            m.nnz0 = graphs[i].nnz;
+            m.m2 = m2g[i];
+        }
         g->base0 = base0;
+        g->mem = g->mem0;
         g->base = base0;
-        g->m2g = m2g;
+        g->G = count;
+        alloc_union(g, count);
         init_from_host(g, rp_h.data(), e_h.data());
-        batch_set_draws(g, 0, 0);
+        union_upload(g);
+        union_meta(g, 0, g->gidL[2], g->m2nL[2]);
+        HIPCHK(hipStreamSynchronize(g->s));
         *out = g;
         return SLM_OK;
     } catch (const SlmError &e) {
@@ -1192,7 +1296,7 @@ slm_status slm_batch_size(const slm_graph *g, int32_t *count)
 {
     API_BEGIN
     REQUIRE(g != nullptr && count != nullptr, SLM_E_INVALID, "null argument");
-    *count = g->G;
+    *count = (int32_t)g->mem0.size();
     API_END
 }
 
@@ -1201,20 +1305,317 @@ slm_status slm_batch_run(slm_graph *g, const slm_params *p, const uint64_t *seed
 {
     API_BEGIN
     REQUIRE(g != nullptr && p != nullptr && outs != nullptr, SLM_E_INVALID, "null argument");
-    REQUIRE(g->G > 0, SLM_E_STATE, "not a batch handle (use slm_run)");
+    REQUIRE(g->is_union && !g->mem0.empty(), SLM_E_STATE, "not a batch handle (use slm_run)");
     REQUIRE(p->accept_p <= (1ull << 32), SLM_E_INVALID, "accept_p must be at most 2^32");
     REQUIRE(p->max_rounds >= 0 && p->max_levels >= 0, SLM_E_INVALID, "negative cap");
-    for (int i = 0; i < g->G; i++) outs[i] = nullptr;
-    std::vector<slm_result *> res(g->G, nullptr);
+    const int count = (int)g->mem0.size();
+    for (int i = 0; i < count; i++) outs[i] = nullptr;
+    std::vector<slm_result *> res(count, nullptr);
     try {
-        for (int i = 0; i < g->G; i++) res[i] = new slm_result();
+        for (int i = 0; i < count; i++) res[i] = new slm_result();
         batch_run(g, p, seeds, res);
     } catch (...) {
         for (slm_result *r : res) delete r;
         throw;
     }
-    for (int i = 0; i < g->G; i++) outs[i] = res[i];
+    for (int i = 0; i < count; i++) outs[i] = res[i];
     API_END
+}
+
+// ================================================================== serving
+}  // extern "C"
+
+// A lane: one union engine on its own stream, driven by its own thread.
+struct Lane {
+    slm_graph *eng = nullptr;
+    hipStream_t stream = nullptr;
+    std::thread th;
+    std::deque<Member> pending;
+    i64 cap_nodes = 0, cap_entries = 0;
+    int cap_members = 0;
+};
+
+struct slm_server {
+    slm_server_cfg cfg;
+    int device = 0;
+    std::vector<Lane *> lanes;
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::unordered_map<u64, slm_result *> done;
+    std::unordered_map<u64, std::string> failed;
+    std::unordered_set<u64> open;  // submitted and not yet delivered
+    u64 next_ticket = 1;
+    bool stop = false;
+    i64 submitted = 0, completed = 0;
+};
+
+// An empty union engine with room for cap_n nodes, cap_e entries and cap_m
+// members at level 0 (contraction never grows a level).
+static slm_graph *make_engine(i64 cap_n, i64 cap_e, int cap_m, hipStream_t s)
+{
+    slm_graph *g = new slm_graph();
+    try {
+        g->s = s;
+        HIPCHK(hipGetDevice(&g->device));
+        g->n0 = cap_n;
+        g->nnz0 = cap_e;
+        alloc_work(g);
+        alloc_union(g, cap_m);
+        HIPCHK(hipEventCreate(&g->ev0));
+        HIPCHK(hipEventCreate(&g->ev1));
+        g->n = g->nnz = 0;
+        g->G = 0;
+        g->base.assign(1, 0);
+        g->cur = 0;
+        g->level = 1;  // strengths of later levels never reset M2
+    } catch (...) {
+        slm_destroy(g);
+        throw;
+    }
+    return g;
+}
+
+// A failed level leaves the lane's graphs undefined: fail all of them.
+static void lane_fail(slm_server *sv, Lane *L, const std::string &msg)
+{
+    slm_graph *g = L->eng;
+    std::lock_guard<std::mutex> lk(sv->mu);
+    for (Member &m : g->mem) {
+        sv->failed[m.ticket] = msg;
+        delete m.res;
+    }
+    for (Member &m : L->pending) {
+        sv->failed[m.ticket] = msg;
+        delete m.res;
+    }
+    g->mem.clear();
+    L->pending.clear();
+    g->G = 0;
+    sv->cv_done.notify_all();
+}
+
+// Lane loop: at every level boundary admit queued requests (in order, while
+// they fit the lane's free capacity), run one level for every resident
+// graph in the same launches, and hand finished graphs to their tickets.
+static void lane_loop(slm_server *sv, Lane *L)
+{
+    (void)hipSetDevice(sv->device);
+    slm_graph *g = L->eng;
+    std::vector<Member> done;
+    try {
+        while (true) {
+            std::vector<Member> add;
+            {
+                std::unique_lock<std::mutex> lk(sv->mu);
+                sv->cv_work.wait(lk, [&] { return sv->stop || !L->pending.empty() || g->G > 0; });
+                if (sv->stop && g->G == 0) break;
+                i64 n = g->n, e = g->nnz;
+                int G = g->G;
+                while (!sv->stop && !L->pending.empty()) {
+                    const Member &m = L->pending.front();
+                    if (G + 1 > L->cap_members || n + m.n0 > L->cap_nodes ||
+                        e + m.nnz0 > L->cap_entries)
+                        break;
+                    n += m.n0;
+                    e += m.nnz0;
+                    G++;
+                    add.push_back(std::move(L->pending.front()));
+                    L->pending.pop_front();
+                }
+            }
+            if (!add.empty()) union_append(g, add);
+            if (g->G == 0) continue;
+            if (g->n == 0) {  // only graphs without nodes: no level
+                for (Member &m : g->mem) done.push_back(std::move(m));
+                g->mem.clear();
+                g->base.assign(1, 0);
+                g->G = 0;
+            } else {
+                setup_level(g);
+                union_level(g, &sv->cfg.params, done);
+            }
+            if (!done.empty()) {
+                std::lock_guard<std::mutex> lk(sv->mu);
+                for (Member &m : done) {
+                    sv->done[m.ticket] = m.res;
+                    sv->completed++;
+                }
+                done.clear();
+                sv->cv_done.notify_all();
+            }
+        }
+    } catch (const SlmError &e) {
+        lane_fail(sv, L, e.msg);
+    } catch (const std::exception &e) {
+        lane_fail(sv, L, std::string("host failure: ") + e.what());
+    }
+}
+
+extern "C" {
+
+slm_status slm_server_create(const slm_server_cfg *cfg, slm_server **out)
+{
+    slm_server *sv = nullptr;
+    try {
+        REQUIRE(cfg != nullptr && out != nullptr, SLM_E_INVALID, "null argument");
+        *out = nullptr;
+        REQUIRE(cfg->lanes == 1 || cfg->lanes == 2, SLM_E_INVALID, "lanes must be 1 or 2");
+        REQUIRE(cfg->node_capacity >= 0 && cfg->entry_capacity >= 0 && cfg->max_members >= 0,
+                SLM_E_INVALID, "negative capacity");
+        REQUIRE(cfg->params.accept_p <= (1ull << 32), SLM_E_INVALID, "accept_p must be at most 2^32");
+        REQUIRE(cfg->params.max_rounds >= 0 && cfg->params.max_levels >= 0, SLM_E_INVALID,
+                "negative cap");
+        sv = new slm_server();
+        sv->cfg = *cfg;
+        if (sv->cfg.node_capacity == 0) sv->cfg.node_capacity = (i64)1 << 22;
+        if (sv->cfg.entry_capacity == 0) sv->cfg.entry_capacity = (i64)1 << 26;
+        if (sv->cfg.max_members == 0) sv->cfg.max_members = 4096;
+        REQUIRE(sv->cfg.node_capacity < ((i64)1 << 31) - 1, SLM_E_OVERFLOW, "node capacity too large");
+        HIPCHK(hipGetDevice(&sv->device));
+        for (int l = 0; l < sv->cfg.lanes; l++) {
+            Lane *L = new Lane();
+            sv->lanes.push_back(L);
+            HIPCHK(hipStreamCreate(&L->stream));
+            L->cap_nodes = sv->cfg.node_capacity;
+            L->cap_entries = sv->cfg.entry_capacity;
+            L->cap_members = sv->cfg.max_members;
+            L->eng = make_engine(L->cap_nodes, L->cap_entries, L->cap_members, L->stream);
+        }
+        for (Lane *L : sv->lanes) L->th = std::thread(lane_loop, sv, L);
+        *out = sv;
+        return SLM_OK;
+    } catch (const SlmError &e) {
+        if (sv) slm_server_destroy(sv);
+        return fail(e);
+    } catch (const std::bad_alloc &) {
+        if (sv) slm_server_destroy(sv);
+        return fail(SlmError{SLM_E_NOMEM, "host allocation failed"});
+    }
+}
+
+slm_status slm_server_submit(slm_server *sv, const slm_graph_desc *d, uint64_t seed,
+                             uint64_t *ticket)
+{
+    API_BEGIN
+    REQUIRE(sv != nullptr && d != nullptr && ticket != nullptr, SLM_E_INVALID, "null argument");
+    REQUIRE(d->n >= 0 && d->nnz >= 0 && d->row_ptr != nullptr, SLM_E_INVALID, "bad graph");
+    REQUIRE(d->nnz == 0 || (d->col && d->w), SLM_E_INVALID, "null col or w");
+    const int lane = (sv->cfg.lanes == 2 && d->n > sv->cfg.large_nodes) ? 1 : 0;
+    Lane *L = sv->lanes[lane];
+    REQUIRE(d->n <= L->cap_nodes && d->nnz <= L->cap_entries, SLM_E_NOMEM,
+            "the graph exceeds the capacity of its lane");
+    Member m;
+    m.n0 = d->n;
+    m.nnz0 = d->nnz;
+    m.rp.assign(d->row_ptr, d->row_ptr + d->n + 1);
+    if (sv->cfg.validate) {
+        validate_host(d->n, d->nnz, m.rp, d->col, d->w, &m.m2);
+    } else {
+        REQUIRE(m.rp[0] == 0 && m.rp[d->n] == d->nnz, SLM_E_INVALID,
+                "row_ptr must start at 0 and end at nnz");
+        for (i64 j = 0; j < d->nnz; j++) m.m2 += d->w[j];
+    }
+    REQUIRE(m.m2 < ((i64)1 << 31), SLM_E_OVERFLOW, "total weight M2 must be below 2^31");
+    m.col.assign(d->col, d->col + d->nnz);
+    m.w.assign(d->w, d->w + d->nnz);
+    m.seed = seed;
+    m.comp.resize(d->n);
+    for (i64 v = 0; v < d->n; v++) m.comp[v] = (i32)v;
+    m.res = new slm_result();
+    m.res->n0 = d->n;
+    {
+        std::lock_guard<std::mutex> lk(sv->mu);
+        REQUIRE(!sv->stop, SLM_E_STATE, "the server is stopping");
+        m.ticket = sv->next_ticket++;
+        *ticket = m.ticket;
+        sv->open.insert(m.ticket);
+        L->pending.push_back(std::move(m));
+        sv->submitted++;
+    }
+    sv->cv_work.notify_all();
+    API_END
+}
+
+static slm_status take_result(slm_server *sv, uint64_t ticket, slm_result **out, bool wait)
+{
+    std::unique_lock<std::mutex> lk(sv->mu);
+    while (true) {
+        if (!sv->open.count(ticket)) {
+            g_err = "unknown or already delivered ticket";
+            return SLM_E_INVALID;
+        }
+        auto it = sv->done.find(ticket);
+        if (it != sv->done.end()) {
+            *out = it->second;
+            sv->done.erase(it);
+            sv->open.erase(ticket);
+            return SLM_OK;
+        }
+        auto f = sv->failed.find(ticket);
+        if (f != sv->failed.end()) {
+            g_err = f->second;
+            sv->failed.erase(f);
+            sv->open.erase(ticket);
+            return SLM_E_DEVICE;
+        }
+        if (!wait) {
+            *out = nullptr;
+            return SLM_OK;
+        }
+        sv->cv_done.wait(lk);
+    }
+}
+
+slm_status slm_server_poll(slm_server *sv, uint64_t ticket, slm_result **out)
+{
+    API_BEGIN
+    REQUIRE(sv != nullptr && out != nullptr, SLM_E_INVALID, "null argument");
+    return take_result(sv, ticket, out, false);
+    API_END
+}
+
+slm_status slm_server_wait(slm_server *sv, uint64_t ticket, slm_result **out)
+{
+    API_BEGIN
+    REQUIRE(sv != nullptr && out != nullptr, SLM_E_INVALID, "null argument");
+    return take_result(sv, ticket, out, true);
+    API_END
+}
+
+slm_status slm_server_stats(slm_server *sv, int64_t *submitted, int64_t *completed,
+                            int64_t *reserved_bytes)
+{
+    API_BEGIN
+    REQUIRE(sv != nullptr, SLM_E_INVALID, "null argument");
+    std::lock_guard<std::mutex> lk(sv->mu);
+    if (submitted) *submitted = sv->submitted;
+    if (completed) *completed = sv->completed;
+    if (reserved_bytes) {
+        i64 b = 0;
+        for (Lane *L : sv->lanes) b += L->eng ? L->eng->reserved : 0;
+        *reserved_bytes = b;
+    }
+    API_END
+}
+
+void slm_server_destroy(slm_server *sv)
+{
+    if (!sv) return;
+    {
+        std::lock_guard<std::mutex> lk(sv->mu);
+        sv->stop = true;
+    }
+    sv->cv_work.notify_all();
+    for (Lane *L : sv->lanes)
+        if (L->th.joinable()) L->th.join();
+    for (Lane *L : sv->lanes) {
+        for (Member &m : L->pending) delete m.res;
+        if (L->eng) slm_destroy(L->eng);
+        if (L->stream) (void)hipStreamDestroy(L->stream);
+        delete L;
+    }
+    for (auto &kv : sv->done) delete kv.second;
+    delete sv;
 }
 
 }  // extern "C"

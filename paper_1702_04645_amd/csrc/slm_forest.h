@@ -153,11 +153,7 @@ void run_strength_binned(const i64 *rp, const int2 *e, const Bins &Bn, i32 *k, i
 
 // ---------------------------------------------------------------- batches
 void batch_first_labels(const i32 *lab, const i64 *gbase, int G, i64 *first, hipStream_t s);
-void batch_compose(i32 *composed, const i32 *lab, const i32 *gid0, const uint8_t *flag, i64 n0,
-                   hipStream_t s);
-void batch_compose_shift(i32 *composed, const i32 *gid0, const i64 *shift, i64 n0,
-                         hipStream_t s);
-void batch_relabel(const i32 *lab, const i32 *gid, const i32 *m2n, const i64 *shift, i64 n,
-                   i32 *lab2, i32 *gid2, i32 *m2n2, hipStream_t s);
-void batch_meta(const i64 *gbase, int G, const i64 *m2g, i64 max_nodes, i32 *gid, i32 *m2n,
-                hipStream_t s);
+void batch_relabel(const i32 *lab, const i32 *gid, const i32 *m2n, const i64 *shift,
+                   const i32 *newpos, i64 n, i32 *lab2, i32 *gid2, i32 *m2n2, hipStream_t s);
+void batch_meta(const i64 *gbase, int p0, int count, const i64 *m2p, i64 max_nodes, i32 *gid,
+                i32 *m2n, hipStream_t s);

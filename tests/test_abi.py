@@ -84,3 +84,15 @@ def test_batch_arguments_are_rejected_without_a_device():
     short = (np.array([0, 1, 1], np.int64), np.array([1, 0], np.int32), np.array([1, 1], np.int32))
     d = descs(short)
     assert lib.slm_batch_create(1, d, 0, None, C.byref(h)) == slm.SLM_E_INVALID
+
+
+def test_server_arguments_are_rejected_without_a_device():
+    import paper_1702_04645_amd as slm
+    lib = slm.lib()
+    h = C.c_void_p()
+    for lanes, ncap in ((3, 0), (0, 0), (1, -5)):
+        cfg = slm._ServerCfg(ncap, 0, 0, lanes, 0, 1, 0, slm.params())
+        assert lib.slm_server_create(C.byref(cfg), C.byref(h)) == slm.SLM_E_INVALID
+    bad = slm.params(accept_p=(1 << 32) + 1)
+    cfg = slm._ServerCfg(0, 0, 0, 1, 0, 1, 0, bad)
+    assert lib.slm_server_create(C.byref(cfg), C.byref(h)) == slm.SLM_E_INVALID
