@@ -201,6 +201,103 @@ def batch_bench(args):
     print(json.dumps(out), flush=True)
 
 
+def _gen_rmat(seed):
+    import graphgen as gg
+    return gg.rmat(20, 16, 0.57, 0.19, 0.19, seed)
+
+
+def serve_bench(args):
+    """Serving: Poisson arrivals at a fixed rate of graphs from the batch
+    family plus, one request in 200, an R-MAT scale-20 graph; two lanes
+    (R-MAT graphs take the second), admission by lane capacity at level
+    boundaries.  Latency is measured by the library from submission to the
+    end of the request's last level."""
+    import multiprocessing as mp
+    import threading
+    import graphgen as gg
+    count, rate = args.serve_count, args.serve_rate
+    seed = gg.CONFIG_SEEDS["serve"]
+    rg = np.random.default_rng(seed)
+    is_rmat = rg.random(count) < 1.0 / 200.0
+    arrive = np.cumsum(rg.exponential(1.0 / rate, count))
+    procs = max(1, min(16, os.cpu_count() or 1))
+    t = time.time()
+    small_idx = [i for i in range(count) if not is_rmat[i]]
+    rmat_seeds = [gg.batch_member_seed(seed, 100000 + j) for j in range(min(4, int(is_rmat.sum())))]
+    with mp.get_context("fork").Pool(procs) as pool:
+        small = pool.map(_gen_member, [(seed, i, count) for i in small_idx], chunksize=8)
+        rmats = pool.map(_gen_rmat, rmat_seeds) if rmat_seeds else []
+    graphs = [None] * count
+    for i, gph in zip(small_idx, small):
+        graphs[i] = gph
+    j = 0
+    for i in range(count):
+        if is_rmat[i]:
+            graphs[i] = rmats[j % len(rmats)]
+            j += 1
+    seeds = [gg.batch_member_seed(args.seed, i) for i in range(count)]
+    log("serve: %d requests (%d R-MAT) at %.0f/s, generated in %.1fs"
+        % (count, int(is_rmat.sum()), rate, time.time() - t))
+
+    import torch
+    import paper_1702_04645_amd as slm
+    sv = slm.Server(lanes=args.serve_lanes, large_lanes=1, large_nodes=200_000,
+                    node_capacity=1 << 23, entry_capacity=1 << 28, max_members=4096,
+                    validate=False)
+    tickets = [None] * count
+    t0 = time.perf_counter()
+    for i in range(count):
+        dt = arrive[i] - (time.perf_counter() - t0)
+        if dt > 0:
+            time.sleep(dt)
+        tickets[i] = sv.submit(*graphs[i], seed=seeds[i])
+    t_sub = time.perf_counter() - t0
+    log("submitted in %.1fs" % t_sub)
+    lat = np.zeros(count)
+    levels = 0
+    for i in range(count):
+        res, lat[i] = sv.wait_timed(tickets[i])
+        levels += len(res)
+        if is_rmat[i] or i % 500 == 499:
+            log("request %d done (%s): %.1f ms" % (i, "R-MAT" if is_rmat[i] else "small",
+                                                  lat[i] * 1e3))
+    t_all = time.perf_counter() - t0
+    st = sv.stats()
+    sv.close()
+
+    def pct(x, q):
+        return round(float(np.percentile(x, q)) * 1e3, 3) if x.size else None
+    small_l, rmat_l = lat[~is_rmat], lat[is_rmat]
+    out = {
+        "metric": "served graphs/s; p50/p99 latency",
+        "value": round(count / t_all, 2),
+        "unit": "graphs/s",
+        "n_gpus": 1,
+        "steps": 1,
+        "warmup": 0,
+        "ms_per_step": round(t_all * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int64",
+        "data": "synthetic",
+        "config": dict(workload="serve", requests=count, rate_per_s=rate, rmat_share="1/200",
+                       small="batch family, n in [64, 65536]", lanes=args.serve_lanes,
+                       large_lanes=1,
+                       lane_capacity=dict(nodes=1 << 23, entries=1 << 28, members=4096),
+                       seed=seed, emitted_levels=levels),
+        "p50_ms": pct(lat, 50),
+        "p99_ms": pct(lat, 99),
+        "small_p50_ms": pct(small_l, 50),
+        "small_p99_ms": pct(small_l, 99),
+        "rmat_p50_ms": pct(rmat_l, 50),
+        "rmat_max_ms": round(float(rmat_l.max()) * 1e3, 3) if rmat_l.size else None,
+        "submit_span_s": round(t_sub, 3),
+        "reserved_hbm_gb": round(st["reserved_bytes"] / 1e9, 2),
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -212,6 +309,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--batch-count", type=int, default=2048)
     ap.add_argument("--plain-sample", type=int, default=128)
+    ap.add_argument("--serve-count", type=int, default=2000)
+    ap.add_argument("--serve-rate", type=float, default=400.0)
+    ap.add_argument("--serve-lanes", type=int, default=4)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -220,6 +320,8 @@ def main():
     rank = int(os.environ.get("RANK", "0"))
     if args.workload == "batch2048":
         return batch_bench(args)
+    if args.workload == "serve":
+        return serve_bench(args)
 
     import torch
     import paper_1702_04645_amd as slm

@@ -181,6 +181,9 @@ slm_status slm_result_num_levels(const slm_result *r, int32_t *levels);
 slm_status slm_result_level(const slm_result *r, int32_t level, int64_t *n_c,
                             const int32_t **labels, int64_t *nq, double *q,
                             int32_t *rounds, int32_t *converged);
+/* For a served request: steady-clock times (ns) of its submission and of
+ * the end of its last level; 0 for results of slm_run / slm_batch_run. */
+slm_status slm_result_times(const slm_result *r, int64_t *submit_ns, int64_t *done_ns);
 void slm_result_free(slm_result *r);
 
 /* ---------------------------------------------------------------- batches
@@ -227,9 +230,11 @@ slm_status slm_batch_run(slm_graph *g, const slm_params *p, const uint64_t *seed
  * capacity, runs one level for all resident graphs in the same launches, and
  * hands finished graphs to their tickets.  A graph keeps its CSR and labels
  * in HBM for its whole run.  Each result is the one slm_run gives for that
- * graph alone with the request's seed, whatever else is resident.  With two
- * lanes, graphs above large_nodes nodes use the second lane, so long runs of
- * large graphs overlap on the device with the stream of small ones.  The
+ * graph alone with the request's seed, whatever else is resident.  Lanes of
+ * one class (small or large graphs) take requests from one shared queue, so
+ * a lane held by a long level does not hold up arrivals while another lane
+ * of its class reaches a level boundary; large graphs get lanes of their own
+ * so their long levels overlap on the device with the small ones.  The
  * serving loop is an extension for throughput and latency; the paper runs
  * one graph at a time. */
 typedef struct slm_server slm_server;
@@ -238,10 +243,10 @@ typedef struct {
     int64_t node_capacity;   /* nodes resident at once per lane (0: 2^22)       */
     int64_t entry_capacity;  /* CSR entries resident at once per lane (0: 2^26) */
     int32_t max_members;     /* graphs resident at once per lane (0: 4096)      */
-    int32_t lanes;           /* 1 or 2                                          */
-    int64_t large_nodes;     /* with 2 lanes: graphs with more nodes use lane 1 */
+    int32_t lanes;           /* lanes in all, 1..16                             */
+    int64_t large_nodes;     /* graphs with more nodes are "large"              */
+    int32_t large_lanes;     /* lanes kept for large graphs (0: one queue for all) */
     int32_t validate;        /* check every submitted CSR                       */
-    int32_t reserved;
     slm_params params;       /* accept_p, max_rounds, max_levels of every run   */
 } slm_server_cfg;
 

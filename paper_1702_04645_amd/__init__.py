@@ -74,6 +74,7 @@ def lib():
         "slm_result_level": (st, [P, i32, pi64, C.POINTER(C.POINTER(C.c_int32)), pi64,
                                   C.POINTER(C.c_double), pi32, pi32]),
         "slm_result_free": (None, [P]),
+        "slm_result_times": (st, [P, pi64, pi64]),
         "slm_timing_enable": (st, [P, C.c_int]),
         "slm_timing_read": (st, [P, C.POINTER(C.c_double), pi64, pi64, pi64]),
         "slm_last_error": (C.c_char_p, []),
@@ -356,20 +357,20 @@ class Batch(Graph):
 class _ServerCfg(C.Structure):
     _fields_ = [("node_capacity", C.c_int64), ("entry_capacity", C.c_int64),
                 ("max_members", C.c_int32), ("lanes", C.c_int32), ("large_nodes", C.c_int64),
-                ("validate", C.c_int32), ("reserved", C.c_int32), ("params", Params)]
+                ("large_lanes", C.c_int32), ("validate", C.c_int32), ("params", Params)]
 
 
 class Server:
     """Serving loop of the library: requests run as they arrive, admitted at
-    level boundaries while they fit a lane's capacity; one or two lanes
-    (graphs above ``large_nodes`` nodes take the second)."""
+    level boundaries while they fit a lane's capacity.  ``lanes`` lanes in
+    all, ``large_lanes`` of them for graphs above ``large_nodes`` nodes."""
 
     def __init__(self, node_capacity: int = 0, entry_capacity: int = 0, max_members: int = 0,
-                 lanes: int = 1, large_nodes: int = 1 << 62, validate: bool = True,
-                 p: Params | None = None):
+                 lanes: int = 1, large_nodes: int = 1 << 62, large_lanes: int = 0,
+                 validate: bool = True, p: Params | None = None):
         self._h = C.c_void_p()
         cfg = _ServerCfg(node_capacity, entry_capacity, max_members, lanes, large_nodes,
-                         int(validate), 0, p if p is not None else params())
+                         large_lanes, int(validate), p if p is not None else params())
         _check(lib().slm_server_create(C.byref(cfg), C.byref(self._h)))
         self._n0 = {}
 
@@ -395,6 +396,14 @@ class Server:
         res = C.c_void_p()
         _check(lib().slm_server_wait(self._h, ticket, C.byref(res)))
         return _take_result(res, self._n0.pop(ticket))
+
+    def wait_timed(self, ticket: int):
+        """(levels, seconds from submission to the end of the last level)."""
+        res = C.c_void_p()
+        _check(lib().slm_server_wait(self._h, ticket, C.byref(res)))
+        a, b = C.c_int64(), C.c_int64()
+        _check(lib().slm_result_times(res, C.byref(a), C.byref(b)))
+        return _take_result(res, self._n0.pop(ticket)), (b.value - a.value) / 1e9
 
     def stats(self):
         a, b, c = C.c_int64(), C.c_int64(), C.c_int64()

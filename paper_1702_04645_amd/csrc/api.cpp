@@ -4,6 +4,9 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdio>
+#include <cstdlib>
+#include <chrono>
 #include <condition_variable>
 #include <deque>
 #include <mutex>
@@ -21,6 +24,7 @@ static thread_local std::string g_err;
 
 struct slm_result {
     i64 n0 = 0;
+    i64 t_submit_ns = 0, t_done_ns = 0;  // served requests: steady-clock times
     std::vector<i64> nc, nq;
     std::vector<double> q;
     std::vector<i32> rounds, conv;
@@ -121,22 +125,26 @@ static LevelView view(slm_graph *g)
     return L;
 }
 
-static void free_bins(slm_graph *g)
+// Device buffers that only grow.
+template <typename T>
+static void grow_buf(T *&p, i64 &cap, i64 need)
+{
+    if (need <= cap) return;
+    if (p) HIPCHK(hipFree(p));
+    p = nullptr;
+    const i64 c = need + need / 2 + 64;
+    HIPCHK(hipMalloc(&p, sizeof(T) * c));
+    cap = c;
+}
+
+static void release_bins(slm_graph *g)
 {
     Bins &B = g->bins;
     for (void *p : {(void *)B.hub_tab_off, (void *)B.chunk_hub, (void *)B.chunk_beg,
-                    (void *)B.chunk_off_of_hub, (void *)B.tile_hub, (void *)B.tile_off_of_hub})
+                    (void *)B.chunk_off_of_hub, (void *)B.tile_hub, (void *)B.tile_off_of_hub,
+                    (void *)B.span})
         if (p) (void)hipFree(p);
-    B.tile_hub = nullptr;
-    B.tile_off_of_hub = nullptr;
-    B.ntile = 0;
-    B.hub_tab_off = nullptr;
-    B.chunk_hub = nullptr;
-    B.chunk_beg = nullptr;
-    B.chunk_off_of_hub = nullptr;
-    B.nhub = 0;
-    B.nchunk = 0;
-    B.table_total = 0;
+    B = Bins();
 }
 
 static void grow_i32(i32 *&p, i64 &cap, i64 need)
@@ -155,7 +163,10 @@ static void setup_level(slm_graph *g)
     hipStream_t s = g->s;
     Work &W = g->W;
     Bins &B = g->bins;
-    free_bins(g);
+    B.nhub = 0;
+    B.nchunk = 0;
+    B.ntile = 0;
+    B.table_total = 0;
     const i64 n = g->n;
     const i64 *rp = g->cur < 0 ? g->rp0 : g->rpL[g->cur];
     const int2 *e = g->cur < 0 ? g->e0 : g->eL[g->cur];
@@ -171,14 +182,12 @@ static void setup_level(slm_graph *g)
         B.nhub = (i32)nhub;
         B.hub_node = B.nodes + B.off[BIN_HUB];
         if (nhub > 0) {
-            i64 *span_d = nullptr;
-            HIPCHK(hipMalloc(&span_d, sizeof(i64) * 2 * nhub));
-            launch_hub_degrees(rp, B.hub_node, (i32)nhub, span_d, s);
+            grow_buf(B.span, B.cap_span, 2 * nhub);
+            launch_hub_degrees(rp, B.hub_node, (i32)nhub, B.span, s);
             std::vector<i64> span(2 * nhub);
-            HIPCHK(hipMemcpyAsync(span.data(), span_d, sizeof(i64) * 2 * nhub,
+            HIPCHK(hipMemcpyAsync(span.data(), B.span, sizeof(i64) * 2 * nhub,
                                   hipMemcpyDeviceToHost, s));
             HIPCHK(hipStreamSynchronize(s));
-            HIPCHK(hipFree(span_d));
             std::vector<i64> tab_off(nhub + 1, 0);
             std::vector<i32> chunk_first(nhub + 1, 0);
             std::vector<i32> chunk_hub;
@@ -201,8 +210,8 @@ static void setup_level(slm_graph *g)
             chunk_first[nhub] = (i32)chunk_hub.size();
             tile_first[nhub] = (i32)tile_hub.size();
             B.ntile = (i64)tile_hub.size();
-            HIPCHK(hipMalloc(&B.tile_hub, sizeof(i32) * B.ntile));
-            HIPCHK(hipMalloc(&B.tile_off_of_hub, sizeof(i32) * (nhub + 1)));
+            grow_buf(B.tile_hub, B.cap_tile_hub, B.ntile);
+            grow_buf(B.tile_off_of_hub, B.cap_tile_off, nhub + 1);
             HIPCHK(hipMemcpyAsync(B.tile_hub, tile_hub.data(), sizeof(i32) * B.ntile,
                                   hipMemcpyHostToDevice, s));
             HIPCHK(hipMemcpyAsync(B.tile_off_of_hub, tile_first.data(), sizeof(i32) * (nhub + 1),
@@ -216,10 +225,10 @@ static void setup_level(slm_graph *g)
             }
             B.nchunk = (i64)chunk_hub.size();
             B.table_total = tab_off[nhub];
-            HIPCHK(hipMalloc(&B.hub_tab_off, sizeof(i64) * (nhub + 1)));
-            HIPCHK(hipMalloc(&B.chunk_off_of_hub, sizeof(i32) * (nhub + 1)));
-            HIPCHK(hipMalloc(&B.chunk_hub, sizeof(i32) * B.nchunk));
-            HIPCHK(hipMalloc(&B.chunk_beg, sizeof(i64) * B.nchunk));
+            grow_buf(B.hub_tab_off, B.cap_tab_off, nhub + 1);
+            grow_buf(B.chunk_off_of_hub, B.cap_chunk_off, nhub + 1);
+            grow_buf(B.chunk_hub, B.cap_chunk_hub, B.nchunk);
+            grow_buf(B.chunk_beg, B.cap_chunk_beg, B.nchunk);
             HIPCHK(hipMemcpyAsync(B.hub_tab_off, tab_off.data(), sizeof(i64) * (nhub + 1),
                                   hipMemcpyHostToDevice, s));
             HIPCHK(hipMemcpyAsync(B.chunk_off_of_hub, chunk_first.data(), sizeof(i32) * (nhub + 1),
@@ -828,7 +837,7 @@ void slm_destroy(slm_graph *g)
 {
     if (!g) return;
     (void)hipStreamSynchronize(g->s);
-    free_bins(g);
+    release_bins(g);
     for (void *p : g->allocs) (void)hipFree(p);
     Work &W = g->W;
     for (void *p : {(void *)W.W, (void *)W.hist, (void *)W.hub_keys, (void *)W.hub_vals,
@@ -1190,6 +1199,15 @@ slm_status slm_result_level(const slm_result *r, int32_t level, int64_t *n_c,
     API_END
 }
 
+slm_status slm_result_times(const slm_result *r, int64_t *submit_ns, int64_t *done_ns)
+{
+    API_BEGIN
+    REQUIRE(r != nullptr, SLM_E_INVALID, "null result");
+    if (submit_ns) *submit_ns = r->t_submit_ns;
+    if (done_ns) *done_ns = r->t_done_ns;
+    API_END
+}
+
 void slm_result_free(slm_result *r)
 {
     delete r;
@@ -1330,7 +1348,8 @@ struct Lane {
     slm_graph *eng = nullptr;
     hipStream_t stream = nullptr;
     std::thread th;
-    std::deque<Member> pending;
+    std::deque<Member> *queue = nullptr;  // the queue of its class (small or large graphs)
+    bool dead = false;                    // stopped after a failure
     i64 cap_nodes = 0, cap_entries = 0;
     int cap_members = 0;
 };
@@ -1339,6 +1358,7 @@ struct slm_server {
     slm_server_cfg cfg;
     int device = 0;
     std::vector<Lane *> lanes;
+    std::deque<Member> q_small, q_large;  // requests not yet admitted
     std::mutex mu;
     std::condition_variable cv_work, cv_done;
     std::unordered_map<u64, slm_result *> done;
@@ -1351,6 +1371,13 @@ struct slm_server {
 
 // An empty union engine with room for cap_n nodes, cap_e entries and cap_m
 // members at level 0 (contraction never grows a level).
+static i64 now_ns()
+{
+    return (i64)std::chrono::duration_cast<std::chrono::nanoseconds>(
+               std::chrono::steady_clock::now().time_since_epoch())
+        .count();
+}
+
 static slm_graph *make_engine(i64 cap_n, i64 cap_e, int cap_m, hipStream_t s)
 {
     slm_graph *g = new slm_graph();
@@ -1384,13 +1411,19 @@ static void lane_fail(slm_server *sv, Lane *L, const std::string &msg)
         sv->failed[m.ticket] = msg;
         delete m.res;
     }
-    for (Member &m : L->pending) {
-        sv->failed[m.ticket] = msg;
-        delete m.res;
-    }
     g->mem.clear();
-    L->pending.clear();
     g->G = 0;
+    L->dead = true;
+    // with no live lane left for its class, the class queue fails too
+    bool live = false;
+    for (Lane *o : sv->lanes) live |= (!o->dead && o->queue == L->queue);
+    if (!live) {
+        for (Member &m : *L->queue) {
+            sv->failed[m.ticket] = msg;
+            delete m.res;
+        }
+        L->queue->clear();
+    }
     sv->cv_done.notify_all();
 }
 
@@ -1407,22 +1440,23 @@ static void lane_loop(slm_server *sv, Lane *L)
             std::vector<Member> add;
             {
                 std::unique_lock<std::mutex> lk(sv->mu);
-                sv->cv_work.wait(lk, [&] { return sv->stop || !L->pending.empty() || g->G > 0; });
+                sv->cv_work.wait(lk, [&] { return sv->stop || !L->queue->empty() || g->G > 0; });
                 if (sv->stop && g->G == 0) break;
                 i64 n = g->n, e = g->nnz;
                 int G = g->G;
-                while (!sv->stop && !L->pending.empty()) {
-                    const Member &m = L->pending.front();
+                while (!sv->stop && !L->queue->empty()) {
+                    const Member &m = L->queue->front();
                     if (G + 1 > L->cap_members || n + m.n0 > L->cap_nodes ||
                         e + m.nnz0 > L->cap_entries)
                         break;
                     n += m.n0;
                     e += m.nnz0;
                     G++;
-                    add.push_back(std::move(L->pending.front()));
-                    L->pending.pop_front();
+                    add.push_back(std::move(L->queue->front()));
+                    L->queue->pop_front();
                 }
             }
+            const size_t nadd = add.size();
             if (!add.empty()) union_append(g, add);
             if (g->G == 0) continue;
             if (g->n == 0) {  // only graphs without nodes: no level
@@ -1431,12 +1465,22 @@ static void lane_loop(slm_server *sv, Lane *L)
                 g->base.assign(1, 0);
                 g->G = 0;
             } else {
+                const i64 t0 = now_ns();
+                const int G0 = g->G;
+                const i64 n0 = g->n, e0 = g->nnz;
                 setup_level(g);
+                const i64 t1 = now_ns();
                 union_level(g, &sv->cfg.params, done);
+                if (getenv("SLM_TRACE"))
+                    fprintf(stderr, "lane %p level: G %d n %lld nnz %lld admitted %zu setup %.2f ms level %.2f ms done %zu\n",
+                            (void *)L, G0, (long long)n0, (long long)e0, nadd, (t1 - t0) / 1e6,
+                            (now_ns() - t1) / 1e6, done.size());
             }
             if (!done.empty()) {
                 std::lock_guard<std::mutex> lk(sv->mu);
+                const i64 t = now_ns();
                 for (Member &m : done) {
+                    m.res->t_done_ns = t;
                     sv->done[m.ticket] = m.res;
                     sv->completed++;
                 }
@@ -1459,7 +1503,9 @@ slm_status slm_server_create(const slm_server_cfg *cfg, slm_server **out)
     try {
         REQUIRE(cfg != nullptr && out != nullptr, SLM_E_INVALID, "null argument");
         *out = nullptr;
-        REQUIRE(cfg->lanes == 1 || cfg->lanes == 2, SLM_E_INVALID, "lanes must be 1 or 2");
+        REQUIRE(cfg->lanes >= 1 && cfg->lanes <= 16, SLM_E_INVALID, "lanes must be 1..16");
+        REQUIRE(cfg->large_lanes >= 0 && cfg->large_lanes < cfg->lanes, SLM_E_INVALID,
+                "large_lanes must leave at least one lane for small graphs");
         REQUIRE(cfg->node_capacity >= 0 && cfg->entry_capacity >= 0 && cfg->max_members >= 0,
                 SLM_E_INVALID, "negative capacity");
         REQUIRE(cfg->params.accept_p <= (1ull << 32), SLM_E_INVALID, "accept_p must be at most 2^32");
@@ -1480,6 +1526,7 @@ slm_status slm_server_create(const slm_server_cfg *cfg, slm_server **out)
             L->cap_entries = sv->cfg.entry_capacity;
             L->cap_members = sv->cfg.max_members;
             L->eng = make_engine(L->cap_nodes, L->cap_entries, L->cap_members, L->stream);
+            L->queue = l < sv->cfg.lanes - sv->cfg.large_lanes ? &sv->q_small : &sv->q_large;
         }
         for (Lane *L : sv->lanes) L->th = std::thread(lane_loop, sv, L);
         *out = sv;
@@ -1500,10 +1547,9 @@ slm_status slm_server_submit(slm_server *sv, const slm_graph_desc *d, uint64_t s
     REQUIRE(sv != nullptr && d != nullptr && ticket != nullptr, SLM_E_INVALID, "null argument");
     REQUIRE(d->n >= 0 && d->nnz >= 0 && d->row_ptr != nullptr, SLM_E_INVALID, "bad graph");
     REQUIRE(d->nnz == 0 || (d->col && d->w), SLM_E_INVALID, "null col or w");
-    const int lane = (sv->cfg.lanes == 2 && d->n > sv->cfg.large_nodes) ? 1 : 0;
-    Lane *L = sv->lanes[lane];
-    REQUIRE(d->n <= L->cap_nodes && d->nnz <= L->cap_entries, SLM_E_NOMEM,
-            "the graph exceeds the capacity of its lane");
+    const bool large = sv->cfg.large_lanes > 0 && d->n > sv->cfg.large_nodes;
+    REQUIRE(d->n <= sv->cfg.node_capacity && d->nnz <= sv->cfg.entry_capacity, SLM_E_NOMEM,
+            "the graph exceeds the capacity of a lane");
     Member m;
     m.n0 = d->n;
     m.nnz0 = d->nnz;
@@ -1523,13 +1569,14 @@ slm_status slm_server_submit(slm_server *sv, const slm_graph_desc *d, uint64_t s
     for (i64 v = 0; v < d->n; v++) m.comp[v] = (i32)v;
     m.res = new slm_result();
     m.res->n0 = d->n;
+    m.res->t_submit_ns = now_ns();
     {
         std::lock_guard<std::mutex> lk(sv->mu);
         REQUIRE(!sv->stop, SLM_E_STATE, "the server is stopping");
         m.ticket = sv->next_ticket++;
         *ticket = m.ticket;
         sv->open.insert(m.ticket);
-        L->pending.push_back(std::move(m));
+        (large ? sv->q_large : sv->q_small).push_back(std::move(m));
         sv->submitted++;
     }
     sv->cv_work.notify_all();
@@ -1608,8 +1655,9 @@ void slm_server_destroy(slm_server *sv)
     sv->cv_work.notify_all();
     for (Lane *L : sv->lanes)
         if (L->th.joinable()) L->th.join();
+    for (Member &m : sv->q_small) delete m.res;
+    for (Member &m : sv->q_large) delete m.res;
     for (Lane *L : sv->lanes) {
-        for (Member &m : L->pending) delete m.res;
         if (L->eng) slm_destroy(L->eng);
         if (L->stream) (void)hipStreamDestroy(L->stream);
         delete L;

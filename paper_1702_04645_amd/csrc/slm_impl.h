@@ -54,6 +54,11 @@ struct Bins {
     i64 ntile = 0;             // table tiles (HUB_TILE slots each)
     i32 *tile_hub = nullptr;   // device [ntile] hub index of each tile
     i32 *tile_off_of_hub = nullptr; // device [nhub+1] first tile of each hub
+    i64 *span = nullptr;       // device [2*nhub] entry range of each hub
+    // capacities of the arrays above: they only grow, so setting up a level
+    // frees nothing (a free would synchronise the whole device)
+    i64 cap_tab_off = 0, cap_chunk_hub = 0, cap_chunk_beg = 0, cap_chunk_off = 0,
+        cap_tile_hub = 0, cap_tile_off = 0, cap_span = 0;
 };
 
 // Read-only view of one level's graph as the kernels see it.

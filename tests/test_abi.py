@@ -90,9 +90,9 @@ def test_server_arguments_are_rejected_without_a_device():
     import paper_1702_04645_amd as slm
     lib = slm.lib()
     h = C.c_void_p()
-    for lanes, ncap in ((3, 0), (0, 0), (1, -5)):
-        cfg = slm._ServerCfg(ncap, 0, 0, lanes, 0, 1, 0, slm.params())
+    for lanes, large, ncap in ((17, 0, 0), (0, 0, 0), (1, 0, -5), (2, 2, 0), (2, -1, 0)):
+        cfg = slm._ServerCfg(ncap, 0, 0, lanes, 0, large, 1, slm.params())
         assert lib.slm_server_create(C.byref(cfg), C.byref(h)) == slm.SLM_E_INVALID
     bad = slm.params(accept_p=(1 << 32) + 1)
-    cfg = slm._ServerCfg(0, 0, 0, 1, 0, 1, 0, bad)
+    cfg = slm._ServerCfg(0, 0, 0, 1, 0, 0, 1, bad)
     assert lib.slm_server_create(C.byref(cfg), C.byref(h)) == slm.SLM_E_INVALID

@@ -41,13 +41,13 @@ def _mix():
     return out
 
 
-@pytest.mark.parametrize("lanes", [1, 2])
-def test_serve_mix_matches_alone(slm, lanes):
+@pytest.mark.parametrize("lanes,large", [(1, 0), (2, 1), (4, 1)])
+def test_serve_mix_matches_alone(slm, lanes, large):
     graphs = _mix()
     seeds = [1000 + 17 * i for i in range(len(graphs))]
     rg = np.random.default_rng(5)
-    say("serve mix", len(graphs), "lanes", lanes)
-    with slm.Server(lanes=lanes, large_nodes=3000, node_capacity=1 << 16,
+    say("serve mix", len(graphs), "lanes", lanes, large)
+    with slm.Server(lanes=lanes, large_lanes=large, large_nodes=3000, node_capacity=1 << 16,
                     entry_capacity=1 << 20, max_members=64) as sv:
         tickets = []
         for i, (rp, col, w) in enumerate(graphs):
