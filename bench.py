@@ -30,6 +30,23 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def measured_traffic(workload: str):
+    """HBM bytes per sweep from the committed rocprofv3 counter summary, when
+    it was taken on this workload with the current sweep source; else None."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "%s_sweep_hbm_traffic.json" % workload)
+    src = os.path.join(ROOT, "paper_1702_04645_amd", "csrc", "k_sweep.hip")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    with open(src, "rb") as f:
+        h = hashlib.sha256(f.read()).hexdigest()[:16]
+    if rec.get("sweep_source_sha256_16") != h:
+        return None
+    return round(rec["sweep_traffic_bytes"] / 1e9, 4)
+
+
 def workload(name: str):
     import graphgen as gg
     if name == "rmat20":
@@ -312,7 +329,18 @@ def main():
     ap.add_argument("--serve-count", type=int, default=2000)
     ap.add_argument("--serve-rate", type=float, default=400.0)
     ap.add_argument("--serve-lanes", type=int, default=4)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only copy 1 GiB device to device (calibrates HBM byte counters)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        a = torch.ones(1 << 28, dtype=torch.int32, device="cuda")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": a.numel() * 4}), flush=True)
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
@@ -380,7 +408,9 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": None,
+            "traffic": measured_traffic(args.workload),
+            "traffic_unit": "GB per sweep (HBM read + write, counters scaled by a copy)",
+            "algorithmic_gb_per_sweep": round(tm["bytes"] / max(tm["sweeps"], 1) / 1e9, 4),
         },
     }
     if rank == 0 and not args.no_cpu:

@@ -178,6 +178,7 @@ static void setup_level(slm_graph *g)
         for (int b = 0; b < NBINS; b++) B.off[b + 1] = B.off[b] + W.h_scal[b];
         HIPCHK(hipMemcpyAsync(W.counters, B.off, sizeof(i64) * NBINS, hipMemcpyHostToDevice, s));
         launch_bin_scatter(rp, n, W.counters, B.nodes, s);
+        launch_rowdesc(B.nodes, rp, n, B.rowd, s);
         const i64 nhub = B.off[BIN_HUB + 1] - B.off[BIN_HUB];
         B.nhub = (i32)nhub;
         B.hub_node = B.nodes + B.off[BIN_HUB];
@@ -355,6 +356,8 @@ static void alloc_work(slm_graph *g)
     W.head_e = dalloc<uint8_t>(g, nnz);
     W.rank_e = dalloc<i64>(g, nnz + 1);
     g->bins.nodes = dalloc<i32>(g, n);
+    g->bins.rowd = dalloc<int4>(g, n);
+    g->bins.ls = dalloc<int2>(g, n);
     g->composed = dalloc<i32>(g, n);
     g->rpL[0] = dalloc<i64>(g, n + 1);
     g->rpL[1] = dalloc<i64>(g, n + 1);
@@ -363,6 +366,15 @@ static void alloc_work(slm_graph *g)
     void *hs = nullptr;
     HIPCHK(hipHostMalloc(&hs, sizeof(i64) * 64, hipHostMallocDefault));
     W.h_scal = (i64 *)hs;
+    // SLM_SERIAL_SWEEP=1 keeps every bin of the sweep on the handle's stream
+    // (per-kernel timing without overlap)
+    if (!getenv("SLM_SERIAL_SWEEP")) {
+        HIPCHK(hipEventCreateWithFlags(&W.fan.fork, hipEventDisableTiming));
+        for (int q = 0; q < FAN_SIDE; q++) {
+            HIPCHK(hipStreamCreateWithFlags(&W.fan.side[q], hipStreamNonBlocking));
+            HIPCHK(hipEventCreateWithFlags(&W.fan.join[q], hipEventDisableTiming));
+        }
+    }
 }
 
 static slm_status fail(const SlmError &e)
@@ -845,6 +857,11 @@ void slm_destroy(slm_graph *g)
                     (void *)W.hub_tkey, (void *)W.hub_tid})
         if (p) (void)hipFree(p);
     if (W.h_scal) (void)hipHostFree(W.h_scal);
+    for (int q = 0; q < FAN_SIDE; q++) {
+        if (W.fan.side[q]) (void)hipStreamDestroy(W.fan.side[q]);
+        if (W.fan.join[q]) (void)hipEventDestroy(W.fan.join[q]);
+    }
+    if (W.fan.fork) (void)hipEventDestroy(W.fan.fork);
     if (g->ev0) (void)hipEventDestroy(g->ev0);
     if (g->ev1) (void)hipEventDestroy(g->ev1);
     delete g;
@@ -1045,7 +1062,8 @@ slm_status slm_sweep(slm_graph *g, const int32_t *lab_dev, int64_t n_c, int32_t 
     community_totals(g->W, L, lab_dev, n_c, g->s);
     if (g->timing) HIPCHK(hipEventRecord(g->ev0, g->s));
     run_sweep(L, g->bins, lab_dev, g->W.sigma, best_c_dev, delta_dev, w_own_dev, g->W.hub_keys,
-              g->W.hub_vals, g->W.hub_win, g->W.hub_tkey, g->W.hub_tid, g->s);
+              g->W.hub_vals, g->W.hub_win, g->W.hub_tkey, g->W.hub_tid, g->s,
+              g->W.fan.side[0] ? &g->W.fan : nullptr);
     if (g->timing) {
         HIPCHK(hipEventRecord(g->ev1, g->s));
         HIPCHK(hipEventSynchronize(g->ev1));

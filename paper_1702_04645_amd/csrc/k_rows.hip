@@ -429,6 +429,28 @@ __global__ __launch_bounds__(SLM_BS) void k_bin_count(const i64 *__restrict__ rp
         atomicAdd((unsigned long long *)&bin_cnt[threadIdx.x], (unsigned long long)cnt[threadIdx.x]);
 }
 
+// Row descriptors in bin order: one coalesced load gives a row its node, its
+// degree and its first entry.
+__global__ void k_rowdesc(const i32 *__restrict__ nodes, const i64 *__restrict__ rp, i64 n,
+                          int4 *__restrict__ rowd)
+{
+    for (i64 t = (i64)blockIdx.x * blockDim.x + threadIdx.x; t < n;
+         t += (i64)gridDim.x * blockDim.x) {
+        const i32 u = nodes[t];
+        const i64 b = rp[u];
+        rowd[t] = make_int4(u, (i32)(rp[u + 1] - b), (i32)(u32)(b & 0xffffffffll),
+                            (i32)(b >> 32));
+    }
+}
+
+void launch_rowdesc(const i32 *nodes, const i64 *rp, i64 n, int4 *rowd, hipStream_t s)
+{
+    if (n <= 0) return;
+    i64 g = (n + SLM_BS - 1) / SLM_BS;
+    if (g > 16384) g = 16384;
+    k_rowdesc<<<(unsigned)g, SLM_BS, 0, s>>>(nodes, rp, n, rowd);
+}
+
 // bin_fill[b] starts at the bin's offset; waves reserve runs of consecutive ids.
 __global__ __launch_bounds__(SLM_BS) void k_bin_scatter(const i64 *__restrict__ rp, i64 n,
                                                        i64 *__restrict__ bin_fill,

@@ -68,6 +68,101 @@ __global__ __launch_bounds__(SLM_BS) void k_sweep_zero(const i32 *__restrict__ n
     }
 }
 
+// ------------------------------------------------------------------ short rows
+// ls[v] = (c_v, S_{c_v}): the short-row kernels gather a neighbour's label and
+// its community's total in one load, so a row needs no second gather.
+__global__ void k_pack_ls(const i32 *__restrict__ lab, const i32 *__restrict__ sigma, i64 n,
+                          int2 *__restrict__ ls)
+{
+    for (i64 v = (i64)blockIdx.x * blockDim.x + threadIdx.x; v < n;
+         v += (i64)gridDim.x * blockDim.x) {
+        const i32 c = lab[v];
+        ls[v] = make_int2(c, sigma[c]);
+    }
+}
+
+// Rows of at most G*U entries: G lanes per row, U entries per lane, all in
+// registers.  A row needs three dependent loads (its descriptor, its entries
+// with its own (label, total), the neighbours' (label, total)); equal labels
+// are found by comparing every entry of the group with every other through
+// shuffles, and the first entry of each label (in row order) evaluates it.
+template <int G, int U>
+__global__ __launch_bounds__(SLM_BS) void k_sweep_reg(LevelView L, const int4 *__restrict__ rowd,
+                                                     i64 count, const int2 *__restrict__ ls,
+                                                     i32 *__restrict__ best_c,
+                                                     i64 *__restrict__ delta,
+                                                     i32 *__restrict__ w_own)
+{
+    constexpr int NG = SLM_BS / G;
+    const int gl = threadIdx.x % G;
+    const i64 slot = (i64)blockIdx.x * NG + threadIdx.x / G;
+    const bool valid = slot < count;
+    const int4 rd = valid ? rowd[slot] : make_int4(0, 0, 0, 0);
+    const i32 node = rd.x;
+    const int deg = rd.y;
+    const i64 e0 = (i64)(u32)rd.z | ((i64)rd.w << 32);
+    int2 ed[U];
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+        const int j = gl + u * G;
+        ed[u] = (valid && j < deg) ? L.e[e0 + j] : make_int2(-1, 0);
+    }
+    const int2 own = valid ? ls[node] : make_int2(-1, 0);
+    const i64 ki = valid ? L.k[node] : 0;
+    const i64 m2 = valid ? node_m2(L, node) : 0;
+    int2 lc[U];  // (label, total) of each entry's column; label -1: none
+#pragma unroll
+    for (int u = 0; u < U; u++)
+        lc[u] = (ed[u].x >= 0 && ed[u].x != node) ? ls[ed[u].x] : make_int2(-1, 0);
+    i64 win = 0;
+    i64 tot[U];
+    bool first[U];
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+        if (lc[u].x == own.x) win += ed[u].y;
+        tot[u] = 0;
+        first[u] = lc[u].x >= 0 && lc[u].x != own.x;
+    }
+#pragma unroll
+    for (int v = 0; v < U; v++) {
+        for (int j = 0; j < G; j++) {
+            const i32 cj = __shfl(lc[v].x, j, G);
+            const i32 wj = __shfl(ed[v].y, j, G);
+#pragma unroll
+            for (int u = 0; u < U; u++) {
+                if (cj == lc[u].x) {
+                    tot[u] += wj;
+                    if (v * G + j < u * G + gl) first[u] = false;
+                }
+            }
+        }
+    }
+    i64 bk = INT64_MIN;
+    i32 bc = INT32_MAX;
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+        if (!first[u]) continue;
+        const i64 key = m2 * tot[u] - ki * (i64)lc[u].y;
+        if (better_key(key, lc[u].x, bk, bc)) {
+            bk = key;
+            bc = lc[u].x;
+        }
+    }
+    win = group_sum<G, i64>(win);
+    group_best<G>(bk, bc);
+    if (valid && gl == 0) {
+        const i64 stay = m2 * win - ki * ((i64)own.y - ki);
+        if (bc != INT32_MAX && bk > stay) {
+            best_c[node] = bc;
+            delta[node] = bk - stay;
+        } else {
+            best_c[node] = own.x;
+            delta[node] = 0;
+        }
+        w_own[node] = (i32)win;
+    }
+}
+
 // ------------------------------------------------------------------ tiny rows
 template <int G>
 __global__ __launch_bounds__(SLM_BS) void k_sweep_tiny(LevelView L, const i32 *__restrict__ nodes,
@@ -359,45 +454,52 @@ static unsigned persistent_grid(i64 count, int per_block, int max_blocks)
 
 void run_sweep(const LevelView &L, const Bins &Bn, const i32 *lab, const i32 *sigma,
                i32 *best_c, i64 *delta, i32 *w_own, i32 *hub_keys, i32 *hub_vals,
-               i32 *hub_win, i64 *hub_tile_key, i32 *hub_tile_id, hipStream_t s)
+               i32 *hub_win, i64 *hub_tile_key, i32 *hub_tile_id, hipStream_t s,
+               const Fanout *F)
 {
+    // streams: the hub chain and the zero rows stay on s; the other bins go
+    // to the side streams, longest first
+    hipStream_t st[FAN_SIDE];
+    for (int q = 0; q < FAN_SIDE; q++) st[q] = F ? F->side[q] : s;
+    if (L.n > 0) {
+        i64 gp = (L.n + SLM_BS - 1) / SLM_BS;
+        if (gp > 16384) gp = 16384;
+        k_pack_ls<<<(unsigned)gp, SLM_BS, 0, s>>>(lab, sigma, L.n, Bn.ls);
+    }
+    if (F) {
+        HIPCHK(hipEventRecord(F->fork, s));
+        for (int q = 0; q < FAN_SIDE; q++) HIPCHK(hipStreamWaitEvent(F->side[q], F->fork, 0));
+    }
     const i32 *nodes;
     i64 cnt;
-    cnt = Bn.off[BIN_ZERO + 1] - Bn.off[BIN_ZERO];
-    nodes = Bn.nodes + Bn.off[BIN_ZERO];
+    cnt = Bn.off[BIN_512 + 1] - Bn.off[BIN_512];
+    nodes = Bn.nodes + Bn.off[BIN_512];
     if (cnt > 0)
-        k_sweep_zero<<<persistent_grid(cnt, SLM_BS, 2048), SLM_BS, 0, s>>>(nodes, cnt, lab, best_c,
-                                                                          delta, w_own);
-    cnt = Bn.off[BIN_8 + 1] - Bn.off[BIN_8];
-    nodes = Bn.nodes + Bn.off[BIN_8];
-    if (cnt > 0)
-        k_sweep_tiny<8><<<grid_for(cnt, SLM_BS / 8), SLM_BS, 0, s>>>(L, nodes, cnt, lab, sigma,
-                                                                   best_c, delta, w_own);
-    cnt = Bn.off[BIN_32 + 1] - Bn.off[BIN_32];
-    nodes = Bn.nodes + Bn.off[BIN_32];
-    if (cnt > 0)
-        k_sweep_hash<32, 64, 1><<<persistent_grid(cnt, SLM_BS / 32, 8192), SLM_BS, 0, s>>>(
+        k_sweep_hash<64, 1024, 8><<<persistent_grid(cnt, SLM_BS / 64, 4096), SLM_BS, 0, st[0]>>>(
             L, nodes, cnt, lab, sigma, best_c, delta, w_own);
     cnt = Bn.off[BIN_128 + 1] - Bn.off[BIN_128];
     nodes = Bn.nodes + Bn.off[BIN_128];
     if (cnt > 0)
-        k_sweep_hash<64, 256, 2><<<persistent_grid(cnt, SLM_BS / 64, 8192), SLM_BS, 0, s>>>(
+        k_sweep_hash<64, 256, 2><<<persistent_grid(cnt, SLM_BS / 64, 8192), SLM_BS, 0, st[1]>>>(
             L, nodes, cnt, lab, sigma, best_c, delta, w_own);
-    cnt = Bn.off[BIN_512 + 1] - Bn.off[BIN_512];
-    nodes = Bn.nodes + Bn.off[BIN_512];
+    cnt = Bn.off[BIN_32 + 1] - Bn.off[BIN_32];
     if (cnt > 0)
-        k_sweep_hash<64, 1024, 8><<<persistent_grid(cnt, SLM_BS / 64, 4096), SLM_BS, 0, s>>>(
-            L, nodes, cnt, lab, sigma, best_c, delta, w_own);
+        k_sweep_reg<8, 4><<<grid_for(cnt, SLM_BS / 8), SLM_BS, 0, st[1]>>>(
+            L, Bn.rowd + Bn.off[BIN_32], cnt, Bn.ls, best_c, delta, w_own);
     cnt = Bn.off[BIN_2048 + 1] - Bn.off[BIN_2048];
     nodes = Bn.nodes + Bn.off[BIN_2048];
     if (cnt > 0)
-        k_sweep_hash<256, 4096, 8><<<persistent_grid(cnt, 1, 4096), 256, 0, s>>>(
+        k_sweep_hash<256, 4096, 8><<<persistent_grid(cnt, 1, 4096), 256, 0, st[2]>>>(
             L, nodes, cnt, lab, sigma, best_c, delta, w_own);
     cnt = Bn.off[BIN_4096 + 1] - Bn.off[BIN_4096];
     nodes = Bn.nodes + Bn.off[BIN_4096];
     if (cnt > 0)
-        k_sweep_hash<512, 8192, 8><<<persistent_grid(cnt, 1, 2048), 512, 0, s>>>(
+        k_sweep_hash<512, 8192, 8><<<persistent_grid(cnt, 1, 2048), 512, 0, st[2]>>>(
             L, nodes, cnt, lab, sigma, best_c, delta, w_own);
+    cnt = Bn.off[BIN_8 + 1] - Bn.off[BIN_8];
+    if (cnt > 0)
+        k_sweep_reg<4, 2><<<grid_for(cnt, SLM_BS / 4), SLM_BS, 0, st[2]>>>(
+            L, Bn.rowd + Bn.off[BIN_8], cnt, Bn.ls, best_c, delta, w_own);
     if (Bn.nhub > 0) {
         launch_fill_i32(hub_keys, -1, Bn.table_total, s);
         launch_fill_i32(hub_vals, 0, Bn.table_total, s);
@@ -412,5 +514,16 @@ void run_sweep(const LevelView &L, const Bins &Bn, const i32 *lab, const i32 *si
         k_sweep_hub_final<<<(unsigned)Bn.nhub, 64, 0, s>>>(L, Bn.hub_node, Bn.tile_off_of_hub, lab,
                                                           sigma, hub_tile_key, hub_tile_id,
                                                           hub_win, best_c, delta, w_own);
+    }
+    cnt = Bn.off[BIN_ZERO + 1] - Bn.off[BIN_ZERO];
+    nodes = Bn.nodes + Bn.off[BIN_ZERO];
+    if (cnt > 0)
+        k_sweep_zero<<<persistent_grid(cnt, SLM_BS, 2048), SLM_BS, 0, s>>>(nodes, cnt, lab, best_c,
+                                                                          delta, w_own);
+    if (F) {
+        for (int q = 0; q < FAN_SIDE; q++) {
+            HIPCHK(hipEventRecord(F->join[q], F->side[q]));
+            HIPCHK(hipStreamWaitEvent(s, F->join[q], 0));
+        }
     }
 }

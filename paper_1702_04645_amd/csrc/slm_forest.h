@@ -25,6 +25,7 @@ struct Work {
     i64 *wsz = nullptr, *nsz = nullptr;
     int4 *pstk = nullptr;
     i32 *stamp = nullptr;  // POSITIVE: candidate-set epoch of every node
+    Fanout fan;            // side streams of the sweep
     i32 *A0 = nullptr, *A1 = nullptr, *M0 = nullptr, *M1 = nullptr;
     i32 *J = nullptr;  // kmax tables of n0
     i32 *D0 = nullptr, *D1 = nullptr;

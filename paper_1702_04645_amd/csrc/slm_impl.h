@@ -55,6 +55,9 @@ struct Bins {
     i32 *tile_hub = nullptr;   // device [ntile] hub index of each tile
     i32 *tile_off_of_hub = nullptr; // device [nhub+1] first tile of each hub
     i64 *span = nullptr;       // device [2*nhub] entry range of each hub
+    int4 *rowd = nullptr;      // device [n] per node in bin order: (node, degree,
+                               // first entry low 32 bits, high 32 bits)
+    int2 *ls = nullptr;        // device [n] scratch of the sweep: (label, S_label)
     // capacities of the arrays above: they only grow, so setting up a level
     // frees nothing (a free would synchronise the whole device)
     i64 cap_tab_off = 0, cap_chunk_hub = 0, cap_chunk_beg = 0, cap_chunk_off = 0,
@@ -203,6 +206,7 @@ void launch_scan_u8(const uint8_t *in, i64 *out, i64 n, i64 *tmp, hipStream_t s)
 // ---------------------------------------------------------------- level setup (k_rows.hip)
 void launch_bin_count(const i64 *rp, i64 n, i64 *bin_cnt, hipStream_t s);
 void launch_bin_scatter(const i64 *rp, i64 n, i64 *bin_fill, i32 *bin_nodes, hipStream_t s);
+void launch_rowdesc(const i32 *nodes, const i64 *rp, i64 n, int4 *rowd, hipStream_t s);
 // span_out[2h], span_out[2h+1] = entry range of hub h's row.
 void launch_hub_degrees(const i64 *rp, const i32 *hub_node, i32 nhub, i64 *span_out,
                         hipStream_t s);
@@ -211,11 +215,21 @@ void launch_hub_degrees(const i64 *rp, const i32 *hub_node, i32 nhub, i64 *span_
 // ASSIGN (Sec. 3.1): a[i] = best neighbour or i.
 void run_assign(const LevelView &L, const Bins &B, i32 *a, i64 *hub_key, i32 *hub_id,
                 hipStream_t s);
+// Side streams of a handle: the degree bins of a sweep are independent, so
+// they run concurrently (fork after the work already queued on the main
+// stream, join before anything after them).
+#define FAN_SIDE 3
+struct Fanout {
+    hipStream_t side[FAN_SIDE] = {nullptr, nullptr, nullptr};
+    hipEvent_t fork = nullptr, join[FAN_SIDE] = {nullptr, nullptr, nullptr};
+};
 // MAXIMAL sweep (Sec. 3.4): best_c, delta, w_own from labels and totals.
-// hub_tile_key / hub_tile_id: one slot per table tile.
+// hub_tile_key / hub_tile_id: one slot per table tile.  F may be null (all
+// bins on s).
 void run_sweep(const LevelView &L, const Bins &B, const i32 *lab, const i32 *sigma,
                i32 *best_c, i64 *delta, i32 *w_own, i32 *hub_keys, i32 *hub_vals,
-               i32 *hub_win, i64 *hub_tile_key, i32 *hub_tile_id, hipStream_t s);
+               i32 *hub_win, i64 *hub_tile_key, i32 *hub_tile_id, hipStream_t s,
+               const Fanout *F);
 // wc[i] = sum of A_ij over j with lab[j] == lab[i] (diagonal included); only
 // for nodes with active[lab[i]] != 0 when active is given.
 void run_own_weight(const LevelView &L, const Bins &B, const i32 *lab, const uint8_t *active,
