@@ -68,13 +68,16 @@ struct PwShared {
     // split search: the nodes of the candidate set are evaluated exactly at
     // every split; every other node of the part is bounded by the bucket of
     // its value at the last full scan (see pw_thr / pw_lb)
-    int need_scan, epoch, ncand, cand_over;
+    int need_scan, epoch, ncand, cand_over, cand_cap;
     i64 sig_scan;  // S_P at the last full scan
     u64 kmax[PW_NB];  // per bucket of subtree strength: max branch key (order-mapped)
     u64 kpair[PW_NB]; // per bucket: lowest cut pair among its nodes whose key is that max
     u64 gmin[PW_NB];  // per bucket of strength: min local gain (order-mapped)
     i32 cand[PW_CAND];
+    uint8_t cflag[PW_CAND];  // CF_DIRTY: cached terms stale; CF_GONE: left the part
 };
+
+enum { CF_DIRTY = 1, CF_GONE = 2 };
 
 __device__ __forceinline__ u64 ord_map(i64 v) { return (u64)v ^ (1ull << 63); }
 __device__ __forceinline__ i64 ord_unmap(u64 v) { return (i64)(v ^ (1ull << 63)); }
@@ -115,13 +118,35 @@ __device__ __forceinline__ i64 pw_lb(const PwShared &S, i64 D)
     return t;
 }
 
-// Adds v to the candidate set once per scan epoch.
-__device__ __forceinline__ void pw_add_cand(PwShared &S, i32 *stamp, i32 v)
+// Adds v to the candidate set once per scan epoch; a node already in the set
+// is marked dirty (its cached terms are re-read at the next evaluation).
+__device__ __forceinline__ void pw_add_cand(PwShared &S, i32 *stamp, i32 *cidx, i32 v)
 {
-    if (atomicExch(&stamp[v], S.epoch) == S.epoch) return;
+    if (atomicExch(&stamp[v], S.epoch) == S.epoch) {
+        // a concurrent add may not have stored its index yet: then the stale
+        // index is ignored or marks another slot, and the adder's own flag is
+        // dirty anyway
+        const i32 c = cidx[v];
+        if (c >= 0 && c < S.cand_cap) S.cflag[c] |= CF_DIRTY;
+        return;
+    }
     const int i = atomicAdd(&S.ncand, 1);
-    if (i < PW_CAND) S.cand[i] = v;
-    else S.cand_over = 1;
+    if (i < S.cand_cap) {
+        S.cand[i] = v;
+        S.cflag[i] = CF_DIRTY;
+        cidx[v] = i;
+    } else {
+        S.cand_over = 1;
+    }
+}
+
+// A candidate that leaves the part with a cut-off subtree.
+__device__ __forceinline__ void pw_drop_cand(PwShared &S, const i32 *stamp, const i32 *cidx,
+                                             i32 v)
+{
+    if (stamp[v] != S.epoch) return;
+    const i32 c = cidx[v];
+    if (c >= 0 && c < S.cand_cap && S.cand[c] == v) S.cflag[c] |= CF_GONE;
 }
 
 // Ranges for the subtrees cut off the finished part: consecutive from off.
@@ -320,6 +345,8 @@ __global__ __launch_bounds__(PW_BS) void k_positive_wg(PosArgs A)
     uint8_t *cyc = A.cyc;
 
     i32 *stamp = A.stamp;
+    i32 *cidx = A.cidx;
+    int4 *CV = A.cval + base;  // candidate cache: at most min(PW_CAND, m0) entries
     // iterations: at most one pass per part and, per split, one full scan
     // and one split step; parts and splits are fewer than 2*m0
     const int iter_cap = 6 * m0 + 16;
@@ -330,6 +357,7 @@ __global__ __launch_bounds__(PW_BS) void k_positive_wg(PosArgs A)
         S.chl_top = 0;
         S.iters = 0;
         S.epoch = 0;
+        S.cand_cap = m0 < PW_CAND ? m0 : PW_CAND;
     }
     __syncthreads();
     while (true) {
@@ -713,8 +741,8 @@ __global__ __launch_bounds__(PW_BS) void k_positive_wg(PosArgs A)
                 __syncthreads();
 #pragma unroll
                 for (int q = 0; q < PW_TOP; q++)
-                    if (tp[q] != ~0ull) pw_add_cand(S, stamp, (i32)(tp[q] >> 32));
-                if (gu >= 0) pw_add_cand(S, stamp, gu);
+                    if (tp[q] != ~0ull) pw_add_cand(S, stamp, cidx, (i32)(tp[q] >> 32));
+                if (gu >= 0) pw_add_cand(S, stamp, cidx, gu);
                 live = wg_sum(live, S);
                 if (m > 2 * live + PW_BS) {  // most of the range has left: compact
                     const int kept =
@@ -724,17 +752,33 @@ __global__ __launch_bounds__(PW_BS) void k_positive_wg(PosArgs A)
                     m = kept;
                 }
             } else {
-                // ---- the candidate set, exactly
-                const int nc = min(S.ncand, PW_CAND);
+                // ---- the candidate set, exactly: clean candidates from the
+                // cache (their terms are unchanged since read), dirty ones
+                // from the node arrays
+                const int nc = min(S.ncand, S.cand_cap);
                 i64 gm = INT64_MAX;
                 for (int i = threadIdx.x; i < nc; i += PW_BS) {
+                    const int fl = S.cflag[i];
+                    if (fl & CF_GONE) continue;
                     const i32 u = S.cand[i];
-                    if (A.part[u] != pid) continue;
-                    const i64 ku = G.k[u];
-                    gm = min(gm, m2 * (i64)A.win[u] - ku * (sig - ku));
-                    if (!cyc[u]) {
-                        const i64 sx = A.subk[u];
-                        const i64 key = sx * (sig - sx) - m2 * (i64)A.cut[u];
+                    int4 cv;
+                    if (fl & CF_DIRTY) {
+                        if (A.part[u] != pid) {
+                            S.cflag[i] = CF_GONE;
+                            continue;
+                        }
+                        cv = make_int4(A.subk[u], A.cut[u], A.win[u],
+                                       G.k[u] | (cyc[u] ? (i32)0x80000000 : 0));
+                        CV[i] = cv;
+                        S.cflag[i] = 0;
+                    } else {
+                        cv = CV[i];
+                    }
+                    const i64 ku = cv.w & 0x7fffffff;
+                    gm = min(gm, m2 * (i64)cv.z - ku * (sig - ku));
+                    if (cv.w >= 0) {
+                        const i64 sx = cv.x;
+                        const i64 key = sx * (sig - sx) - m2 * (i64)cv.y;
                         const u64 pr = ((u64)(u32)u << 32) | (u64)(u32)u;
                         if (key > bk || (key == bk && pr < bp)) {
                             bk = key;
@@ -842,6 +886,7 @@ __global__ __launch_bounds__(PW_BS) void k_positive_wg(PosArgs A)
                 S.tail = 1;
                 S.lev_end = 1;
                 A.part[x] = x;
+                pw_drop_cand(S, stamp, cidx, x);
             }
             __syncthreads();
             while (true) {
@@ -857,6 +902,7 @@ __global__ __launch_bounds__(PW_BS) void k_positive_wg(PosArgs A)
                         int q = atomicAdd(&S.tail, 1);
                         TMP[q] = ch;
                         A.part[ch] = x;
+                        pw_drop_cand(S, stamp, cidx, ch);
                     }
                 }
                 __syncthreads();
@@ -877,7 +923,7 @@ __global__ __launch_bounds__(PW_BS) void k_positive_wg(PosArgs A)
                         break;
                     }
                     A.subk[yv] -= (i32)sx;
-                    pw_add_cand(S, stamp, yv);
+                    pw_add_cand(S, stamp, cidx, yv);
                     if (cyc[yv]) break;
                     yv = a[yv];
                 }
@@ -900,25 +946,25 @@ __global__ __launch_bounds__(PW_BS) void k_positive_wg(PosArgs A)
                         val = ed.y;
                         const i32 A_ = ed.y;
                         atomicSub(&A.win[u], A_);
-                        pw_add_cand(S, stamp, u);
+                        pw_add_cand(S, stamp, cidx, u);
                         // paths u -> lca and px -> lca in the part before the cut
                         i32 p1 = u, p2 = px;
                         int guard = 0;
                         while (A.dep[p1] > A.dep[p2] && guard++ < 2 * m) {
                             atomicSub(&A.cut[p1], A_);
-                            pw_add_cand(S, stamp, p1);
+                            pw_add_cand(S, stamp, cidx, p1);
                             p1 = a[p1];
                         }
                         while (A.dep[p2] > A.dep[p1] && guard++ < 2 * m) {
                             atomicSub(&A.cut[p2], A_);
-                            pw_add_cand(S, stamp, p2);
+                            pw_add_cand(S, stamp, cidx, p2);
                             p2 = a[p2];
                         }
                         while (p1 != p2 && guard++ < 2 * m) {
                             atomicSub(&A.cut[p1], A_);
                             atomicSub(&A.cut[p2], A_);
-                            pw_add_cand(S, stamp, p1);
-                            pw_add_cand(S, stamp, p2);
+                            pw_add_cand(S, stamp, cidx, p1);
+                            pw_add_cand(S, stamp, cidx, p2);
                             if (cyc[p1] && cyc[p2]) break;
                             p1 = a[p1];
                             p2 = a[p2];
