@@ -65,6 +65,7 @@ struct slm_graph {
     i64 sweeps = 0, entries = 0, bytes = 0;
     std::vector<void *> allocs;
     i64 reserved = 0;  // device bytes held by allocs
+    bool no_fanout = false;  // keep every sweep bin on the handle's stream
 
     // A union handle (a batch, or a lane of a server) holds G independent
     // graphs ("members") as one disjoint union; G = 0 for a plain graph.
@@ -368,9 +369,11 @@ static void alloc_work(slm_graph *g)
     void *hs = nullptr;
     HIPCHK(hipHostMalloc(&hs, sizeof(i64) * 64, hipHostMallocDefault));
     W.h_scal = (i64 *)hs;
-    // SLM_SERIAL_SWEEP=1 keeps every bin of the sweep on the handle's stream
-    // (per-kernel timing without overlap)
-    if (!getenv("SLM_SERIAL_SWEEP")) {
+    // Side streams for the sweep of large levels.  A server lane has none:
+    // its streams would share the device's few hardware queues with the other
+    // lanes and wait behind their long kernels.  SLM_SERIAL_SWEEP=1 keeps
+    // every bin on the handle's stream (per-kernel timing without overlap).
+    if (!g->no_fanout && !getenv("SLM_SERIAL_SWEEP")) {
         HIPCHK(hipEventCreateWithFlags(&W.fan.fork, hipEventDisableTiming));
         for (int q = 0; q < FAN_SIDE; q++) {
             HIPCHK(hipStreamCreateWithFlags(&W.fan.side[q], hipStreamNonBlocking));
@@ -1065,7 +1068,7 @@ slm_status slm_sweep(slm_graph *g, const int32_t *lab_dev, int64_t n_c, int32_t 
     if (g->timing) HIPCHK(hipEventRecord(g->ev0, g->s));
     run_sweep(L, g->bins, lab_dev, g->W.sigma, best_c_dev, delta_dev, w_own_dev, g->W.hub_keys,
               g->W.hub_vals, g->W.hub_win, g->W.hub_tkey, g->W.hub_tid, g->s,
-              g->W.fan.side[0] ? &g->W.fan : nullptr);
+              g->W.fan.side[0] && g->nnz >= FAN_MIN_ENTRIES ? &g->W.fan : nullptr);
     if (g->timing) {
         HIPCHK(hipEventRecord(g->ev1, g->s));
         HIPCHK(hipEventSynchronize(g->ev1));
@@ -1403,6 +1406,7 @@ static slm_graph *make_engine(i64 cap_n, i64 cap_e, int cap_m, hipStream_t s)
     slm_graph *g = new slm_graph();
     try {
         g->s = s;
+        g->no_fanout = true;
         HIPCHK(hipGetDevice(&g->device));
         g->n0 = cap_n;
         g->nnz0 = cap_e;

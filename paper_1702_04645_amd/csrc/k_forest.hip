@@ -747,7 +747,8 @@ i64 maximal_moves(Work &W, const LevelView &Lv, const Bins &B, i64 nc, u64 seed,
     community_totals(W, Lv, W.lab, nc, s);
     if (timing) HIPCHK(hipEventRecord(ev0, s));
     run_sweep(Lv, B, W.lab, W.sigma, W.best_c, W.delta, W.w_own, W.hub_keys, W.hub_vals,
-              W.hub_win, W.hub_tkey, W.hub_tid, s, W.fan.side[0] ? &W.fan : nullptr);
+              W.hub_win, W.hub_tkey, W.hub_tid, s,
+              W.fan.side[0] && Lv.nnz >= FAN_MIN_ENTRIES ? &W.fan : nullptr);
     if (timing) HIPCHK(hipEventRecord(ev1, s));
     // candidates
     launch_fill_u8(W.act, 0, nc, s);

@@ -219,6 +219,7 @@ void run_assign(const LevelView &L, const Bins &B, i32 *a, i64 *hub_key, i32 *hu
 // they run concurrently (fork after the work already queued on the main
 // stream, join before anything after them).
 #define FAN_SIDE 3
+#define FAN_MIN_ENTRIES ((i64)1 << 22)  // smaller levels: the fork costs more than it saves
 struct Fanout {
     hipStream_t side[FAN_SIDE] = {nullptr, nullptr, nullptr};
     hipEvent_t fork = nullptr, join[FAN_SIDE] = {nullptr, nullptr, nullptr};
