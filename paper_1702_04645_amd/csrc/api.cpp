@@ -245,6 +245,9 @@ static void setup_level(slm_graph *g)
             grow_i32(W.hub_vals, cap_vals, B.table_total);
             W.hub_tab_cap = cap_keys;
             grow_i32(W.hub_win, W.hub_win_cap, nhub);
+            // the sweep leaves its hub tables empty; a new level starts them so
+            launch_fill_i32(W.hub_keys, -1, B.table_total, s);
+            launch_fill_i32(W.hub_vals, 0, B.table_total, s);
             if (B.nchunk > W.hub_chunk_cap) {
                 if (W.hub_ckey) HIPCHK(hipFree(W.hub_ckey));
                 if (W.hub_cid) HIPCHK(hipFree(W.hub_cid));

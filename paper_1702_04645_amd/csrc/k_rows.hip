@@ -14,8 +14,11 @@ template <int B> struct BinShape;
 template <> struct BinShape<BIN_ZERO> { static constexpr int G = 1, H = 2; };
 template <> struct BinShape<BIN_8> { static constexpr int G = 8, H = 16; };
 template <> struct BinShape<BIN_32> { static constexpr int G = 32, H = 64; };
+template <> struct BinShape<BIN_64> { static constexpr int G = 32, H = 128; };
 template <> struct BinShape<BIN_128> { static constexpr int G = 64, H = 256; };
+template <> struct BinShape<BIN_256> { static constexpr int G = 64, H = 512; };
 template <> struct BinShape<BIN_512> { static constexpr int G = 64, H = 1024; };
+template <> struct BinShape<BIN_1024> { static constexpr int G = 128, H = 2048; };
 template <> struct BinShape<BIN_2048> { static constexpr int G = 256, H = 4096; };
 template <> struct BinShape<BIN_4096> { static constexpr int G = 512, H = 8192; };
 
@@ -409,8 +412,11 @@ __device__ __forceinline__ int bin_of_degree(i64 d)
     if (d == 0) return BIN_ZERO;
     if (d <= 8) return BIN_8;
     if (d <= 32) return BIN_32;
+    if (d <= 64) return BIN_64;
     if (d <= 128) return BIN_128;
+    if (d <= 256) return BIN_256;
     if (d <= 512) return BIN_512;
+    if (d <= 1024) return BIN_1024;
     if (d <= 2048) return BIN_2048;
     if (d <= 4096) return BIN_4096;
     return BIN_HUB;
@@ -510,7 +516,9 @@ static void bin_launch_geom(const Bins &Bn, i64 &count, const i32 *&nodes, unsig
     block = GroupGeom<G>::BSZ;
 }
 
-#define FOR_LDS_BINS(X) X(BIN_ZERO) X(BIN_8) X(BIN_32) X(BIN_128) X(BIN_512) X(BIN_2048) X(BIN_4096)
+#define FOR_LDS_BINS(X)                                                               \
+    X(BIN_ZERO) X(BIN_8) X(BIN_32) X(BIN_64) X(BIN_128) X(BIN_256) X(BIN_512) X(BIN_1024)     \
+    X(BIN_2048) X(BIN_4096)
 
 void run_strength_binned(const i64 *rp, const int2 *e, const Bins &Bn, i32 *k, i32 *diag,
                          i64 *m2_acc, hipStream_t s)

@@ -327,8 +327,8 @@ __global__ __launch_bounds__(G <= 64 ? SLM_BS : G) void k_sweep_hash(
 
 // ------------------------------------------------------------------ hub rows
 // Chunk totals in LDS, then the distinct labels go to the hub's HBM table.
-#define HUB_H 8192
-#define HUB_BS 512
+#define HUB_H 4096
+#define HUB_BS 256
 __global__ __launch_bounds__(HUB_BS) void k_sweep_hub_chunk(
     LevelView L, const i32 *__restrict__ hub_node, const i32 *__restrict__ chunk_hub,
     const i64 *__restrict__ chunk_beg, const i64 *__restrict__ tab_off,
@@ -391,11 +391,13 @@ __global__ __launch_bounds__(HUB_BS) void k_sweep_hub_chunk(
     if (threadIdx.x == 0 && win) atomicAdd(&hub_win[h], (i32)win);
 }
 
-// Best entry of one HUB_TILE-slot tile of a hub table.
+// Best entry of one HUB_TILE-slot tile of a hub table; the occupied slots are
+// cleared behind, so the tables are empty again for the next sweep (level
+// set-up clears them once).
 __global__ __launch_bounds__(SLM_BS) void k_sweep_hub_tile(
     LevelView L, const i32 *__restrict__ hub_node, const i32 *__restrict__ tile_hub,
     const i64 *__restrict__ tab_off, const i32 *__restrict__ tile_first,
-    const i32 *__restrict__ sigma, const i32 *__restrict__ tkey, const i32 *__restrict__ tval,
+    const i32 *__restrict__ sigma, i32 *__restrict__ tkey, i32 *__restrict__ tval,
     i64 *__restrict__ tile_key, i32 *__restrict__ tile_id)
 {
     __shared__ i64 red[32];
@@ -413,6 +415,8 @@ __global__ __launch_bounds__(SLM_BS) void k_sweep_hub_tile(
                 bk = key;
                 bc = c;
             }
+            tkey[base + i] = -1;
+            tval[base + i] = 0;
         }
     }
     block_best(bk, bc, red);
@@ -472,37 +476,30 @@ void run_sweep(const LevelView &L, const Bins &Bn, const i32 *lab, const i32 *si
     }
     const i32 *nodes;
     i64 cnt;
-    cnt = Bn.off[BIN_512 + 1] - Bn.off[BIN_512];
-    nodes = Bn.nodes + Bn.off[BIN_512];
-    if (cnt > 0)
-        k_sweep_hash<64, 1024, 8><<<persistent_grid(cnt, SLM_BS / 64, 4096), SLM_BS, 0, st[0]>>>(
-            L, nodes, cnt, lab, sigma, best_c, delta, w_own);
-    cnt = Bn.off[BIN_128 + 1] - Bn.off[BIN_128];
-    nodes = Bn.nodes + Bn.off[BIN_128];
-    if (cnt > 0)
-        k_sweep_hash<64, 256, 2><<<persistent_grid(cnt, SLM_BS / 64, 8192), SLM_BS, 0, st[1]>>>(
-            L, nodes, cnt, lab, sigma, best_c, delta, w_own);
+#define HASH_BIN(B, G, H, U, STREAM)                                                   \
+    cnt = Bn.off[B + 1] - Bn.off[B];                                                   \
+    nodes = Bn.nodes + Bn.off[B];                                                      \
+    if (cnt > 0)                                                                       \
+        k_sweep_hash<G, H, U>                                                          \
+            <<<persistent_grid(cnt, G <= 64 ? SLM_BS / G : 1, 8192), G <= 64 ? SLM_BS : G, \
+               0, STREAM>>>(L, nodes, cnt, lab, sigma, best_c, delta, w_own);
+    HASH_BIN(BIN_512, 64, 1024, 8, st[0])
+    HASH_BIN(BIN_256, 64, 512, 4, st[0])
+    HASH_BIN(BIN_128, 64, 256, 2, st[1])
+    HASH_BIN(BIN_64, 32, 128, 2, st[1])
+    HASH_BIN(BIN_2048, 256, 4096, 8, st[2])
+    HASH_BIN(BIN_1024, 128, 2048, 8, st[2])
+    HASH_BIN(BIN_4096, 512, 8192, 8, st[2])
+#undef HASH_BIN
     cnt = Bn.off[BIN_32 + 1] - Bn.off[BIN_32];
     if (cnt > 0)
         k_sweep_reg<8, 4><<<grid_for(cnt, SLM_BS / 8), SLM_BS, 0, st[1]>>>(
             L, Bn.rowd + Bn.off[BIN_32], cnt, Bn.ls, best_c, delta, w_own);
-    cnt = Bn.off[BIN_2048 + 1] - Bn.off[BIN_2048];
-    nodes = Bn.nodes + Bn.off[BIN_2048];
-    if (cnt > 0)
-        k_sweep_hash<256, 4096, 8><<<persistent_grid(cnt, 1, 4096), 256, 0, st[2]>>>(
-            L, nodes, cnt, lab, sigma, best_c, delta, w_own);
-    cnt = Bn.off[BIN_4096 + 1] - Bn.off[BIN_4096];
-    nodes = Bn.nodes + Bn.off[BIN_4096];
-    if (cnt > 0)
-        k_sweep_hash<512, 8192, 8><<<persistent_grid(cnt, 1, 2048), 512, 0, st[2]>>>(
-            L, nodes, cnt, lab, sigma, best_c, delta, w_own);
     cnt = Bn.off[BIN_8 + 1] - Bn.off[BIN_8];
     if (cnt > 0)
         k_sweep_reg<4, 2><<<grid_for(cnt, SLM_BS / 4), SLM_BS, 0, st[2]>>>(
             L, Bn.rowd + Bn.off[BIN_8], cnt, Bn.ls, best_c, delta, w_own);
     if (Bn.nhub > 0) {
-        launch_fill_i32(hub_keys, -1, Bn.table_total, s);
-        launch_fill_i32(hub_vals, 0, Bn.table_total, s);
         launch_fill_i32(hub_win, 0, Bn.nhub, s);
         k_sweep_hub_chunk<<<(unsigned)Bn.nchunk, HUB_BS, 0, s>>>(
             L, Bn.hub_node, Bn.chunk_hub, Bn.chunk_beg, Bn.hub_tab_off, lab, hub_keys, hub_vals,

@@ -34,9 +34,12 @@ struct SlmError {
 // the per-node community table in LDS; bin 7 ("hub") rows are split in
 // chunks of HUB_CHUNK entries spread over many workgroups, with the table in
 // HBM.  Bin 0 holds isolated nodes.
-enum { BIN_ZERO = 0, BIN_8, BIN_32, BIN_128, BIN_512, BIN_2048, BIN_4096, BIN_HUB, NBINS };
-static const i64 kBinMaxDeg[NBINS] = {0, 8, 32, 128, 512, 2048, 4096, INT64_MAX};
-#define HUB_CHUNK 4096
+enum {
+    BIN_ZERO = 0, BIN_8, BIN_32, BIN_64, BIN_128, BIN_256, BIN_512, BIN_1024, BIN_2048, BIN_4096,
+    BIN_HUB, NBINS
+};
+static const i64 kBinMaxDeg[NBINS] = {0, 8, 32, 64, 128, 256, 512, 1024, 2048, 4096, INT64_MAX};
+#define HUB_CHUNK 2048
 #define HUB_TILE 8192  // slots of a hub table finalized by one workgroup
 
 struct Bins {
