@@ -325,6 +325,155 @@ __global__ __launch_bounds__(G <= 64 ? SLM_BS : G) void k_sweep_hash(
     }
 }
 
+// Pipelined rows of a bin for groups of at most 64 lanes.  A row's loads form
+// a chain (descriptor -> entries -> neighbours' (label, total)); the loop
+// keeps three rows in flight: while row i is inserted into the table, the
+// entries of row i+1 and the descriptor of row i+2 are loading, and while
+// row i's table is read, row i+1's labels are.  The community total of each
+// table entry comes with its label (ls) and is kept beside the slot list, so
+// the table's read-out needs no further load.
+template <int H>
+__device__ __forceinline__ void table_insert_s(i32 *keys, i32 *vals, i32 *list, i32 *lsig,
+                                               i32 *cnt, i32 c, i32 w, i32 sg)
+{
+    u32 h = sw_slot<H>(c);
+    for (int probe = 0; probe < H; probe++) {
+        const i32 old = atomicCAS(&keys[h], -1, c);
+        if (old == -1) {
+            atomicAdd(&vals[h], w);
+            const int p = atomicAdd(cnt, 1);
+            list[p] = (i32)h;
+            lsig[p] = sg;
+            return;
+        }
+        if (old == c) {
+            atomicAdd(&vals[h], w);
+            return;
+        }
+        h = (h + 1) & (H - 1);
+    }
+}
+
+template <int G, int H, int U>
+__global__ __launch_bounds__(SLM_BS) void k_sweep_pipe(LevelView L, const int4 *__restrict__ rowd,
+                                                      i64 count, const int2 *__restrict__ ls,
+                                                      i32 *__restrict__ best_c,
+                                                      i64 *__restrict__ delta,
+                                                      i32 *__restrict__ w_own)
+{
+    static_assert(G <= 64, "one wavefront per group at most");
+    constexpr int NG = SLM_BS / G;
+    constexpr int LIST = H / 2;
+    __shared__ i32 s_key[NG * H];
+    __shared__ i32 s_val[NG * H];
+    __shared__ i32 s_list[NG * LIST];
+    __shared__ i32 s_lsig[NG * LIST];
+    __shared__ i32 s_cnt[NG];
+    const int gl = threadIdx.x % G, gi = threadIdx.x / G;
+    i32 *keys = s_key + gi * H;
+    i32 *vals = s_val + gi * H;
+    i32 *list = s_list + gi * LIST;
+    i32 *lsig = s_lsig + gi * LIST;
+    for (int i = threadIdx.x; i < NG * H; i += SLM_BS) {
+        s_key[i] = -1;
+        s_val[i] = 0;
+    }
+    if (threadIdx.x < NG) s_cnt[threadIdx.x] = 0;
+    __syncthreads();
+    const i64 stride = (i64)gridDim.x * NG;
+    i64 slot = (i64)blockIdx.x * NG + gi;
+    // row i (current), row i+1 (next: descriptor and entries), row i+2 (descriptor)
+    int4 rd = slot < count ? rowd[slot] : make_int4(-1, 0, 0, 0);
+    int4 rd1 = slot + stride < count ? rowd[slot + stride] : make_int4(-1, 0, 0, 0);
+    int2 ed[U], lc[U];
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+        const int j = gl + u * G;
+        ed[u] = (rd.x >= 0 && j < rd.y)
+                    ? L.e[((i64)(u32)rd.z | ((i64)rd.w << 32)) + j]
+                    : make_int2(-1, 0);
+    }
+#pragma unroll
+    for (int u = 0; u < U; u++)
+        lc[u] = (ed[u].x >= 0 && ed[u].x != rd.x) ? ls[ed[u].x] : make_int2(-1, 0);
+    int2 own = rd.x >= 0 ? ls[rd.x] : make_int2(-1, 0);
+    i64 ki = rd.x >= 0 ? (i64)L.k[rd.x] : 0;
+    i64 m2 = rd.x >= 0 ? node_m2(L, rd.x) : 0;
+    while (slot < count) {
+        // next rows' loads: entries of i+1, descriptor of i+2
+        const i64 s2 = slot + 2 * stride;
+        const int4 rd2 = s2 < count ? rowd[s2] : make_int4(-1, 0, 0, 0);
+        int2 ed1[U];
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            const int j = gl + u * G;
+            ed1[u] = (rd1.x >= 0 && j < rd1.y)
+                         ? L.e[((i64)(u32)rd1.z | ((i64)rd1.w << 32)) + j]
+                         : make_int2(-1, 0);
+        }
+        // row i into the table
+        i64 win = 0;
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            const i32 c = lc[u].x;
+            if (c < 0) continue;
+            if (c == own.x) win += ed[u].y;
+            else table_insert_s<H>(keys, vals, list, lsig, &s_cnt[gi], c, ed[u].y, lc[u].y);
+        }
+        sw_sync<G>();
+        // labels of row i+1 while row i's table is read
+        int2 lc1[U];
+#pragma unroll
+        for (int u = 0; u < U; u++)
+            lc1[u] = (ed1[u].x >= 0 && ed1[u].x != rd1.x) ? ls[ed1[u].x] : make_int2(-1, 0);
+        const int2 own1 = rd1.x >= 0 ? ls[rd1.x] : make_int2(-1, 0);
+        const i64 ki1 = rd1.x >= 0 ? (i64)L.k[rd1.x] : 0;
+        const i64 m21 = rd1.x >= 0 ? node_m2(L, rd1.x) : 0;
+        const int nd = s_cnt[gi];
+        i64 bk = INT64_MIN;
+        i32 bc = INT32_MAX;
+        for (int i = gl; i < nd; i += G) {
+            const i32 h = list[i];
+            const i32 cc = keys[h];
+            const i64 key = m2 * (i64)vals[h] - ki * (i64)lsig[i];
+            if (better_key(key, cc, bk, bc)) {
+                bk = key;
+                bc = cc;
+            }
+            keys[h] = -1;
+            vals[h] = 0;
+        }
+        win = group_sum<G, i64>(win);
+        group_best<G>(bk, bc);
+        if (gl == 0) {
+            const i32 node = rd.x;
+            const i64 stay = m2 * win - ki * ((i64)own.y - ki);
+            if (bc != INT32_MAX && bk > stay) {
+                best_c[node] = bc;
+                delta[node] = bk - stay;
+            } else {
+                best_c[node] = own.x;
+                delta[node] = 0;
+            }
+            w_own[node] = (i32)win;
+            s_cnt[gi] = 0;
+        }
+        sw_sync<G>();
+        // advance
+        slot += stride;
+        rd = rd1;
+        rd1 = rd2;
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            ed[u] = ed1[u];
+            lc[u] = lc1[u];
+        }
+        own = own1;
+        ki = ki1;
+        m2 = m21;
+    }
+}
+
 // ------------------------------------------------------------------ hub rows
 // Chunk totals in LDS, then the distinct labels go to the hub's HBM table.
 #define HUB_H 4096
@@ -483,14 +632,20 @@ void run_sweep(const LevelView &L, const Bins &Bn, const i32 *lab, const i32 *si
         k_sweep_hash<G, H, U>                                                          \
             <<<persistent_grid(cnt, G <= 64 ? SLM_BS / G : 1, 8192), G <= 64 ? SLM_BS : G, \
                0, STREAM>>>(L, nodes, cnt, lab, sigma, best_c, delta, w_own);
-    HASH_BIN(BIN_512, 64, 1024, 8, st[0])
-    HASH_BIN(BIN_256, 64, 512, 4, st[0])
-    HASH_BIN(BIN_128, 64, 256, 2, st[1])
-    HASH_BIN(BIN_64, 32, 128, 2, st[1])
+#define PIPE_BIN(B, G, H, U, STREAM)                                                   \
+    cnt = Bn.off[B + 1] - Bn.off[B];                                                   \
+    if (cnt > 0)                                                                       \
+        k_sweep_pipe<G, H, U><<<persistent_grid(cnt, SLM_BS / G, 8192), SLM_BS, 0, STREAM>>>( \
+            L, Bn.rowd + Bn.off[B], cnt, Bn.ls, best_c, delta, w_own);
+    PIPE_BIN(BIN_512, 64, 1024, 8, st[0])
+    PIPE_BIN(BIN_256, 64, 512, 4, st[0])
+    PIPE_BIN(BIN_128, 64, 256, 2, st[1])
+    PIPE_BIN(BIN_64, 32, 128, 2, st[1])
     HASH_BIN(BIN_2048, 256, 4096, 8, st[2])
     HASH_BIN(BIN_1024, 128, 2048, 8, st[2])
     HASH_BIN(BIN_4096, 512, 8192, 8, st[2])
 #undef HASH_BIN
+#undef PIPE_BIN
     cnt = Bn.off[BIN_32 + 1] - Bn.off[BIN_32];
     if (cnt > 0)
         k_sweep_reg<8, 4><<<grid_for(cnt, SLM_BS / 8), SLM_BS, 0, st[1]>>>(
