@@ -3,20 +3,24 @@
 // the best C != c_i (key desc, label asc), and a move when it beats
 // stay(i) = M2 w(i, c_i \ i) - k_i (S_ci - k_i).
 //
-// Rows are handled by lane groups sized to their degree:
-//   deg <= 8       8-lane group, one entry per lane; equal labels are found
-//                  by shuffles inside the group (no LDS);
+// Rows are handled by lane groups sized to their degree class:
+//   deg <= 32      4 or 8 lanes per row, every entry in registers; equal
+//                  labels are found by shuffles (k_sweep_reg);
 //   deg <= 512     32- or 64-lane groups with an LDS open-addressing table
 //                  and a list of the occupied slots, so reading and clearing
 //                  the table costs the number of distinct labels; groups loop
-//                  over the nodes of their bin;
-//   deg <= 4096    one 256- or 512-lane workgroup per node, same table;
+//                  over the rows of their bin with three rows in flight
+//                  (k_sweep_pipe);
+//   deg <= 4096    one 128- to 512-lane workgroup per row, same table
+//                  (k_sweep_hash);
 //   larger (hubs)  rows cut in HUB_CHUNK-entry chunks; a workgroup totals its
 //                  chunk in LDS and adds the distinct labels to the hub's HBM
-//                  table; table tiles are then scanned in parallel.
-// The own community's weight never enters a table: it is summed in
-// registers.  Entries are int2 (column, weight), read once, coalesced per
-// group.
+//                  table; table tiles are then read (and cleared) in parallel.
+// A row starts from its descriptor (node, degree, first entry) in bin order;
+// the short and pipelined rows gather a neighbour's (label, community total)
+// in one 8-byte load.  The own community's weight never enters a table: it
+// is summed in registers.  The bins are independent and may run on several
+// streams at once.
 #include "slm_forest.h"
 
 template <int H> __device__ __forceinline__ u32 sw_slot(i32 c)
@@ -161,64 +165,6 @@ __global__ __launch_bounds__(SLM_BS) void k_sweep_reg(LevelView L, const int4 *_
         }
         w_own[node] = (i32)win;
     }
-}
-
-// ------------------------------------------------------------------ tiny rows
-template <int G>
-__global__ __launch_bounds__(SLM_BS) void k_sweep_tiny(LevelView L, const i32 *__restrict__ nodes,
-                                                      i64 count, const i32 *__restrict__ lab,
-                                                      const i32 *__restrict__ sigma,
-                                                      i32 *__restrict__ best_c,
-                                                      i64 *__restrict__ delta,
-                                                      i32 *__restrict__ w_own)
-{
-    constexpr int NG = SLM_BS / G;
-    const int gl = threadIdx.x % G;
-    const i64 slot = (i64)blockIdx.x * NG + threadIdx.x / G;
-    const bool valid = slot < count;
-    const i32 node = valid ? nodes[slot] : 0;
-    i32 ci = 0;
-    i64 ki = 0;
-    i32 c = -1;
-    i64 wv = 0, win = 0;
-    if (valid) {
-        ci = lab[node];
-        ki = L.k[node];
-        const i64 e0 = L.rp[node], deg = L.rp[node + 1] - e0;
-        if (gl < deg) {
-            const int2 ed = L.e[e0 + gl];
-            if (ed.x != node) {
-                const i32 cv = lab[ed.x];
-                if (cv == ci) win = ed.y;
-                else {
-                    c = cv;
-                    wv = ed.y;
-                }
-            }
-        }
-    }
-    // total weight of this lane's label over the group; the first lane of a
-    // label evaluates it
-    i64 tot = 0;
-    bool first = true;
-#pragma unroll
-    for (int j = 0; j < G; j++) {
-        const i32 cj = __shfl(c, j, G);
-        const i64 wj = __shfl(wv, j, G);
-        if (cj == c) {
-            tot += wj;
-            if (j < gl) first = false;
-        }
-    }
-    i64 bk = INT64_MIN;
-    i32 bc = INT32_MAX;
-    if (c >= 0 && first) {
-        bk = node_m2(L, node) * tot - ki * (i64)sigma[c];
-        bc = c;
-    }
-    win = group_sum<G, i64>(win);
-    group_best<G>(bk, bc);
-    if (valid && gl == 0) write_move(L, node, ci, ki, win, bk, bc, sigma, best_c, delta, w_own);
 }
 
 // ------------------------------------------------------------------ LDS table with slot list
