@@ -54,6 +54,7 @@ enum { ST_INIT = 1, ST_GATHER = 2 };
 
 struct PwShared {
     i64 red[2 * PW_NW + 2];
+    int redf[PW_NW];
     i64 sig;       // S_P
     i64 bkey;      // best key
     u64 bpair;     // best (first, second)
@@ -63,7 +64,6 @@ struct PwShared {
     int tail, head, lev_end;
     int L;         // cycle length of the part
     int chl_top;   // next free slot of the children arena
-    int iters;     // loop guard (workgroup-uniform loops)
     int sp0;       // stack size when the current part started
     // split search: the nodes of the candidate set are evaluated exactly at
     // every split; every other node of the part is bounded by the bucket of
@@ -201,6 +201,42 @@ __device__ __forceinline__ void wg_best(i64 &key, u64 &pair, PwShared &S)
     for (int w = 1; w < PW_NW; w++) {
         i64 k2 = S.red[2 * w];
         u64 p2 = (u64)S.red[2 * w + 1];
+        if (k2 > key || (k2 == key && p2 < pair)) {
+            key = k2;
+            pair = p2;
+        }
+    }
+    __syncthreads();
+}
+
+// wg_best plus the OR of one flag per thread, in the same two barriers.
+__device__ __forceinline__ void wg_best_or(i64 &key, u64 &pair, int &flag, PwShared &S)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        i64 ok = __shfl_xor(key, off, 64);
+        u64 op = __shfl_xor(pair, off, 64);
+        flag |= __shfl_xor(flag, off, 64);
+        if (ok > key || (ok == key && op < pair)) {
+            key = ok;
+            pair = op;
+        }
+    }
+    const int wid = threadIdx.x / 64;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) {
+        S.red[2 * wid] = key;
+        S.red[2 * wid + 1] = (i64)pair;
+        S.redf[wid] = flag;
+    }
+    __syncthreads();
+    key = S.red[0];
+    pair = (u64)S.red[1];
+    flag = S.redf[0];
+    for (int w = 1; w < PW_NW; w++) {
+        i64 k2 = S.red[2 * w];
+        u64 p2 = (u64)S.red[2 * w + 1];
+        flag |= S.redf[w];
         if (k2 > key || (k2 == key && p2 < pair)) {
             key = k2;
             pair = p2;
@@ -355,15 +391,15 @@ __global__ __launch_bounds__(PW_BS) void k_positive_wg(PosArgs A)
         STK[0] = make_int4(0, m0, A.flist[f], ST_INIT);
         S.sp = 1;
         S.chl_top = 0;
-        S.iters = 0;
         S.epoch = 0;
         S.cand_cap = m0 < PW_CAND ? m0 : PW_CAND;
     }
     __syncthreads();
+    int iters = 0;  // every thread counts the same passes (uniform loops)
     while (true) {
         __syncthreads();
         if (S.sp == 0) break;
-        if (S.iters > iter_cap) {
+        if (++iters > iter_cap) {
             if (threadIdx.x == 0) report(A.err, 5);
             break;
         }
@@ -375,7 +411,6 @@ __global__ __launch_bounds__(PW_BS) void k_positive_wg(PosArgs A)
             S.flags = t.w;
             S.sp0 = S.sp;
             S.need_scan = 1;
-            S.iters++;
         }
         __syncthreads();
         if (S.s < 0 || S.e < S.s || S.e > m0) {  // a range outside the community
@@ -608,11 +643,10 @@ __global__ __launch_bounds__(PW_BS) void k_positive_wg(PosArgs A)
             __syncthreads();
         }
         // -------------------------------------------------- split loop
+        // every pass of this loop starts after a barrier (the part's set-up or
+        // the end of the previous pass), so the shared state is settled
         while (true) {
-            __syncthreads();
-            if (threadIdx.x == 0) S.iters++;
-            __syncthreads();
-            if (S.iters > iter_cap) {
+            if (++iters > iter_cap) {
                 if (threadIdx.x == 0) report(A.err, 6);
                 break;
             }
@@ -622,7 +656,6 @@ __global__ __launch_bounds__(PW_BS) void k_positive_wg(PosArgs A)
             const int L = S.L;
             if (m <= 1) break;
             const bool scanned = S.need_scan != 0;
-            __syncthreads();
             i64 bk = INT64_MIN;
             u64 bp = ~0ull;
             int neg = 0;
@@ -636,6 +669,7 @@ __global__ __launch_bounds__(PW_BS) void k_positive_wg(PosArgs A)
                     S.kpair[b] = ~0ull;
                     S.gmin[b] = ~0ull;
                 }
+                __syncthreads();  // every thread has read need_scan
                 if (threadIdx.x == 0) {
                     S.epoch++;
                     S.ncand = 0;
@@ -809,8 +843,7 @@ __global__ __launch_bounds__(PW_BS) void k_positive_wg(PosArgs A)
                     }
                 }
             }
-            neg = (int)wg_sum(neg, S);
-            wg_best(bk, bp, S);
+            wg_best_or(bk, bp, neg, S);
             if (!scanned) {
                 // the set decides only if no node outside it can change the
                 // answer; otherwise scan the whole part
@@ -822,8 +855,8 @@ __global__ __launch_bounds__(PW_BS) void k_positive_wg(PosArgs A)
                 if (neg && bp != ~0ull && !(bk > thr || (bk == thr && bp < tpair))) sure = false;
                 if (neg && bp == ~0ull && thr != INT64_MIN) sure = false;
                 if (!sure) {
-                    __syncthreads();
                     if (threadIdx.x == 0) S.need_scan = 1;
+                    __syncthreads();
                     continue;
                 }
             }
@@ -889,7 +922,9 @@ __global__ __launch_bounds__(PW_BS) void k_positive_wg(PosArgs A)
                 pw_drop_cand(S, stamp, cidx, x);
             }
             __syncthreads();
-            while (true) {
+            // a node without children is T_x by itself
+            const bool leaf = A.chc[x] == 0;
+            while (!leaf) {
                 const int lb = S.head, le = S.lev_end;
                 if (lb == le) break;
                 for (int i = lb + threadIdx.x; i < le; i += PW_BS) {
@@ -931,16 +966,18 @@ __global__ __launch_bounds__(PW_BS) void k_positive_wg(PosArgs A)
                 cyc[x] = 1;
             }
             __syncthreads();
-            // entries between T_x and the rest of the part
-            const i64 tot = wg_degree_prefix(TMP, tcount, G.rp, DP, S);
+            // entries between T_x and the rest of the part (a single node's
+            // entries need no degree prefix)
+            const i64 tot = tcount == 1 ? G.rp[x + 1] - G.rp[x]
+                                        : wg_degree_prefix(TMP, tcount, G.rp, DP, S);
             for (i64 b = 0; b < tot; b += PW_BS) {
                 const i64 t = b + threadIdx.x;
                 i32 v = 0;
                 i64 val = 0;
                 if (t < tot) {
-                    int slot = find_slot(DP, tcount, t);
+                    int slot = tcount == 1 ? 0 : find_slot(DP, tcount, t);
                     v = TMP[slot];
-                    int2 ed = G.e[G.rp[v] + (t - DP[slot])];
+                    int2 ed = G.e[G.rp[v] + (t - (tcount == 1 ? 0 : DP[slot]))];
                     i32 u = ed.x;
                     if (A.part[u] == pid) {
                         val = ed.y;
