@@ -77,6 +77,7 @@ def lib():
         "slm_result_times": (st, [P, pi64, pi64]),
         "slm_timing_enable": (st, [P, C.c_int]),
         "slm_timing_read": (st, [P, C.POINTER(C.c_double), pi64, pi64, pi64]),
+        "slm_set_option": (st, [P, C.c_char_p, i64]),
         "slm_last_error": (C.c_char_p, []),
         "slm_batch_create": (st, [i32, P, C.c_int, P, C.POINTER(P)]),
         "slm_batch_size": (st, [P, pi32]),
@@ -273,6 +274,10 @@ class Graph:
         return _take_result(res, self.n0)
 
     # -------------------------------------------------------------- timing
+    def set_option(self, name: str, value: int):
+        """Tuning knob of the sweep (`slm_set_option`); results never change."""
+        _check(lib().slm_set_option(self._h, name.encode(), int(value)))
+
     def timing(self, enable: bool = True):
         _check(lib().slm_timing_enable(self._h, int(enable)))
 

@@ -141,11 +141,14 @@ static void grow_buf(T *&p, i64 &cap, i64 need)
 static void release_bins(slm_graph *g)
 {
     Bins &B = g->bins;
-    for (void *p : {(void *)B.hub_tab_off, (void *)B.chunk_hub, (void *)B.chunk_beg,
-                    (void *)B.chunk_off_of_hub, (void *)B.tile_hub, (void *)B.tile_off_of_hub,
-                    (void *)B.span})
+    for (void *p : {(void *)B.hub_logp, (void *)B.chunk_hub, (void *)B.chunk_beg,
+                    (void *)B.chunk_out, (void *)B.chunk_pbase, (void *)B.chunk_off_of_hub,
+                    (void *)B.tile_hub, (void *)B.tile_off_of_hub, (void *)B.span})
         if (p) (void)hipFree(p);
+    const int cap = B.hub_cap, tbits = B.hub_tbits;
     B = Bins();
+    B.hub_cap = cap;
+    B.hub_tbits = tbits;
 }
 
 static void grow_i32(i32 *&p, i64 &cap, i64 need)
@@ -167,7 +170,8 @@ static void setup_level(slm_graph *g)
     B.nhub = 0;
     B.nchunk = 0;
     B.ntile = 0;
-    B.table_total = 0;
+    B.hub_entries = 0;
+    B.npoff = 0;
     const i64 n = g->n;
     const i64 *rp = g->cur < 0 ? g->rp0 : g->rpL[g->cur];
     const int2 *e = g->cur < 0 ? g->e0 : g->eL[g->cur];
@@ -190,33 +194,59 @@ static void setup_level(slm_graph *g)
             HIPCHK(hipMemcpyAsync(span.data(), B.span, sizeof(i64) * 2 * nhub,
                                   hipMemcpyDeviceToHost, s));
             HIPCHK(hipStreamSynchronize(s));
-            std::vector<i64> tab_off(nhub + 1, 0);
+            std::vector<i32> logp(nhub);
             std::vector<i32> chunk_first(nhub + 1, 0);
             std::vector<i32> chunk_hub;
-            std::vector<i64> chunk_beg;
+            std::vector<i64> chunk_beg, chunk_out, chunk_pbase;
             std::vector<i32> tile_first(nhub + 1, 0);
             std::vector<i32> tile_hub;
+            i64 out = 0, pb = 0;
             for (i64 h = 0; h < nhub; h++) {
                 const i64 b0 = span[2 * h], b1 = span[2 * h + 1], deg = b1 - b0;
-                i64 t = HUB_TILE;
-                while (t < 2 * deg) t <<= 1;
-                tab_off[h + 1] = tab_off[h] + t;
+                int lp = 0;
+                while (((i64)HUB_PART << lp) < deg && (1 << lp) < HUB_PMAX) lp++;
+                logp[h] = lp;
                 tile_first[h] = (i32)tile_hub.size();
-                for (i64 q = 0; q < t / HUB_TILE; q++) tile_hub.push_back((i32)h);
+                for (i64 q = 0; q < ((i64)1 << lp); q++) tile_hub.push_back((i32)h);
                 chunk_first[h] = (i32)chunk_hub.size();
                 for (i64 c = b0; c < b1; c += HUB_CHUNK) {
                     chunk_hub.push_back((i32)h);
                     chunk_beg.push_back(c);
+                    chunk_out.push_back(out + (c - b0));
+                    chunk_pbase.push_back(pb);
+                    pb += ((i64)1 << lp) + 1;
                 }
+                out += deg;
             }
             chunk_first[nhub] = (i32)chunk_hub.size();
             tile_first[nhub] = (i32)tile_hub.size();
             B.ntile = (i64)tile_hub.size();
+            B.nchunk = (i64)chunk_hub.size();
+            B.hub_entries = out;
+            B.npoff = pb;
+            grow_buf(B.hub_logp, B.cap_logp, nhub);
             grow_buf(B.tile_hub, B.cap_tile_hub, B.ntile);
             grow_buf(B.tile_off_of_hub, B.cap_tile_off, nhub + 1);
+            grow_buf(B.chunk_off_of_hub, B.cap_chunk_off, nhub + 1);
+            grow_buf(B.chunk_hub, B.cap_chunk_hub, B.nchunk);
+            grow_buf(B.chunk_beg, B.cap_chunk_beg, B.nchunk);
+            grow_buf(B.chunk_out, B.cap_chunk_out, B.nchunk);
+            grow_buf(B.chunk_pbase, B.cap_chunk_pbase, B.nchunk);
+            HIPCHK(hipMemcpyAsync(B.hub_logp, logp.data(), sizeof(i32) * nhub,
+                                  hipMemcpyHostToDevice, s));
             HIPCHK(hipMemcpyAsync(B.tile_hub, tile_hub.data(), sizeof(i32) * B.ntile,
                                   hipMemcpyHostToDevice, s));
             HIPCHK(hipMemcpyAsync(B.tile_off_of_hub, tile_first.data(), sizeof(i32) * (nhub + 1),
+                                  hipMemcpyHostToDevice, s));
+            HIPCHK(hipMemcpyAsync(B.chunk_off_of_hub, chunk_first.data(), sizeof(i32) * (nhub + 1),
+                                  hipMemcpyHostToDevice, s));
+            HIPCHK(hipMemcpyAsync(B.chunk_hub, chunk_hub.data(), sizeof(i32) * B.nchunk,
+                                  hipMemcpyHostToDevice, s));
+            HIPCHK(hipMemcpyAsync(B.chunk_beg, chunk_beg.data(), sizeof(i64) * B.nchunk,
+                                  hipMemcpyHostToDevice, s));
+            HIPCHK(hipMemcpyAsync(B.chunk_out, chunk_out.data(), sizeof(i64) * B.nchunk,
+                                  hipMemcpyHostToDevice, s));
+            HIPCHK(hipMemcpyAsync(B.chunk_pbase, chunk_pbase.data(), sizeof(i64) * B.nchunk,
                                   hipMemcpyHostToDevice, s));
             if (B.ntile > W.hub_tile_cap) {
                 if (W.hub_tkey) HIPCHK(hipFree(W.hub_tkey));
@@ -225,29 +255,9 @@ static void setup_level(slm_graph *g)
                 HIPCHK(hipMalloc(&W.hub_tkey, sizeof(i64) * W.hub_tile_cap));
                 HIPCHK(hipMalloc(&W.hub_tid, sizeof(i32) * W.hub_tile_cap));
             }
-            B.nchunk = (i64)chunk_hub.size();
-            B.table_total = tab_off[nhub];
-            grow_buf(B.hub_tab_off, B.cap_tab_off, nhub + 1);
-            grow_buf(B.chunk_off_of_hub, B.cap_chunk_off, nhub + 1);
-            grow_buf(B.chunk_hub, B.cap_chunk_hub, B.nchunk);
-            grow_buf(B.chunk_beg, B.cap_chunk_beg, B.nchunk);
-            HIPCHK(hipMemcpyAsync(B.hub_tab_off, tab_off.data(), sizeof(i64) * (nhub + 1),
-                                  hipMemcpyHostToDevice, s));
-            HIPCHK(hipMemcpyAsync(B.chunk_off_of_hub, chunk_first.data(), sizeof(i32) * (nhub + 1),
-                                  hipMemcpyHostToDevice, s));
-            HIPCHK(hipMemcpyAsync(B.chunk_hub, chunk_hub.data(), sizeof(i32) * B.nchunk,
-                                  hipMemcpyHostToDevice, s));
-            HIPCHK(hipMemcpyAsync(B.chunk_beg, chunk_beg.data(), sizeof(i64) * B.nchunk,
-                                  hipMemcpyHostToDevice, s));
-            i64 cap_keys = W.hub_tab_cap;
-            grow_i32(W.hub_keys, cap_keys, B.table_total);
-            i64 cap_vals = W.hub_tab_cap;
-            grow_i32(W.hub_vals, cap_vals, B.table_total);
-            W.hub_tab_cap = cap_keys;
-            grow_i32(W.hub_win, W.hub_win_cap, nhub);
-            // the sweep leaves its hub tables empty; a new level starts them so
-            launch_fill_i32(W.hub_keys, -1, B.table_total, s);
-            launch_fill_i32(W.hub_vals, 0, B.table_total, s);
+            grow_buf(W.hub_part, W.hub_part_cap, B.hub_entries);
+            grow_buf(W.hub_poff, W.hub_poff_cap, B.npoff);
+            grow_buf(W.hub_cwin, W.hub_cwin_cap, B.nchunk);
             if (B.nchunk > W.hub_chunk_cap) {
                 if (W.hub_ckey) HIPCHK(hipFree(W.hub_ckey));
                 if (W.hub_cid) HIPCHK(hipFree(W.hub_cid));
@@ -860,8 +870,8 @@ void slm_destroy(slm_graph *g)
     release_bins(g);
     for (void *p : g->allocs) (void)hipFree(p);
     Work &W = g->W;
-    for (void *p : {(void *)W.W, (void *)W.hist, (void *)W.hub_keys, (void *)W.hub_vals,
-                    (void *)W.hub_win, (void *)W.hub_ckey, (void *)W.hub_cid,
+    for (void *p : {(void *)W.W, (void *)W.hist, (void *)W.hub_part, (void *)W.hub_poff,
+                    (void *)W.hub_cwin, (void *)W.hub_ckey, (void *)W.hub_cid,
                     (void *)W.hub_tkey, (void *)W.hub_tid})
         if (p) (void)hipFree(p);
     if (W.h_scal) (void)hipHostFree(W.h_scal);
@@ -1069,8 +1079,8 @@ slm_status slm_sweep(slm_graph *g, const int32_t *lab_dev, int64_t n_c, int32_t 
     LevelView L = view(g);
     community_totals(g->W, L, lab_dev, n_c, g->s);
     if (g->timing) HIPCHK(hipEventRecord(g->ev0, g->s));
-    run_sweep(L, g->bins, lab_dev, g->W.sigma, best_c_dev, delta_dev, w_own_dev, g->W.hub_keys,
-              g->W.hub_vals, g->W.hub_win, g->W.hub_tkey, g->W.hub_tid, g->s,
+    run_sweep(L, g->bins, lab_dev, g->W.sigma, best_c_dev, delta_dev, w_own_dev, g->W.hub_part,
+              g->W.hub_poff, g->W.hub_cwin, g->W.hub_tkey, g->W.hub_tid, g->s,
               g->W.fan.side[0] && g->nnz >= FAN_MIN_ENTRIES ? &g->W.fan : nullptr);
     if (g->timing) {
         HIPCHK(hipEventRecord(g->ev1, g->s));
@@ -1244,6 +1254,25 @@ slm_status slm_timing_enable(slm_graph *g, int enable)
     API_BEGIN
     REQUIRE(g != nullptr, SLM_E_INVALID, "null handle");
     g->timing = enable != 0;
+    API_END
+}
+
+slm_status slm_set_option(slm_graph *g, const char *name, int64_t value)
+{
+    API_BEGIN
+    REQUIRE(g != nullptr && name != nullptr, SLM_E_INVALID, "null argument");
+    const std::string k(name);
+    if (k == "hub_table_bits") {
+        REQUIRE(value >= 4 && (1 << value) <= HUB_TH, SLM_E_INVALID,
+                "hub_table_bits must be in 4..12");
+        g->bins.hub_tbits = (int)value;
+    } else if (k == "hub_pass_pairs") {
+        REQUIRE(value >= 1 && value <= ((int64_t)1 << 30), SLM_E_INVALID,
+                "hub_pass_pairs must be in 1..2^30");
+        g->bins.hub_cap = (int)value;
+    } else {
+        REQUIRE(false, SLM_E_INVALID, "unknown option");
+    }
     API_END
 }
 

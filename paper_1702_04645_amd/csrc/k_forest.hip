@@ -746,8 +746,8 @@ i64 maximal_moves(Work &W, const LevelView &Lv, const Bins &B, i64 nc, u64 seed,
     const unsigned g = node_grid(n);
     community_totals(W, Lv, W.lab, nc, s);
     if (timing) HIPCHK(hipEventRecord(ev0, s));
-    run_sweep(Lv, B, W.lab, W.sigma, W.best_c, W.delta, W.w_own, W.hub_keys, W.hub_vals,
-              W.hub_win, W.hub_tkey, W.hub_tid, s,
+    run_sweep(Lv, B, W.lab, W.sigma, W.best_c, W.delta, W.w_own, W.hub_part, W.hub_poff,
+              W.hub_cwin, W.hub_tkey, W.hub_tid, s,
               W.fan.side[0] && Lv.nnz >= FAN_MIN_ENTRIES ? &W.fan : nullptr);
     if (timing) HIPCHK(hipEventRecord(ev1, s));
     // candidates

@@ -421,27 +421,69 @@ __global__ __launch_bounds__(SLM_BS) void k_sweep_pipe(LevelView L, const int4 *
 }
 
 // ------------------------------------------------------------------ hub rows
-// Chunk totals in LDS, then the distinct labels go to the hub's HBM table.
-#define HUB_H 4096
+// A hub row is cut in HUB_CHUNK-entry chunks.  A chunk totals its entries by
+// label in LDS, then writes its distinct (label, weight) pairs grouped by a
+// partition of the label space (the top bits of a second hash, P_h = 2^logp
+// partitions per hub, about HUB_PART labels each): poff gives, for every
+// partition, where the chunk's group starts.  One workgroup per (hub,
+// partition) then totals the groups of all the hub's chunks in LDS and keeps
+// its best label.  No step needs an atomic on HBM.
+#define HUB_H 4096      // LDS slots of a chunk table
 #define HUB_BS 256
+
+__device__ __forceinline__ u32 hub_part_hash(i32 c)
+{
+    return (u32)c * 0x85EBCA77u;  // odd: a bijection of the 32-bit labels
+}
+
+// Exclusive prefix sum over the 256 threads of a workgroup; *total gets the
+// sum.  wsum: 4 slots of LDS.
+__device__ __forceinline__ i32 block_excl_scan(i32 v, i32 *wsum, i32 *total)
+{
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    i32 x = v;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const i32 y = __shfl_up(x, d, 64);
+        if (lane >= d) x += y;
+    }
+    __syncthreads();
+    if (lane == 63) wsum[wid] = x;
+    __syncthreads();
+    i32 off = 0, tot = 0;
+#pragma unroll
+    for (int w = 0; w < SLM_BS / 64; w++) {
+        if (w < wid) off += wsum[w];
+        tot += wsum[w];
+    }
+    *total = tot;
+    return off + x - v;
+}
+
 __global__ __launch_bounds__(HUB_BS) void k_sweep_hub_chunk(
-    LevelView L, const i32 *__restrict__ hub_node, const i32 *__restrict__ chunk_hub,
-    const i64 *__restrict__ chunk_beg, const i64 *__restrict__ tab_off,
-    const i32 *__restrict__ lab, i32 *__restrict__ tkey, i32 *__restrict__ tval,
-    i32 *__restrict__ hub_win)
+    LevelView L, const i32 *__restrict__ hub_node, const i32 *__restrict__ hub_logp,
+    const i32 *__restrict__ chunk_hub, const i64 *__restrict__ chunk_beg,
+    const i64 *__restrict__ chunk_out, const i64 *__restrict__ chunk_pbase,
+    const i32 *__restrict__ lab, int2 *__restrict__ part, i64 *__restrict__ poff,
+    i32 *__restrict__ cwin)
 {
     __shared__ i32 keys[HUB_H];
     __shared__ i32 vals[HUB_H];
     __shared__ i32 list[HUB_CHUNK];
+    __shared__ i32 hist[HUB_PMAX];
     __shared__ int cnt;
+    __shared__ i32 wsum[SLM_BS / 64];
     __shared__ i64 red[32];
+    const i32 h = chunk_hub[blockIdx.x];
+    const int logp = hub_logp[h];
+    const int P = 1 << logp;
     for (int i = threadIdx.x; i < HUB_H; i += HUB_BS) {
         keys[i] = -1;
         vals[i] = 0;
     }
+    for (int i = threadIdx.x; i < P; i += HUB_BS) hist[i] = 0;
     if (threadIdx.x == 0) cnt = 0;
     __syncthreads();
-    const i32 h = chunk_hub[blockIdx.x];
     const i32 node = hub_node[h];
     const i32 ci = lab[node];
     const i64 b = chunk_beg[blockIdx.x];
@@ -465,54 +507,165 @@ __global__ __launch_bounds__(HUB_BS) void k_sweep_hub_chunk(
         else table_insert<HUB_H>(keys, vals, list, &cnt, c[u], ed[u].y);
     }
     __syncthreads();
-    const i64 t0 = tab_off[h];
-    const u32 tmask = (u32)(tab_off[h + 1] - t0 - 1);
-    const int log2t = 31 - __builtin_clz(tmask + 1);
-    for (int i = threadIdx.x; i < cnt; i += HUB_BS) {
-        const i32 s = list[i];
-        const i32 c = keys[s];
-        const i32 v = vals[s];
-        u32 slot = hash_label(c) >> (32 - log2t);
-        for (u32 probe = 0; probe <= tmask; probe++) {
-            const i32 old = atomicCAS(&tkey[t0 + slot], -1, c);
-            if (old == -1 || old == c) {
-                atomicAdd(&tval[t0 + slot], v);
-                break;
-            }
-            slot = (slot + 1) & tmask;
+    // partition of each distinct label, and its rank inside the partition
+    const int nd = cnt;
+    int pr[U], rk[U];
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+        const int i = threadIdx.x + u * HUB_BS;
+        pr[u] = -1;
+        if (i < nd) {
+            const i32 cc = keys[list[i]];
+            pr[u] = logp ? (int)(hub_part_hash(cc) >> (32 - logp)) : 0;
+            rk[u] = atomicAdd(&hist[pr[u]], 1);
         }
     }
+    __syncthreads();
+    // exclusive prefix of the partition counts (P <= 4 * HUB_BS)
+    constexpr int PT = HUB_PMAX / HUB_BS;
+    i32 loc[PT];
+    i32 mine = 0;
+#pragma unroll
+    for (int q = 0; q < PT; q++) {
+        const int p = threadIdx.x * PT + q;
+        loc[q] = p < P ? hist[p] : 0;
+        mine += loc[q];
+    }
+    i32 tot;
+    i32 run = block_excl_scan(mine, wsum, &tot);
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < PT; q++) {
+        const int p = threadIdx.x * PT + q;
+        if (p < P) hist[p] = run;
+        run += loc[q];
+    }
+    __syncthreads();
+    const i64 ob = chunk_out[blockIdx.x];
+    const i64 pb = chunk_pbase[blockIdx.x];
+    for (int p = threadIdx.x; p <= P; p += HUB_BS) poff[pb + p] = ob + (p < P ? hist[p] : nd);
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+        if (pr[u] < 0) continue;
+        const i32 s = list[threadIdx.x + u * HUB_BS];
+        part[ob + hist[pr[u]] + rk[u]] = make_int2(keys[s], vals[s]);
+    }
     win = block_sum<i64>(win, red);
-    if (threadIdx.x == 0 && win) atomicAdd(&hub_win[h], (i32)win);
+    if (threadIdx.x == 0) cwin[blockIdx.x] = (i32)win;
 }
 
-// Best entry of one HUB_TILE-slot tile of a hub table; the occupied slots are
-// cleared behind, so the tables are empty again for the next sweep (level
-// set-up clears them once).
-__global__ __launch_bounds__(SLM_BS) void k_sweep_hub_tile(
-    LevelView L, const i32 *__restrict__ hub_node, const i32 *__restrict__ tile_hub,
-    const i64 *__restrict__ tab_off, const i32 *__restrict__ tile_first,
-    const i32 *__restrict__ sigma, i32 *__restrict__ tkey, i32 *__restrict__ tval,
-    i64 *__restrict__ tile_key, i32 *__restrict__ tile_id)
+// Adds w to label c in an LDS table of 2^tbits slots (tbits <= log2 HUB_TH);
+// false if the table is full (then nothing changes).
+__device__ __forceinline__ bool tile_insert(i32 *keys, i32 *vals, int tbits, i32 c, i32 w)
 {
+    const u32 mask = (1u << tbits) - 1;
+    u32 h = hash_label(c) >> (32 - tbits);
+    for (u32 probe = 0; probe <= mask; probe++) {
+        const i32 old = atomicCAS(&keys[h], -1, c);
+        if (old == -1 || old == c) {
+            atomicAdd(&vals[h], w);
+            return true;
+        }
+        h = (h + 1) & mask;
+    }
+    return false;
+}
+
+// Best label of one partition of one hub: the pairs of every chunk of the
+// hub that fall in the partition are totalled in an LDS table of 2^tbits
+// slots, then keyed.  A partition holding more than cap pairs is taken in
+// 2^logs passes, each over the labels whose next logs hash bits equal the
+// pass number.  As the hash is a bijection, a pass can see at most
+// 2^(32-logp-logs) distinct labels, so doubling the passes after a pass
+// filled the table ends with every pass fitting.
+__global__ __launch_bounds__(SLM_BS) void k_sweep_hub_tile(
+    LevelView L, const i32 *__restrict__ hub_node, const i32 *__restrict__ hub_logp,
+    const i32 *__restrict__ tile_hub, const i32 *__restrict__ tile_first,
+    const i32 *__restrict__ chunk_first, const i64 *__restrict__ chunk_pbase,
+    const int2 *__restrict__ part, const i64 *__restrict__ poff, const i32 *__restrict__ sigma,
+    int cap, int tbits, i64 *__restrict__ tile_key, i32 *__restrict__ tile_id)
+{
+    __shared__ i32 keys[HUB_TH];
+    __shared__ i32 vals[HUB_TH];
+    __shared__ i64 segb[SLM_BS];
+    __shared__ i32 pre[SLM_BS];
+    __shared__ i32 wsum[SLM_BS / 64];
+    __shared__ int full;
     __shared__ i64 red[32];
     const i32 h = tile_hub[blockIdx.x];
-    const i64 ki = L.k[hub_node[h]];
-    const i64 m2 = node_m2(L, hub_node[h]);
-    const i64 base = tab_off[h] + (i64)(blockIdx.x - tile_first[h]) * HUB_TILE;
+    const int p = blockIdx.x - tile_first[h];
+    const int logp = hub_logp[h];
+    const i32 c0 = chunk_first[h], c1 = chunk_first[h + 1];
+    const i32 node = hub_node[h];
+    const i64 ki = L.k[node];
+    const i64 m2 = node_m2(L, node);
+    // pairs in this partition over all chunks
+    i64 tot = 0;
+    for (i32 ch = c0 + threadIdx.x; ch < c1; ch += SLM_BS) {
+        const i64 pb = chunk_pbase[ch];
+        tot += poff[pb + p + 1] - poff[pb + p];
+    }
+    tot = block_sum<i64>(tot, red);
+    int logs = 0;
+    while (((i64)cap << logs) < tot && logp + logs < 32) logs++;
     i64 bk = INT64_MIN;
     i32 bc = INT32_MAX;
-    for (int i = threadIdx.x; i < HUB_TILE; i += SLM_BS) {
-        const i32 c = tkey[base + i];
-        if (c >= 0) {
-            const i64 key = m2 * (i64)tval[base + i] - ki * (i64)sigma[c];
-            if (better_key(key, c, bk, bc)) {
-                bk = key;
-                bc = c;
+    for (;;) {
+        bool failed = false;
+        for (int q = 0; q < (1 << logs) && !failed; q++) {
+            for (int i = threadIdx.x; i < (1 << tbits); i += SLM_BS) {
+                keys[i] = -1;
+                vals[i] = 0;
             }
-            tkey[base + i] = -1;
-            tval[base + i] = 0;
+            if (threadIdx.x == 0) full = 0;
+            for (i32 cb = c0; cb < c1; cb += SLM_BS) {
+                const i32 ch = cb + threadIdx.x;
+                i64 lo = 0, hi = 0;
+                if (ch < c1) {
+                    const i64 pb = chunk_pbase[ch];
+                    lo = poff[pb + p];
+                    hi = poff[pb + p + 1];
+                }
+                i32 n_all;
+                const i32 ex = block_excl_scan((i32)(hi - lo), wsum, &n_all);
+                segb[threadIdx.x] = lo;
+                pre[threadIdx.x] = ex;
+                __syncthreads();
+                const int nb = c1 - cb < SLM_BS ? c1 - cb : SLM_BS;
+                for (i32 j = threadIdx.x; j < n_all; j += SLM_BS) {
+                    int k0 = 0, k1 = nb;  // last k with pre[k] <= j
+                    while (k1 - k0 > 1) {
+                        const int mid = (k0 + k1) >> 1;
+                        if (pre[mid] <= j) k0 = mid;
+                        else k1 = mid;
+                    }
+                    const int2 cv = part[segb[k0] + (j - pre[k0])];
+                    if (logs > 0 &&
+                        (int)((hub_part_hash(cv.x) << logp) >> (32 - logs)) != q)
+                        continue;
+                    if (!tile_insert(keys, vals, tbits, cv.x, cv.y)) full = 1;
+                }
+                __syncthreads();
+            }
+            failed = full != 0;
+            __syncthreads();  // every thread has read full before it is reset
+            if (failed) break;
+            for (int i = threadIdx.x; i < (1 << tbits); i += SLM_BS) {
+                const i32 cc = keys[i];
+                if (cc >= 0) {
+                    const i64 key = m2 * (i64)vals[i] - ki * (i64)sigma[cc];
+                    if (better_key(key, cc, bk, bc)) {
+                        bk = key;
+                        bc = cc;
+                    }
+                }
+            }
+            __syncthreads();
         }
+        if (!failed) break;
+        logs++;
+        bk = INT64_MIN;
+        bc = INT32_MAX;
     }
     block_best(bk, bc, red);
     if (threadIdx.x == 0) {
@@ -523,8 +676,9 @@ __global__ __launch_bounds__(SLM_BS) void k_sweep_hub_tile(
 
 __global__ __launch_bounds__(64) void k_sweep_hub_final(
     LevelView L, const i32 *__restrict__ hub_node, const i32 *__restrict__ tile_first,
-    const i32 *__restrict__ lab, const i32 *__restrict__ sigma, const i64 *__restrict__ tile_key,
-    const i32 *__restrict__ tile_id, const i32 *__restrict__ hub_win, i32 *__restrict__ best_c,
+    const i32 *__restrict__ chunk_first, const i32 *__restrict__ lab,
+    const i32 *__restrict__ sigma, const i64 *__restrict__ tile_key,
+    const i32 *__restrict__ tile_id, const i32 *__restrict__ cwin, i32 *__restrict__ best_c,
     i64 *__restrict__ delta, i32 *__restrict__ w_own)
 {
     const i32 h = blockIdx.x;
@@ -536,9 +690,12 @@ __global__ __launch_bounds__(64) void k_sweep_hub_final(
             bc = tile_id[t];
         }
     group_best<64>(bk, bc);
+    i64 win = 0;
+    for (i32 ch = chunk_first[h] + threadIdx.x; ch < chunk_first[h + 1]; ch += 64) win += cwin[ch];
+    win = group_sum<64>(win);
     if (threadIdx.x == 0) {
         const i32 node = hub_node[h];
-        write_move(L, node, lab[node], L.k[node], hub_win[h], bk, bc, sigma, best_c, delta, w_own);
+        write_move(L, node, lab[node], L.k[node], win, bk, bc, sigma, best_c, delta, w_own);
     }
 }
 
@@ -552,8 +709,8 @@ static unsigned persistent_grid(i64 count, int per_block, int max_blocks)
 }
 
 void run_sweep(const LevelView &L, const Bins &Bn, const i32 *lab, const i32 *sigma,
-               i32 *best_c, i64 *delta, i32 *w_own, i32 *hub_keys, i32 *hub_vals,
-               i32 *hub_win, i64 *hub_tile_key, i32 *hub_tile_id, hipStream_t s,
+               i32 *best_c, i64 *delta, i32 *w_own, int2 *hub_part, i64 *hub_poff,
+               i32 *hub_cwin, i64 *hub_tile_key, i32 *hub_tile_id, hipStream_t s,
                const Fanout *F)
 {
     // streams: the hub chain and the zero rows stay on s; the other bins go
@@ -601,17 +758,16 @@ void run_sweep(const LevelView &L, const Bins &Bn, const i32 *lab, const i32 *si
         k_sweep_reg<4, 2><<<grid_for(cnt, SLM_BS / 4), SLM_BS, 0, st[2]>>>(
             L, Bn.rowd + Bn.off[BIN_8], cnt, Bn.ls, best_c, delta, w_own);
     if (Bn.nhub > 0) {
-        launch_fill_i32(hub_win, 0, Bn.nhub, s);
         k_sweep_hub_chunk<<<(unsigned)Bn.nchunk, HUB_BS, 0, s>>>(
-            L, Bn.hub_node, Bn.chunk_hub, Bn.chunk_beg, Bn.hub_tab_off, lab, hub_keys, hub_vals,
-            hub_win);
-        k_sweep_hub_tile<<<(unsigned)Bn.ntile, SLM_BS, 0, s>>>(L, Bn.hub_node, Bn.tile_hub,
-                                                              Bn.hub_tab_off, Bn.tile_off_of_hub,
-                                                              sigma, hub_keys, hub_vals,
-                                                              hub_tile_key, hub_tile_id);
-        k_sweep_hub_final<<<(unsigned)Bn.nhub, 64, 0, s>>>(L, Bn.hub_node, Bn.tile_off_of_hub, lab,
-                                                          sigma, hub_tile_key, hub_tile_id,
-                                                          hub_win, best_c, delta, w_own);
+            L, Bn.hub_node, Bn.hub_logp, Bn.chunk_hub, Bn.chunk_beg, Bn.chunk_out, Bn.chunk_pbase,
+            lab, hub_part, hub_poff, hub_cwin);
+        k_sweep_hub_tile<<<(unsigned)Bn.ntile, SLM_BS, 0, s>>>(
+            L, Bn.hub_node, Bn.hub_logp, Bn.tile_hub, Bn.tile_off_of_hub, Bn.chunk_off_of_hub,
+            Bn.chunk_pbase, hub_part, hub_poff, sigma, Bn.hub_cap, Bn.hub_tbits, hub_tile_key,
+            hub_tile_id);
+        k_sweep_hub_final<<<(unsigned)Bn.nhub, 64, 0, s>>>(
+            L, Bn.hub_node, Bn.tile_off_of_hub, Bn.chunk_off_of_hub, lab, sigma, hub_tile_key,
+            hub_tile_id, hub_cwin, best_c, delta, w_own);
     }
     cnt = Bn.off[BIN_ZERO + 1] - Bn.off[BIN_ZERO];
     nodes = Bn.nodes + Bn.off[BIN_ZERO];

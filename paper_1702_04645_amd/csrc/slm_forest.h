@@ -58,14 +58,18 @@ struct Work {
     uint8_t *head_e = nullptr; // nnz0 segment heads
     i64 *rank_e = nullptr;     // nnz0 + 1
 
-    // hub work space
-    i32 *hub_keys = nullptr, *hub_vals = nullptr, *hub_win = nullptr;
-    i64 hub_tab_cap = 0;
-    i64 hub_win_cap = 0;
+    // hub work space of the sweep (pairs, partition offsets, chunk weights)
+    // and of ASSIGN / re-pointing (per-chunk best)
+    int2 *hub_part = nullptr;
+    i64 hub_part_cap = 0;
+    i64 *hub_poff = nullptr;
+    i64 hub_poff_cap = 0;
+    i32 *hub_cwin = nullptr;
+    i64 hub_cwin_cap = 0;
     i64 *hub_ckey = nullptr;
     i32 *hub_cid = nullptr;
     i64 hub_chunk_cap = 0;
-    i64 *hub_tkey = nullptr;   // per table tile
+    i64 *hub_tkey = nullptr;   // per partition
     i32 *hub_tid = nullptr;
     i64 hub_tile_cap = 0;
 };

@@ -40,31 +40,40 @@ enum {
 };
 static const i64 kBinMaxDeg[NBINS] = {0, 8, 32, 64, 128, 256, 512, 1024, 2048, 4096, INT64_MAX};
 #define HUB_CHUNK 2048
-#define HUB_TILE 8192  // slots of a hub table finalized by one workgroup
+#define HUB_PART 1024  // distinct labels expected in one partition of a hub row
+#define HUB_PMAX 1024  // partitions of one hub row at most
+#define HUB_TH 4096    // LDS slots of a partition table
+#define HUB_TCAP 3072  // pairs a partition table takes in one pass
 
 struct Bins {
     i32 *nodes = nullptr;      // device: node ids grouped by bin
     i64 off[NBINS + 1] = {0};  // host: bin b = nodes[off[b] .. off[b+1])
-    // hub rows: work items (hub index, first entry) and per-hub tables
+    // hub rows: chunks of HUB_CHUNK entries, and 2^logp label partitions
+    // ("tiles") per hub
     i32 nhub = 0;
     i64 nchunk = 0;
-    i64 table_total = 0;       // sum of the hubs' table sizes
+    i64 hub_entries = 0;       // sum of the hubs' degrees
+    i64 npoff = 0;             // sum over chunks of (partitions of its hub + 1)
     i32 *hub_node = nullptr;   // device [nhub]
-    i64 *hub_tab_off = nullptr;// device [nhub+1] offsets into the HBM tables
+    i32 *hub_logp = nullptr;   // device [nhub] log2 of the hub's partition count
     i32 *chunk_hub = nullptr;  // device [nchunk] hub index of each chunk
     i64 *chunk_beg = nullptr;  // device [nchunk] first entry of each chunk
+    i64 *chunk_out = nullptr;  // device [nchunk] first slot of its pairs in the pair buffer
+    i64 *chunk_pbase = nullptr;// device [nchunk] first slot of its partition offsets
     i32 *chunk_off_of_hub = nullptr; // device [nhub+1] first chunk of each hub
-    i64 ntile = 0;             // table tiles (HUB_TILE slots each)
-    i32 *tile_hub = nullptr;   // device [ntile] hub index of each tile
-    i32 *tile_off_of_hub = nullptr; // device [nhub+1] first tile of each hub
+    i64 ntile = 0;             // partitions over all hubs
+    i32 *tile_hub = nullptr;   // device [ntile] hub index of each partition
+    i32 *tile_off_of_hub = nullptr; // device [nhub+1] first partition of each hub
+    int hub_cap = HUB_TCAP;    // pairs per pass of a partition table
+    int hub_tbits = 12;        // log2 of the partition table's slots (<= log2 HUB_TH)
     i64 *span = nullptr;       // device [2*nhub] entry range of each hub
     int4 *rowd = nullptr;      // device [n] per node in bin order: (node, degree,
                                // first entry low 32 bits, high 32 bits)
     int2 *ls = nullptr;        // device [n] scratch of the sweep: (label, S_label)
     // capacities of the arrays above: they only grow, so setting up a level
     // frees nothing (a free would synchronise the whole device)
-    i64 cap_tab_off = 0, cap_chunk_hub = 0, cap_chunk_beg = 0, cap_chunk_off = 0,
-        cap_tile_hub = 0, cap_tile_off = 0, cap_span = 0;
+    i64 cap_logp = 0, cap_chunk_hub = 0, cap_chunk_beg = 0, cap_chunk_out = 0,
+        cap_chunk_pbase = 0, cap_chunk_off = 0, cap_tile_hub = 0, cap_tile_off = 0, cap_span = 0;
 };
 
 // Read-only view of one level's graph as the kernels see it.
@@ -228,11 +237,11 @@ struct Fanout {
     hipEvent_t fork = nullptr, join[FAN_SIDE] = {nullptr, nullptr, nullptr};
 };
 // MAXIMAL sweep (Sec. 3.4): best_c, delta, w_own from labels and totals.
-// hub_tile_key / hub_tile_id: one slot per table tile.  F may be null (all
-// bins on s).
+// Hub scratch: hub_part [hub_entries] pairs, hub_poff [npoff], hub_cwin
+// [nchunk], hub_tile_key / hub_tile_id [ntile].  F may be null (all bins on s).
 void run_sweep(const LevelView &L, const Bins &B, const i32 *lab, const i32 *sigma,
-               i32 *best_c, i64 *delta, i32 *w_own, i32 *hub_keys, i32 *hub_vals,
-               i32 *hub_win, i64 *hub_tile_key, i32 *hub_tile_id, hipStream_t s,
+               i32 *best_c, i64 *delta, i32 *w_own, int2 *hub_part, i64 *hub_poff,
+               i32 *hub_cwin, i64 *hub_tile_key, i32 *hub_tile_id, hipStream_t s,
                const Fanout *F);
 // wc[i] = sum of A_ij over j with lab[j] == lab[i] (diagonal included); only
 // for nodes with active[lab[i]] != 0 when active is given.

@@ -96,3 +96,10 @@ def test_server_arguments_are_rejected_without_a_device():
     bad = slm.params(accept_p=(1 << 32) + 1)
     cfg = slm._ServerCfg(0, 0, 0, 1, 0, 0, 1, bad)
     assert lib.slm_server_create(C.byref(cfg), C.byref(h)) == slm.SLM_E_INVALID
+
+
+def test_set_option_rejects_without_a_device():
+    import paper_1702_04645_amd as slm
+    lib = slm.lib()
+    assert lib.slm_set_option(None, b"hub_table_bits", 8) == slm.SLM_E_INVALID
+    assert b"null" in lib.slm_last_error()

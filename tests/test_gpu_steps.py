@@ -95,6 +95,34 @@ def test_sweep(slm, name):
             assert np.array_equal(_np(wo), w_o)
 
 
+@pytest.mark.parametrize("name", ["star5000", "mixed_hub"])
+@pytest.mark.parametrize("bits,pairs", [(4, 8), (6, 1), (5, 3072), (12, 100)])
+def test_sweep_hub_passes(slm, name, bits, pairs):
+    """Hub rows with small partition tables: partitions cut into many passes,
+    and passes that fill the table cut again, give the same sweep."""
+    rp, col, w = GRAPHS[name]
+    say("sweep hub passes", name, bits, pairs)
+    g_or, a0, a1, lab1, nc1 = oracle_states(rp, col, w)
+    n = rp.size - 1
+    r = np.random.default_rng(4).integers(0, max(2, n // 3), n)
+    first = {}
+    canon = np.array([first.setdefault(int(c), len(first)) for c in r], np.int32)
+    labs = [(lab1, nc1), (np.arange(n, dtype=np.int32), n), (canon, len(first))]
+    with slm.Graph(rp, col, w) as g:
+        g.set_option("hub_table_bits", bits)
+        g.set_option("hub_pass_pairs", pairs)
+        for lab, nc in labs:
+            b_o, d_o, w_o = oracle.sweep(g_or, lab, nc)
+            b, d, wo = g.sweep(_t(lab), nc)
+            assert np.array_equal(_np(b), b_o)
+            assert np.array_equal(_np(d), d_o)
+            assert np.array_equal(_np(wo), w_o)
+        with pytest.raises(slm.SlmError):
+            g.set_option("hub_table_bits", 13)
+        with pytest.raises(slm.SlmError):
+            g.set_option("no_such_option", 1)
+
+
 @pytest.mark.parametrize("name", NAMES)
 def test_round(slm, name):
     rp, col, w = GRAPHS[name]
