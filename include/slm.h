@@ -287,16 +287,21 @@ slm_status slm_timing_enable(slm_graph *g, int enable);
 slm_status slm_timing_read(slm_graph *g, double *sweep_ms, int64_t *sweeps,
                            int64_t *entries, int64_t *bytes);
 
-/* Tuning of the sweep's hub rows (rows of more than 4096 entries, Sec. 3.4):
- * their distinct labels are totalled per partition of the label space in an
- * LDS table.  name:
- *   "hub_table_bits"  log2 of that table's slots, 4..12 (default 12);
- *   "hub_pass_pairs"  pairs one pass over a partition takes, 1..2^30
- *                     (default 3072); a larger partition is cut into more
- *                     passes, and a pass that fills the table is cut again.
- * Results never depend on these: they trade LDS use against passes.  Takes
- * effect from the next sweep.  SLM_E_INVALID for an unknown name or a value
- * out of range (nothing changes). */
+/* Launch tuning of the MAXIMAL sweep (Sec. 3.4).  name:
+ *   "hub_table_bits"      hub rows (more than 4096 entries) total their
+ *                         distinct labels per partition of the label space
+ *                         in an LDS table of 2^value slots, 4..11 (default 11);
+ *   "hub_pass_pairs"      pairs one pass over such a partition takes, 1..2^30
+ *                         (default 1536); a larger partition is cut into more
+ *                         passes, and a pass that fills the table is cut again;
+ *   "grid_<d>"            workgroups of the persistent kernel of the degree bin
+ *                         whose largest degree is d (64, 128, ..., 4096),
+ *                         0..65535 (0: the default);
+ *   "fanout_min_entries"  the degree bins run on the handle's side streams at
+ *                         levels of at least this many entries (default 2^22).
+ * Results never depend on these.  Takes effect from the next sweep.
+ * SLM_E_INVALID for an unknown name or a value out of range (nothing
+ * changes). */
 slm_status slm_set_option(slm_graph *g, const char *name, int64_t value);
 
 /* Message of the calling thread's last failed call. */

@@ -340,6 +340,10 @@ class Batch(Graph):
     def __len__(self):
         return len(self.sizes)
 
+    def set_option(self, name: str, value: int):
+        """Tuning knob of the sweep (`slm_set_option`); results never change."""
+        _check(lib().slm_set_option(self._h, name.encode(), int(value)))
+
     def run(self, p: Params | None = None, seeds=None):
         """Full runs of every graph; returns one list of LevelResult per graph."""
         if p is None:

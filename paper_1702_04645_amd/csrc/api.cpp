@@ -141,14 +141,17 @@ static void grow_buf(T *&p, i64 &cap, i64 need)
 static void release_bins(slm_graph *g)
 {
     Bins &B = g->bins;
-    for (void *p : {(void *)B.hub_logp, (void *)B.chunk_hub, (void *)B.chunk_beg,
-                    (void *)B.chunk_out, (void *)B.chunk_pbase, (void *)B.chunk_off_of_hub,
-                    (void *)B.tile_hub, (void *)B.tile_off_of_hub, (void *)B.span})
+    for (void *p : {(void *)B.chunk_hub, (void *)B.chunk_beg, (void *)B.hchunk,
+                    (void *)B.chunk_off_of_hub, (void *)B.htile, (void *)B.tile_off_of_hub,
+                    (void *)B.span})
         if (p) (void)hipFree(p);
     const int cap = B.hub_cap, tbits = B.hub_tbits;
+    i32 grid[NBINS];
+    for (int b = 0; b < NBINS; b++) grid[b] = B.grid_cap[b];
     B = Bins();
     B.hub_cap = cap;
     B.hub_tbits = tbits;
+    for (int b = 0; b < NBINS; b++) B.grid_cap[b] = grid[b];
 }
 
 static void grow_i32(i32 *&p, i64 &cap, i64 need)
@@ -194,47 +197,62 @@ static void setup_level(slm_graph *g)
             HIPCHK(hipMemcpyAsync(span.data(), B.span, sizeof(i64) * 2 * nhub,
                                   hipMemcpyDeviceToHost, s));
             HIPCHK(hipStreamSynchronize(s));
-            std::vector<i32> logp(nhub);
+            std::vector<i32> hnode(nhub);
+            HIPCHK(hipMemcpyAsync(hnode.data(), B.hub_node, sizeof(i32) * nhub,
+                                  hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
             std::vector<i32> chunk_first(nhub + 1, 0);
             std::vector<i32> chunk_hub;
-            std::vector<i64> chunk_beg, chunk_out, chunk_pbase;
+            std::vector<i64> chunk_beg;
+            std::vector<HubChunk> hchunk;
             std::vector<i32> tile_first(nhub + 1, 0);
-            std::vector<i32> tile_hub;
+            std::vector<HubTile> htile;
             i64 out = 0, pb = 0;
             for (i64 h = 0; h < nhub; h++) {
                 const i64 b0 = span[2 * h], b1 = span[2 * h + 1], deg = b1 - b0;
                 int lp = 0;
                 while (((i64)HUB_PART << lp) < deg && (1 << lp) < HUB_PMAX) lp++;
-                logp[h] = lp;
-                tile_first[h] = (i32)tile_hub.size();
-                for (i64 q = 0; q < ((i64)1 << lp); q++) tile_hub.push_back((i32)h);
+                const i64 pb0 = pb;
                 chunk_first[h] = (i32)chunk_hub.size();
                 for (i64 c = b0; c < b1; c += HUB_CHUNK) {
                     chunk_hub.push_back((i32)h);
                     chunk_beg.push_back(c);
-                    chunk_out.push_back(out + (c - b0));
-                    chunk_pbase.push_back(pb);
+                    HubChunk hc{};
+                    hc.beg = c;
+                    hc.end = c + HUB_CHUNK < b1 ? c + HUB_CHUNK : b1;
+                    hc.out = out + (c - b0);
+                    hc.pbase = pb;
+                    hc.node = hnode[h];
+                    hc.logp = lp;
+                    hchunk.push_back(hc);
                     pb += ((i64)1 << lp) + 1;
+                }
+                tile_first[h] = (i32)htile.size();
+                for (i32 q = 0; q < (1 << lp); q++) {
+                    HubTile ht{};
+                    ht.pbase0 = pb0;
+                    ht.node = hnode[h];
+                    ht.c0 = chunk_first[h];
+                    ht.nch = (i32)chunk_hub.size() - chunk_first[h];
+                    ht.logp = lp;
+                    ht.p = q;
+                    htile.push_back(ht);
                 }
                 out += deg;
             }
             chunk_first[nhub] = (i32)chunk_hub.size();
-            tile_first[nhub] = (i32)tile_hub.size();
-            B.ntile = (i64)tile_hub.size();
+            tile_first[nhub] = (i32)htile.size();
+            B.ntile = (i64)htile.size();
             B.nchunk = (i64)chunk_hub.size();
             B.hub_entries = out;
             B.npoff = pb;
-            grow_buf(B.hub_logp, B.cap_logp, nhub);
-            grow_buf(B.tile_hub, B.cap_tile_hub, B.ntile);
+            grow_buf(B.htile, B.cap_htile, B.ntile);
             grow_buf(B.tile_off_of_hub, B.cap_tile_off, nhub + 1);
             grow_buf(B.chunk_off_of_hub, B.cap_chunk_off, nhub + 1);
             grow_buf(B.chunk_hub, B.cap_chunk_hub, B.nchunk);
             grow_buf(B.chunk_beg, B.cap_chunk_beg, B.nchunk);
-            grow_buf(B.chunk_out, B.cap_chunk_out, B.nchunk);
-            grow_buf(B.chunk_pbase, B.cap_chunk_pbase, B.nchunk);
-            HIPCHK(hipMemcpyAsync(B.hub_logp, logp.data(), sizeof(i32) * nhub,
-                                  hipMemcpyHostToDevice, s));
-            HIPCHK(hipMemcpyAsync(B.tile_hub, tile_hub.data(), sizeof(i32) * B.ntile,
+            grow_buf(B.hchunk, B.cap_hchunk, B.nchunk);
+            HIPCHK(hipMemcpyAsync(B.htile, htile.data(), sizeof(HubTile) * B.ntile,
                                   hipMemcpyHostToDevice, s));
             HIPCHK(hipMemcpyAsync(B.tile_off_of_hub, tile_first.data(), sizeof(i32) * (nhub + 1),
                                   hipMemcpyHostToDevice, s));
@@ -244,9 +262,7 @@ static void setup_level(slm_graph *g)
                                   hipMemcpyHostToDevice, s));
             HIPCHK(hipMemcpyAsync(B.chunk_beg, chunk_beg.data(), sizeof(i64) * B.nchunk,
                                   hipMemcpyHostToDevice, s));
-            HIPCHK(hipMemcpyAsync(B.chunk_out, chunk_out.data(), sizeof(i64) * B.nchunk,
-                                  hipMemcpyHostToDevice, s));
-            HIPCHK(hipMemcpyAsync(B.chunk_pbase, chunk_pbase.data(), sizeof(i64) * B.nchunk,
+            HIPCHK(hipMemcpyAsync(B.hchunk, hchunk.data(), sizeof(HubChunk) * B.nchunk,
                                   hipMemcpyHostToDevice, s));
             if (B.ntile > W.hub_tile_cap) {
                 if (W.hub_tkey) HIPCHK(hipFree(W.hub_tkey));
@@ -1081,7 +1097,7 @@ slm_status slm_sweep(slm_graph *g, const int32_t *lab_dev, int64_t n_c, int32_t 
     if (g->timing) HIPCHK(hipEventRecord(g->ev0, g->s));
     run_sweep(L, g->bins, lab_dev, g->W.sigma, best_c_dev, delta_dev, w_own_dev, g->W.hub_part,
               g->W.hub_poff, g->W.hub_cwin, g->W.hub_tkey, g->W.hub_tid, g->s,
-              g->W.fan.side[0] && g->nnz >= FAN_MIN_ENTRIES ? &g->W.fan : nullptr);
+              g->W.fan.use(g->nnz));
     if (g->timing) {
         HIPCHK(hipEventRecord(g->ev1, g->s));
         HIPCHK(hipEventSynchronize(g->ev1));
@@ -1263,13 +1279,23 @@ slm_status slm_set_option(slm_graph *g, const char *name, int64_t value)
     REQUIRE(g != nullptr && name != nullptr, SLM_E_INVALID, "null argument");
     const std::string k(name);
     if (k == "hub_table_bits") {
-        REQUIRE(value >= 4 && (1 << value) <= HUB_TH, SLM_E_INVALID,
-                "hub_table_bits must be in 4..12");
+        REQUIRE(value >= 4 && value <= 30 && (1 << value) <= HUB_TH, SLM_E_INVALID,
+                "hub_table_bits must be in 4..11");
         g->bins.hub_tbits = (int)value;
     } else if (k == "hub_pass_pairs") {
         REQUIRE(value >= 1 && value <= ((int64_t)1 << 30), SLM_E_INVALID,
                 "hub_pass_pairs must be in 1..2^30");
         g->bins.hub_cap = (int)value;
+    } else if (k.rfind("grid_", 0) == 0) {
+        int b = -1;
+        for (int q = BIN_64; q <= BIN_4096; q++)
+            if (k == "grid_" + std::to_string(kBinMaxDeg[q])) b = q;
+        REQUIRE(b >= 0, SLM_E_INVALID, "grid_<d> needs d in 64..4096, a bin's largest degree");
+        REQUIRE(value >= 0 && value <= 65535, SLM_E_INVALID, "grid_<d> must be in 0..65535");
+        g->bins.grid_cap[b] = (i32)value;
+    } else if (k == "fanout_min_entries") {
+        REQUIRE(value >= 0, SLM_E_INVALID, "fanout_min_entries must be >= 0");
+        g->W.fan.min_entries = value;
     } else {
         REQUIRE(false, SLM_E_INVALID, "unknown option");
     }

@@ -748,7 +748,7 @@ i64 maximal_moves(Work &W, const LevelView &Lv, const Bins &B, i64 nc, u64 seed,
     if (timing) HIPCHK(hipEventRecord(ev0, s));
     run_sweep(Lv, B, W.lab, W.sigma, W.best_c, W.delta, W.w_own, W.hub_part, W.hub_poff,
               W.hub_cwin, W.hub_tkey, W.hub_tid, s,
-              W.fan.side[0] && Lv.nnz >= FAN_MIN_ENTRIES ? &W.fan : nullptr);
+              W.fan.use(Lv.nnz));
     if (timing) HIPCHK(hipEventRecord(ev1, s));
     // candidates
     launch_fill_u8(W.act, 0, nc, s);

@@ -461,11 +461,8 @@ __device__ __forceinline__ i32 block_excl_scan(i32 v, i32 *wsum, i32 *total)
 }
 
 __global__ __launch_bounds__(HUB_BS) void k_sweep_hub_chunk(
-    LevelView L, const i32 *__restrict__ hub_node, const i32 *__restrict__ hub_logp,
-    const i32 *__restrict__ chunk_hub, const i64 *__restrict__ chunk_beg,
-    const i64 *__restrict__ chunk_out, const i64 *__restrict__ chunk_pbase,
-    const i32 *__restrict__ lab, int2 *__restrict__ part, i64 *__restrict__ poff,
-    i32 *__restrict__ cwin)
+    LevelView L, const HubChunk *__restrict__ hchunk, const i32 *__restrict__ lab,
+    int2 *__restrict__ part, i64 *__restrict__ poff, i32 *__restrict__ cwin)
 {
     __shared__ i32 keys[HUB_H];
     __shared__ i32 vals[HUB_H];
@@ -474,8 +471,8 @@ __global__ __launch_bounds__(HUB_BS) void k_sweep_hub_chunk(
     __shared__ int cnt;
     __shared__ i32 wsum[SLM_BS / 64];
     __shared__ i64 red[32];
-    const i32 h = chunk_hub[blockIdx.x];
-    const int logp = hub_logp[h];
+    const HubChunk hc = hchunk[blockIdx.x];
+    const int logp = hc.logp;
     const int P = 1 << logp;
     for (int i = threadIdx.x; i < HUB_H; i += HUB_BS) {
         keys[i] = -1;
@@ -484,11 +481,9 @@ __global__ __launch_bounds__(HUB_BS) void k_sweep_hub_chunk(
     for (int i = threadIdx.x; i < P; i += HUB_BS) hist[i] = 0;
     if (threadIdx.x == 0) cnt = 0;
     __syncthreads();
-    const i32 node = hub_node[h];
+    const i32 node = hc.node;
     const i32 ci = lab[node];
-    const i64 b = chunk_beg[blockIdx.x];
-    i64 end = b + HUB_CHUNK;
-    if (end > L.rp[node + 1]) end = L.rp[node + 1];
+    const i64 b = hc.beg, end = hc.end;
     constexpr int U = HUB_CHUNK / HUB_BS;
     int2 ed[U];
     i32 c[U];
@@ -541,8 +536,8 @@ __global__ __launch_bounds__(HUB_BS) void k_sweep_hub_chunk(
         run += loc[q];
     }
     __syncthreads();
-    const i64 ob = chunk_out[blockIdx.x];
-    const i64 pb = chunk_pbase[blockIdx.x];
+    const i64 ob = hc.out;
+    const i64 pb = hc.pbase;
     for (int p = threadIdx.x; p <= P; p += HUB_BS) poff[pb + p] = ob + (p < P ? hist[p] : nd);
 #pragma unroll
     for (int u = 0; u < U; u++) {
@@ -579,11 +574,9 @@ __device__ __forceinline__ bool tile_insert(i32 *keys, i32 *vals, int tbits, i32
 // 2^(32-logp-logs) distinct labels, so doubling the passes after a pass
 // filled the table ends with every pass fitting.
 __global__ __launch_bounds__(SLM_BS) void k_sweep_hub_tile(
-    LevelView L, const i32 *__restrict__ hub_node, const i32 *__restrict__ hub_logp,
-    const i32 *__restrict__ tile_hub, const i32 *__restrict__ tile_first,
-    const i32 *__restrict__ chunk_first, const i64 *__restrict__ chunk_pbase,
-    const int2 *__restrict__ part, const i64 *__restrict__ poff, const i32 *__restrict__ sigma,
-    int cap, int tbits, i64 *__restrict__ tile_key, i32 *__restrict__ tile_id)
+    LevelView L, const HubTile *__restrict__ htile, const int2 *__restrict__ part,
+    const i64 *__restrict__ poff, const i32 *__restrict__ sigma, int cap, int tbits,
+    i64 *__restrict__ tile_key, i32 *__restrict__ tile_id)
 {
     __shared__ i32 keys[HUB_TH];
     __shared__ i32 vals[HUB_TH];
@@ -592,18 +585,20 @@ __global__ __launch_bounds__(SLM_BS) void k_sweep_hub_tile(
     __shared__ i32 wsum[SLM_BS / 64];
     __shared__ int full;
     __shared__ i64 red[32];
-    const i32 h = tile_hub[blockIdx.x];
-    const int p = blockIdx.x - tile_first[h];
-    const int logp = hub_logp[h];
-    const i32 c0 = chunk_first[h], c1 = chunk_first[h + 1];
-    const i32 node = hub_node[h];
+    const HubTile ht = htile[blockIdx.x];
+    const int p = ht.p;
+    const int logp = ht.logp;
+    const i64 pstride = ((i64)1 << logp) + 1;  // offsets per chunk
+    const i64 pb0 = ht.pbase0 + p;              // this partition's offset in chunk 0
+    const i32 c0 = 0, c1 = ht.nch;              // chunks, numbered within the hub
+    const i32 node = ht.node;
     const i64 ki = L.k[node];
     const i64 m2 = node_m2(L, node);
     // pairs in this partition over all chunks
     i64 tot = 0;
     for (i32 ch = c0 + threadIdx.x; ch < c1; ch += SLM_BS) {
-        const i64 pb = chunk_pbase[ch];
-        tot += poff[pb + p + 1] - poff[pb + p];
+        const i64 pb = pb0 + ch * pstride;
+        tot += poff[pb + 1] - poff[pb];
     }
     tot = block_sum<i64>(tot, red);
     int logs = 0;
@@ -622,9 +617,9 @@ __global__ __launch_bounds__(SLM_BS) void k_sweep_hub_tile(
                 const i32 ch = cb + threadIdx.x;
                 i64 lo = 0, hi = 0;
                 if (ch < c1) {
-                    const i64 pb = chunk_pbase[ch];
-                    lo = poff[pb + p];
-                    hi = poff[pb + p + 1];
+                    const i64 pb = pb0 + ch * pstride;
+                    lo = poff[pb];
+                    hi = poff[pb + 1];
                 }
                 i32 n_all;
                 const i32 ex = block_excl_scan((i32)(hi - lo), wsum, &n_all);
@@ -708,6 +703,11 @@ static unsigned persistent_grid(i64 count, int per_block, int max_blocks)
     return (unsigned)g;
 }
 
+static int grid_of(const Bins &Bn, int b)
+{
+    return Bn.grid_cap[b] > 0 ? Bn.grid_cap[b] : 8192;
+}
+
 void run_sweep(const LevelView &L, const Bins &Bn, const i32 *lab, const i32 *sigma,
                i32 *best_c, i64 *delta, i32 *w_own, int2 *hub_part, i64 *hub_poff,
                i32 *hub_cwin, i64 *hub_tile_key, i32 *hub_tile_id, hipStream_t s,
@@ -733,12 +733,14 @@ void run_sweep(const LevelView &L, const Bins &Bn, const i32 *lab, const i32 *si
     nodes = Bn.nodes + Bn.off[B];                                                      \
     if (cnt > 0)                                                                       \
         k_sweep_hash<G, H, U>                                                          \
-            <<<persistent_grid(cnt, G <= 64 ? SLM_BS / G : 1, 8192), G <= 64 ? SLM_BS : G, \
+            <<<persistent_grid(cnt, G <= 64 ? SLM_BS / G : 1, grid_of(Bn, B)),               \
+               G <= 64 ? SLM_BS : G,                                                   \
                0, STREAM>>>(L, nodes, cnt, lab, sigma, best_c, delta, w_own);
 #define PIPE_BIN(B, G, H, U, STREAM)                                                   \
     cnt = Bn.off[B + 1] - Bn.off[B];                                                   \
     if (cnt > 0)                                                                       \
-        k_sweep_pipe<G, H, U><<<persistent_grid(cnt, SLM_BS / G, 8192), SLM_BS, 0, STREAM>>>( \
+        k_sweep_pipe<G, H, U><<<persistent_grid(cnt, SLM_BS / G, grid_of(Bn, B)), SLM_BS, 0,  \
+                                STREAM>>>(                                             \
             L, Bn.rowd + Bn.off[B], cnt, Bn.ls, best_c, delta, w_own);
     PIPE_BIN(BIN_512, 64, 1024, 8, st[0])
     PIPE_BIN(BIN_256, 64, 512, 4, st[0])
@@ -758,13 +760,11 @@ void run_sweep(const LevelView &L, const Bins &Bn, const i32 *lab, const i32 *si
         k_sweep_reg<4, 2><<<grid_for(cnt, SLM_BS / 4), SLM_BS, 0, st[2]>>>(
             L, Bn.rowd + Bn.off[BIN_8], cnt, Bn.ls, best_c, delta, w_own);
     if (Bn.nhub > 0) {
-        k_sweep_hub_chunk<<<(unsigned)Bn.nchunk, HUB_BS, 0, s>>>(
-            L, Bn.hub_node, Bn.hub_logp, Bn.chunk_hub, Bn.chunk_beg, Bn.chunk_out, Bn.chunk_pbase,
-            lab, hub_part, hub_poff, hub_cwin);
-        k_sweep_hub_tile<<<(unsigned)Bn.ntile, SLM_BS, 0, s>>>(
-            L, Bn.hub_node, Bn.hub_logp, Bn.tile_hub, Bn.tile_off_of_hub, Bn.chunk_off_of_hub,
-            Bn.chunk_pbase, hub_part, hub_poff, sigma, Bn.hub_cap, Bn.hub_tbits, hub_tile_key,
-            hub_tile_id);
+        k_sweep_hub_chunk<<<(unsigned)Bn.nchunk, HUB_BS, 0, s>>>(L, Bn.hchunk, lab, hub_part,
+                                                                hub_poff, hub_cwin);
+        k_sweep_hub_tile<<<(unsigned)Bn.ntile, SLM_BS, 0, s>>>(L, Bn.htile, hub_part, hub_poff,
+                                                              sigma, Bn.hub_cap, Bn.hub_tbits,
+                                                              hub_tile_key, hub_tile_id);
         k_sweep_hub_final<<<(unsigned)Bn.nhub, 64, 0, s>>>(
             L, Bn.hub_node, Bn.tile_off_of_hub, Bn.chunk_off_of_hub, lab, sigma, hub_tile_key,
             hub_tile_id, hub_cwin, best_c, delta, w_own);

@@ -42,8 +42,23 @@ static const i64 kBinMaxDeg[NBINS] = {0, 8, 32, 64, 128, 256, 512, 1024, 2048, 4
 #define HUB_CHUNK 2048
 #define HUB_PART 1024  // distinct labels expected in one partition of a hub row
 #define HUB_PMAX 1024  // partitions of one hub row at most
-#define HUB_TH 4096    // LDS slots of a partition table
-#define HUB_TCAP 3072  // pairs a partition table takes in one pass
+#define HUB_TH 2048    // LDS slots of a partition table
+#define HUB_TCAP 1536  // pairs a partition table takes in one pass
+
+// Work item of the sweep's hub chunk kernel: entries [beg, end) of hub row
+// `node`; its distinct labels go to pairs [out ..) and its partition offsets
+// to [pbase, pbase + 2^logp].
+struct HubChunk {
+    i64 beg, end, out, pbase;
+    i32 node, logp, pad0, pad1;
+};
+// Work item of the hub partition kernel: partition p of hub row `node`,
+// whose nch chunks (from c0) keep their offsets from pbase0 on, 2^logp + 1
+// per chunk.
+struct HubTile {
+    i64 pbase0;
+    i32 node, c0, nch, logp, p, pad;
+};
 
 struct Bins {
     i32 *nodes = nullptr;      // device: node ids grouped by bin
@@ -55,25 +70,25 @@ struct Bins {
     i64 hub_entries = 0;       // sum of the hubs' degrees
     i64 npoff = 0;             // sum over chunks of (partitions of its hub + 1)
     i32 *hub_node = nullptr;   // device [nhub]
-    i32 *hub_logp = nullptr;   // device [nhub] log2 of the hub's partition count
     i32 *chunk_hub = nullptr;  // device [nchunk] hub index of each chunk
     i64 *chunk_beg = nullptr;  // device [nchunk] first entry of each chunk
-    i64 *chunk_out = nullptr;  // device [nchunk] first slot of its pairs in the pair buffer
-    i64 *chunk_pbase = nullptr;// device [nchunk] first slot of its partition offsets
+    HubChunk *hchunk = nullptr;// device [nchunk]
     i32 *chunk_off_of_hub = nullptr; // device [nhub+1] first chunk of each hub
     i64 ntile = 0;             // partitions over all hubs
-    i32 *tile_hub = nullptr;   // device [ntile] hub index of each partition
+    HubTile *htile = nullptr;  // device [ntile]
     i32 *tile_off_of_hub = nullptr; // device [nhub+1] first partition of each hub
     int hub_cap = HUB_TCAP;    // pairs per pass of a partition table
-    int hub_tbits = 12;        // log2 of the partition table's slots (<= log2 HUB_TH)
+    int hub_tbits = 11;        // log2 of the partition table's slots (<= log2 HUB_TH)
+    // workgroups of the persistent sweep kernel of each bin (0: the default)
+    i32 grid_cap[NBINS] = {0};
     i64 *span = nullptr;       // device [2*nhub] entry range of each hub
     int4 *rowd = nullptr;      // device [n] per node in bin order: (node, degree,
                                // first entry low 32 bits, high 32 bits)
     int2 *ls = nullptr;        // device [n] scratch of the sweep: (label, S_label)
     // capacities of the arrays above: they only grow, so setting up a level
     // frees nothing (a free would synchronise the whole device)
-    i64 cap_logp = 0, cap_chunk_hub = 0, cap_chunk_beg = 0, cap_chunk_out = 0,
-        cap_chunk_pbase = 0, cap_chunk_off = 0, cap_tile_hub = 0, cap_tile_off = 0, cap_span = 0;
+    i64 cap_chunk_hub = 0, cap_chunk_beg = 0, cap_hchunk = 0, cap_chunk_off = 0, cap_htile = 0,
+        cap_tile_off = 0, cap_span = 0;
 };
 
 // Read-only view of one level's graph as the kernels see it.
@@ -235,6 +250,9 @@ void run_assign(const LevelView &L, const Bins &B, i32 *a, i64 *hub_key, i32 *hu
 struct Fanout {
     hipStream_t side[FAN_SIDE] = {nullptr, nullptr, nullptr};
     hipEvent_t fork = nullptr, join[FAN_SIDE] = {nullptr, nullptr, nullptr};
+    i64 min_entries = FAN_MIN_ENTRIES;  // levels with fewer entries stay on one stream
+    // the fan-out to use for a level of nnz entries (null: one stream)
+    const Fanout *use(i64 nnz) const { return side[0] && nnz >= min_entries ? this : nullptr; }
 };
 // MAXIMAL sweep (Sec. 3.4): best_c, delta, w_own from labels and totals.
 // Hub scratch: hub_part [hub_entries] pairs, hub_poff [npoff], hub_cwin
