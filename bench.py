@@ -30,21 +30,37 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def sweep_source_hash():
+    """First 16 hex digits of the sha256 of the sweep's sources (kernels and
+    the constants they share with the host)."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("k_sweep.hip", "slm_impl.h"):
+        with open(os.path.join(ROOT, "paper_1702_04645_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
 def measured_traffic(workload: str):
     """HBM bytes per sweep from the committed rocprofv3 counter summary, when
-    it was taken on this workload with the current sweep source; else None."""
-    import hashlib
+    it was taken on this workload with the current sweep sources; else None."""
     path = os.path.join(ROOT, "profiles", "%s_sweep_hbm_traffic.json" % workload)
-    src = os.path.join(ROOT, "paper_1702_04645_amd", "csrc", "k_sweep.hip")
     if not os.path.exists(path):
         return None
     with open(path) as f:
         rec = json.load(f)
-    with open(src, "rb") as f:
-        h = hashlib.sha256(f.read()).hexdigest()[:16]
-    if rec.get("sweep_source_sha256_16") != h:
+    if rec.get("sweep_source_sha256_16") != sweep_source_hash():
         return None
     return round(rec["sweep_traffic_bytes"] / 1e9, 4)
+
+
+def tuned_options(workload: str):
+    """Sweep launch options the autotuner picked for this workload, if kept."""
+    path = os.path.join(ROOT, "paper_1702_04645_amd", "tuned", "%s.json" % workload)
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        return json.load(f)["options"]
 
 
 def workload(name: str):
@@ -208,6 +224,7 @@ def batch_bench(args):
         "plain_sample": "%d members (every %d-th)" % (len(sample), stride),
         "create_s": round(t_create, 3),
         "sweep_gteps": round(tm["entries"] / sweep_s / 1e9, 3) if sweep_s > 0 else 0.0,
+        "launch_options": tuned or "library defaults",
         "sweeps_timed": tm["sweeps"],
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
@@ -329,6 +346,8 @@ def main():
     ap.add_argument("--serve-count", type=int, default=2000)
     ap.add_argument("--serve-rate", type=float, default=400.0)
     ap.add_argument("--serve-lanes", type=int, default=4)
+    ap.add_argument("--no-tune", action="store_true",
+                    help="library default launch options (no tuned/<workload>.json)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy 1 GiB device to device (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -362,6 +381,11 @@ def main():
     params = slm.params(seed=args.seed)
     g = slm.Graph(rp, col, w)
     info = g.level_info()
+    tuned = tuned_options(args.workload) if not args.no_tune else None
+    if tuned:
+        from paper_1702_04645_amd import autotune
+        autotune.apply(g, tuned)
+        log("launch options from tuned/%s.json" % args.workload)
     for i in range(args.warmup):
         log("warmup %d" % i)
         g.run(params)
@@ -397,6 +421,7 @@ def main():
         "data": "synthetic",
         "config": dict(cfg, nodes=n, entries=nnz, m2=info["m2"], seed_run=args.seed,
                        accept_p="1/2", max_rounds=64),
+        "launch_options": tuned or "library defaults",
         "sweeps_timed": tm["sweeps"],
         "sweep_ms_mean": round(tm["sweep_ms"] / max(tm["sweeps"], 1), 4),
         "levels": len(last) if last else 0,

@@ -174,23 +174,43 @@ __global__ __launch_bounds__(SLM_BS) void k_sweep_reg(LevelView L, const int4 *_
 // entries per lane: a lane issues all its entry loads, then all its label
 // gathers, before touching the table, so the memory latency of a row is paid
 // about once.
+// Adds w to label c in an LDS table of H slots (linear probing).  Returns the
+// slot when c was new to the table, else -1.
 template <int H>
-__device__ __forceinline__ void table_insert(i32 *keys, i32 *vals, i32 *list, i32 *cnt, i32 c,
-                                             i32 w)
+__device__ __forceinline__ i32 table_add(i32 *keys, i32 *vals, i32 c, i32 w)
 {
     u32 h = sw_slot<H>(c);
     for (int probe = 0; probe < H; probe++) {
         const i32 old = atomicCAS(&keys[h], -1, c);
-        if (old == -1) {
+        if (old == -1 || old == c) {
             atomicAdd(&vals[h], w);
-            list[atomicAdd(cnt, 1)] = (i32)h;
-            return;
-        }
-        if (old == c) {
-            atomicAdd(&vals[h], w);
-            return;
+            return old == -1 ? (i32)h : -1;
         }
         h = (h + 1) & (H - 1);
+    }
+    return -1;
+}
+
+// Appends the slot s of every lane with s >= 0 to list[*cnt ..] (and x to
+// xlist when X), one LDS atomic per group of G lanes in a wavefront instead
+// of one per lane: the lanes of a group take consecutive places in lane
+// order.  Groups of G >= 64 lanes may span several wavefronts sharing cnt.
+template <int G, bool X>
+__device__ __forceinline__ void group_append(i32 s, i32 *cnt, i32 *list, i32 *xlist, i32 x)
+{
+    const int lane = threadIdx.x & 63;
+    const u64 bal = __ballot(s >= 0);
+    u64 gm = ~0ull;
+    if constexpr (G < 64) gm = (((u64)1 << G) - 1) << (lane & (64 - G));
+    const u64 mine = bal & gm;
+    const int rank = __popcll(mine & (((u64)1 << lane) - 1));
+    const int leader = mine ? __ffsll((unsigned long long)mine) - 1 : lane;
+    i32 base = 0;
+    if (mine && lane == leader) base = atomicAdd(cnt, __popcll(mine));
+    base = __shfl(base, leader, 64);
+    if (s >= 0) {
+        list[base + rank] = s;
+        if constexpr (X) xlist[base + rank] = x;
     }
 }
 
@@ -237,9 +257,12 @@ __global__ __launch_bounds__(G <= 64 ? SLM_BS : G) void k_sweep_hash(
         i64 win = 0;
 #pragma unroll
         for (int u = 0; u < U; u++) {
-            if (c[u] < 0) continue;
-            if (c[u] == ci) win += ed[u].y;
-            else table_insert<H>(keys, vals, list, &s_cnt[gi], c[u], ed[u].y);
+            i32 sl = -1;
+            if (c[u] >= 0) {
+                if (c[u] == ci) win += ed[u].y;
+                else sl = table_add<H>(keys, vals, c[u], ed[u].y);
+            }
+            group_append<G, false>(sl, &s_cnt[gi], list, nullptr, 0);
         }
         sw_sync<G>();
         const int nd = s_cnt[gi];
@@ -278,28 +301,6 @@ __global__ __launch_bounds__(G <= 64 ? SLM_BS : G) void k_sweep_hash(
 // row i's table is read, row i+1's labels are.  The community total of each
 // table entry comes with its label (ls) and is kept beside the slot list, so
 // the table's read-out needs no further load.
-template <int H>
-__device__ __forceinline__ void table_insert_s(i32 *keys, i32 *vals, i32 *list, i32 *lsig,
-                                               i32 *cnt, i32 c, i32 w, i32 sg)
-{
-    u32 h = sw_slot<H>(c);
-    for (int probe = 0; probe < H; probe++) {
-        const i32 old = atomicCAS(&keys[h], -1, c);
-        if (old == -1) {
-            atomicAdd(&vals[h], w);
-            const int p = atomicAdd(cnt, 1);
-            list[p] = (i32)h;
-            lsig[p] = sg;
-            return;
-        }
-        if (old == c) {
-            atomicAdd(&vals[h], w);
-            return;
-        }
-        h = (h + 1) & (H - 1);
-    }
-}
-
 template <int G, int H, int U>
 __global__ __launch_bounds__(SLM_BS) void k_sweep_pipe(LevelView L, const int4 *__restrict__ rowd,
                                                       i64 count, const int2 *__restrict__ ls,
@@ -362,9 +363,12 @@ __global__ __launch_bounds__(SLM_BS) void k_sweep_pipe(LevelView L, const int4 *
 #pragma unroll
         for (int u = 0; u < U; u++) {
             const i32 c = lc[u].x;
-            if (c < 0) continue;
-            if (c == own.x) win += ed[u].y;
-            else table_insert_s<H>(keys, vals, list, lsig, &s_cnt[gi], c, ed[u].y, lc[u].y);
+            i32 sl = -1;
+            if (c >= 0) {
+                if (c == own.x) win += ed[u].y;
+                else sl = table_add<H>(keys, vals, c, ed[u].y);
+            }
+            group_append<G, true>(sl, &s_cnt[gi], list, lsig, lc[u].y);
         }
         sw_sync<G>();
         // labels of row i+1 while row i's table is read
@@ -497,9 +501,12 @@ __global__ __launch_bounds__(HUB_BS) void k_sweep_hub_chunk(
     i64 win = 0;
 #pragma unroll
     for (int u = 0; u < U; u++) {
-        if (c[u] < 0) continue;
-        if (c[u] == ci) win += ed[u].y;
-        else table_insert<HUB_H>(keys, vals, list, &cnt, c[u], ed[u].y);
+        i32 sl = -1;
+        if (c[u] >= 0) {
+            if (c[u] == ci) win += ed[u].y;
+            else sl = table_add<HUB_H>(keys, vals, c[u], ed[u].y);
+        }
+        group_append<64, false>(sl, &cnt, list, nullptr, 0);
     }
     __syncthreads();
     // partition of each distinct label, and its rank inside the partition
