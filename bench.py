@@ -224,7 +224,7 @@ def batch_bench(args):
         "plain_sample": "%d members (every %d-th)" % (len(sample), stride),
         "create_s": round(t_create, 3),
         "sweep_gteps": round(tm["entries"] / sweep_s / 1e9, 3) if sweep_s > 0 else 0.0,
-        "launch_options": tuned or "library defaults",
+        "launch_options": "library defaults",
         "sweeps_timed": tm["sweeps"],
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
