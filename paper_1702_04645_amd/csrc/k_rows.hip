@@ -190,6 +190,93 @@ __global__ __launch_bounds__(GroupGeom<G>::BSZ) void k_own(
     if (act && gl == 0) wc[node] = (i32)s;
 }
 
+// ------------------------------------------------------------------ short rows in registers
+// Rows of at most G*U entries (degree bins up to 64): G lanes per row, U
+// entries per lane, loaded together from the row descriptor (node, degree,
+// first entry), then every neighbour gathered together: two dependent loads
+// per row instead of a loop.
+template <int G, int U, bool REPOINT>
+__global__ __launch_bounds__(SLM_BS) void k_argmax_reg(
+    LevelView L, const int4 *__restrict__ rowd, i64 count, const i32 *__restrict__ lab,
+    const i32 *__restrict__ best_c, const uint8_t *__restrict__ accept, i32 *__restrict__ a)
+{
+    constexpr int NG = SLM_BS / G;
+    const int gl = threadIdx.x % G;
+    const i64 slot = (i64)blockIdx.x * NG + threadIdx.x / G;
+    const bool valid = slot < count;
+    const int4 rd = valid ? rowd[slot] : make_int4(0, 0, 0, 0);
+    const i32 node = rd.x;
+    const i64 e0 = (i64)(u32)rd.z | ((i64)rd.w << 32);
+    bool active = valid;
+    if constexpr (REPOINT) active = valid && accept[node];
+    int2 ed[U];
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+        const int j = gl + u * G;
+        ed[u] = (active && j < rd.y) ? L.e[e0 + j] : make_int2(-1, 0);
+    }
+    const i64 ki = active ? (i64)L.k[node] : 0;
+    const i64 m2 = active ? node_m2(L, node) : 0;
+    const i32 D = (REPOINT && active) ? best_c[node] : 0;
+    i32 kv[U], lv[U];
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+        const i32 v = ed[u].x;
+        const bool ok = v >= 0 && v != node;
+        kv[u] = ok ? L.k[v] : 0;
+        lv[u] = (REPOINT && ok) ? lab[v] : 0;
+    }
+    i64 bk = INT64_MIN;
+    i32 bj = INT32_MAX;
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+        const i32 v = ed[u].x;
+        if (v < 0 || v == node) continue;
+        if (REPOINT && lv[u] != D) continue;
+        const i64 key = m2 * (i64)ed[u].y - ki * (i64)kv[u];
+        if (better_key(key, v, bk, bj)) {
+            bk = key;
+            bj = v;
+        }
+    }
+    group_best<G>(bk, bj);
+    if (active && gl == 0) {
+        if (REPOINT) a[node] = bj;
+        else a[node] = (bj != INT32_MAX && bk > 0) ? bj : node;
+    }
+}
+
+template <int G, int U>
+__global__ __launch_bounds__(SLM_BS) void k_own_reg(
+    LevelView L, const int4 *__restrict__ rowd, i64 count, const i32 *__restrict__ lab,
+    const uint8_t *__restrict__ active, i32 *__restrict__ wc)
+{
+    constexpr int NG = SLM_BS / G;
+    const int gl = threadIdx.x % G;
+    const i64 slot = (i64)blockIdx.x * NG + threadIdx.x / G;
+    const bool valid = slot < count;
+    const int4 rd = valid ? rowd[slot] : make_int4(0, 0, 0, 0);
+    const i32 node = rd.x;
+    const i64 e0 = (i64)(u32)rd.z | ((i64)rd.w << 32);
+    const i32 ci = valid ? lab[node] : 0;
+    int2 ed[U];
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+        const int j = gl + u * G;
+        ed[u] = (valid && j < rd.y) ? L.e[e0 + j] : make_int2(-1, 0);
+    }
+    const bool act = valid && (active == nullptr || active[ci]);
+    i32 lv[U];
+#pragma unroll
+    for (int u = 0; u < U; u++) lv[u] = (act && ed[u].x >= 0) ? lab[ed[u].x] : -1;
+    i64 s = 0;
+#pragma unroll
+    for (int u = 0; u < U; u++)
+        if (lv[u] == ci && ed[u].x >= 0) s += ed[u].y;
+    s = group_sum<G, i64>(s);
+    if (act && gl == 0) wc[node] = (i32)s;
+}
+
 // ------------------------------------------------------------------ contraction rows
 // Per row u: distinct (lab_u, lab_v) with summed weights (own community and
 // diagonal included), written at rec[rp[u] ..]; cnt[u] = their number.
@@ -519,6 +606,11 @@ static void bin_launch_geom(const Bins &Bn, i64 &count, const i32 *&nodes, unsig
 #define FOR_LDS_BINS(X)                                                               \
     X(BIN_ZERO) X(BIN_8) X(BIN_32) X(BIN_64) X(BIN_128) X(BIN_256) X(BIN_512) X(BIN_1024)     \
     X(BIN_2048) X(BIN_4096)
+// ASSIGN, re-pointing and own weights: rows of degree <= 64 in registers
+// (bin, lanes per row, entries per lane), the others by lane-group loops
+#define FOR_SHORT_BINS(X) X(BIN_8, 4, 2) X(BIN_32, 8, 4) X(BIN_64, 16, 4)
+#define FOR_LONG_BINS(X)                                                              \
+    X(BIN_ZERO) X(BIN_128) X(BIN_256) X(BIN_512) X(BIN_1024) X(BIN_2048) X(BIN_4096)
 
 void run_strength_binned(const i64 *rp, const int2 *e, const Bins &Bn, i32 *k, i32 *diag,
                          i64 *m2_acc, hipStream_t s)
@@ -554,7 +646,16 @@ void run_assign(const LevelView &L, const Bins &Bn, i32 *a, i64 *hub_key, i32 *h
             k_argmax<BinShape<B>::G, false><<<gr, bl, 0, s>>>(L, nd, cnt, nullptr, nullptr, \
                                                               nullptr, a);            \
     }
-    FOR_LDS_BINS(X)
+    FOR_LONG_BINS(X)
+#undef X
+#define X(B, G, U)                                                                    \
+    {                                                                                 \
+        const i64 cnt = Bn.off[B + 1] - Bn.off[B];                                    \
+        if (cnt > 0)                                                                  \
+            k_argmax_reg<G, U, false><<<grid_for(cnt, SLM_BS / G), SLM_BS, 0, s>>>(   \
+                L, Bn.rowd + Bn.off[B], cnt, nullptr, nullptr, nullptr, a);           \
+    }
+    FOR_SHORT_BINS(X)
 #undef X
     if (Bn.nhub > 0) {
         k_hub_argmax<false><<<(unsigned)Bn.nchunk, SLM_BS, 0, s>>>(
@@ -576,7 +677,16 @@ void run_repoint(const LevelView &L, const Bins &Bn, const i32 *lab, const i32 *
         if (cnt > 0 && B != BIN_ZERO)                                                 \
             k_argmax<BinShape<B>::G, true><<<gr, bl, 0, s>>>(L, nd, cnt, lab, best_c, accept, a); \
     }
-    FOR_LDS_BINS(X)
+    FOR_LONG_BINS(X)
+#undef X
+#define X(B, G, U)                                                                    \
+    {                                                                                 \
+        const i64 cnt = Bn.off[B + 1] - Bn.off[B];                                    \
+        if (cnt > 0)                                                                  \
+            k_argmax_reg<G, U, true><<<grid_for(cnt, SLM_BS / G), SLM_BS, 0, s>>>(    \
+                L, Bn.rowd + Bn.off[B], cnt, lab, best_c, accept, a);                 \
+    }
+    FOR_SHORT_BINS(X)
 #undef X
     if (Bn.nhub > 0) {
         k_hub_argmax<true><<<(unsigned)Bn.nchunk, SLM_BS, 0, s>>>(
@@ -597,7 +707,16 @@ void run_own_weight(const LevelView &L, const Bins &Bn, const i32 *lab, const ui
         bin_launch_geom<B>(Bn, cnt, nd, gr, bl);                                      \
         if (cnt > 0) k_own<BinShape<B>::G><<<gr, bl, 0, s>>>(L, nd, cnt, lab, active, wc); \
     }
-    FOR_LDS_BINS(X)
+    FOR_LONG_BINS(X)
+#undef X
+#define X(B, G, U)                                                                    \
+    {                                                                                 \
+        const i64 cnt = Bn.off[B + 1] - Bn.off[B];                                    \
+        if (cnt > 0)                                                                  \
+            k_own_reg<G, U><<<grid_for(cnt, SLM_BS / G), SLM_BS, 0, s>>>(             \
+                L, Bn.rowd + Bn.off[B], cnt, lab, active, wc);                        \
+    }
+    FOR_SHORT_BINS(X)
 #undef X
     if (Bn.nhub > 0) {
         k_hub_own_zero<<<grid_for(Bn.nhub, SLM_BS), SLM_BS, 0, s>>>(Bn.hub_node, Bn.nhub, lab,
