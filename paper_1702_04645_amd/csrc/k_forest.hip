@@ -193,25 +193,88 @@ __device__ __forceinline__ i32 lca(i32 u, i32 v, const i32 *__restrict__ depth,
     return J[u];
 }
 
-// val[lca(u,v)] -= A_uv for every ordered pair (u,v), u != v, of one tree of
-// an active community (flat pass over CSR entries with their row ids).
-__global__ void k_lca_pass(const i32 *__restrict__ src, const int2 *__restrict__ e, i64 nnz,
-                           const i32 *__restrict__ comp, const uint8_t *__restrict__ act,
-                           const i32 *__restrict__ root, const i32 *__restrict__ depth,
-                           const i32 *__restrict__ J, i64 n, int K, i64 *__restrict__ val)
+// Row visitors: an operation on the entries of the rows whose community is
+// in play.  begin() reads a row's state and says whether the row takes part
+// (once per row, so rows of communities out of play cost one check), visit()
+// handles one of its entries.  Rows run by degree bin from their descriptors
+// (G lanes per row), hub rows by their chunks.
+template <int G, class Op>
+__global__ __launch_bounds__(G <= 64 ? SLM_BS : G) void k_visit_rows(LevelView L,
+                                                                    const int4 *__restrict__ rowd,
+                                                                    i64 count, Op op)
 {
-    for (i64 j = (i64)blockIdx.x * blockDim.x + threadIdx.x; j < nnz;
-         j += (i64)gridDim.x * blockDim.x) {
-        i32 u = src[j];
-        i32 c = comp[u];
-        if (!act[c]) continue;
-        int2 ed = e[j];
-        i32 v = ed.x;
-        if (v == u || comp[v] != c || root[v] != root[u]) continue;
-        i32 l = lca(u, v, depth, J, n, K);
+    constexpr int NG = G <= 64 ? SLM_BS / G : 1;
+    const int gl = threadIdx.x % G;
+    const i64 slot = (i64)blockIdx.x * NG + threadIdx.x / G;
+    if (slot >= count) return;
+    const int4 rd = rowd[slot];
+    typename Op::Row R;
+    if (!op.begin(rd.x, R)) return;
+    const i64 e0 = (i64)(u32)rd.z | ((i64)rd.w << 32);
+    for (int j = gl; j < rd.y; j += G) op.visit(R, L.e[e0 + j]);
+}
+
+template <class Op>
+__global__ __launch_bounds__(SLM_BS) void k_visit_hub(LevelView L,
+                                                     const HubChunk *__restrict__ hchunk, Op op)
+{
+    const HubChunk c = hchunk[blockIdx.x];
+    typename Op::Row R;
+    if (!op.begin(c.node, R)) return;
+    for (i64 j = c.beg + threadIdx.x; j < c.end; j += SLM_BS) op.visit(R, L.e[j]);
+}
+
+template <class Op>
+static void visit_rows(const LevelView &L, const Bins &Bn, const Op &op, hipStream_t s)
+{
+#define VISIT_BIN(B, G)                                                                \
+    {                                                                                  \
+        const i64 cnt = Bn.off[B + 1] - Bn.off[B];                                     \
+        if (cnt > 0)                                                                   \
+            k_visit_rows<G, Op><<<grid_for(cnt, G <= 64 ? SLM_BS / G : 1),               \
+                                  G <= 64 ? SLM_BS : G, 0, s>>>(L, Bn.rowd + Bn.off[B], cnt, op); \
+    }
+    VISIT_BIN(BIN_8, 4)
+    VISIT_BIN(BIN_32, 8)
+    VISIT_BIN(BIN_64, 16)
+    VISIT_BIN(BIN_128, 32)
+    VISIT_BIN(BIN_256, 64)
+    VISIT_BIN(BIN_512, 64)
+    VISIT_BIN(BIN_1024, 128)
+    VISIT_BIN(BIN_2048, 256)
+    VISIT_BIN(BIN_4096, 512)
+#undef VISIT_BIN
+    if (Bn.nhub > 0) k_visit_hub<Op><<<(unsigned)Bn.nchunk, SLM_BS, 0, s>>>(L, Bn.hchunk, op);
+}
+
+// val[lca(u,v)] -= A_uv for every ordered pair (u,v), u != v, of one tree of
+// an active community.
+struct LcaVisit {
+    const i32 *comp;
+    const uint8_t *act;
+    const i32 *root, *depth, *J;
+    i64 n;
+    int K;
+    i64 *val;
+    struct Row {
+        i32 u, c, r;
+    };
+    __device__ bool begin(i32 u, Row &R) const
+    {
+        R.u = u;
+        R.c = comp[u];
+        if (!act[R.c]) return false;
+        R.r = root[u];
+        return true;
+    }
+    __device__ void visit(const Row &R, int2 ed) const
+    {
+        const i32 v = ed.x;
+        if (v == R.u || comp[v] != R.c || root[v] != R.r) return;
+        const i32 l = lca(R.u, v, depth, J, n, K);
         atomicAdd((unsigned long long *)&val[l], (unsigned long long)(-(i64)ed.y));
     }
-}
+};
 
 // ------------------------------------------------------------------ block-aggregated totals
 // out[key[i]] (op)= val[i] for i < n, with an LDS hash per workgroup so that
@@ -401,35 +464,47 @@ __global__ void k_nca_step(const i32 *__restrict__ lab, const i32 *__restrict__ 
 
 // w(B, D) of every candidate: each cross entry (u, v), D = lab v, adds its
 // weight to the candidates whose tail holds u and whose target is D.
-__global__ void k_max_cross(const i32 *__restrict__ src, const int2 *__restrict__ e, i64 nnz,
-                            const i32 *__restrict__ lab, const uint8_t *__restrict__ hasc,
-                            const uint8_t *__restrict__ act, const i32 *__restrict__ nca,
-                            const i32 *__restrict__ P, const i32 *__restrict__ best_c,
-                            const i64 *__restrict__ coff, const i32 *__restrict__ clist,
-                            i32 *__restrict__ wbd)
-{
-    for (i64 j = (i64)blockIdx.x * blockDim.x + threadIdx.x; j < nnz;
-         j += (i64)gridDim.x * blockDim.x) {
-        i32 u = src[j];
-        i32 c = lab[u];
-        if (!hasc[c]) continue;
-        int2 ed = e[j];
-        i32 D = lab[ed.x];
-        if (D == c) continue;
-        if (act[c]) {
-            i32 x = nca[u];
+// w(B, D) for the candidates of MAXIMAL: every entry (u, v) from a community
+// holding candidates to another community D adds its weight to the nearest
+// candidate ancestors of u that move to D, and to the community's cycle
+// candidates that move to D.
+struct CrossVisit {
+    const i32 *lab;
+    const uint8_t *hasc, *act;
+    const i32 *nca, *P, *best_c;
+    const i64 *coff;
+    const i32 *clist;
+    i32 *wbd;
+    struct Row {
+        i32 u, c;
+        bool act;
+    };
+    __device__ bool begin(i32 u, Row &R) const
+    {
+        R.u = u;
+        R.c = lab[u];
+        if (!hasc[R.c]) return false;
+        R.act = act[R.c] != 0;
+        return true;
+    }
+    __device__ void visit(const Row &R, int2 ed) const
+    {
+        const i32 D = lab[ed.x];
+        if (D == R.c) return;
+        if (R.act) {
+            i32 x = nca[R.u];
             // every step climbs strictly; the bound only guards the loop
             for (int guard = 0; x >= 0 && guard < (1 << 30); guard++) {
                 if (best_c[x] == D) atomicAdd(&wbd[x], ed.y);
                 x = nca[P[x]];
             }
         }
-        for (i64 t = coff[c]; t < coff[c + 1]; t++) {
-            i32 z = clist[t];
+        for (i64 t = coff[R.c]; t < coff[R.c + 1]; t++) {
+            const i32 z = clist[t];
             if (best_c[z] == D) atomicAdd(&wbd[z], ed.y);
         }
     }
-}
+};
 
 __device__ __forceinline__ u32 accept_draw(u64 seed, int level, int round, i32 node)
 {
@@ -631,16 +706,16 @@ static void subtree_sums(Work &W, const i32 *comp, const uint8_t *act, i64 n, co
 // cut(T_x) = w(T_x, c \ T_x) for every node of the active communities:
 // subtree sums of w(u, c \ u) minus, at every lowest common ancestor, the
 // weight of the tree pairs meeting there.
-static void subtree_cuts(Work &W, const LevelView &Lv, const i32 *comp, const uint8_t *act,
-                         const Forest &F, const i32 *w_other, i64 *cut, hipStream_t s)
+static void subtree_cuts(Work &W, const LevelView &Lv, const Bins &B, const i32 *comp,
+                         const uint8_t *act, const Forest &F, const i32 *w_other, i64 *cut,
+                         hipStream_t s)
 {
     const i64 n = Lv.n;
     const unsigned g = node_grid(n);
     i64 *val = W.key;  // temporary
     k_sub_init<<<g, SLM_BS, 0, s>>>(comp, act, n, w_other, nullptr, val);
     if (Lv.nnz > 0)
-        k_lca_pass<<<node_grid(Lv.nnz), SLM_BS, 0, s>>>(W.src, Lv.e, Lv.nnz, comp, act, F.root,
-                                                        F.depth, W.J, n, F.K, val);
+        visit_rows(Lv, B, LcaVisit{comp, act, F.root, F.depth, W.J, n, F.K, val}, s);
     subtree_sums(W, comp, act, n, F, nullptr, val, cut, s);
 }
 
@@ -768,7 +843,7 @@ i64 maximal_moves(Work &W, const LevelView &Lv, const Bins &B, i64 nc, u64 seed,
     // forest of the communities with non-cycle candidates
     Forest F = build_forest(W, W.a, W.lab, W.act, n, s);
     subtree_sums(W, W.lab, W.act, n, F, Lv.k, nullptr, W.subk, s);
-    subtree_cuts(W, Lv, W.lab, W.act, F, W.w_own, W.cut, s);
+    subtree_cuts(W, Lv, B, W.lab, W.act, F, W.w_own, W.cut, s);
     // nearest candidate ancestors
     k_nca_init<<<g, SLM_BS, 0, s>>>(W.lab, W.act, W.best_c, W.cyc, W.J, n, W.nca0);
     i32 *Fi = W.nca0, *Fo = W.nca1;
@@ -781,9 +856,8 @@ i64 maximal_moves(Work &W, const LevelView &Lv, const Bins &B, i64 nc, u64 seed,
     launch_fill_i32(W.wbd, 0, n, s);
     const i64 entries = Lv.nnz;
     if (entries > 0)
-        k_max_cross<<<node_grid(entries), SLM_BS, 0, s>>>(W.src, Lv.e, entries, W.lab, W.hasc,
-                                                        W.act, Fi, W.J, W.best_c, W.coff,
-                                                        W.clist, W.wbd);
+        visit_rows(Lv, B, CrossVisit{W.lab, W.hasc, W.act, Fi, W.J, W.best_c, W.coff, W.clist,
+                                     W.wbd}, s);
     k_max_valid<<<g, SLM_BS, 0, s>>>(Lv, W.lab, W.best_c, W.cyc, W.sigma, W.subk, W.cut, W.wbd,
                                      seed, level, round, accept_p, W.accept, W.counters,
                                      gvalid);
