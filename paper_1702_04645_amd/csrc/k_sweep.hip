@@ -23,10 +23,23 @@
 // streams at once.
 #include "slm_forest.h"
 
+// Home slot of label c in a table of H slots: the top bits of its hash for a
+// power of two, else the hash scaled to [0, H) (multiply and keep the high
+// word), so that a table can be 1.5x its bin's largest row.
 template <int H> __device__ __forceinline__ u32 sw_slot(i32 c)
 {
-    constexpr int LOG2H = __builtin_ctz(H);
-    return hash_label(c) >> (32 - LOG2H);
+    if constexpr ((H & (H - 1)) == 0) {
+        constexpr int LOG2H = __builtin_ctz(H);
+        return hash_label(c) >> (32 - LOG2H);
+    } else {
+        return (u32)(((u64)hash_label(c) * (u64)H) >> 32);
+    }
+}
+
+template <int H> __device__ __forceinline__ u32 sw_next(u32 h)
+{
+    if constexpr ((H & (H - 1)) == 0) return (h + 1) & (H - 1);
+    else return h + 1 == (u32)H ? 0u : h + 1;
 }
 
 template <int G> __device__ __forceinline__ void sw_sync()
@@ -170,7 +183,7 @@ __global__ __launch_bounds__(SLM_BS) void k_sweep_reg(LevelView L, const int4 *_
 // ------------------------------------------------------------------ LDS table with slot list
 // One table per group; the groups of a workgroup loop over the nodes of the
 // bin.  G lanes per node (G <= 64: the group lives in one wavefront; G > 64:
-// the whole workgroup), H slots (H >= 2 * max degree), U = max degree / G
+// the whole workgroup), H slots (H > max degree, about 1.5 to 2 times it), U = max degree / G
 // entries per lane: a lane issues all its entry loads, then all its label
 // gathers, before touching the table, so the memory latency of a row is paid
 // about once.
@@ -186,7 +199,7 @@ __device__ __forceinline__ i32 table_add(i32 *keys, i32 *vals, i32 c, i32 w)
             atomicAdd(&vals[h], w);
             return old == -1 ? (i32)h : -1;
         }
-        h = (h + 1) & (H - 1);
+        h = sw_next<H>(h);
     }
     return -1;
 }
@@ -222,7 +235,8 @@ __global__ __launch_bounds__(G <= 64 ? SLM_BS : G) void k_sweep_hash(
 {
     constexpr int NG = G <= 64 ? SLM_BS / G : 1;
     constexpr int BSZ = G <= 64 ? SLM_BS : G;
-    constexpr int LIST = H / 2;
+    constexpr int LIST = G * U;  // distinct labels of a row at most
+    static_assert(H > LIST, "the table must exceed the longest row");
     __shared__ i32 s_key[NG * H];
     __shared__ i32 s_val[NG * H];
     __shared__ i32 s_list[NG * LIST];
@@ -310,7 +324,8 @@ __global__ __launch_bounds__(SLM_BS) void k_sweep_pipe(LevelView L, const int4 *
 {
     static_assert(G <= 64, "one wavefront per group at most");
     constexpr int NG = SLM_BS / G;
-    constexpr int LIST = H / 2;
+    constexpr int LIST = G * U;  // distinct labels of a row at most
+    static_assert(H > LIST, "the table must exceed the longest row");
     __shared__ i32 s_key[NG * H];
     __shared__ i32 s_val[NG * H];
     __shared__ i32 s_list[NG * LIST];
@@ -749,13 +764,13 @@ void run_sweep(const LevelView &L, const Bins &Bn, const i32 *lab, const i32 *si
         k_sweep_pipe<G, H, U><<<persistent_grid(cnt, SLM_BS / G, grid_of(Bn, B)), SLM_BS, 0,  \
                                 STREAM>>>(                                             \
             L, Bn.rowd + Bn.off[B], cnt, Bn.ls, best_c, delta, w_own);
-    PIPE_BIN(BIN_512, 64, 1024, 8, st[0])
+    PIPE_BIN(BIN_512, 64, 752, 8, st[0])
     PIPE_BIN(BIN_256, 64, 512, 4, st[0])
     PIPE_BIN(BIN_128, 64, 256, 2, st[1])
     PIPE_BIN(BIN_64, 32, 128, 2, st[1])
-    HASH_BIN(BIN_2048, 256, 4096, 8, st[2])
+    HASH_BIN(BIN_2048, 256, 3008, 8, st[2])
     HASH_BIN(BIN_1024, 128, 2048, 8, st[2])
-    HASH_BIN(BIN_4096, 512, 8192, 8, st[2])
+    HASH_BIN(BIN_4096, 512, 6144, 8, st[2])
 #undef HASH_BIN
 #undef PIPE_BIN
     cnt = Bn.off[BIN_32 + 1] - Bn.off[BIN_32];
