@@ -865,7 +865,12 @@ i64 maximal_moves(Work &W, const LevelView &Lv, const Bins &B, i64 nc, u64 seed,
     stats[1] = W.h_scal[1];
     stats[2] = W.h_scal[2];
     if (stats[1] == 0) return 0;
-    run_repoint(Lv, B, W.lab, W.best_c, W.accept, W.a, W.hub_ckey, W.hub_cid, s);
+    HIPCHK(hipMemsetAsync(W.changed + 2, 0, sizeof(int), s));
+    run_repoint(Lv, B, W.lab, W.best_c, W.accept, W.a, W.hub_ckey, W.hub_cid, W.changed + 2, s);
+    HIPCHK(hipMemcpyAsync(W.h_scal, W.changed + 2, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (*(int *)W.h_scal)
+        throw SlmError{4, "re-pointing found no neighbour in an accepted node's target community"};
     return stats[1];
 }
 

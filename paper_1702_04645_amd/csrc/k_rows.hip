@@ -133,12 +133,29 @@ __global__ __launch_bounds__(GroupGeom<G>::BSZ) void k_strength(
 }
 
 // ------------------------------------------------------------------ ASSIGN / re-point
+// ASSIGN keeps the best neighbour if its pair key is positive, else the node
+// itself.  Re-pointing takes the best neighbour in the target community; an
+// accepted node always has one (its target is a neighbour's label), so
+// finding none means the inputs disagree: the node keeps its pointer and
+// err is raised instead of writing an id that is no node.
+template <bool REPOINT>
+__device__ __forceinline__ void write_assign(i32 *a, i32 node, i64 bk, i32 bj, int *err)
+{
+    if (REPOINT) {
+        if (bj != INT32_MAX) a[node] = bj;
+        else if (err) *err = 1;
+    } else {
+        a[node] = (bj != INT32_MAX && bk > 0) ? bj : node;
+    }
+}
+
 // REPOINT = false: a[i] = argmax_{j != i} pair(i,j) if positive, else i.
 // REPOINT = true : for accepted i, a[i] = argmax_{j: lab j = best_c i} pair(i,j).
 template <int G, bool REPOINT>
 __global__ __launch_bounds__(GroupGeom<G>::BSZ) void k_argmax(
     LevelView L, const i32 *__restrict__ nodes, i64 count, const i32 *__restrict__ lab,
-    const i32 *__restrict__ best_c, const uint8_t *__restrict__ accept, i32 *__restrict__ a)
+    const i32 *__restrict__ best_c, const uint8_t *__restrict__ accept, i32 *__restrict__ a,
+    int *__restrict__ err)
 {
     __shared__ i64 red[32];
     GROUP_PROLOGUE(G)
@@ -163,10 +180,7 @@ __global__ __launch_bounds__(GroupGeom<G>::BSZ) void k_argmax(
         }
     }
     gbest<G>(bk, bj, red);
-    if (active && gl == 0) {
-        if (REPOINT) a[node] = bj;
-        else a[node] = (bj != INT32_MAX && bk > 0) ? bj : node;
-    }
+    if (active && gl == 0) write_assign<REPOINT>(a, node, bk, bj, err);
 }
 
 // ------------------------------------------------------------------ own-community weight
@@ -198,7 +212,8 @@ __global__ __launch_bounds__(GroupGeom<G>::BSZ) void k_own(
 template <int G, int U, bool REPOINT>
 __global__ __launch_bounds__(SLM_BS) void k_argmax_reg(
     LevelView L, const int4 *__restrict__ rowd, i64 count, const i32 *__restrict__ lab,
-    const i32 *__restrict__ best_c, const uint8_t *__restrict__ accept, i32 *__restrict__ a)
+    const i32 *__restrict__ best_c, const uint8_t *__restrict__ accept, i32 *__restrict__ a,
+    int *__restrict__ err)
 {
     constexpr int NG = SLM_BS / G;
     const int gl = threadIdx.x % G;
@@ -240,10 +255,7 @@ __global__ __launch_bounds__(SLM_BS) void k_argmax_reg(
         }
     }
     group_best<G>(bk, bj);
-    if (active && gl == 0) {
-        if (REPOINT) a[node] = bj;
-        else a[node] = (bj != INT32_MAX && bk > 0) ? bj : node;
-    }
+    if (active && gl == 0) write_assign<REPOINT>(a, node, bk, bj, err);
 }
 
 template <int G, int U>
@@ -418,7 +430,7 @@ template <bool REPOINT>
 __global__ __launch_bounds__(SLM_BS) void k_hub_argmax_final(
     const i32 *__restrict__ hub_node, const i32 *__restrict__ chunk_first,
     const uint8_t *__restrict__ accept, const i64 *__restrict__ chunk_key,
-    const i32 *__restrict__ chunk_id, i32 *__restrict__ a)
+    const i32 *__restrict__ chunk_id, i32 *__restrict__ a, int *__restrict__ err)
 {
     __shared__ i64 red[32];
     const i32 h = blockIdx.x;
@@ -432,10 +444,7 @@ __global__ __launch_bounds__(SLM_BS) void k_hub_argmax_final(
             bj = chunk_id[c];
         }
     block_best(bk, bj, red);
-    if (threadIdx.x == 0) {
-        if (REPOINT) a[node] = bj;
-        else a[node] = (bj != INT32_MAX && bk > 0) ? bj : node;
-    }
+    if (threadIdx.x == 0) write_assign<REPOINT>(a, node, bk, bj, err);
 }
 
 __global__ __launch_bounds__(SLM_BS) void k_hub_own(
@@ -644,7 +653,7 @@ void run_assign(const LevelView &L, const Bins &Bn, i32 *a, i64 *hub_key, i32 *h
         bin_launch_geom<B>(Bn, cnt, nd, gr, bl);                                      \
         if (cnt > 0)                                                                  \
             k_argmax<BinShape<B>::G, false><<<gr, bl, 0, s>>>(L, nd, cnt, nullptr, nullptr, \
-                                                              nullptr, a);            \
+                                                              nullptr, a, nullptr);   \
     }
     FOR_LONG_BINS(X)
 #undef X
@@ -653,7 +662,7 @@ void run_assign(const LevelView &L, const Bins &Bn, i32 *a, i64 *hub_key, i32 *h
         const i64 cnt = Bn.off[B + 1] - Bn.off[B];                                    \
         if (cnt > 0)                                                                  \
             k_argmax_reg<G, U, false><<<grid_for(cnt, SLM_BS / G), SLM_BS, 0, s>>>(   \
-                L, Bn.rowd + Bn.off[B], cnt, nullptr, nullptr, nullptr, a);           \
+                L, Bn.rowd + Bn.off[B], cnt, nullptr, nullptr, nullptr, a, nullptr);  \
     }
     FOR_SHORT_BINS(X)
 #undef X
@@ -661,12 +670,13 @@ void run_assign(const LevelView &L, const Bins &Bn, i32 *a, i64 *hub_key, i32 *h
         k_hub_argmax<false><<<(unsigned)Bn.nchunk, SLM_BS, 0, s>>>(
             L, Bn.hub_node, Bn.chunk_hub, Bn.chunk_beg, nullptr, nullptr, nullptr, hub_key, hub_id);
         k_hub_argmax_final<false><<<(unsigned)Bn.nhub, SLM_BS, 0, s>>>(
-            Bn.hub_node, Bn.chunk_off_of_hub, nullptr, hub_key, hub_id, a);
+            Bn.hub_node, Bn.chunk_off_of_hub, nullptr, hub_key, hub_id, a, nullptr);
     }
 }
 
 void run_repoint(const LevelView &L, const Bins &Bn, const i32 *lab, const i32 *best_c,
-                 const uint8_t *accept, i32 *a, i64 *hub_key, i32 *hub_id, hipStream_t s)
+                 const uint8_t *accept, i32 *a, i64 *hub_key, i32 *hub_id, int *err,
+                 hipStream_t s)
 {
 #define X(B)                                                                          \
     {                                                                                 \
@@ -675,7 +685,8 @@ void run_repoint(const LevelView &L, const Bins &Bn, const i32 *lab, const i32 *
         unsigned gr, bl;                                                              \
         bin_launch_geom<B>(Bn, cnt, nd, gr, bl);                                      \
         if (cnt > 0 && B != BIN_ZERO)                                                 \
-            k_argmax<BinShape<B>::G, true><<<gr, bl, 0, s>>>(L, nd, cnt, lab, best_c, accept, a); \
+            k_argmax<BinShape<B>::G, true><<<gr, bl, 0, s>>>(L, nd, cnt, lab, best_c, accept, a, \
+                                                             err);                    \
     }
     FOR_LONG_BINS(X)
 #undef X
@@ -684,7 +695,7 @@ void run_repoint(const LevelView &L, const Bins &Bn, const i32 *lab, const i32 *
         const i64 cnt = Bn.off[B + 1] - Bn.off[B];                                    \
         if (cnt > 0)                                                                  \
             k_argmax_reg<G, U, true><<<grid_for(cnt, SLM_BS / G), SLM_BS, 0, s>>>(    \
-                L, Bn.rowd + Bn.off[B], cnt, lab, best_c, accept, a);                 \
+                L, Bn.rowd + Bn.off[B], cnt, lab, best_c, accept, a, err);            \
     }
     FOR_SHORT_BINS(X)
 #undef X
@@ -692,7 +703,7 @@ void run_repoint(const LevelView &L, const Bins &Bn, const i32 *lab, const i32 *
         k_hub_argmax<true><<<(unsigned)Bn.nchunk, SLM_BS, 0, s>>>(
             L, Bn.hub_node, Bn.chunk_hub, Bn.chunk_beg, lab, best_c, accept, hub_key, hub_id);
         k_hub_argmax_final<true><<<(unsigned)Bn.nhub, SLM_BS, 0, s>>>(
-            Bn.hub_node, Bn.chunk_off_of_hub, accept, hub_key, hub_id, a);
+            Bn.hub_node, Bn.chunk_off_of_hub, accept, hub_key, hub_id, a, err);
     }
 }
 

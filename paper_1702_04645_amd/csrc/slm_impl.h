@@ -267,8 +267,11 @@ void run_own_weight(const LevelView &L, const Bins &B, const i32 *lab, const uin
                     i32 *wc, hipStream_t s);
 // Re-pointing (Sec. 3.4): for nodes with accept[i], a[i] = argmax over
 // neighbours j with lab[j] == best_c[i] of pair(i,j), ties to the lowest j.
+// err (device int, may be null) is set when an accepted node has no
+// neighbour in its target community; that node's pointer is then unchanged.
 void run_repoint(const LevelView &L, const Bins &B, const i32 *lab, const i32 *best_c,
-                 const uint8_t *accept, i32 *a, i64 *hub_key, i32 *hub_id, hipStream_t s);
+                 const uint8_t *accept, i32 *a, i64 *hub_key, i32 *hub_id, int *err,
+                 hipStream_t s);
 // Contraction records of every row: distinct (lab_u, lab_v) pairs with summed
 // weights, written at rec_key/rec_w[rp[u] ..]; cnt[u] = their number.
 void run_contract_rows(const LevelView &L, const Bins &B, const i32 *lab, int lab_bits,
