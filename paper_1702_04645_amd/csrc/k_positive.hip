@@ -67,7 +67,7 @@ struct PwShared {
     int sp0;       // stack size when the current part started
     // split search: the nodes of the candidate set are evaluated exactly at
     // every split; every other node of the part is bounded by the bucket of
-    // its value at the last full scan (see pw_thr / pw_lb)
+    // its value at the last full scan (see pw_bounds)
     int need_scan, epoch, ncand, cand_over, cand_cap;
     i64 sig_scan;  // S_P at the last full scan
     u64 kmax[PW_NB];  // per bucket of subtree strength: max branch key (order-mapped)
@@ -84,38 +84,44 @@ __device__ __forceinline__ i64 ord_unmap(u64 v) { return (i64)(v ^ (1ull << 63))
 __device__ __forceinline__ int pw_bucket(i64 v) { return v <= 0 ? 0 : 64 - __clzll((u64)v); }
 __device__ __forceinline__ i64 pw_floor(int b) { return b ? ((i64)1 << (b - 1)) : 0; }
 
-// Upper bound on the branch key of every node outside the candidate set.
-// Such a node kept its subtree strength and cut since the last scan, so its
-// key fell by (strength) * D, D = the drop of S_P since then; a node of
-// bucket b has strength >= pw_floor(b).  Only a node whose key was its
-// bucket's maximum can reach the bound, so *tpair = the lowest cut pair of
-// those nodes over the buckets that reach it (ties go to the lowest pair).
-__device__ __forceinline__ i64 pw_thr(const PwShared &S, i64 D, u64 *tpair)
+// Bounds for the nodes outside the candidate set, from the value buckets of
+// the last full scan; D = the drop of S_P since then.
+//   thr: upper bound on their branch keys.  Such a node kept its subtree
+//        strength and cut since the scan, so its key fell by (strength) * D;
+//        a node of bucket b has strength >= pw_floor(b).  Only a node whose
+//        key was its bucket's maximum can reach the bound, so tpair = the
+//        lowest cut pair of those nodes over the buckets that reach it.
+//   lb:  lower bound on their local gains g = M2 w_in - k (S_P - k), which
+//        rose by k * D.
+// One bucket per lane and a wavefront reduction; every lane of every
+// wavefront gets the result.
+__device__ __forceinline__ void pw_bounds(const PwShared &S, i64 D, i64 &thr, u64 &tpair,
+                                          i64 &lb)
 {
-    i64 t = INT64_MIN;
+    const int lane = threadIdx.x & 63;
+    i64 t = INT64_MIN, l = INT64_MAX;
     u64 tp = ~0ull;
-    for (int b = 0; b < PW_NB; b++) {
-        if (S.kmax[b] == 0) continue;
-        const i64 v = ord_unmap(S.kmax[b]) - pw_floor(b) * D;
-        if (v > t) {
-            t = v;
-            tp = S.kpair[b];
-        } else if (v == t) {
-            tp = min(tp, (u64)S.kpair[b]);
+    if (lane < PW_NB) {
+        const u64 km = S.kmax[lane], gm = S.gmin[lane];
+        if (km != 0) {
+            t = ord_unmap(km) - pw_floor(lane) * D;
+            tp = S.kpair[lane];
         }
+        if (gm != ~0ull) l = ord_unmap(gm) + pw_floor(lane) * D;
     }
-    *tpair = tp;
-    return t;
-}
-
-// Lower bound on the local gain g = M2 w_in - k (S_P - k) of every node
-// outside the candidate set: it rose by k * D.
-__device__ __forceinline__ i64 pw_lb(const PwShared &S, i64 D)
-{
-    i64 t = INT64_MAX;
-    for (int b = 0; b < PW_NB; b++)
-        if (S.gmin[b] != ~0ull) t = min(t, ord_unmap(S.gmin[b]) + pw_floor(b) * D);
-    return t;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        const i64 ot = __shfl_xor(t, off, 64), ol = __shfl_xor(l, off, 64);
+        const u64 otp = __shfl_xor(tp, off, 64);
+        if (ot > t || (ot == t && otp < tp)) {
+            t = ot;
+            tp = otp;
+        }
+        l = min(l, ol);
+    }
+    thr = t;
+    tpair = tp;
+    lb = l;
 }
 
 // Adds v to the candidate set once per scan epoch; a node already in the set
@@ -849,7 +855,8 @@ __global__ __launch_bounds__(PW_BS) void k_positive_wg(PosArgs A)
                 // answer; otherwise scan the whole part
                 const i64 D = S.sig_scan - sig;
                 u64 tpair;
-                const i64 thr = pw_thr(S, D, &tpair), lb = pw_lb(S, D);
+                i64 thr, lb;
+                pw_bounds(S, D, thr, tpair, lb);
                 bool sure = true;
                 if (!neg && lb < 0) sure = false;
                 if (neg && bp != ~0ull && !(bk > thr || (bk == thr && bp < tpair))) sure = false;
@@ -949,8 +956,13 @@ __global__ __launch_bounds__(PW_BS) void k_positive_wg(PosArgs A)
             }
             const int tcount = S.tail;
             for (int i = threadIdx.x; i < tcount; i += PW_BS) A.root[TMP[i]] = x;
-            if (threadIdx.x == 0) {
-                // ancestors of x lose S_{T_x}
+            // The ancestors of x lose S_{T_x}; the last thread walks them while
+            // the others take the entries below.  The two touch disjoint data:
+            // the walk writes subk, a[x] and cyc[x], and the entry pass reads
+            // only nodes outside T_x and paths that never reach x (nothing
+            // else there writes subk).  A cut of more than one node computes a
+            // degree prefix first, whose barriers the walk precedes.
+            if (threadIdx.x == PW_BS - 1) {
                 i32 yv = px;
                 for (int guard = 0;; guard++) {
                     if (guard >= m) {
@@ -965,7 +977,6 @@ __global__ __launch_bounds__(PW_BS) void k_positive_wg(PosArgs A)
                 a[x] = x;
                 cyc[x] = 1;
             }
-            __syncthreads();
             // entries between T_x and the rest of the part (a single node's
             // entries need no degree prefix)
             const i64 tot = tcount == 1 ? G.rp[x + 1] - G.rp[x]
