@@ -661,7 +661,7 @@ __global__ __launch_bounds__(PW_BS) void k_positive_wg(PosArgs A)
             const i64 sig = S.sig;
             const int L = S.L;
             if (m <= 1) break;
-            const bool scanned = S.need_scan != 0;
+            const bool scanned = S.need_scan != 0 || S.cand_over != 0;
             i64 bk = INT64_MIN;
             u64 bp = ~0ull;
             int neg = 0;
@@ -915,10 +915,10 @@ __global__ __launch_bounds__(PW_BS) void k_positive_wg(PosArgs A)
                 break;
             }
             // ---------------- branch cut at x: T_x leaves the part
+            // (thread 0 writes below none of what the others read here)
             const i32 px = a[x];
             const i32 rx = A.root[x];
             const i64 sx = A.subk[x];
-            __syncthreads();
             // T_x in level order: TMP[0..t)
             if (threadIdx.x == 0) {
                 TMP[0] = x;
@@ -1032,16 +1032,16 @@ __global__ __launch_bounds__(PW_BS) void k_positive_wg(PosArgs A)
                 }
                 wave_run_add(t < tot, v, -val, A.win);
             }
-            __syncthreads();
             // T_x stays in the range, marked by its id, and waits on the stack
-            // for a range of its own (a single node needs none)
+            // for a range of its own (a single node needs none); nothing in
+            // the pass reads S.sp or S.sig.  A candidate set that overflowed
+            // in this pass makes the next pass scan (read at its start).
             if (threadIdx.x == 0) {
                 if (tcount > 1) {
                     if (S.sp >= m0) report(A.err, 10);
                     else STK[S.sp++] = make_int4(-1, tcount, x, ST_GATHER);
                 }
                 S.sig = sig - sx;
-                if (S.cand_over) S.need_scan = 1;
             }
             __syncthreads();
         }
