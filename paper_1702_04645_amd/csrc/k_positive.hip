@@ -642,11 +642,21 @@ __global__ __launch_bounds__(PW_BS) void k_positive_wg(PosArgs A)
             i64 sg = 0;
             for (int i = threadIdx.x; i < m; i += PW_BS) sg += G.k[P[i]];
             sg = wg_sum(sg, S);
+            // the first pass would scan the part and stop at once unless a
+            // member has a negative local gain: decide that here
+            i64 nneg = 0;
+            for (int i = threadIdx.x; i < m; i += PW_BS) {
+                const i32 u = P[i];
+                const i64 ku = G.k[u];
+                if (m2 * (i64)A.win[u] - ku * (sg - ku) < 0) nneg++;
+            }
+            nneg = wg_sum(nneg, S);
             if (threadIdx.x == 0) {
                 S.sig = sg;
                 S.L = 1;
             }
             __syncthreads();
+            if (nneg == 0) continue;  // no split: the part is final
         }
         // -------------------------------------------------- split loop
         // every pass of this loop starts after a barrier (the part's set-up or
