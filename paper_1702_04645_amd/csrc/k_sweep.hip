@@ -14,8 +14,9 @@
 //   deg <= 4096    one 128- to 512-lane workgroup per row, same table
 //                  (k_sweep_hash);
 //   larger (hubs)  rows cut in HUB_CHUNK-entry chunks; a workgroup totals its
-//                  chunk in LDS and adds the distinct labels to the hub's HBM
-//                  table; table tiles are then read (and cleared) in parallel.
+//                  chunk in LDS and writes its distinct labels grouped by a
+//                  hash partition of the label space; one workgroup per
+//                  (hub, partition) then totals them in LDS (no HBM atomics).
 // A row starts from its descriptor (node, degree, first entry) in bin order;
 // the short and pipelined rows gather a neighbour's (label, community total)
 // in one 8-byte load.  The own community's weight never enters a table: it
