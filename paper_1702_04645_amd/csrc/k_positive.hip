@@ -73,6 +73,8 @@ struct PwShared {
     u64 kmax[PW_NB];  // per bucket of subtree strength: max branch key (order-mapped)
     u64 kpair[PW_NB]; // per bucket: lowest cut pair among its nodes whose key is that max
     u64 gmin[PW_NB];  // per bucket of strength: min local gain (order-mapped)
+    i64 dpw[PW_BS + 1];  // degree-prefix window of one block of entries
+    int snext;           // first member of the next block of entries
     i32 cand[PW_CAND];
     uint8_t cflag[PW_CAND];  // CF_DIRTY: cached terms stale; CF_GONE: left the part
 };
@@ -332,6 +334,43 @@ __device__ __forceinline__ int find_slot(const i64 *dp, int cnt, i64 t)
     return lo;
 }
 
+// Member (slot, with its prefix dp[slot]) of entry t = b + threadIdx.x of a
+// flattened member list with prefix dp[0..cnt], for the block [b, b+PW_BS)
+// whose first entry belongs to member s_lo.  The block's prefix values are
+// staged in LDS: every member of a community has an entry, so a block spans
+// at most PW_BS + 1 of them (a member beyond that window is searched in dp
+// itself).  *s_next gets the member of the block's last entry, the first
+// member of the next block.  Every thread of the workgroup calls it.
+__device__ __forceinline__ void wg_block_slot(const i64 *dp, int cnt, i64 tot, i64 b, int s_lo,
+                                              int &slot, i64 &d0, int &s_next, PwShared &S)
+{
+    const int j = s_lo + threadIdx.x;
+    S.dpw[threadIdx.x] = j <= cnt ? dp[j] : INT64_MAX;
+    if (threadIdx.x == 0) S.dpw[PW_BS] = s_lo + PW_BS <= cnt ? dp[s_lo + PW_BS] : INT64_MAX;
+    __syncthreads();
+    const i64 t = b + threadIdx.x;
+    slot = 0;
+    d0 = 0;
+    if (t < tot) {
+        if (S.dpw[PW_BS] <= t) {
+            slot = find_slot(dp, cnt, t);
+            d0 = dp[slot];
+        } else {
+            int lo = 0, hi = PW_BS;  // dpw[lo] <= t < dpw[hi]
+            while (hi - lo > 1) {
+                const int mid = (lo + hi) >> 1;
+                if (S.dpw[mid] <= t) lo = mid;
+                else hi = mid;
+            }
+            slot = s_lo + lo;
+            d0 = S.dpw[lo];
+        }
+    }
+    if (threadIdx.x == PW_BS - 1) S.snext = slot;
+    __syncthreads();
+    s_next = S.snext;
+}
+
 // Stable partition of r[0..m): members with keep(u) first; others after.
 // Uses out as temporary; returns the number kept.
 template <class Keep>
@@ -541,14 +580,17 @@ __global__ __launch_bounds__(PW_BS) void k_positive_wg(PosArgs A)
             if (L >= 2)
                 for (int i = threadIdx.x; i < L * L; i += PW_BS) Wm[i] = 0;
             const i64 tot = wg_degree_prefix(P, m, G.rp, DP, S);
-            for (i64 b = 0; b < tot; b += PW_BS) {
+            for (i64 b = 0, sl = 0; b < tot; b += PW_BS) {
                 const i64 t = b + threadIdx.x;
+                int slot, snx;
+                i64 d0;
+                wg_block_slot(DP, m, tot, b, (int)sl, slot, d0, snx, S);
+                sl = snx;
                 i32 u = 0;
                 i64 val = 0;
                 if (t < tot) {
-                    int slot = find_slot(DP, m, t);
                     u = P[slot];
-                    int2 ed = G.e[G.rp[u] + (t - DP[slot])];
+                    int2 ed = G.e[G.rp[u] + (t - d0)];
                     i32 v = ed.x;
                     if (v != u && A.part[v] == pid) {
                         val = ed.y;
@@ -565,12 +607,15 @@ __global__ __launch_bounds__(PW_BS) void k_positive_wg(PosArgs A)
             // inside one tree, the weight of the pairs meeting there
             for (int i = threadIdx.x; i < m; i += PW_BS) A.cut[P[i]] = A.win[P[i]];
             __syncthreads();
-            for (i64 b = 0; b < tot; b += PW_BS) {
+            for (i64 b = 0, sl = 0; b < tot; b += PW_BS) {
                 const i64 t = b + threadIdx.x;
+                int slot, snx;
+                i64 d0;
+                wg_block_slot(DP, m, tot, b, (int)sl, slot, d0, snx, S);
+                sl = snx;
                 if (t < tot) {
-                    int slot = find_slot(DP, m, t);
                     i32 u = P[slot];
-                    int2 ed = G.e[G.rp[u] + (t - DP[slot])];
+                    int2 ed = G.e[G.rp[u] + (t - d0)];
                     i32 v = ed.x;
                     if (v != u && A.part[v] == pid && A.root[u] == A.root[v]) {
                         i32 x = u, y = v;
@@ -991,14 +1036,17 @@ __global__ __launch_bounds__(PW_BS) void k_positive_wg(PosArgs A)
             // entries need no degree prefix)
             const i64 tot = tcount == 1 ? G.rp[x + 1] - G.rp[x]
                                         : wg_degree_prefix(TMP, tcount, G.rp, DP, S);
-            for (i64 b = 0; b < tot; b += PW_BS) {
+            for (i64 b = 0, sl = 0; b < tot; b += PW_BS) {
                 const i64 t = b + threadIdx.x;
+                int slot = 0, snx = 0;
+                i64 d0 = 0;
+                if (tcount > 1) wg_block_slot(DP, tcount, tot, b, (int)sl, slot, d0, snx, S);
+                sl = snx;
                 i32 v = 0;
                 i64 val = 0;
                 if (t < tot) {
-                    int slot = tcount == 1 ? 0 : find_slot(DP, tcount, t);
                     v = TMP[slot];
-                    int2 ed = G.e[G.rp[v] + (t - (tcount == 1 ? 0 : DP[slot]))];
+                    int2 ed = G.e[G.rp[v] + (t - d0)];
                     i32 u = ed.x;
                     if (A.part[u] == pid) {
                         val = ed.y;
