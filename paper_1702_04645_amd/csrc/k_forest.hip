@@ -791,7 +791,6 @@ i64 positive(Work &W, const LevelView &Lv, const Bins &B, i64 *nc_out, hipStream
         A.splits = W.counters;
         A.stamp = W.stamp;
         A.cidx = W.cidx;
-        A.cval = W.cval;
         HIPCHK(hipMemsetAsync(W.changed, 0, sizeof(int), s));
         A.err = W.changed;
         launch_positive_wg(A, nflag, s);

@@ -427,7 +427,9 @@ __global__ __launch_bounds__(PW_BS) void k_positive_wg(PosArgs A)
 
     i32 *stamp = A.stamp;
     i32 *cidx = A.cidx;
-    int4 *CV = A.cval + base;  // candidate cache: at most min(PW_CAND, m0) entries
+    // candidate cache in LDS (the kernel's registers allow one workgroup per
+    // CU, so its LDS is there): at most min(PW_CAND, m0) entries
+    __shared__ int4 CV[PW_CAND];
     // iterations: at most one pass per part and, per split, one full scan
     // and one split step; parts and splits are fewer than 2*m0
     const int iter_cap = 6 * m0 + 16;

@@ -26,7 +26,6 @@ struct Work {
     int4 *pstk = nullptr;
     i32 *stamp = nullptr;  // POSITIVE: candidate-set epoch of every node
     i32 *cidx = nullptr;   // POSITIVE: index of a node in its community's candidate set
-    int4 *cval = nullptr;  // POSITIVE: cached terms of the candidates (per community)
     Fanout fan;            // side streams of the sweep
     i32 *A0 = nullptr, *A1 = nullptr, *M0 = nullptr, *M1 = nullptr;
     i32 *J = nullptr;  // kmax tables of n0
@@ -90,7 +89,6 @@ struct PosArgs {
     i32 *part, *win, *subk, *cut, *dep, *root, *chs, *chc, *cpos;  // per node
     i32 *stamp;          // per node: scan epoch in which it joined the candidate set
     i32 *cidx;           // per node: its index in the candidate set (valid with stamp)
-    int4 *cval;          // per candidate (member offsets): (subk, cut, win, k | cyc << 31)
     const i32 *lcyc;     // cycle length of every flagged community
     const i64 *woff;     // cycle weight matrix offsets (L*L entries when L >= 2)
     i64 *W;
