@@ -60,6 +60,7 @@ struct PwShared {
     u64 bpair;     // best (first, second)
     int neg;
     int sp;        // stack size
+    int stop;      // the stack was empty at the last pop
     int s, e, pid, flags;
     int tail, head, lev_end;
     int L;         // cycle length of the part
@@ -76,7 +77,7 @@ struct PwShared {
     i64 dpw[PW_BS + 1];  // degree-prefix window of one block of entries
     int snext;           // first member of the next block of entries
     i32 cand[PW_CAND];
-    uint8_t cflag[PW_CAND];  // CF_DIRTY: cached terms stale; CF_GONE: left the part
+    int cflag[PW_CAND];  // CF_DIRTY: cached terms stale; CF_GONE: left the part
 };
 
 enum { CF_DIRTY = 1, CF_GONE = 2 };
@@ -133,9 +134,10 @@ __device__ __forceinline__ void pw_add_cand(PwShared &S, i32 *stamp, i32 *cidx, 
     if (atomicExch(&stamp[v], S.epoch) == S.epoch) {
         // a concurrent add may not have stored its index yet: then the stale
         // index is ignored or marks another slot, and the adder's own flag is
-        // dirty anyway
+        // dirty anyway.  The mark is an atomic OR: a plain read-modify-write
+        // could store a flag read before a concurrent add reset that slot
         const i32 c = cidx[v];
-        if (c >= 0 && c < S.cand_cap) S.cflag[c] |= CF_DIRTY;
+        if (c >= 0 && c < S.cand_cap) atomicOr(&S.cflag[c], CF_DIRTY);
         return;
     }
     const int i = atomicAdd(&S.ncand, 1);
@@ -154,7 +156,7 @@ __device__ __forceinline__ void pw_drop_cand(PwShared &S, const i32 *stamp, cons
 {
     if (stamp[v] != S.epoch) return;
     const i32 c = cidx[v];
-    if (c >= 0 && c < S.cand_cap && S.cand[c] == v) S.cflag[c] |= CF_GONE;
+    if (c >= 0 && c < S.cand_cap && S.cand[c] == v) atomicOr(&S.cflag[c], CF_GONE);
 }
 
 // Ranges for the subtrees cut off the finished part: consecutive from off.
@@ -444,22 +446,28 @@ __global__ __launch_bounds__(PW_BS) void k_positive_wg(PosArgs A)
     __syncthreads();
     int iters = 0;  // every thread counts the same passes (uniform loops)
     while (true) {
+        // thread 0 pops the next part, or records that the stack is empty,
+        // between two barriers; every thread decides from that record, never
+        // from the stack size, which the pop changes
         __syncthreads();
-        if (S.sp == 0) break;
+        if (threadIdx.x == 0) {
+            S.stop = S.sp == 0;
+            if (!S.stop) {
+                int4 t = STK[--S.sp];
+                S.s = t.x;
+                S.e = t.y;
+                S.pid = t.z;
+                S.flags = t.w;
+                S.sp0 = S.sp;
+                S.need_scan = 1;
+            }
+        }
+        __syncthreads();
+        if (S.stop) break;
         if (++iters > iter_cap) {
             if (threadIdx.x == 0) report(A.err, 5);
             break;
         }
-        if (threadIdx.x == 0) {
-            int4 t = STK[--S.sp];
-            S.s = t.x;
-            S.e = t.y;
-            S.pid = t.z;
-            S.flags = t.w;
-            S.sp0 = S.sp;
-            S.need_scan = 1;
-        }
-        __syncthreads();
         if (S.s < 0 || S.e < S.s || S.e > m0) {  // a range outside the community
             if (threadIdx.x == 0) report(A.err, 9);
             break;
