@@ -116,7 +116,7 @@ def test_emulated_positive_matches_oracle(emulators, config, tmp_path):
     for name in GRAPHS:
         rp, col, w = graphs[name]
         cases += positive_inputs(rp, col, w, seed=1)
-    orders = [11, 12]
+    orders = [11, 12] if CONFIGS[config][0] <= 64 else [11]
     res = run_emulator(emulators[config], cases, orders, skew_us=20, tmp=tmp_path)
     splits = flagged = 0
     i = 0
@@ -131,4 +131,4 @@ def test_emulated_positive_matches_oracle(emulators, config, tmp_path):
             splits += int(hdr[0])
             flagged += int(hdr[2])
     # the cases exercise the kernel: many communities split, many splits
-    assert flagged > 50 and splits > 100, (flagged, splits)
+    assert flagged > 30 * len(orders) and splits > 60 * len(orders), (flagged, splits)
