@@ -50,7 +50,9 @@ extern std::barrier<> *emu_block_bar;
 extern EmuWave *emu_waves;
 extern std::vector<int> emu_seq[1024];  // per thread: source lines of its barriers
 extern volatile long emu_progress;
-extern int emu_skew_us;  // > 0: lanes other than 0 wait this long after a barrier
+extern int emu_skew_us;  // > 0: lanes other than 0 wait this long after a barrier;
+                         // < 0: every lane waits a random 0..-emu_skew_us
+extern thread_local uint64_t emu_rng;
 
 void emu_sleep_us(int us);
 
@@ -60,6 +62,12 @@ static inline void emu_sync(int line)
     emu_block_bar->arrive_and_wait();
     __atomic_fetch_add(&emu_progress, 1, __ATOMIC_RELAXED);
     if (emu_skew_us > 0 && threadIdx.x != 0) emu_sleep_us(emu_skew_us);
+    if (emu_skew_us < 0) {
+        emu_rng ^= emu_rng << 13;
+        emu_rng ^= emu_rng >> 7;
+        emu_rng ^= emu_rng << 17;
+        emu_sleep_us((int)(emu_rng % (uint64_t)(1 - emu_skew_us)));
+    }
 }
 #define __syncthreads() emu_sync(__LINE__)
 

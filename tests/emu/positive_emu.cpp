@@ -27,6 +27,7 @@ EmuWave *emu_waves;
 std::vector<int> emu_seq[1024];
 volatile long emu_progress;
 int emu_skew_us;
+thread_local uint64_t emu_rng;
 
 void emu_sleep_us(int us) { std::this_thread::sleep_for(std::chrono::microseconds(us)); }
 
@@ -214,6 +215,7 @@ static void run_case(i64 n, const std::vector<i64> &rp, const std::vector<i32> &
     for (int t = 0; t < PW_BS; t++)
         th.emplace_back([&, t] {
             threadIdx.x = t;
+            emu_rng = (seed + 1) * 0x9E3779B97F4A7C15ull + (u64)t * 0xD1B54A32D192ED03ull + 1;
             emu_seq[t].clear();
             for (i64 b = 0; b < nflag; b++) {
                 blockIdx.x = (unsigned)b;

@@ -5,9 +5,10 @@ of oracle runs: the assignment after ASSIGN and after each MAXIMAL round's
 re-pointing, at every level.  Community and member orders are shuffled (on
 the device they come from atomics), workgroups are shrunk so that every
 loop runs over several blocks and the candidate set overflows, and lanes
-other than 0 are held back after every barrier, so that a read of shared
-state that a single thread changes before the next barrier shows up as a
-stuck barrier or a different result.  Needs no GPU."""
+other than 0 are held back after every barrier (or all lanes by random
+amounts), so that a read of shared state that a single thread changes
+before the next barrier shows up as a stuck barrier or a different result.
+Needs no GPU."""
 import os
 import re
 import shutil
@@ -109,15 +110,18 @@ GRAPHS = ["random0", "random1", "random2", "random3", "random4", "random5", "pat
           "cliques", "sbm1000"]
 
 
-@pytest.mark.parametrize("config", sorted(CONFIGS))
-def test_emulated_positive_matches_oracle(emulators, config, tmp_path):
+# skew > 0: lanes other than 0 wait that many microseconds after every
+# barrier (a single writer runs ahead of the readers); skew < 0: every lane
+# waits a random 0..-skew microseconds (seeded per lane and case)
+@pytest.mark.parametrize("config,skew", [("wg512", 20), ("wg64", 20), ("wg64", -30)])
+def test_emulated_positive_matches_oracle(emulators, config, skew, tmp_path):
     graphs = small_graphs()
     cases = []
     for name in GRAPHS:
         rp, col, w = graphs[name]
         cases += positive_inputs(rp, col, w, seed=1)
     orders = [11, 12] if CONFIGS[config][0] <= 64 else [11]
-    res = run_emulator(emulators[config], cases, orders, skew_us=20, tmp=tmp_path)
+    res = run_emulator(emulators[config], cases, orders, skew_us=skew, tmp=tmp_path)
     splits = flagged = 0
     i = 0
     for g, a in cases:
