@@ -982,6 +982,7 @@ __global__ __launch_bounds__(PW_BS) void k_positive_wg(PosArgs A)
             // ---------------- branch cut at x: T_x leaves the part
             // (thread 0 writes below none of what the others read here)
             const i32 px = a[x];
+            const int dpx = A.dep[px];
             const i32 rx = A.root[x];
             const i64 sx = A.subk[x];
             // T_x in level order: TMP[0..t)
@@ -1034,10 +1035,14 @@ __global__ __launch_bounds__(PW_BS) void k_positive_wg(PosArgs A)
                         report(A.err, 4);
                         break;
                     }
+                    // the next ancestor and the cycle flag are loaded before
+                    // the candidate add, whose atomic the walk then overlaps
+                    const i32 ny = a[yv];
+                    const bool top = cyc[yv] != 0;
                     A.subk[yv] -= (i32)sx;
                     pw_add_cand(S, stamp, cidx, yv);
-                    if (cyc[yv]) break;
-                    yv = a[yv];
+                    if (top) break;
+                    yv = ny;
                 }
                 a[x] = x;
                 cyc[x] = 1;
@@ -1063,27 +1068,38 @@ __global__ __launch_bounds__(PW_BS) void k_positive_wg(PosArgs A)
                         const i32 A_ = ed.y;
                         atomicSub(&A.win[u], A_);
                         pw_add_cand(S, stamp, cidx, u);
-                        // paths u -> lca and px -> lca in the part before the cut
+                        // paths u -> lca and px -> lca in the part before the
+                        // cut.  Inside a part a parent is one level above its
+                        // child, so the depths are counted down instead of
+                        // loaded, and each step loads the next node before
+                        // its candidate add
                         i32 p1 = u, p2 = px;
+                        int d1 = A.dep[u], d2 = dpx;
                         int guard = 0;
-                        while (A.dep[p1] > A.dep[p2] && guard++ < 2 * m) {
+                        while (d1 > d2 && guard++ < 2 * m) {
+                            const i32 n1 = a[p1];
                             atomicSub(&A.cut[p1], A_);
                             pw_add_cand(S, stamp, cidx, p1);
-                            p1 = a[p1];
+                            p1 = n1;
+                            d1--;
                         }
-                        while (A.dep[p2] > A.dep[p1] && guard++ < 2 * m) {
+                        while (d2 > d1 && guard++ < 2 * m) {
+                            const i32 n2 = a[p2];
                             atomicSub(&A.cut[p2], A_);
                             pw_add_cand(S, stamp, cidx, p2);
-                            p2 = a[p2];
+                            p2 = n2;
+                            d2--;
                         }
                         while (p1 != p2 && guard++ < 2 * m) {
+                            const i32 n1 = a[p1], n2 = a[p2];
+                            const bool top = cyc[p1] && cyc[p2];
                             atomicSub(&A.cut[p1], A_);
                             atomicSub(&A.cut[p2], A_);
                             pw_add_cand(S, stamp, cidx, p1);
                             pw_add_cand(S, stamp, cidx, p2);
-                            if (cyc[p1] && cyc[p2]) break;
-                            p1 = a[p1];
-                            p2 = a[p2];
+                            if (top) break;
+                            p1 = n1;
+                            p2 = n2;
                         }
                         if (guard >= 2 * m) report(A.err, 2);
                         // path v -> x inside T_x
