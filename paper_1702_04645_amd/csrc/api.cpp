@@ -370,8 +370,6 @@ static void alloc_work(slm_graph *g)
     W.wsz = dalloc<i64>(g, n);
     W.nsz = dalloc<i64>(g, n);
     W.pstk = dalloc<int4>(g, n);
-    W.stamp = dalloc<i32>(g, n);
-    W.cidx = dalloc<i32>(g, n);
     W.minm = dalloc<i32>(g, n);
     W.rank = dalloc<i64>(g, n + 1);
     W.scan_tmp = dalloc<i64>(g, scan_tmp_elems(std::max(n, nnz) + 1) + 16);

@@ -789,8 +789,6 @@ i64 positive(Work &W, const LevelView &Lv, const Bins &B, i64 *nc_out, hipStream
         A.noff = W.noff_f;
         A.cn = W.cnode;
         A.splits = W.counters;
-        A.stamp = W.stamp;
-        A.cidx = W.cidx;
         HIPCHK(hipMemsetAsync(W.changed, 0, sizeof(int), s));
         A.err = W.changed;
         launch_positive_wg(A, nflag, s);

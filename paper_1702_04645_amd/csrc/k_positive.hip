@@ -51,6 +51,16 @@ enum { ST_INIT = 1, ST_GATHER = 2 };
 #define PW_CAND 4096  // candidate set of the split search
 #define PW_TOP 4      // branch-key candidates kept per lane by a full scan
 #define PW_NB 33      // value buckets: 0 for v <= 0, else 1 + floor(log2 v)
+// membership of the candidate set: an open-addressing table of node ids in
+// LDS, twice the set's size (a power of two), cleared at every full scan
+#define PW_CT (2 * PW_CAND)
+static_assert((PW_CT & (PW_CT - 1)) == 0, "the candidate table size must be a power of two");
+constexpr int pw_ct_bits()
+{
+    int b = 0;
+    while ((1 << b) < PW_CT) b++;
+    return b;
+}
 
 struct PwShared {
     i64 red[2 * PW_NW + 2];
@@ -69,7 +79,7 @@ struct PwShared {
     // split search: the nodes of the candidate set are evaluated exactly at
     // every split; every other node of the part is bounded by the bucket of
     // its value at the last full scan (see pw_bounds)
-    int need_scan, epoch, ncand, cand_over, cand_cap;
+    int need_scan, ncand, cand_over, cand_cap;
     i64 sig_scan;  // S_P at the last full scan
     u64 kmax[PW_NB];  // per bucket of subtree strength: max branch key (order-mapped)
     u64 kpair[PW_NB]; // per bucket: lowest cut pair among its nodes whose key is that max
@@ -77,6 +87,8 @@ struct PwShared {
     i64 dpw[PW_BS + 1];  // degree-prefix window of one block of entries
     int snext;           // first member of the next block of entries
     i32 cand[PW_CAND];
+    i32 ctab[PW_CT];     // node ids of the candidate set (-1: empty slot)
+    short cslot[PW_CT];  // per table slot: the node's index in cand (-1: none)
     int cflag[PW_CAND];  // CF_DIRTY: cached terms stale; CF_GONE: left the part
 };
 
@@ -127,36 +139,61 @@ __device__ __forceinline__ void pw_bounds(const PwShared &S, i64 D, i64 &thr, u6
     lb = l;
 }
 
-// Adds v to the candidate set once per scan epoch; a node already in the set
-// is marked dirty (its cached terms are re-read at the next evaluation).
-__device__ __forceinline__ void pw_add_cand(PwShared &S, i32 *stamp, i32 *cidx, i32 v)
+__device__ __forceinline__ u32 pw_ct_hash(i32 v)
 {
-    if (atomicExch(&stamp[v], S.epoch) == S.epoch) {
-        // a concurrent add may not have stored its index yet: then the stale
-        // index is ignored or marks another slot, and the adder's own flag is
-        // dirty anyway.  The mark is an atomic OR: a plain read-modify-write
-        // could store a flag read before a concurrent add reset that slot
-        const i32 c = cidx[v];
-        if (c >= 0 && c < S.cand_cap) atomicOr(&S.cflag[c], CF_DIRTY);
-        return;
-    }
-    const int i = atomicAdd(&S.ncand, 1);
-    if (i < S.cand_cap) {
-        S.cand[i] = v;
-        S.cflag[i] = CF_DIRTY;
-        cidx[v] = i;
-    } else {
-        S.cand_over = 1;
-    }
+    return ((u32)v * 0x9E3779B1u) >> (32 - pw_ct_bits());
 }
 
-// A candidate that leaves the part with a cut-off subtree.
-__device__ __forceinline__ void pw_drop_cand(PwShared &S, const i32 *stamp, const i32 *cidx,
-                                             i32 v)
+// Adds v to the candidate set once per scan; a node already in the set is
+// marked dirty (its cached terms are re-read at the next evaluation).  Once
+// the set has overflowed the next pass scans anyway, so nothing more is
+// recorded; the table then holds at most PW_CAND + PW_BS ids.
+__device__ __forceinline__ void pw_add_cand(PwShared &S, i32 v)
 {
-    if (stamp[v] != S.epoch) return;
-    const i32 c = cidx[v];
-    if (c >= 0 && c < S.cand_cap && S.cand[c] == v) atomicOr(&S.cflag[c], CF_GONE);
+    if (S.cand_over) return;
+    u32 h = pw_ct_hash(v);
+    for (int probe = 0; probe < PW_CT; probe++, h = (h + 1) & (PW_CT - 1)) {
+        const i32 old = atomicCAS(&S.ctab[h], -1, v);
+        if (old == -1) {
+            const int i = atomicAdd(&S.ncand, 1);
+            if (i < S.cand_cap) {
+                S.cand[i] = v;
+                S.cflag[i] = CF_DIRTY;
+                S.cslot[h] = (short)i;
+            } else {
+                S.cslot[h] = -1;
+                S.cand_over = 1;
+            }
+            return;
+        }
+        if (old == v) {
+            // the adder may not have stored the index yet: then a stale
+            // index marks another candidate (a mark only forces a re-read),
+            // and the adder's own flag is dirty anyway.  The mark is an
+            // atomic OR: a plain read-modify-write could store a flag read
+            // before a concurrent add reset that slot
+            const int c = S.cslot[h];
+            if (c >= 0 && c < S.cand_cap) atomicOr(&S.cflag[c], CF_DIRTY);
+            return;
+        }
+    }
+    S.cand_over = 1;  // table full (not reached: it has room for every add)
+}
+
+// A candidate that leaves the part with a cut-off subtree (no add runs
+// concurrently, so the table and its indices are settled).
+__device__ __forceinline__ void pw_drop_cand(PwShared &S, i32 v)
+{
+    u32 h = pw_ct_hash(v);
+    for (int probe = 0; probe < PW_CT; probe++, h = (h + 1) & (PW_CT - 1)) {
+        const i32 k = S.ctab[h];
+        if (k == -1) return;
+        if (k == v) {
+            const int c = S.cslot[h];
+            if (c >= 0 && c < S.cand_cap && S.cand[c] == v) atomicOr(&S.cflag[c], CF_GONE);
+            return;
+        }
+    }
 }
 
 // Ranges for the subtrees cut off the finished part: consecutive from off.
@@ -427,8 +464,6 @@ __global__ __launch_bounds__(PW_BS) void k_positive_wg(PosArgs A)
     i32 *a = A.a;
     uint8_t *cyc = A.cyc;
 
-    i32 *stamp = A.stamp;
-    i32 *cidx = A.cidx;
     // candidate cache in LDS (the kernel's registers allow one workgroup per
     // CU, so its LDS is there): at most min(PW_CAND, m0) entries
     __shared__ int4 CV[PW_CAND];
@@ -440,7 +475,6 @@ __global__ __launch_bounds__(PW_BS) void k_positive_wg(PosArgs A)
         STK[0] = make_int4(0, m0, A.flist[f], ST_INIT);
         S.sp = 1;
         S.chl_top = 0;
-        S.epoch = 0;
         S.cand_cap = m0 < PW_CAND ? m0 : PW_CAND;
     }
     __syncthreads();
@@ -482,7 +516,6 @@ __global__ __launch_bounds__(PW_BS) void k_positive_wg(PosArgs A)
             for (int i = threadIdx.x; i < m; i += PW_BS) {
                 i32 u = P[i];
                 A.part[u] = pid;
-                stamp[u] = -1;
                 A.win[u] = 0;
                 A.chc[u] = 0;
                 A.subk[u] = G.k[u];
@@ -740,9 +773,9 @@ __global__ __launch_bounds__(PW_BS) void k_positive_wg(PosArgs A)
                     S.kpair[b] = ~0ull;
                     S.gmin[b] = ~0ull;
                 }
+                for (int i = threadIdx.x; i < PW_CT; i += PW_BS) S.ctab[i] = -1;
                 __syncthreads();  // every thread has read need_scan
                 if (threadIdx.x == 0) {
-                    S.epoch++;
                     S.ncand = 0;
                     S.cand_over = 0;
                     S.sig_scan = sig;
@@ -846,8 +879,8 @@ __global__ __launch_bounds__(PW_BS) void k_positive_wg(PosArgs A)
                 __syncthreads();
 #pragma unroll
                 for (int q = 0; q < PW_TOP; q++)
-                    if (tp[q] != ~0ull) pw_add_cand(S, stamp, cidx, (i32)(tp[q] >> 32));
-                if (gu >= 0) pw_add_cand(S, stamp, cidx, gu);
+                    if (tp[q] != ~0ull) pw_add_cand(S, (i32)(tp[q] >> 32));
+                if (gu >= 0) pw_add_cand(S, gu);
                 live = wg_sum(live, S);
                 if (m > 2 * live + PW_BS) {  // most of the range has left: compact
                     const int kept =
@@ -992,7 +1025,7 @@ __global__ __launch_bounds__(PW_BS) void k_positive_wg(PosArgs A)
                 S.tail = 1;
                 S.lev_end = 1;
                 A.part[x] = x;
-                pw_drop_cand(S, stamp, cidx, x);
+                pw_drop_cand(S, x);
             }
             __syncthreads();
             // a node without children is T_x by itself
@@ -1010,7 +1043,7 @@ __global__ __launch_bounds__(PW_BS) void k_positive_wg(PosArgs A)
                         int q = atomicAdd(&S.tail, 1);
                         TMP[q] = ch;
                         A.part[ch] = x;
-                        pw_drop_cand(S, stamp, cidx, ch);
+                        pw_drop_cand(S, ch);
                     }
                 }
                 __syncthreads();
@@ -1040,7 +1073,7 @@ __global__ __launch_bounds__(PW_BS) void k_positive_wg(PosArgs A)
                     const i32 ny = a[yv];
                     const bool top = cyc[yv] != 0;
                     A.subk[yv] -= (i32)sx;
-                    pw_add_cand(S, stamp, cidx, yv);
+                    pw_add_cand(S, yv);
                     if (top) break;
                     yv = ny;
                 }
@@ -1067,7 +1100,7 @@ __global__ __launch_bounds__(PW_BS) void k_positive_wg(PosArgs A)
                         val = ed.y;
                         const i32 A_ = ed.y;
                         atomicSub(&A.win[u], A_);
-                        pw_add_cand(S, stamp, cidx, u);
+                        pw_add_cand(S, u);
                         // paths u -> lca and px -> lca in the part before the
                         // cut.  Inside a part a parent is one level above its
                         // child, so the depths are counted down instead of
@@ -1079,14 +1112,14 @@ __global__ __launch_bounds__(PW_BS) void k_positive_wg(PosArgs A)
                         while (d1 > d2 && guard++ < 2 * m) {
                             const i32 n1 = a[p1];
                             atomicSub(&A.cut[p1], A_);
-                            pw_add_cand(S, stamp, cidx, p1);
+                            pw_add_cand(S, p1);
                             p1 = n1;
                             d1--;
                         }
                         while (d2 > d1 && guard++ < 2 * m) {
                             const i32 n2 = a[p2];
                             atomicSub(&A.cut[p2], A_);
-                            pw_add_cand(S, stamp, cidx, p2);
+                            pw_add_cand(S, p2);
                             p2 = n2;
                             d2--;
                         }
@@ -1095,8 +1128,8 @@ __global__ __launch_bounds__(PW_BS) void k_positive_wg(PosArgs A)
                             const bool top = cyc[p1] && cyc[p2];
                             atomicSub(&A.cut[p1], A_);
                             atomicSub(&A.cut[p2], A_);
-                            pw_add_cand(S, stamp, cidx, p1);
-                            pw_add_cand(S, stamp, cidx, p2);
+                            pw_add_cand(S, p1);
+                            pw_add_cand(S, p2);
                             if (top) break;
                             p1 = n1;
                             p2 = n2;

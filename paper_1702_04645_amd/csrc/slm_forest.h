@@ -24,8 +24,6 @@ struct Work {
     i64 *mem_off = nullptr, *pdp = nullptr, *woff_f = nullptr, *noff_f = nullptr;
     i64 *wsz = nullptr, *nsz = nullptr;
     int4 *pstk = nullptr;
-    i32 *stamp = nullptr;  // POSITIVE: candidate-set epoch of every node
-    i32 *cidx = nullptr;   // POSITIVE: index of a node in its community's candidate set
     Fanout fan;            // side streams of the sweep
     i32 *A0 = nullptr, *A1 = nullptr, *M0 = nullptr, *M1 = nullptr;
     i32 *J = nullptr;  // kmax tables of n0
@@ -87,8 +85,6 @@ struct PosArgs {
     i32 *lvl;            // level starts (n + nflag entries)
     int4 *stk;           // part stack (n entries)
     i32 *part, *win, *subk, *cut, *dep, *root, *chs, *chc, *cpos;  // per node
-    i32 *stamp;          // per node: scan epoch in which it joined the candidate set
-    i32 *cidx;           // per node: its index in the candidate set (valid with stamp)
     const i32 *lcyc;     // cycle length of every flagged community
     const i64 *woff;     // cycle weight matrix offsets (L*L entries when L >= 2)
     i64 *W;

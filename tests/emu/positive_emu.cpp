@@ -136,8 +136,8 @@ static void run_case(i64 n, const std::vector<i64> &rp, const std::vector<i32> &
     auto stk = junk<int4>(n, rng);
     auto win = junk<i32>(n, rng), subk = junk<i32>(n, rng), cut = junk<i32>(n, rng);
     auto dep = junk<i32>(n, rng), root = junk<i32>(n, rng), chs = junk<i32>(n, rng);
-    auto chc = junk<i32>(n, rng), cpos = junk<i32>(n, rng), stamp = junk<i32>(n, rng);
-    auto cidx = junk<i32>(n, rng), cn = junk<i32>(noff[nflag], rng);
+    auto chc = junk<i32>(n, rng), cpos = junk<i32>(n, rng);
+    auto cn = junk<i32>(noff[nflag], rng);
     auto W = junk<i64>(woff[nflag], rng);
     int err = 0;
     unsigned long long spl = 0;
@@ -169,8 +169,6 @@ static void run_case(i64 n, const std::vector<i64> &rp, const std::vector<i32> &
     A.chs = chs.data();
     A.chc = chc.data();
     A.cpos = cpos.data();
-    A.stamp = stamp.data();
-    A.cidx = cidx.data();
     A.lcyc = flen.data();
     A.woff = woff.data();
     A.W = W.data();
