@@ -1014,10 +1014,14 @@ __global__ __launch_bounds__(PW_BS) void k_positive_wg(PosArgs A)
             }
             // ---------------- branch cut at x: T_x leaves the part
             // (thread 0 writes below none of what the others read here)
+            // every load that depends on x alone is issued here, before the
+            // set-up barrier (which the compiler does not move loads across)
             const i32 px = a[x];
-            const int dpx = A.dep[px];
             const i32 rx = A.root[x];
             const i64 sx = A.subk[x];
+            const bool leaf = A.chc[x] == 0;  // a node without children is T_x by itself
+            const i64 rpx0 = G.rp[x], rpx1 = G.rp[x + 1];
+            const int dpx = A.dep[px];
             // T_x in level order: TMP[0..t)
             if (threadIdx.x == 0) {
                 TMP[0] = x;
@@ -1028,8 +1032,6 @@ __global__ __launch_bounds__(PW_BS) void k_positive_wg(PosArgs A)
                 pw_drop_cand(S, x);
             }
             __syncthreads();
-            // a node without children is T_x by itself
-            const bool leaf = A.chc[x] == 0;
             while (!leaf) {
                 const int lb = S.head, le = S.lev_end;
                 if (lb == le) break;
@@ -1082,7 +1084,7 @@ __global__ __launch_bounds__(PW_BS) void k_positive_wg(PosArgs A)
             }
             // entries between T_x and the rest of the part (a single node's
             // entries need no degree prefix)
-            const i64 tot = tcount == 1 ? G.rp[x + 1] - G.rp[x]
+            const i64 tot = tcount == 1 ? rpx1 - rpx0
                                         : wg_degree_prefix(TMP, tcount, G.rp, DP, S);
             for (i64 b = 0, sl = 0; b < tot; b += PW_BS) {
                 const i64 t = b + threadIdx.x;
@@ -1093,8 +1095,8 @@ __global__ __launch_bounds__(PW_BS) void k_positive_wg(PosArgs A)
                 i32 v = 0;
                 i64 val = 0;
                 if (t < tot) {
-                    v = TMP[slot];
-                    int2 ed = G.e[G.rp[v] + (t - d0)];
+                    v = tcount == 1 ? x : TMP[slot];
+                    int2 ed = G.e[(tcount == 1 ? rpx0 : G.rp[v]) + (t - d0)];
                     i32 u = ed.x;
                     if (A.part[u] == pid) {
                         val = ed.y;
