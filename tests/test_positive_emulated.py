@@ -28,7 +28,7 @@ from gpu_common import small_graphs  # noqa: E402
 CSRC = os.path.join(ROOT, "paper_1702_04645_amd", "csrc")
 EMU = os.path.join(ROOT, "tests", "emu")
 # (workgroup lanes, candidate-set size, lane bests kept by a scan)
-CONFIGS = {"wg512": (512, 4096, 4), "wg64": (64, 16, 1)}
+WORKGROUPS = {"wg512": (512, 4096, 4), "wg64": (64, 16, 1)}
 
 pytestmark = pytest.mark.skipif(shutil.which("g++") is None, reason="needs g++")
 
@@ -49,7 +49,7 @@ def emulators(tmp_path_factory):
     d = tmp_path_factory.mktemp("positive_emu")
     (d / "k_positive_emu.inc").write_text(_kernel_source())
     out = {}
-    for name, (bs, cand, top) in CONFIGS.items():
+    for name, (bs, cand, top) in WORKGROUPS.items():
         exe = str(d / ("emu_" + name))
         cmd = ["g++", "-std=c++20", "-O1", "-pthread", "-I", EMU, "-I", CSRC, "-I", str(d),
                "-DPW_BS=%d" % bs, "-DPW_CAND=%d" % cand, "-DPW_TOP=%d" % top,
@@ -120,7 +120,7 @@ def test_emulated_positive_matches_oracle(emulators, config, skew, tmp_path):
     for name in GRAPHS:
         rp, col, w = graphs[name]
         cases += positive_inputs(rp, col, w, seed=1)
-    orders = [11, 12] if CONFIGS[config][0] <= 64 and skew > 0 else [11]
+    orders = [11, 12] if WORKGROUPS[config][0] <= 64 and skew > 0 else [11]
     res = run_emulator(emulators[config], cases, orders, skew_us=skew, tmp=tmp_path)
     splits = flagged = 0
     i = 0
