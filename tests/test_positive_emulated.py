@@ -120,7 +120,7 @@ def test_emulated_positive_matches_oracle(emulators, config, skew, tmp_path):
     for name in GRAPHS:
         rp, col, w = graphs[name]
         cases += positive_inputs(rp, col, w, seed=1)
-    orders = [11, 12] if WORKGROUPS[config][0] <= 64 and skew > 0 else [11]
+    orders = [11 + WORKGROUPS[config][0] + abs(skew)]  # one member order per case
     res = run_emulator(emulators[config], cases, orders, skew_us=skew, tmp=tmp_path)
     splits = flagged = 0
     i = 0
