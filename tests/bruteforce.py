@@ -211,8 +211,11 @@ def contract(A, lab):
     return S.T @ A @ S
 
 
-def run(A, seed, draw_fn, p_threshold=1 << 31, max_rounds=64):
-    """Algorithm 1 on a dense matrix; returns per-level dicts."""
+def run(A, seed, draw_fn, p_threshold=1 << 31, max_rounds=64, max_levels=0):
+    """Algorithm 1 on a dense matrix; returns per-level dicts.  A level runs
+    MAXIMAL rounds while some move is valid, at most max_rounds of them
+    (converged is False when the cap ends it); the run stops after
+    max_levels emitted levels when max_levels > 0."""
     n0 = A.shape[0]
     composed = np.arange(n0)
     out = []
@@ -237,8 +240,10 @@ def run(A, seed, draw_fn, p_threshold=1 << 31, max_rounds=64):
         composed = lab[composed]
         v = nq(A, lab)
         out.append(dict(labels=composed.copy(), n_c=nc, nq=v, rounds=r, converged=conv))
-        A = contract(A, lab)
         level += 1
+        if max_levels > 0 and level >= max_levels:
+            break
+        A = contract(A, lab)
     return out
 
 

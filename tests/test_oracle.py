@@ -5,6 +5,7 @@ the modularity numerator recomputed from scratch (tests/bruteforce.py), with
 closed forms, with networkx, with exhaustive enumeration, with published
 SplitMix64 outputs, and with structural invariants.
 """
+import functools
 import itertools
 import json
 import os
@@ -258,6 +259,62 @@ def test_full_run_matches_bruteforce():
             assert r1["nq"] == r2["nq"]
             assert r1["rounds"] == r2["rounds"]
             assert r1["converged"] == r2["converged"]
+
+
+@functools.lru_cache(maxsize=1)
+def _cap_cases():
+    """Graphs whose levels need several MAXIMAL rounds, so that small round
+    caps cut them (the tiny graphs and the ring graphs; each is run with a
+    low and the default acceptance threshold), plus unit-weight random graphs
+    of 20-60 nodes whose dense from-scratch run emits at least three levels,
+    so that a cap of two levels cuts a run."""
+    out = [(rp, col, w, i) for i, (rp, col, w) in enumerate(tiny_graphs(30, seed0=900))]
+    out += [(rp, col, w, 100 + i) for i, (rp, col, w, _) in enumerate(ring_graphs(30, seed0=9100))]
+    deep = 0
+    for s in range(400):
+        rg = np.random.default_rng(6000 + s)
+        n = int(rg.integers(20, 60))
+        g = gg.random_sparse(n, int(rg.integers(n, 3 * n)), 1, 6000 + s)
+        if len(bf.run(bf.dense(*g), s, oracle.draw)) >= 3:
+            out.append((*g, s))
+            deep += 1
+            if deep == 3:
+                break
+    assert deep == 3
+    return tuple(out)
+
+
+@pytest.mark.parametrize("max_rounds,max_levels", [(0, 0), (1, 0), (2, 0), (3, 0), (1, 1),
+                                                   (2, 1), (3, 2), (64, 1), (64, 2)])
+def test_round_and_level_caps_match_bruteforce(max_rounds, max_levels):
+    """The inner loop of Algorithm 1 runs MAXIMAL rounds while some move is
+    valid; with a cap on rounds the level ends after that many rounds with
+    converged = False, and the run stops after max_levels emitted levels.
+    Compared with the dense from-scratch run level by level."""
+    cut = short = 0
+    for rp, col, w, idx in _cap_cases():
+        A = bf.dense(rp, col, w)
+        for accept in (1 << 28, 1 << 31):
+            res = oracle.run(rp, col, w, seed=idx, accept_p=accept, max_rounds=max_rounds,
+                             max_levels=max_levels)
+            ref = bf.run(A, idx, oracle.draw, p_threshold=accept, max_rounds=max_rounds,
+                         max_levels=max_levels)
+            full = bf.run(A, idx, oracle.draw, p_threshold=accept, max_rounds=max_rounds)
+            assert len(res) == len(ref)
+            for r1, r2 in zip(res, ref):
+                assert np.array_equal(r1["labels"], r2["labels"])
+                assert r1["n_c"] == r2["n_c"] and r1["nq"] == r2["nq"]
+                assert r1["rounds"] == r2["rounds"] and r1["converged"] == r2["converged"]
+                assert r1["rounds"] <= max_rounds
+                cut += int(not r1["converged"])
+            if max_levels > 0:
+                assert len(res) == min(max_levels, len(full))
+                short += int(len(full) > max_levels)
+    # the fixture really reaches the caps
+    if max_rounds < 64:
+        assert cut > 5
+    if max_levels > 0 and max_rounds > 0:
+        assert short > 0
 
 
 def test_q_non_decreasing_and_below_optimum():
