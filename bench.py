@@ -2,13 +2,19 @@
 
 One step = one full run of Algorithm 1 (every level: ASSIGN, COMPONENTS,
 POSITIVE, MAXIMAL sweeps and resolutions, modularity, AGGREGATE) on the
-R-MAT scale-20 graph (edge factor 16, a=0.57 b=0.19 c=0.19 d=0.05,
-symmetrised, duplicates summed, self-loops dropped), resident in HBM before
-the timed region.  The headline value is the throughput of the synchronous
-move sweep measured live with HIP events on the library's stream: CSR
-entries swept per second over every sweep of the timed steps (GTEPS).
+LFR-style graph of 4,000,000 nodes (power-law degrees, exponent 2.5, mean
+20, max 2000; power-law community sizes, exponent 1.5, 20-5000; mixing 0.3;
+weights uniform 1-16), resident in HBM before the timed region.  The
+headline value is the throughput of the synchronous move sweep measured
+live with HIP events on the library's stream: CSR entries swept per second
+over every sweep of the timed steps (GTEPS).  After the timed steps the same
+line reports the batched run of the 2048-graph planted-partition family
+against the plain per-graph path (graphs/s) and a served Poisson mix with
+R-MAT scale-20 requests (p50/p99 latency), each measured outside the timed
+region.
 
 Prints one JSON line.  Usage: python bench.py [--steps K] [--warmup W]
+[--workload lfr4m|rmat20|sbm4096|batch2048|serve] [--no-extras]
 """
 from __future__ import annotations
 
@@ -105,14 +111,30 @@ def first_sweep(g, nnz: int, n: int, reps: int = 20):
             "communities": int(nc), "repetitions": reps}
 
 
+def cpu_model() -> str:
+    """The host CPU's model name (as lscpu reports it)."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(rp, col, w, budget_s: float):
     """The oracle's sweep (the plain sequential CPU implementation) on the
-    same graph, with the labelling of its own ASSIGN, repeated for about
+    same graph and the same labels as the GPU's first level-0 sweep (the
+    oracle's own ASSIGN, POSITIVE and COMPONENTS), repeated for about
     budget_s seconds on one core."""
     import oracle
     g = oracle.Graph(rp, col, w)
+    t = time.perf_counter()
     a = oracle.assign(g)
+    a, _ = oracle.positive(g, a)
     lab, nc, _ = oracle.components(a)
+    t_setup = time.perf_counter() - t
     reps = 0
     t0 = time.perf_counter()
     while True:
@@ -123,8 +145,10 @@ def cpu_baseline(rp, col, w, budget_s: float):
             break
     entries = int(rp[-1]) * reps
     return dict(value=entries / el / 1e9, unit="GTEPS", cores=1, kind="oracle",
-                sample="%d oracle sweeps of the full graph (labels from its ASSIGN), %.1f s"
-                       % (reps, el))
+                cpu=cpu_model(), host_threads=os.cpu_count(),
+                sample="%d oracle sweeps of the full graph on the labels after its ASSIGN, "
+                       "POSITIVE and COMPONENTS (%.1f s of set-up, not timed), %.1f s"
+                       % (reps, t_setup, el))
 
 
 def _gen_member(args):
@@ -153,10 +177,10 @@ def _oracle_member(args):
     return time.perf_counter() - t
 
 
-def batch_bench(args):
-    """Graphs per second of the batch family: all members in one batched run,
-    against the plain path (one handle and one run per graph) on a sample,
-    and the oracle (one process per host core) on a sample."""
+def batch_inputs(args):
+    """The batch members, their seeds, the plain-path sample and the oracle's
+    graphs/s on a sample (one process per host core).  CPU only: runs before
+    the GPU is touched."""
     import graphgen as gg
     count = args.batch_count
     seed = gg.CONFIG_SEEDS["batch2048"]
@@ -179,28 +203,37 @@ def batch_bench(args):
             times = pool.map(_oracle_member, [(*members[i], seeds[i]) for i in osample])
         el = time.perf_counter() - t
         cpu = dict(value=len(osample) / el, unit="graphs/s", cores=procs, kind="oracle",
+                   cpu=cpu_model(),
                    sample="%d members (every %d-th), one oracle process per core, %.1f s"
                           % (len(osample), stride, el),
                    oracle_seconds_per_graph=sum(times) / len(times))
         log("oracle: %.2f graphs/s on %d cores" % (cpu["value"], procs))
+    return dict(count=count, seed=seed, members=members, seeds=seeds, n_tot=n_tot,
+                nnz_tot=nnz_tot, stride=stride, sample=sample, cpu=cpu)
 
+
+def batch_gpu(args, inp):
+    """Batched run of all members (warm-up, then timed), the plain path (one
+    handle and one run per graph) on the sample, and the sample batched."""
     import torch
     import paper_1702_04645_amd as slm
+    members, seeds, sample = inp["members"], inp["seeds"], inp["sample"]
+    count = inp["count"]
     p = slm.params()
     t = time.perf_counter()
     b = slm.Batch(members, validate=False)
     t_create = time.perf_counter() - t
-    for i in range(args.warmup):
+    for i in range(args.batch_warmup):
         b.run(p, seeds=seeds)
     b.timing(True)
     b.timing_read()
     torch.cuda.synchronize()
     t = time.perf_counter()
-    for i in range(args.steps):
+    for i in range(args.batch_steps):
         res = b.run(p, seeds=seeds)
         log("batched step %d done" % i)
     torch.cuda.synchronize()
-    t_batch = (time.perf_counter() - t) / max(args.steps, 1)
+    t_batch = (time.perf_counter() - t) / max(args.batch_steps, 1)
     tm = b.timing_read()
     b.close()
     del b
@@ -228,35 +261,59 @@ def batch_bench(args):
     sb.close()
     sweep_s = tm["sweep_ms"] / 1e3
     achieved = tm["bytes"] / sweep_s / 1e9 if sweep_s > 0 else 0.0
+    out = dict(
+        graphs_per_s=round(count / t_batch, 2),
+        ms_per_batched_run=round(t_batch * 1e3, 3),
+        plain_graphs_per_s=round(len(sample) / t_plain, 2),
+        sample_batched_graphs_per_s=round(len(sample) / t_sample_batch, 2),
+        plain_sample="%d members (every %d-th)" % (len(sample), inp["stride"]),
+        create_s=round(t_create, 3),
+        sweep_gteps=round(tm["entries"] / sweep_s / 1e9, 3) if sweep_s > 0 else 0.0,
+        sweeps_timed=tm["sweeps"],
+        sweep_frac_of_hbm_peak=round(achieved / HBM_PEAK_GBS, 4),
+        emitted_levels=levels,
+        config=dict(workload="batch2048", graphs=count, nodes=inp["n_tot"],
+                    entries=inp["nnz_tot"], n_range=[64, 65536], block=[16, 256], p_in=0.2,
+                    mean_ext_deg=2, seed=inp["seed"]),
+    )
+    if inp["cpu"]:
+        out["cpu_baseline"] = inp["cpu"]
+    return out, achieved
+
+
+def batch_bench(args):
+    """Graphs per second of the batch family: all members in one batched run,
+    against the plain path (one handle and one run per graph) on a sample,
+    and the oracle (one process per host core) on a sample."""
+    inp = batch_inputs(args)
+    b, achieved = batch_gpu(args, inp)
     out = {
         "metric": "graphs/s batched vs plain",
-        "value": round(count / t_batch, 2),
+        "value": b["graphs_per_s"],
         "unit": "graphs/s",
         "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": round(t_batch * 1e3, 3),
+        "steps": args.batch_steps,
+        "warmup": args.batch_warmup,
+        "ms_per_step": b["ms_per_batched_run"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "int64",
         "data": "synthetic",
-        "config": dict(workload="batch2048", graphs=count, nodes=n_tot, entries=nnz_tot,
-                       n_range=[64, 65536], block=[16, 256], p_in=0.2, mean_ext_deg=2,
-                       seed=seed, emitted_levels=levels),
-        "plain_graphs_per_s": round(len(sample) / t_plain, 2),
-        "sample_batched_graphs_per_s": round(len(sample) / t_sample_batch, 2),
-        "plain_sample": "%d members (every %d-th)" % (len(sample), stride),
-        "create_s": round(t_create, 3),
-        "sweep_gteps": round(tm["entries"] / sweep_s / 1e9, 3) if sweep_s > 0 else 0.0,
+        "config": dict(b["config"], emitted_levels=b["emitted_levels"]),
+        "plain_graphs_per_s": b["plain_graphs_per_s"],
+        "sample_batched_graphs_per_s": b["sample_batched_graphs_per_s"],
+        "plain_sample": b["plain_sample"],
+        "create_s": b["create_s"],
+        "sweep_gteps": b["sweep_gteps"],
         "launch_options": "library defaults",
-        "sweeps_timed": tm["sweeps"],
+        "sweeps_timed": b["sweeps_timed"],
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": None},
     }
-    if cpu:
-        out["cpu_baseline"] = cpu
+    if "cpu_baseline" in b:
+        out["cpu_baseline"] = b["cpu_baseline"]
     print(json.dumps(out), flush=True)
 
 
@@ -265,14 +322,11 @@ def _gen_rmat(seed):
     return gg.rmat(20, 16, 0.57, 0.19, 0.19, seed)
 
 
-def serve_bench(args):
-    """Serving: Poisson arrivals at a fixed rate of graphs from the batch
-    family plus, one request in 200, an R-MAT scale-20 graph; two lanes
-    (R-MAT graphs take the second), admission by lane capacity at level
-    boundaries.  Latency is measured by the library from submission to the
-    end of the request's last level."""
+def serve_inputs(args):
+    """The served requests: Poisson arrivals at a fixed rate of graphs from
+    the batch family plus, one request in 200, an R-MAT scale-20 graph (four
+    distinct seeds, cycled).  CPU only: runs before the GPU is touched."""
     import multiprocessing as mp
-    import threading
     import graphgen as gg
     count, rate = args.serve_count, args.serve_rate
     seed = gg.CONFIG_SEEDS["serve"]
@@ -297,9 +351,17 @@ def serve_bench(args):
     seeds = [gg.batch_member_seed(args.seed, i) for i in range(count)]
     log("serve: %d requests (%d R-MAT) at %.0f/s, generated in %.1fs"
         % (count, int(is_rmat.sum()), rate, time.time() - t))
+    return dict(count=count, rate=rate, seed=seed, is_rmat=is_rmat, arrive=arrive,
+                graphs=graphs, seeds=seeds)
 
-    import torch
+
+def serve_gpu(args, inp):
+    """Submits the requests at their arrival times to a server of
+    args.serve_lanes lanes (one for R-MAT-sized graphs); latency is measured
+    by the library from submission to the end of the request's last level."""
     import paper_1702_04645_amd as slm
+    count, is_rmat, arrive = inp["count"], inp["is_rmat"], inp["arrive"]
+    graphs, seeds = inp["graphs"], inp["seeds"]
     sv = slm.Server(lanes=args.serve_lanes, large_lanes=1, large_nodes=200_000,
                     node_capacity=1 << 23, entry_capacity=1 << 28, max_members=4096,
                     validate=False)
@@ -327,33 +389,48 @@ def serve_bench(args):
     def pct(x, q):
         return round(float(np.percentile(x, q)) * 1e3, 3) if x.size else None
     small_l, rmat_l = lat[~is_rmat], lat[is_rmat]
+    return dict(
+        graphs_per_s=round(count / t_all, 2),
+        span_s=round(t_all, 3),
+        p50_ms=pct(lat, 50),
+        p99_ms=pct(lat, 99),
+        small_p50_ms=pct(small_l, 50),
+        small_p99_ms=pct(small_l, 99),
+        rmat_p50_ms=pct(rmat_l, 50),
+        rmat_max_ms=round(float(rmat_l.max()) * 1e3, 3) if rmat_l.size else None,
+        submit_span_s=round(t_sub, 3),
+        reserved_hbm_gb=round(st["reserved_bytes"] / 1e9, 2),
+        config=dict(workload="serve", requests=count, rate_per_s=inp["rate"],
+                    rmat_share="1/200", rmat_requests=int(is_rmat.sum()),
+                    small="batch family, n in [64, 65536]", lanes=args.serve_lanes,
+                    large_lanes=1,
+                    lane_capacity=dict(nodes=1 << 23, entries=1 << 28, members=4096),
+                    seed=inp["seed"], emitted_levels=levels),
+    )
+
+
+def serve_bench(args):
+    """Serving: served graphs/s and p50/p99 latency of the Poisson mix."""
+    inp = serve_inputs(args)
+    sv = serve_gpu(args, inp)
     out = {
         "metric": "served graphs/s; p50/p99 latency",
-        "value": round(count / t_all, 2),
+        "value": sv["graphs_per_s"],
         "unit": "graphs/s",
         "n_gpus": 1,
         "steps": 1,
         "warmup": 0,
-        "ms_per_step": round(t_all * 1e3, 3),
+        "ms_per_step": round(sv["span_s"] * 1e3, 3),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "int64",
         "data": "synthetic",
-        "config": dict(workload="serve", requests=count, rate_per_s=rate, rmat_share="1/200",
-                       small="batch family, n in [64, 65536]", lanes=args.serve_lanes,
-                       large_lanes=1,
-                       lane_capacity=dict(nodes=1 << 23, entries=1 << 28, members=4096),
-                       seed=seed, emitted_levels=levels),
-        "p50_ms": pct(lat, 50),
-        "p99_ms": pct(lat, 99),
-        "small_p50_ms": pct(small_l, 50),
-        "small_p99_ms": pct(small_l, 99),
-        "rmat_p50_ms": pct(rmat_l, 50),
-        "rmat_max_ms": round(float(rmat_l.max()) * 1e3, 3) if rmat_l.size else None,
-        "submit_span_s": round(t_sub, 3),
-        "reserved_hbm_gb": round(st["reserved_bytes"] / 1e9, 2),
+        "config": sv["config"],
     }
+    for k in ("p50_ms", "p99_ms", "small_p50_ms", "small_p99_ms", "rmat_p50_ms", "rmat_max_ms",
+              "submit_span_s", "reserved_hbm_gb"):
+        out[k] = sv[k]
     print(json.dumps(out), flush=True)
 
 
@@ -362,7 +439,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=0)
-    ap.add_argument("--workload", default="rmat20")
+    ap.add_argument("--workload", default="lfr4m")
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
@@ -371,6 +448,10 @@ def main():
     ap.add_argument("--serve-count", type=int, default=2000)
     ap.add_argument("--serve-rate", type=float, default=400.0)
     ap.add_argument("--serve-lanes", type=int, default=4)
+    ap.add_argument("--batch-steps", type=int, default=1)
+    ap.add_argument("--batch-warmup", type=int, default=1)
+    ap.add_argument("--no-extras", action="store_true",
+                    help="only the sweep line: no batched and served measurements")
     ap.add_argument("--no-tune", action="store_true",
                     help="library default launch options (no tuned/<workload>.json)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -395,14 +476,23 @@ def main():
     if args.workload == "serve":
         return serve_bench(args)
 
-    import torch
-    import paper_1702_04645_amd as slm
-
     t = time.time()
     (rp, col, w), cfg = workload(args.workload)
     n, nnz = rp.size - 1, col.size
     log("workload %s: %d nodes, %d entries, generated in %.1fs" % (args.workload, n, nnz,
                                                                     time.time() - t))
+    # everything that runs on host cores (generators, oracle pools) comes
+    # before the GPU is touched
+    extras = not args.no_extras
+    binp = batch_inputs(args) if extras else None
+    sinp = serve_inputs(args) if extras else None
+    cpu = None
+    if rank == 0 and not args.no_cpu:
+        log("cpu baseline (oracle sweep, about %.0f s)" % args.cpu_seconds)
+        cpu = cpu_baseline(rp, col, w, args.cpu_seconds)
+
+    import torch
+    import paper_1702_04645_amd as slm
     params = slm.params(seed=args.seed)
     g = slm.Graph(rp, col, w)
     info = g.level_info()
@@ -466,9 +556,15 @@ def main():
             "algorithmic_gb_per_sweep": round(tm["bytes"] / max(tm["sweeps"], 1) / 1e9, 4),
         },
     }
-    if rank == 0 and not args.no_cpu:
-        log("cpu baseline (oracle sweep, about %.0f s)" % args.cpu_seconds)
-        out["cpu_baseline"] = cpu_baseline(rp, col, w, args.cpu_seconds)
+    if cpu:
+        out["cpu_baseline"] = cpu
+    if extras:
+        del rp, col, w
+        log("batched run of the 2048-graph family")
+        out["batch"], _ = batch_gpu(args, binp)
+        del binp
+        log("served mix")
+        out["serve"] = serve_gpu(args, sinp)
     print(json.dumps(out), flush=True)
 
 

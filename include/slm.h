@@ -28,8 +28,9 @@
  *
  * Memory.  Pointers named *_dev are device pointers (HBM of the current HIP
  * device), owned by the caller; everything else is host memory.  The handle
- * owns its device copy of the graph and its work space (allocated with
- * hipMalloc at creation, released by slm_destroy).
+ * owns its device copy of the graph and its work space, taken from the
+ * caller's allocator (slm_allocator, e.g. a framework's caching allocator)
+ * when one is given at creation, else from hipMalloc; slm_destroy returns it.
  *
  * Streams.  All device work of a handle runs on the stream given at
  * creation (NULL = the default stream).  Calls that return a device result
@@ -44,6 +45,7 @@
 #ifndef SLM_H
 #define SLM_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -56,8 +58,24 @@ typedef enum {
     SLM_E_OVERFLOW = 2, /* M2 >= 2^31 or n >= 2^31                                     */
     SLM_E_NOMEM = 3,    /* device or host allocation failed                            */
     SLM_E_DEVICE = 4,   /* a HIP call failed                                           */
-    SLM_E_STATE = 5     /* call out of order (e.g. contracting to as many nodes)       */
+    SLM_E_STATE = 5,    /* call out of order (e.g. contracting to as many nodes)       */
+    SLM_E_BUSY = 6,     /* a server queue is full: submit again later                  */
+    SLM_E_CANCELLED = 7 /* the served request was cancelled                            */
 } slm_status;
+
+/* Device memory provider.  alloc(ctx, bytes, stream) returns device memory
+ * of at least `bytes` bytes usable on `stream` (the handle's hipStream_t),
+ * or NULL on failure (the call then fails with SLM_E_NOMEM and the handle,
+ * if any, stays destroyable); free(ctx, p, stream) returns it.  A buffer is
+ * freed only after the work queued on `stream` that uses it has finished.
+ * The callbacks may run on any thread of the library (a server's lanes
+ * call them from their own threads) and must be thread-safe.  ctx is passed
+ * through unchanged.  The allocator must outlive every handle made with it. */
+typedef struct {
+    void *ctx;
+    void *(*alloc)(void *ctx, size_t bytes, void *stream);
+    void (*free)(void *ctx, void *p, void *stream);
+} slm_allocator;
 
 typedef struct slm_graph slm_graph;
 typedef struct slm_result slm_result;
@@ -84,17 +102,21 @@ typedef struct {
 /* Defaults: seed 0, accept_p 2^31, max_rounds 64, max_levels 0, validate 1. */
 void slm_params_default(slm_params *p);
 
-/* Creates a handle holding a device copy of the level-0 graph.
+/* Creates a handle holding a device copy of the level-0 graph G(V, E) of
+ * Algorithm 1 (weighted, Sec. 2.4).
  *   row_ptr        n+1 offsets, int32 (row_ptr_bytes = 4) or int64 (8)
  *   col, w         nnz columns and weights
  *   inputs_on_device  0: the three arrays are host memory; 1: device memory
  *   validate       1: check symmetry, sorted unique columns, weights >= 1
  *   hip_stream     hipStream_t for all device work (NULL = default stream)
+ *   alloc          device memory provider (NULL = hipMalloc / hipFree)
  * The inputs are copied; the caller keeps ownership.  Errors: SLM_E_INVALID,
- * SLM_E_OVERFLOW (M2 or n too large), SLM_E_NOMEM, SLM_E_DEVICE. */
+ * SLM_E_OVERFLOW (M2 or n too large), SLM_E_NOMEM (also when alloc returns
+ * NULL; nothing is left allocated), SLM_E_DEVICE. */
 slm_status slm_create(int64_t n, int64_t nnz, const void *row_ptr, int row_ptr_bytes,
                       const int32_t *col, const int32_t *w, int inputs_on_device,
-                      int validate, void *hip_stream, slm_graph **out);
+                      int validate, void *hip_stream, const slm_allocator *alloc,
+                      slm_graph **out);
 
 void slm_destroy(slm_graph *g);
 
@@ -206,13 +228,14 @@ typedef struct {
 
 /* Creates a batch handle from count >= 1 host graphs (copied; the caller
  * keeps ownership).  Each graph's M2 must be below 2^31 and the batch must
- * hold fewer than 2^31 - 1 nodes.  validate as in slm_create.  On a batch
+ * hold fewer than 2^31 - 1 nodes.  validate, hip_stream and alloc as in
+ * slm_create.  On a batch
  * handle slm_assign, slm_components, slm_positive, slm_sweep, slm_round and
  * slm_level act on the level-0 union (slm_round and slm_level draw with
  * the given seed and level for every graph); slm_run, slm_modularity and
  * slm_contract return SLM_E_STATE. */
 slm_status slm_batch_create(int32_t count, const slm_graph_desc *graphs, int validate,
-                            void *hip_stream, slm_graph **out);
+                            void *hip_stream, const slm_allocator *alloc, slm_graph **out);
 
 /* Number of graphs of a batch handle (0 for a plain handle). */
 slm_status slm_batch_size(const slm_graph *g, int32_t *count);
@@ -222,6 +245,13 @@ slm_status slm_batch_size(const slm_graph *g, int32_t *count);
  * count result pointers, each freed with slm_result_free.  Synchronises. */
 slm_status slm_batch_run(slm_graph *g, const slm_params *p, const uint64_t *seeds,
                          slm_result **outs);
+
+/* One call for a batch used once: slm_batch_create (p->validate decides the
+ * CSR checks), slm_batch_run, slm_destroy.  Same arguments and results;
+ * on failure no result is returned and nothing stays allocated. */
+slm_status slm_batch_solve(int32_t count, const slm_graph_desc *graphs, const slm_params *p,
+                           const uint64_t *seeds, void *hip_stream,
+                           const slm_allocator *alloc, slm_result **outs);
 
 /* ---------------------------------------------------------------- serving
  * A server runs requests as they arrive.  Each lane is a union engine (the
@@ -247,24 +277,39 @@ typedef struct {
     int64_t large_nodes;     /* graphs with more nodes are "large"              */
     int32_t large_lanes;     /* lanes kept for large graphs (0: one queue for all) */
     int32_t validate;        /* check every submitted CSR                       */
+    int32_t queue_cap;       /* requests waiting per class at most (0: no cap)  */
     slm_params params;       /* accept_p, max_rounds, max_levels of every run   */
 } slm_server_cfg;
 
 /* Creates the lanes (each reserves HBM for its capacities at once; the sum is
  * reported by slm_server_stats) on the current device.  The streams are
- * created with the default priority. */
-slm_status slm_server_create(const slm_server_cfg *cfg, slm_server **out);
+ * created with the default priority.  alloc as in slm_create (every lane's
+ * device memory comes from it; NULL = hipMalloc). */
+slm_status slm_server_create(const slm_server_cfg *cfg, const slm_allocator *alloc,
+                             slm_server **out);
 
 /* Queues a host CSR (copied; the caller keeps ownership) with its draw seed.
  * SLM_E_NOMEM when it can never fit its lane; SLM_E_INVALID /
- * SLM_E_OVERFLOW as for slm_create.  *ticket identifies the result. */
+ * SLM_E_OVERFLOW as for slm_create; SLM_E_BUSY when queue_cap requests of
+ * its class already wait (nothing is queued: submit again later);
+ * SLM_E_DEVICE when every lane of its class has failed.  *ticket identifies
+ * the result. */
 slm_status slm_server_submit(slm_server *sv, const slm_graph_desc *g, uint64_t seed,
                              uint64_t *ticket);
+
+/* Cancels a ticket that has not been delivered.  A queued request is dropped
+ * at once; a resident one leaves its lane at the end of the level it is in
+ * (the other graphs of the lane are not affected); a finished, undelivered
+ * result is freed.  Poll or wait on the ticket then gives SLM_E_CANCELLED
+ * once (and delivers the ticket).  SLM_E_INVALID for an unknown or delivered
+ * ticket. */
+slm_status slm_server_cancel(slm_server *sv, uint64_t ticket);
 
 /* The result of a ticket (then owned by the caller, freed with
  * slm_result_free), or *out = NULL while it runs.  A ticket is delivered
  * once; an unknown or delivered ticket gives SLM_E_INVALID.  SLM_E_DEVICE
- * when its lane failed (message in slm_last_error). */
+ * when its lane failed (message in slm_last_error); SLM_E_CANCELLED after
+ * slm_server_cancel. */
 slm_status slm_server_poll(slm_server *sv, uint64_t ticket, slm_result **out);
 
 /* As slm_server_poll, but blocks until the result is there. */

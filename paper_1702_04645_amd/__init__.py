@@ -2,11 +2,12 @@
 Louvain Method (Chiem, Havelange & Van Dooren, arXiv 1702.04645).
 
 Argument marshalling only: every step runs in the HIP kernels behind the C
-ABI declared in include/slm.h.  PyTorch provides device memory (outputs are
-torch CUDA tensors) and the stream (the current torch stream when the graph
-is created).  The library must have been built (``python -m
-paper_1702_04645_amd.build``); importing this module fails loudly when it is
-missing.
+ABI declared in include/slm.h.  PyTorch provides device memory (the
+handles' work space comes from torch's caching allocator through the
+library's allocator callbacks, and outputs are torch CUDA tensors) and the
+stream (the current torch stream when the graph is created).  The library
+must have been built (``python -m paper_1702_04645_amd.build``); importing
+this module fails loudly when it is missing.
 """
 from __future__ import annotations
 
@@ -19,9 +20,10 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libslm.so")
 
-SLM_OK, SLM_E_INVALID, SLM_E_OVERFLOW, SLM_E_NOMEM, SLM_E_DEVICE, SLM_E_STATE = range(6)
+(SLM_OK, SLM_E_INVALID, SLM_E_OVERFLOW, SLM_E_NOMEM, SLM_E_DEVICE, SLM_E_STATE, SLM_E_BUSY,
+ SLM_E_CANCELLED) = range(8)
 _STATUS = {1: "SLM_E_INVALID", 2: "SLM_E_OVERFLOW", 3: "SLM_E_NOMEM", 4: "SLM_E_DEVICE",
-           5: "SLM_E_STATE"}
+           5: "SLM_E_STATE", 6: "SLM_E_BUSY", 7: "SLM_E_CANCELLED"}
 
 
 class SlmError(RuntimeError):
@@ -34,6 +36,65 @@ class Params(C.Structure):
     """slm_params: seed, accept_p (Q32), max_rounds, max_levels, validate."""
     _fields_ = [("seed", C.c_uint64), ("accept_p", C.c_uint64), ("max_rounds", C.c_int32),
                 ("max_levels", C.c_int32), ("validate", C.c_int32), ("reserved", C.c_int32)]
+
+
+_ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p)
+_FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p, C.c_void_p)
+
+
+class _AllocatorC(C.Structure):
+    """slm_allocator: ctx, alloc(ctx, bytes, stream), free(ctx, p, stream)."""
+    _fields_ = [("ctx", C.c_void_p), ("alloc", _ALLOC_FN), ("free", _FREE_FN)]
+
+
+class Allocator:
+    """A device memory provider for the library.  ``alloc(nbytes, stream)``
+    returns a device address (int), or 0 / None when it cannot;
+    ``free(address, stream)`` returns it.  The callbacks may run on the
+    library's own threads (server lanes).  Keep the object alive as long as
+    any handle made with it."""
+
+    def __init__(self, alloc, free):
+        def _a(ctx, nbytes, stream):
+            try:
+                p = alloc(int(nbytes), int(stream or 0))
+                return int(p) if p else None
+            except Exception:
+                return None
+
+        def _f(ctx, ptr, stream):
+            try:
+                free(int(ptr), int(stream or 0))
+            except Exception:
+                pass
+
+        self._fa = _ALLOC_FN(_a)
+        self._ff = _FREE_FN(_f)
+        self.c = _AllocatorC(None, self._fa, self._ff)
+
+
+def torch_allocator(device=None) -> Allocator:
+    """torch's CUDA caching allocator, on the handle's stream."""
+    torch = _torch()
+    dev = torch.cuda.current_device() if device is None else device
+    alloc_fn = torch.cuda.caching_allocator_alloc
+    free_fn = torch.cuda.caching_allocator_delete
+    return Allocator(lambda nbytes, stream: alloc_fn(nbytes, dev, stream),
+                     lambda ptr, stream: free_fn(ptr))
+
+
+def _allocator(allocator):
+    """The Allocator for an ``allocator`` argument: "torch" (the default),
+    None (the library's hipMalloc) or an Allocator."""
+    if allocator == "torch":
+        return torch_allocator()
+    if allocator is None or isinstance(allocator, Allocator):
+        return allocator
+    raise TypeError("allocator must be 'torch', None or an Allocator")
+
+
+def _aptr(a):
+    return C.byref(a.c) if a is not None else None
 
 
 def params(seed: int = 0, accept_p: int = 1 << 31, max_rounds: int = 64, max_levels: int = 0,
@@ -56,7 +117,8 @@ def lib():
     pi32, pi64 = C.POINTER(C.c_int32), C.POINTER(C.c_int64)
     sigs = {
         "slm_params_default": (None, [C.POINTER(Params)]),
-        "slm_create": (st, [i64, i64, P, C.c_int, P, P, C.c_int, C.c_int, P, C.POINTER(P)]),
+        "slm_create": (st, [i64, i64, P, C.c_int, P, P, C.c_int, C.c_int, P,
+                            C.POINTER(_AllocatorC), C.POINTER(P)]),
         "slm_destroy": (None, [P]),
         "slm_level_info": (st, [P, pi32, pi64, pi64, pi64]),
         "slm_reset": (st, [P]),
@@ -79,10 +141,12 @@ def lib():
         "slm_timing_read": (st, [P, C.POINTER(C.c_double), pi64, pi64, pi64]),
         "slm_set_option": (st, [P, C.c_char_p, i64]),
         "slm_last_error": (C.c_char_p, []),
-        "slm_batch_create": (st, [i32, P, C.c_int, P, C.POINTER(P)]),
+        "slm_batch_create": (st, [i32, P, C.c_int, P, C.POINTER(_AllocatorC), C.POINTER(P)]),
         "slm_batch_size": (st, [P, pi32]),
         "slm_batch_run": (st, [P, C.POINTER(Params), P, P]),
-        "slm_server_create": (st, [P, C.POINTER(P)]),
+        "slm_batch_solve": (st, [i32, P, C.POINTER(Params), P, P, C.POINTER(_AllocatorC), P]),
+        "slm_server_create": (st, [P, C.POINTER(_AllocatorC), C.POINTER(P)]),
+        "slm_server_cancel": (st, [P, C.c_uint64]),
         "slm_server_submit": (st, [P, P, C.c_uint64, C.POINTER(C.c_uint64)]),
         "slm_server_poll": (st, [P, C.c_uint64, C.POINTER(P)]),
         "slm_server_wait": (st, [P, C.c_uint64, C.POINTER(P)]),
@@ -134,11 +198,15 @@ class Graph:
     """A handle on a symmetric integer CSR graph resident in HBM.
 
     ``row_ptr`` (int32 or int64), ``col`` and ``w`` (int32) are numpy arrays
-    (host) or torch CUDA tensors (device)."""
+    (host) or torch CUDA tensors (device).  The handle's device memory comes
+    from ``allocator`` ("torch": torch's caching allocator; None: the
+    library's hipMalloc; or an Allocator)."""
 
-    def __init__(self, row_ptr, col, w, validate: bool = True, stream=None):
+    def __init__(self, row_ptr, col, w, validate: bool = True, stream=None,
+                 allocator="torch"):
         torch = _torch()
         self._h = C.c_void_p()
+        self._alloc = _allocator(allocator)
         on_dev = isinstance(row_ptr, torch.Tensor) and row_ptr.is_cuda
         if on_dev:
             rp, cl, ww = row_ptr.contiguous(), col.contiguous().to(torch.int32), \
@@ -164,7 +232,8 @@ class Graph:
             stream = torch.cuda.current_stream()
         self.stream = stream
         _check(lib().slm_create(n, nnz, args[0], rp_bytes, args[1], args[2], int(on_dev),
-                                int(validate), C.c_void_p(stream.cuda_stream), C.byref(self._h)))
+                                int(validate), C.c_void_p(stream.cuda_stream),
+                                _aptr(self._alloc), C.byref(self._h)))
         self._keep = None
         self.n0 = n
         self.nnz0 = nnz
@@ -312,27 +381,62 @@ class _Desc(C.Structure):
                 ("col", C.c_void_p), ("w", C.c_void_p)]
 
 
+def _descs(graphs):
+    """slm_graph_desc array of host CSR triples, and the arrays it points to."""
+    keep = []
+    descs = (_Desc * len(graphs))()
+    for i, (rp, col, w) in enumerate(graphs):
+        rp = np.ascontiguousarray(rp, dtype=np.int64)
+        cl = np.ascontiguousarray(col, dtype=np.int32)
+        ww = np.ascontiguousarray(w, dtype=np.int32)
+        keep.append((rp, cl, ww))
+        descs[i] = _Desc(rp.size - 1, cl.size, rp.ctypes.data, cl.ctypes.data, ww.ctypes.data)
+    return descs, keep
+
+
+def _seed_array(seeds, count):
+    if seeds is None:
+        return None
+    sd = np.ascontiguousarray([int(x) & (2**64 - 1) for x in seeds], dtype=np.uint64)
+    assert sd.size == count
+    return sd
+
+
+def batch_solve(graphs, p: Params | None = None, seeds=None, stream=None, allocator="torch"):
+    """One-shot batched run (slm_batch_solve) of a list of host CSR triples;
+    returns one list of LevelResult per graph."""
+    torch = _torch()
+    if p is None:
+        p = params()
+    a = _allocator(allocator)
+    descs, keep = _descs(graphs)
+    G = len(graphs)
+    sd = _seed_array(seeds, G)
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    outs = (C.c_void_p * max(G, 1))()
+    _check(lib().slm_batch_solve(G, descs, C.byref(p),
+                                 sd.ctypes.data_as(C.c_void_p) if sd is not None else None,
+                                 C.c_void_p(stream.cuda_stream), _aptr(a), outs))
+    return [_take_result(C.c_void_p(outs[i]), keep[i][0].size - 1) for i in range(G)]
+
+
 class Batch(Graph):
     """Many independent graphs (a list of host CSR triples) in one handle,
     run together as one disjoint union.  The single-step methods inherited
     from Graph act on the level-0 union."""
 
-    def __init__(self, graphs, validate: bool = True, stream=None):
+    def __init__(self, graphs, validate: bool = True, stream=None, allocator="torch"):
         torch = _torch()
         self._h = C.c_void_p()
-        keep = []
-        descs = (_Desc * len(graphs))()
-        for i, (rp, col, w) in enumerate(graphs):
-            rp = np.ascontiguousarray(rp, dtype=np.int64)
-            cl = np.ascontiguousarray(col, dtype=np.int32)
-            ww = np.ascontiguousarray(w, dtype=np.int32)
-            keep.append((rp, cl, ww))
-            descs[i] = _Desc(rp.size - 1, cl.size, rp.ctypes.data, cl.ctypes.data, ww.ctypes.data)
+        self._alloc = _allocator(allocator)
+        descs, keep = _descs(graphs)
         if stream is None:
             stream = torch.cuda.current_stream()
         self.stream = stream
         _check(lib().slm_batch_create(len(graphs), descs, int(validate),
-                                      C.c_void_p(stream.cuda_stream), C.byref(self._h)))
+                                      C.c_void_p(stream.cuda_stream), _aptr(self._alloc),
+                                      C.byref(self._h)))
         self.sizes = [k[0].size - 1 for k in keep]
         self.n0 = int(sum(self.sizes))
         self.nnz0 = int(sum(k[1].size for k in keep))
@@ -349,10 +453,7 @@ class Batch(Graph):
         if p is None:
             p = params()
         G = len(self.sizes)
-        sd = None
-        if seeds is not None:
-            sd = np.ascontiguousarray([int(x) & (2**64 - 1) for x in seeds], dtype=np.uint64)
-            assert sd.size == G
+        sd = _seed_array(seeds, G)
         outs = (C.c_void_p * G)()
         _check(lib().slm_batch_run(self._h, C.byref(p),
                                    sd.ctypes.data_as(C.c_void_p) if sd is not None else None,
@@ -366,21 +467,27 @@ class Batch(Graph):
 class _ServerCfg(C.Structure):
     _fields_ = [("node_capacity", C.c_int64), ("entry_capacity", C.c_int64),
                 ("max_members", C.c_int32), ("lanes", C.c_int32), ("large_nodes", C.c_int64),
-                ("large_lanes", C.c_int32), ("validate", C.c_int32), ("params", Params)]
+                ("large_lanes", C.c_int32), ("validate", C.c_int32), ("queue_cap", C.c_int32),
+                ("params", Params)]
 
 
 class Server:
     """Serving loop of the library: requests run as they arrive, admitted at
     level boundaries while they fit a lane's capacity.  ``lanes`` lanes in
-    all, ``large_lanes`` of them for graphs above ``large_nodes`` nodes."""
+    all, ``large_lanes`` of them for graphs above ``large_nodes`` nodes;
+    ``queue_cap`` requests may wait per class (0: no cap; a full queue makes
+    submit raise SLM_E_BUSY)."""
 
     def __init__(self, node_capacity: int = 0, entry_capacity: int = 0, max_members: int = 0,
                  lanes: int = 1, large_nodes: int = 1 << 62, large_lanes: int = 0,
-                 validate: bool = True, p: Params | None = None):
+                 validate: bool = True, p: Params | None = None, queue_cap: int = 0,
+                 allocator="torch"):
         self._h = C.c_void_p()
+        self._alloc = _allocator(allocator)
         cfg = _ServerCfg(node_capacity, entry_capacity, max_members, lanes, large_nodes,
-                         large_lanes, int(validate), p if p is not None else params())
-        _check(lib().slm_server_create(C.byref(cfg), C.byref(self._h)))
+                         large_lanes, int(validate), int(queue_cap),
+                         p if p is not None else params())
+        _check(lib().slm_server_create(C.byref(cfg), _aptr(self._alloc), C.byref(self._h)))
         self._n0 = {}
 
     def submit(self, row_ptr, col, w, seed: int = 0) -> int:
@@ -392,6 +499,10 @@ class Server:
         _check(lib().slm_server_submit(self._h, C.byref(d), seed & (2**64 - 1), C.byref(t)))
         self._n0[t.value] = rp.size - 1
         return t.value
+
+    def cancel(self, ticket: int):
+        """Cancels a request; its poll / wait then raises SLM_E_CANCELLED."""
+        _check(lib().slm_server_cancel(self._h, ticket))
 
     def poll(self, ticket: int):
         """The levels of a finished request (once), else None."""

@@ -9,6 +9,7 @@
 #include <chrono>
 #include <condition_variable>
 #include <deque>
+#include <functional>
 #include <mutex>
 #include <thread>
 #include <unordered_map>
@@ -21,6 +22,12 @@
 #include "slm_forest.h"
 
 static thread_local std::string g_err;
+
+// The calling thread's last error message (also set by noalloc.hip).
+std::string &slm_error_slot()
+{
+    return g_err;
+}
 
 struct slm_result {
     i64 n0 = 0;
@@ -36,6 +43,7 @@ struct Member {
     u64 ticket = 0;           // batch index, or server ticket
     i64 n0 = 0, nnz0 = 0, m2 = 0;
     u64 seed = 0;
+    bool cancel = false;      // a server member whose ticket was cancelled
     int level = 0;            // index of its next level
     std::vector<i32> comp;    // original node -> its node at the current level
     slm_result *res = nullptr;
@@ -63,8 +71,8 @@ struct slm_graph {
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     double sweep_ms = 0;
     i64 sweeps = 0, entries = 0, bytes = 0;
-    std::vector<void *> allocs;
-    i64 reserved = 0;  // device bytes held by allocs
+    DevMem dm;  // every device buffer of the handle (dm.held: bytes held)
+    std::vector<std::pair<void *, size_t>> allocs;  // fixed buffers, freed at destroy
     bool no_fanout = false;  // keep every sweep bin on the handle's stream
 
     // A union handle (a batch, or a lane of a server) holds G independent
@@ -88,16 +96,53 @@ struct slm_graph {
 };
 
 // ------------------------------------------------------------------ helpers
+void *DevMem::get(size_t bytes)
+{
+    if (bytes == 0) bytes = 256;
+    void *p = nullptr;
+    if (fn_alloc) {
+        p = fn_alloc(ctx, bytes, (void *)s);
+    } else if (hipMalloc(&p, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        p = nullptr;
+    }
+    if (!p)
+        throw SlmError{SLM_E_NOMEM, "device allocation of " + std::to_string(bytes) +
+                                        " bytes failed"};
+    held += (i64)bytes;
+    return p;
+}
+
+void DevMem::put(void *p, size_t bytes)
+{
+    if (!p) return;
+    if (bytes == 0) bytes = 256;
+    if (fn_free) fn_free(ctx, p, (void *)s);
+    else (void)hipFree(p);
+    held -= (i64)bytes;
+}
+
+// A buffer the handle keeps until it is destroyed.
 template <typename T>
 static T *dalloc(slm_graph *g, i64 count)
 {
-    void *p = nullptr;
     if (count < 1) count = 1;
-    hipError_t e = hipMalloc(&p, sizeof(T) * (size_t)count);
-    if (e != hipSuccess) throw SlmError{SLM_E_NOMEM, "device allocation failed"};
-    g->allocs.push_back(p);
-    g->reserved += (i64)(sizeof(T) * (size_t)count);
+    const size_t bytes = sizeof(T) * (size_t)count;
+    g->allocs.reserve(g->allocs.size() + 1);
+    void *p = g->dm.get(bytes);
+    g->allocs.push_back({p, bytes});
     return (T *)p;
+}
+
+// Takes the allocator of a create call (null: hipMalloc / hipFree).
+static void set_allocator(slm_graph *g, const slm_allocator *a)
+{
+    if (!a) return;
+    if (!a->alloc || !a->free)
+        throw SlmError{SLM_E_INVALID, "an allocator needs both alloc and free"};
+    g->dm.ctx = a->ctx;
+    g->dm.fn_alloc = a->alloc;
+    g->dm.fn_free = a->free;
 }
 
 static LevelView view(slm_graph *g)
@@ -128,23 +173,22 @@ static LevelView view(slm_graph *g)
 
 // Device buffers that only grow.
 template <typename T>
-static void grow_buf(T *&p, i64 &cap, i64 need)
+static void grow_buf(slm_graph *g, T *&p, i64 &cap, i64 need)
 {
-    if (need <= cap) return;
-    if (p) HIPCHK(hipFree(p));
-    p = nullptr;
-    const i64 c = need + need / 2 + 64;
-    HIPCHK(hipMalloc(&p, sizeof(T) * c));
-    cap = c;
+    dm_grow(g->dm, p, cap, need, 64);
 }
 
 static void release_bins(slm_graph *g)
 {
     Bins &B = g->bins;
-    for (void *p : {(void *)B.chunk_hub, (void *)B.chunk_beg, (void *)B.hchunk,
-                    (void *)B.chunk_off_of_hub, (void *)B.htile, (void *)B.tile_off_of_hub,
-                    (void *)B.span})
-        if (p) (void)hipFree(p);
+    DevMem &dm = g->dm;
+    dm.put(B.chunk_hub, sizeof(i32) * B.cap_chunk_hub);
+    dm.put(B.chunk_beg, sizeof(i64) * B.cap_chunk_beg);
+    dm.put(B.hchunk, sizeof(HubChunk) * B.cap_hchunk);
+    dm.put(B.chunk_off_of_hub, sizeof(i32) * B.cap_chunk_off);
+    dm.put(B.htile, sizeof(HubTile) * B.cap_htile);
+    dm.put(B.tile_off_of_hub, sizeof(i32) * B.cap_tile_off);
+    dm.put(B.span, sizeof(i64) * B.cap_span);
     const int cap = B.hub_cap, tbits = B.hub_tbits;
     i32 grid[NBINS];
     for (int b = 0; b < NBINS; b++) grid[b] = B.grid_cap[b];
@@ -152,16 +196,6 @@ static void release_bins(slm_graph *g)
     B.hub_cap = cap;
     B.hub_tbits = tbits;
     for (int b = 0; b < NBINS; b++) B.grid_cap[b] = grid[b];
-}
-
-static void grow_i32(i32 *&p, i64 &cap, i64 need)
-{
-    if (need <= cap) return;
-    if (p) HIPCHK(hipFree(p));
-    p = nullptr;
-    i64 c = need + need / 2 + 1024;
-    HIPCHK(hipMalloc(&p, sizeof(i32) * c));
-    cap = c;
 }
 
 // Degree bins, hub work lists, strengths and entry rows of the current level.
@@ -191,7 +225,7 @@ static void setup_level(slm_graph *g)
         B.nhub = (i32)nhub;
         B.hub_node = B.nodes + B.off[BIN_HUB];
         if (nhub > 0) {
-            grow_buf(B.span, B.cap_span, 2 * nhub);
+            grow_buf(g, B.span, B.cap_span, 2 * nhub);
             launch_hub_degrees(rp, B.hub_node, (i32)nhub, B.span, s);
             std::vector<i64> span(2 * nhub);
             HIPCHK(hipMemcpyAsync(span.data(), B.span, sizeof(i64) * 2 * nhub,
@@ -246,12 +280,12 @@ static void setup_level(slm_graph *g)
             B.nchunk = (i64)chunk_hub.size();
             B.hub_entries = out;
             B.npoff = pb;
-            grow_buf(B.htile, B.cap_htile, B.ntile);
-            grow_buf(B.tile_off_of_hub, B.cap_tile_off, nhub + 1);
-            grow_buf(B.chunk_off_of_hub, B.cap_chunk_off, nhub + 1);
-            grow_buf(B.chunk_hub, B.cap_chunk_hub, B.nchunk);
-            grow_buf(B.chunk_beg, B.cap_chunk_beg, B.nchunk);
-            grow_buf(B.hchunk, B.cap_hchunk, B.nchunk);
+            grow_buf(g, B.htile, B.cap_htile, B.ntile);
+            grow_buf(g, B.tile_off_of_hub, B.cap_tile_off, nhub + 1);
+            grow_buf(g, B.chunk_off_of_hub, B.cap_chunk_off, nhub + 1);
+            grow_buf(g, B.chunk_hub, B.cap_chunk_hub, B.nchunk);
+            grow_buf(g, B.chunk_beg, B.cap_chunk_beg, B.nchunk);
+            grow_buf(g, B.hchunk, B.cap_hchunk, B.nchunk);
             HIPCHK(hipMemcpyAsync(B.htile, htile.data(), sizeof(HubTile) * B.ntile,
                                   hipMemcpyHostToDevice, s));
             HIPCHK(hipMemcpyAsync(B.tile_off_of_hub, tile_first.data(), sizeof(i32) * (nhub + 1),
@@ -265,21 +299,19 @@ static void setup_level(slm_graph *g)
             HIPCHK(hipMemcpyAsync(B.hchunk, hchunk.data(), sizeof(HubChunk) * B.nchunk,
                                   hipMemcpyHostToDevice, s));
             if (B.ntile > W.hub_tile_cap) {
-                if (W.hub_tkey) HIPCHK(hipFree(W.hub_tkey));
-                if (W.hub_tid) HIPCHK(hipFree(W.hub_tid));
-                W.hub_tile_cap = B.ntile + 64;
-                HIPCHK(hipMalloc(&W.hub_tkey, sizeof(i64) * W.hub_tile_cap));
-                HIPCHK(hipMalloc(&W.hub_tid, sizeof(i32) * W.hub_tile_cap));
+                i64 c1 = W.hub_tile_cap, c2 = W.hub_tile_cap;
+                dm_grow(g->dm, W.hub_tkey, c1, B.ntile, 64);
+                dm_grow(g->dm, W.hub_tid, c2, B.ntile, 64);
+                W.hub_tile_cap = c1;
             }
-            grow_buf(W.hub_part, W.hub_part_cap, B.hub_entries);
-            grow_buf(W.hub_poff, W.hub_poff_cap, B.npoff);
-            grow_buf(W.hub_cwin, W.hub_cwin_cap, B.nchunk);
+            grow_buf(g, W.hub_part, W.hub_part_cap, B.hub_entries);
+            grow_buf(g, W.hub_poff, W.hub_poff_cap, B.npoff);
+            grow_buf(g, W.hub_cwin, W.hub_cwin_cap, B.nchunk);
             if (B.nchunk > W.hub_chunk_cap) {
-                if (W.hub_ckey) HIPCHK(hipFree(W.hub_ckey));
-                if (W.hub_cid) HIPCHK(hipFree(W.hub_cid));
-                W.hub_chunk_cap = B.nchunk + 64;
-                HIPCHK(hipMalloc(&W.hub_ckey, sizeof(i64) * W.hub_chunk_cap));
-                HIPCHK(hipMalloc(&W.hub_cid, sizeof(i32) * W.hub_chunk_cap));
+                i64 c1 = W.hub_chunk_cap, c2 = W.hub_chunk_cap;
+                dm_grow(g->dm, W.hub_ckey, c1, B.nchunk, 64);
+                dm_grow(g->dm, W.hub_cid, c2, B.nchunk, 64);
+                W.hub_chunk_cap = c1;
             }
             HIPCHK(hipStreamSynchronize(s));
         }
@@ -293,6 +325,8 @@ static void setup_level(slm_graph *g)
 static void alloc_work(slm_graph *g)
 {
     Work &W = g->W;
+    W.dm = &g->dm;
+    g->dm.s = g->s;
     const i64 n = g->n0, nnz = g->nnz0;
     W.n0 = n;
     W.nnz0 = nnz;
@@ -720,7 +754,11 @@ static void union_append(slm_graph *g, std::vector<Member> &add)
 // converged), and leaves when the partition is the identity or max_levels is
 // reached; the others are contracted together (setup_level is left to the
 // caller, which may append members first).  Leaving members go to `done`.
-static void union_level(slm_graph *g, const slm_params *p, std::vector<Member> &done)
+// mark_cancel (may be null) is called once the level's work is done and sets
+// Member::cancel on members whose request was cancelled: they leave without
+// output.
+static void union_level(slm_graph *g, const slm_params *p, std::vector<Member> &done,
+                        const std::function<void(std::vector<Member> &)> *mark_cancel = nullptr)
 {
     const int G = g->G;
     Work &W = g->W;
@@ -749,10 +787,12 @@ static void union_level(slm_graph *g, const slm_params *p, std::vector<Member> &
     std::vector<i64> gcb(G + 1);
     gcb[G] = nc;
     for (int q = G - 1; q >= 0; q--) gcb[q] = first[q] >= 0 ? first[q] : gcb[q + 1];
+    if (mark_cancel) (*mark_cancel)(g->mem);
     std::vector<char> emit(G, 0), leave(G, 0);
     bool any_emit = false;
     for (int q = 0; q < G; q++) {
-        if (gcb[q + 1] - gcb[q] == g->base[q + 1] - g->base[q]) leave[q] = 1;  // identity
+        if (g->mem[q].cancel) leave[q] = 1;  // a cancelled request: no output
+        else if (gcb[q + 1] - gcb[q] == g->base[q + 1] - g->base[q]) leave[q] = 1;  // identity
         else emit[q] = any_emit = true;
     }
     if (any_emit) {
@@ -881,12 +921,18 @@ void slm_destroy(slm_graph *g)
     if (!g) return;
     (void)hipStreamSynchronize(g->s);
     release_bins(g);
-    for (void *p : g->allocs) (void)hipFree(p);
+    for (auto &pb : g->allocs) g->dm.put(pb.first, pb.second);
     Work &W = g->W;
-    for (void *p : {(void *)W.W, (void *)W.hist, (void *)W.hub_part, (void *)W.hub_poff,
-                    (void *)W.hub_cwin, (void *)W.hub_ckey, (void *)W.hub_cid,
-                    (void *)W.hub_tkey, (void *)W.hub_tid})
-        if (p) (void)hipFree(p);
+    DevMem &dm = g->dm;
+    dm.put(W.W, sizeof(i64) * W.W_cap);
+    dm.put(W.hist, sizeof(i64) * 2 * W.hist_cap);
+    dm.put(W.hub_part, sizeof(int2) * W.hub_part_cap);
+    dm.put(W.hub_poff, sizeof(i64) * W.hub_poff_cap);
+    dm.put(W.hub_cwin, sizeof(i32) * W.hub_cwin_cap);
+    dm.put(W.hub_ckey, sizeof(i64) * W.hub_chunk_cap);
+    dm.put(W.hub_cid, sizeof(i32) * W.hub_chunk_cap);
+    dm.put(W.hub_tkey, sizeof(i64) * W.hub_tile_cap);
+    dm.put(W.hub_tid, sizeof(i32) * W.hub_tile_cap);
     if (W.h_scal) (void)hipHostFree(W.h_scal);
     for (int q = 0; q < FAN_SIDE; q++) {
         if (W.fan.side[q]) (void)hipStreamDestroy(W.fan.side[q]);
@@ -900,7 +946,7 @@ void slm_destroy(slm_graph *g)
 
 slm_status slm_create(int64_t n, int64_t nnz, const void *row_ptr, int row_ptr_bytes,
                       const int32_t *col, const int32_t *w, int inputs_on_device, int validate,
-                      void *hip_stream, slm_graph **out)
+                      void *hip_stream, const slm_allocator *alloc, slm_graph **out)
 {
     slm_graph *g = nullptr;
     try {
@@ -914,6 +960,7 @@ slm_status slm_create(int64_t n, int64_t nnz, const void *row_ptr, int row_ptr_b
         REQUIRE(nnz < ((i64)1 << 40), SLM_E_OVERFLOW, "too many entries");
         g = new slm_graph();
         g->s = (hipStream_t)hip_stream;
+        set_allocator(g, alloc);
         HIPCHK(hipGetDevice(&g->device));
         g->n0 = g->n = n;
         g->nnz0 = g->nnz = nnz;
@@ -1315,7 +1362,7 @@ slm_status slm_timing_read(slm_graph *g, double *sweep_ms, int64_t *sweeps, int6
 }
 
 slm_status slm_batch_create(int32_t count, const slm_graph_desc *graphs, int validate,
-                            void *hip_stream, slm_graph **out)
+                            void *hip_stream, const slm_allocator *alloc, slm_graph **out)
 {
     slm_graph *g = nullptr;
     try {
@@ -1357,6 +1404,7 @@ slm_status slm_batch_create(int32_t count, const slm_graph_desc *graphs, int val
         rp_h[N] = NNZ;
         g = new slm_graph();
         g->s = (hipStream_t)hip_stream;
+        set_allocator(g, alloc);
         HIPCHK(hipGetDevice(&g->device));
         g->n0 = g->n = N;
         g->nnz0 = g->nnz = NNZ;
@@ -1418,6 +1466,23 @@ slm_status slm_batch_run(slm_graph *g, const slm_params *p, const uint64_t *seed
     API_END
 }
 
+slm_status slm_batch_solve(int32_t count, const slm_graph_desc *graphs, const slm_params *p,
+                           const uint64_t *seeds, void *hip_stream, const slm_allocator *alloc,
+                           slm_result **outs)
+{
+    if (!p || !outs) {
+        g_err = "null argument";
+        return SLM_E_INVALID;
+    }
+    slm_graph *g = nullptr;
+    for (int i = 0; i < count; i++) outs[i] = nullptr;
+    slm_status st = slm_batch_create(count, graphs, p->validate, hip_stream, alloc, &g);
+    if (st != SLM_OK) return st;
+    st = slm_batch_run(g, p, seeds, outs);
+    slm_destroy(g);
+    return st;
+}
+
 // ================================================================== serving
 }  // extern "C"
 
@@ -1434,6 +1499,8 @@ struct Lane {
 
 struct slm_server {
     slm_server_cfg cfg;
+    slm_allocator alloc{};
+    bool has_alloc = false;
     int device = 0;
     std::vector<Lane *> lanes;
     std::deque<Member> q_small, q_large;  // requests not yet admitted
@@ -1442,6 +1509,8 @@ struct slm_server {
     std::unordered_map<u64, slm_result *> done;
     std::unordered_map<u64, std::string> failed;
     std::unordered_set<u64> open;  // submitted and not yet delivered
+    std::unordered_set<u64> cancel_req;  // cancelled while resident in a lane
+    std::unordered_set<u64> cancelled;   // cancelled, not yet reported
     u64 next_ticket = 1;
     bool stop = false;
     i64 submitted = 0, completed = 0;
@@ -1456,11 +1525,13 @@ static i64 now_ns()
         .count();
 }
 
-static slm_graph *make_engine(i64 cap_n, i64 cap_e, int cap_m, hipStream_t s)
+static slm_graph *make_engine(i64 cap_n, i64 cap_e, int cap_m, hipStream_t s,
+                              const slm_allocator *alloc)
 {
     slm_graph *g = new slm_graph();
     try {
         g->s = s;
+        set_allocator(g, alloc);
         g->no_fanout = true;
         HIPCHK(hipGetDevice(&g->device));
         g->n0 = cap_n;
@@ -1487,7 +1558,8 @@ static void lane_fail(slm_server *sv, Lane *L, const std::string &msg)
     slm_graph *g = L->eng;
     std::lock_guard<std::mutex> lk(sv->mu);
     for (Member &m : g->mem) {
-        sv->failed[m.ticket] = msg;
+        if (sv->cancel_req.erase(m.ticket)) sv->cancelled.insert(m.ticket);
+        else sv->failed[m.ticket] = msg;
         delete m.res;
     }
     g->mem.clear();
@@ -1549,7 +1621,13 @@ static void lane_loop(slm_server *sv, Lane *L)
                 const i64 n0 = g->n, e0 = g->nnz;
                 setup_level(g);
                 const i64 t1 = now_ns();
-                union_level(g, &sv->cfg.params, done);
+                const std::function<void(std::vector<Member> &)> mark =
+                    [sv](std::vector<Member> &mem) {
+                        std::lock_guard<std::mutex> lk(sv->mu);
+                        if (sv->cancel_req.empty()) return;
+                        for (Member &m : mem) m.cancel |= sv->cancel_req.count(m.ticket) > 0;
+                    };
+                union_level(g, &sv->cfg.params, done, &mark);
                 if (getenv("SLM_TRACE"))
                     fprintf(stderr, "lane %p level: G %d n %lld nnz %lld admitted %zu setup %.2f ms level %.2f ms done %zu\n",
                             (void *)L, G0, (long long)n0, (long long)e0, nadd, (t1 - t0) / 1e6,
@@ -1559,6 +1637,11 @@ static void lane_loop(slm_server *sv, Lane *L)
                 std::lock_guard<std::mutex> lk(sv->mu);
                 const i64 t = now_ns();
                 for (Member &m : done) {
+                    if (sv->cancel_req.erase(m.ticket)) {
+                        delete m.res;
+                        sv->cancelled.insert(m.ticket);
+                        continue;
+                    }
                     m.res->t_done_ns = t;
                     sv->done[m.ticket] = m.res;
                     sv->completed++;
@@ -1576,7 +1659,8 @@ static void lane_loop(slm_server *sv, Lane *L)
 
 extern "C" {
 
-slm_status slm_server_create(const slm_server_cfg *cfg, slm_server **out)
+slm_status slm_server_create(const slm_server_cfg *cfg, const slm_allocator *alloc,
+                             slm_server **out)
 {
     slm_server *sv = nullptr;
     try {
@@ -1587,11 +1671,18 @@ slm_status slm_server_create(const slm_server_cfg *cfg, slm_server **out)
                 "large_lanes must leave at least one lane for small graphs");
         REQUIRE(cfg->node_capacity >= 0 && cfg->entry_capacity >= 0 && cfg->max_members >= 0,
                 SLM_E_INVALID, "negative capacity");
+        REQUIRE(cfg->queue_cap >= 0, SLM_E_INVALID, "negative queue_cap");
+        REQUIRE(!alloc || (alloc->alloc && alloc->free), SLM_E_INVALID,
+                "an allocator needs both alloc and free");
         REQUIRE(cfg->params.accept_p <= (1ull << 32), SLM_E_INVALID, "accept_p must be at most 2^32");
         REQUIRE(cfg->params.max_rounds >= 0 && cfg->params.max_levels >= 0, SLM_E_INVALID,
                 "negative cap");
         sv = new slm_server();
         sv->cfg = *cfg;
+        if (alloc) {
+            sv->alloc = *alloc;
+            sv->has_alloc = true;
+        }
         if (sv->cfg.node_capacity == 0) sv->cfg.node_capacity = (i64)1 << 22;
         if (sv->cfg.entry_capacity == 0) sv->cfg.entry_capacity = (i64)1 << 26;
         if (sv->cfg.max_members == 0) sv->cfg.max_members = 4096;
@@ -1604,7 +1695,8 @@ slm_status slm_server_create(const slm_server_cfg *cfg, slm_server **out)
             L->cap_nodes = sv->cfg.node_capacity;
             L->cap_entries = sv->cfg.entry_capacity;
             L->cap_members = sv->cfg.max_members;
-            L->eng = make_engine(L->cap_nodes, L->cap_entries, L->cap_members, L->stream);
+            L->eng = make_engine(L->cap_nodes, L->cap_entries, L->cap_members, L->stream,
+                                 sv->has_alloc ? &sv->alloc : nullptr);
             L->queue = l < sv->cfg.lanes - sv->cfg.large_lanes ? &sv->q_small : &sv->q_large;
         }
         for (Lane *L : sv->lanes) L->th = std::thread(lane_loop, sv, L);
@@ -1646,16 +1738,22 @@ slm_status slm_server_submit(slm_server *sv, const slm_graph_desc *d, uint64_t s
     m.seed = seed;
     m.comp.resize(d->n);
     for (i64 v = 0; v < d->n; v++) m.comp[v] = (i32)v;
-    m.res = new slm_result();
-    m.res->n0 = d->n;
-    m.res->t_submit_ns = now_ns();
     {
         std::lock_guard<std::mutex> lk(sv->mu);
         REQUIRE(!sv->stop, SLM_E_STATE, "the server is stopping");
+        std::deque<Member> &q = large ? sv->q_large : sv->q_small;
+        bool live = false;
+        for (Lane *L : sv->lanes) live |= (!L->dead && L->queue == &q);
+        REQUIRE(live, SLM_E_DEVICE, "every lane serving this graph's class has failed");
+        REQUIRE(sv->cfg.queue_cap == 0 || (i64)q.size() < (i64)sv->cfg.queue_cap, SLM_E_BUSY,
+                "the queue of this graph's class is full");
+        m.res = new slm_result();
+        m.res->n0 = d->n;
+        m.res->t_submit_ns = now_ns();
         m.ticket = sv->next_ticket++;
         *ticket = m.ticket;
         sv->open.insert(m.ticket);
-        (large ? sv->q_large : sv->q_small).push_back(std::move(m));
+        q.push_back(std::move(m));
         sv->submitted++;
     }
     sv->cv_work.notify_all();
@@ -1677,6 +1775,11 @@ static slm_status take_result(slm_server *sv, uint64_t ticket, slm_result **out,
             sv->open.erase(ticket);
             return SLM_OK;
         }
+        if (sv->cancelled.erase(ticket)) {
+            g_err = "the request was cancelled";
+            sv->open.erase(ticket);
+            return SLM_E_CANCELLED;
+        }
         auto f = sv->failed.find(ticket);
         if (f != sv->failed.end()) {
             g_err = f->second;
@@ -1690,6 +1793,39 @@ static slm_status take_result(slm_server *sv, uint64_t ticket, slm_result **out,
         }
         sv->cv_done.wait(lk);
     }
+}
+
+slm_status slm_server_cancel(slm_server *sv, uint64_t ticket)
+{
+    API_BEGIN
+    REQUIRE(sv != nullptr, SLM_E_INVALID, "null argument");
+    std::lock_guard<std::mutex> lk(sv->mu);
+    REQUIRE(sv->open.count(ticket) > 0, SLM_E_INVALID, "unknown or already delivered ticket");
+    if (sv->cancelled.count(ticket) || sv->cancel_req.count(ticket)) return SLM_OK;
+    auto d = sv->done.find(ticket);
+    if (d != sv->done.end()) {
+        delete d->second;
+        sv->done.erase(d);
+        sv->cancelled.insert(ticket);
+        sv->cv_done.notify_all();
+        return SLM_OK;
+    }
+    if (sv->failed.erase(ticket)) {
+        sv->cancelled.insert(ticket);
+        sv->cv_done.notify_all();
+        return SLM_OK;
+    }
+    for (std::deque<Member> *q : {&sv->q_small, &sv->q_large})
+        for (auto it = q->begin(); it != q->end(); ++it)
+            if (it->ticket == ticket) {
+                delete it->res;
+                q->erase(it);
+                sv->cancelled.insert(ticket);
+                sv->cv_done.notify_all();
+                return SLM_OK;
+            }
+    sv->cancel_req.insert(ticket);  // resident: leaves at the end of its level
+    API_END
 }
 
 slm_status slm_server_poll(slm_server *sv, uint64_t ticket, slm_result **out)
@@ -1718,7 +1854,7 @@ slm_status slm_server_stats(slm_server *sv, int64_t *submitted, int64_t *complet
     if (completed) *completed = sv->completed;
     if (reserved_bytes) {
         i64 b = 0;
-        for (Lane *L : sv->lanes) b += L->eng ? L->eng->reserved : 0;
+        for (Lane *L : sv->lanes) b += L->eng ? L->eng->dm.held : 0;
         *reserved_bytes = b;
     }
     API_END

@@ -151,10 +151,15 @@ static void radix_sort(Work &W, u64 *&k, i32 *&v, u64 *&k2, i32 *&v2, i64 n, int
     const i64 nblk = (n + RS_TILE - 1) / RS_TILE;
     const i64 hn = nblk * RS_BINS;
     if (hn + 1 > W.hist_cap) {
-        if (W.hist) HIPCHK(hipFree(W.hist));
+        if (W.hist) {
+            HIPCHK(hipStreamSynchronize(s));
+            W.dm->put(W.hist, sizeof(i64) * 2 * (size_t)W.hist_cap);
+        }
         W.hist = nullptr;
-        W.hist_cap = hn + 1 + 4096;
-        HIPCHK(hipMalloc(&W.hist, sizeof(i64) * 2 * W.hist_cap));
+        W.hist_cap = 0;
+        const i64 cap = hn + 1 + 4096;
+        W.hist = (i64 *)W.dm->get(sizeof(i64) * 2 * (size_t)cap);
+        W.hist_cap = cap;
     }
     i64 *hist = W.hist, *offs = W.hist + W.hist_cap;
     i64 *tmp = W.scan_tmp;  // scan_tmp is sized for n0 + nnz0

@@ -752,13 +752,7 @@ i64 positive(Work &W, const LevelView &Lv, const Bins &B, i64 *nc_out, hipStream
         launch_scan_i64(W.nsz, W.noff_f, nflag, W.scan_tmp, s);
         read_scalars(W, W.woff_f + nflag, 1, s);
         const i64 wtotal = W.h_scal[0];
-        if (wtotal > W.W_cap) {
-            if (W.W) HIPCHK(hipFree(W.W));
-            W.W = nullptr;
-            i64 cap = wtotal + wtotal / 2 + 1024;
-            HIPCHK(hipMalloc(&W.W, sizeof(i64) * cap));
-            W.W_cap = cap;
-        }
+        dm_grow(*W.dm, W.W, W.W_cap, wtotal, 1024);
         HIPCHK(hipMemcpyAsync(W.part, W.comp, sizeof(i32) * n, hipMemcpyDeviceToDevice, s));
         launch_fill_i64(W.counters, 0, 1, s);
         PosArgs A;

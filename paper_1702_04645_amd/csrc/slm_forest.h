@@ -6,6 +6,7 @@
 #include "slm_impl.h"
 
 struct Work {
+    DevMem *dm = nullptr;  // the handle's device memory
     i64 n0 = 0, nnz0 = 0;
     int kmax = 0;  // number of jump tables held
 

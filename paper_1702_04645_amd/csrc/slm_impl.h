@@ -29,6 +29,40 @@ struct SlmError {
             throw SlmError{4, std::string(#call) + ": " + hipGetErrorString(e_)};     \
     } while (0)
 
+// ---------------------------------------------------------------- device memory
+// Every device buffer of a handle comes from here: the caller's allocator
+// (alloc/free callbacks with an opaque context, told the handle's stream)
+// when one was given at creation, else hipMalloc / hipFree.  get() throws
+// SlmError{SLM_E_NOMEM} when the allocator returns null; put() never throws.
+// Buffers that grow are released only after the handle's stream is idle, so
+// a stream-ordered allocator may hand the memory to other work at once.
+struct DevMem {
+    void *ctx = nullptr;
+    void *(*fn_alloc)(void *ctx, size_t bytes, void *stream) = nullptr;
+    void (*fn_free)(void *ctx, void *p, void *stream) = nullptr;
+    hipStream_t s = nullptr;
+    i64 held = 0;  // bytes currently held
+    void *get(size_t bytes);
+    void put(void *p, size_t bytes);
+};
+
+// Grows a device buffer of `cap` elements to at least `need` (new capacity
+// need * 1.5 + pad); the old contents are dropped.
+template <typename T>
+static void dm_grow(DevMem &dm, T *&p, i64 &cap, i64 need, i64 pad)
+{
+    if (need <= cap) return;
+    if (p) {
+        HIPCHK(hipStreamSynchronize(dm.s));
+        dm.put(p, sizeof(T) * (size_t)cap);
+    }
+    p = nullptr;
+    cap = 0;
+    const i64 c = need + need / 2 + pad;
+    p = (T *)dm.get(sizeof(T) * (size_t)c);
+    cap = c;
+}
+
 // ---------------------------------------------------------------- degree bins
 // A node is handled by a group of lanes sized to its degree.  Bins 1..6 keep
 // the per-node community table in LDS; bin 7 ("hub") rows are split in

@@ -18,6 +18,17 @@ def say(*args):
     sys.stdout.flush()
 
 
+_configs = {}
+
+
+def config_graph(name):
+    """graphgen.config_graph(name), generated once per test session."""
+    if name not in _configs:
+        say("generating", name)
+        _configs[name] = gg.config_graph(name)
+    return _configs[name]
+
+
 def small_graphs():
     """Named small graphs covering every degree bin, hubs, loops, isolated
     nodes and ragged sizes."""

@@ -7,14 +7,15 @@ oracle element by element on the whole graph.  Whole runs are checked by
 properties that hold at any size (N_Q of every emitted level equals the
 oracle's modularity of the GPU labels on the original graph, canonical
 labels, Q non-decreasing, no negative local gain after the first level).
-The 2048-graph batch runs whole on the GPU; a spread sample of its members
-is compared with the oracle run of that member alone."""
+The 2048-graph batch runs whole on the GPU; every member's levels are
+compared with the stored oracle runs of each member alone, and a spread
+sample with oracle runs made in the test."""
 import numpy as np
 import pytest
 
 import graphgen as gg
 import oracle
-from gpu_common import say
+from gpu_common import config_graph, say
 
 pytestmark = pytest.mark.gpu
 
@@ -28,14 +29,8 @@ def slm():
     return slm
 
 
-_cache = {}
-
-
 def graph(name):
-    if name not in _cache:
-        say("generating", name)
-        _cache[name] = gg.config_graph(name)
-    return _cache[name]
+    return config_graph(name)
 
 
 def _canonical(lab):
@@ -124,10 +119,31 @@ def _gen_member(args):
     return gg.sbm_batch(count, 64, 65536, seed, indices=[i])[0]
 
 
+def batch2048_golden():
+    """Per member, the list of its emitted levels (n_c, N_Q, rounds,
+    converged, sha256 of the composed labels) from the stored oracle runs
+    (tests/golden/make_batch2048_golden.py)."""
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "batch2048_levels.txt")
+    out = {}
+    for ln in open(path):
+        if ln.startswith("#") or not ln.strip():
+            continue
+        f = ln.split()
+        m, lv = int(f[0]), int(f[1])
+        out.setdefault(m, [])
+        assert len(out[m]) == lv
+        out[m].append((int(f[2]), int(f[3]), int(f[4]), bool(int(f[5])), f[6]))
+    return out
+
+
 @pytest.mark.timeout(900)
 def test_fullsize_batch2048(slm):
-    """The 2048-member planted-partition batch in one batched run; a spread
-    sample of members (and the largest) against the oracle run alone."""
+    """The 2048-member planted-partition batch in one batched run: every
+    member's every level (n_c, N_Q, Q, rounds, converged, composed labels)
+    equals the stored oracle run of that member alone; a spread sample and
+    the largest member are also run through the oracle here."""
+    import hashlib
     import multiprocessing as mp
     count, seed = 2048, gg.CONFIG_SEEDS["batch2048"]
     say("batch2048 generating")
@@ -137,6 +153,17 @@ def test_fullsize_batch2048(slm):
     say("batch2048 gpu run", sum(m[1].size for m in members))
     with slm.Batch(members, validate=False) as b:
         res = b.run(slm.params(), seeds=seeds)
+    gold = batch2048_golden()
+    say("batch2048 against the stored oracle runs of all members")
+    for i in range(count):
+        rg, go = res[i], gold[i]
+        assert len(rg) == len(go), i
+        m2 = int(members[i][2].sum())
+        for lv, (x, (nc, nq, rounds, conv, h)) in enumerate(zip(rg, go)):
+            assert (x.n_c, x.nq, x.rounds, bool(x.converged)) == (nc, nq, rounds, conv), (i, lv)
+            assert x.q == nq / m2 / m2, (i, lv)
+            lab = np.ascontiguousarray(x.labels, dtype=np.int32)
+            assert hashlib.sha256(lab.tobytes()).hexdigest() == h, (i, lv)
     sizes = np.array([m[0].size - 1 for m in members])
     pick = sorted(set(list(range(0, count, 97)) + [int(np.argmax(sizes))]))
     say("batch2048 oracle on", len(pick), "members")

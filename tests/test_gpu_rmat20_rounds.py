@@ -16,7 +16,7 @@ import numpy as np
 import pytest
 
 import graphgen as gg
-from gpu_common import say
+from gpu_common import config_graph, say
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 GOLDEN = os.path.join(HERE, "golden", "rmat20_level0_rounds.txt")
@@ -54,7 +54,7 @@ def test_rmat20_level0_rounds_match_the_oracle():
     assert torch.cuda.is_available()
     import paper_1702_04645_amd as slm
     rows = golden_rounds()
-    rp, col, w = gg.config_graph("rmat20")
+    rp, col, w = config_graph("rmat20")
     say("rmat20 level-0 rounds:", rows.shape[0])
     p = slm.params(seed=1)
     with slm.Graph(rp, col, w, validate=False) as g:
@@ -75,7 +75,7 @@ def test_rmat20_full_run_matches_the_oracle():
     assert torch.cuda.is_available()
     import paper_1702_04645_amd as slm
     lv = golden_levels()
-    rp, col, w = gg.config_graph("rmat20")
+    rp, col, w = config_graph("rmat20")
     say("rmat20 full run, seed 1:", len(lv), "levels")
     with slm.Graph(rp, col, w, validate=False) as g:
         res = g.run(slm.params(seed=1))

@@ -98,3 +98,42 @@ def test_serve_parameters(slm):
     for i, g in enumerate(graphs):
         _compare(res[i], oracle.run(*g, seed=i + 1, accept_p=1 << 30, max_rounds=3,
                                     max_levels=2), i)
+
+
+@pytest.mark.timeout(600)
+def test_serve_mix_with_rmat20(slm):
+    """Four lanes, one of them for large graphs: the R-MAT scale-20 graph
+    (seed 1) served among small graphs arriving before, during and after it.
+    The R-MAT result equals the stored oracle run (every level's n_c, N_Q,
+    rounds, convergence and the SHA-256 of the composed labels); every small
+    result equals its oracle run alone."""
+    import hashlib
+    from test_gpu_rmat20_rounds import golden_levels
+    lv = golden_levels()
+    from gpu_common import config_graph
+    rmat = config_graph("rmat20")
+    small = _mix() + gg.sbm_batch(40, 64, 20000, 778)
+    seeds = [3000 + 11 * i for i in range(len(small))]
+    rg = np.random.default_rng(9)
+    say("serve mix with R-MAT-20:", len(small), "small graphs")
+    with slm.Server(lanes=4, large_lanes=1, large_nodes=200_000, node_capacity=1 << 21,
+                    entry_capacity=1 << 26, max_members=256, validate=False) as sv:
+        tickets = []
+        for i in range(len(small) // 3):
+            tickets.append(sv.submit(*small[i], seed=seeds[i]))
+        t_rmat = sv.submit(*rmat, seed=1)
+        for i in range(len(small) // 3, len(small)):
+            tickets.append(sv.submit(*small[i], seed=seeds[i]))
+            time.sleep(float(rg.uniform(0, 0.05)))  # arrivals during the R-MAT levels
+        res = [sv.wait(t) for t in tickets]
+        say("small graphs done")
+        r_rmat = sv.wait(t_rmat)
+        say("R-MAT done")
+    assert len(r_rmat) == len(lv)
+    for i, (r, (nc, nq, q, rounds, conv, h)) in enumerate(zip(r_rmat, lv)):
+        assert (r.n_c, r.nq, r.rounds, bool(r.converged)) == (nc, nq, rounds, conv), i
+        assert abs(r.q - q) <= 1e-12
+        lab = np.ascontiguousarray(r.labels, dtype=np.int32)
+        assert hashlib.sha256(lab.tobytes()).hexdigest() == h, "level %d labels differ" % i
+    for i, g in enumerate(small):
+        _compare(res[i], oracle.run(*g, seed=seeds[i]), i)
