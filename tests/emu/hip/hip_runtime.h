@@ -29,6 +29,7 @@ typedef int hipError_t;
 typedef struct ihipStream_t *hipStream_t;
 typedef struct ihipEvent_t *hipEvent_t;
 static inline const char *hipGetErrorString(hipError_t) { return "host emulation"; }
+static inline hipError_t hipStreamSynchronize(hipStream_t) { return hipSuccess; }
 
 #define __global__
 #define __device__
