@@ -349,6 +349,33 @@ slm_status slm_timing_read(slm_graph *g, double *sweep_ms, int64_t *sweeps,
  * changes). */
 slm_status slm_set_option(slm_graph *g, const char *name, int64_t value);
 
+/* Modularity of a labelling without a handle and without allocating: for
+ * callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc) and so cannot
+ * create a handle.  Returns what slm_modularity returns for a handle at
+ * level 0 of the same graph: N_Q = M2 * sum_C w(C,C) - sum_C S_C^2 (exact,
+ * *nq) and Q = N_Q / M2 / M2 (IEEE double, *q), M2 = sum of all entries.
+ *   n, nnz       nodes and entries of a symmetric CSR (the convention above)
+ *   row_ptr_dev  int64[n+1] device offsets
+ *   col_dev, w_dev  int32[nnz] device columns and weights (>= 1)
+ *   lab_dev      int32[n] device labels, each in [0, n_c)
+ *   n_c          community count, at most SLM_NOALLOC_MAX_COMMUNITIES
+ *   hip_stream   stream of the call's kernels (NULL = default stream)
+ * nq and q are host pointers (either may be NULL); the call synchronises
+ * the stream.  It calls no allocator: its work space (the community totals
+ * and a few accumulators) is one fixed array per GPU, held by the library
+ * until the process ends.  Every call on a GPU uses that GPU's array, so
+ * calls that overlap on one GPU (several threads or streams) race; calls in
+ * sequence are independent (each clears what it uses).  The matrix is not
+ * checked for symmetry; out-of-range labels or columns, an inconsistent
+ * row_ptr or a weight below 1 give SLM_E_INVALID (detected inside the
+ * kernels, which skip the bad index), M2 >= 2^31 gives SLM_E_OVERFLOW. */
+#define SLM_NOALLOC_MAX_COMMUNITIES (1 << 22)
+slm_status slm_modularity_noalloc(int64_t n, int64_t nnz, const int64_t *row_ptr_dev,
+                                  const int32_t *col_dev, const int32_t *w_dev,
+                                  const int32_t *lab_dev, int64_t n_c, int64_t *nq, double *q,
+                                  void *hip_stream);
+
 /* Message of the calling thread's last failed call. */
 const char *slm_last_error(void);
 

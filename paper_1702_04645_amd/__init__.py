@@ -24,6 +24,7 @@ LIB_PATH = os.path.join(_HERE, "libslm.so")
  SLM_E_CANCELLED) = range(8)
 _STATUS = {1: "SLM_E_INVALID", 2: "SLM_E_OVERFLOW", 3: "SLM_E_NOMEM", 4: "SLM_E_DEVICE",
            5: "SLM_E_STATE", 6: "SLM_E_BUSY", 7: "SLM_E_CANCELLED"}
+SLM_NOALLOC_MAX_COMMUNITIES = 1 << 22  # include/slm.h
 
 
 class SlmError(RuntimeError):
@@ -152,6 +153,8 @@ def lib():
         "slm_server_wait": (st, [P, C.c_uint64, C.POINTER(P)]),
         "slm_server_stats": (st, [P, pi64, pi64, pi64]),
         "slm_server_destroy": (None, [P]),
+        "slm_modularity_noalloc": (st, [i64, i64, P, P, P, P, i64, pi64,
+                                        C.POINTER(C.c_double), P]),
     }
     for name, (res, args) in sigs.items():
         f = getattr(L, name)
@@ -553,3 +556,26 @@ def run(row_ptr, col, w, seed: int = 0, accept_p: int = 1 << 31, max_rounds: int
     """Full run of Algorithm 1 on the GPU; returns a list of LevelResult."""
     with Graph(row_ptr, col, w) as g:
         return g.run(params(seed, accept_p, max_rounds, max_levels))
+
+
+def modularity_noalloc(row_ptr, col, w, lab, nc: int, stream=None):
+    """N_Q and Q of a labelling of a device CSR through slm_modularity_noalloc
+    (no handle, no device allocation).  ``row_ptr`` int64, ``col``, ``w`` and
+    ``lab`` int32 CUDA tensors."""
+    torch = _torch()
+    for t in (row_ptr, col, w, lab):
+        if not (isinstance(t, torch.Tensor) and t.is_cuda and t.is_contiguous()):
+            raise TypeError("row_ptr, col, w and lab must be contiguous CUDA tensors")
+    if row_ptr.dtype != torch.int64 or col.dtype != torch.int32 or w.dtype != torch.int32 \
+            or lab.dtype != torch.int32:
+        raise TypeError("row_ptr must be int64; col, w and lab int32")
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    n = row_ptr.numel() - 1
+    if lab.numel() < n:
+        raise ValueError("lab holds fewer than n labels")
+    nq, q = C.c_int64(), C.c_double()
+    _check(lib().slm_modularity_noalloc(n, col.numel(), _ptr(row_ptr), _ptr(col), _ptr(w),
+                                        _ptr(lab), int(nc), C.byref(nq), C.byref(q),
+                                        C.c_void_p(stream.cuda_stream)))
+    return nq.value, q.value

@@ -125,3 +125,19 @@ def test_set_option_rejects_without_a_device():
     lib = slm.lib()
     assert lib.slm_set_option(None, b"hub_table_bits", 8) == slm.SLM_E_INVALID
     assert b"null" in lib.slm_last_error()
+
+
+def test_noalloc_rejects_sizes_without_a_device():
+    """slm_modularity_noalloc checks its sizes before touching a device."""
+    import paper_1702_04645_amd as slm
+    lib = slm.lib()
+    big = slm.SLM_NOALLOC_MAX_COMMUNITIES + 1
+    dummy = C.c_void_p(1)  # never dereferenced: the call fails first
+    st = lib.slm_modularity_noalloc(big, 0, dummy, None, None, dummy, big, None, None, None)
+    assert st == slm.SLM_E_INVALID and b"at most" in lib.slm_last_error()
+    st = lib.slm_modularity_noalloc(-1, 0, dummy, None, None, dummy, 0, None, None, None)
+    assert st == slm.SLM_E_INVALID
+    st = lib.slm_modularity_noalloc(4, 0, dummy, None, None, dummy, 5, None, None, None)
+    assert st == slm.SLM_E_INVALID and b"community count" in lib.slm_last_error()
+    st = lib.slm_modularity_noalloc(1 << 31, 0, dummy, None, None, dummy, 0, None, None, None)
+    assert st == slm.SLM_E_OVERFLOW
