@@ -324,6 +324,19 @@ def star(leaves: int):
     return csr_from_pairs(leaves + 1, u, np.arange(1, leaves + 1))
 
 
+def random_directed(n: int, m: int, w_max: int, seed: int, loops: bool = False):
+    """A directed graph W: m random arcs u -> v (repeats summed), weights
+    uniform 1..w_max, stored by source row; with ``loops`` some W_uu > 0."""
+    g = rng(seed)
+    u = g.integers(0, n, m)
+    v = g.integers(0, n, m)
+    if not loops:
+        keep = u != v
+        u, v = u[keep], v[keep]
+    wt = g.integers(1, w_max + 1, u.size)
+    return csr_from_pairs(n, u, v, wt, symmetrise=False)
+
+
 def random_sparse(n: int, m: int, w_max: int, seed: int, loops: bool = False):
     """m random pairs (repeats summed), weights uniform 1..w_max; with
     ``loops`` some diagonal entries appear."""

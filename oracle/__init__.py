@@ -56,6 +56,18 @@ def _load():
         "or_contract": (i64, [i64, P, P, P, P, i64, P, P, P]),
         "or_level": (i32, [i64, P, P, P, P, i64, u64, i32, u64, i32, P, P, P]),
         "or_run": (i32, [i64, P, P, P, u64, u64, i32, i32, i32, P, P, P, P, P, P]),
+        "or_assign_nm": (None, [i64, P, P, P, P, P, i64, P]),
+        "or_local_gain_nm": (None, [i64, P, P, P, P, P, i64, P, i64, P]),
+        "or_positive_nm": (i64, [i64, P, P, P, P, P, i64, P]),
+        "or_sweep_nm": (None, [i64, P, P, P, P, P, i64, P, i64, P, P, P]),
+        "or_maximal_round_nm": (i64, [i64, P, P, P, P, P, i64, P, u64, i32, i32, u64, P, P]),
+        "or_modularity_num_nm": (i64, [i64, P, P, P, P, P, i64, P, i64]),
+        "or_modularity_nm": (C.c_double, [i64, i64, i64]),
+        "or_level_nm": (i32, [i64, P, P, P, P, P, i64, u64, i32, u64, i32, P, P, P]),
+        "or_symmetrize": (i64, [i64, P, P, P, P, P, P]),
+        "or_null_strengths": (i32, [i32, i64, i64, i64, P, P, P, P, P, P]),
+        "or_run_null": (i32, [i64, P, P, P, i32, i64, i64, u64, u64, i32, i32, i32, P, P, P,
+                              P, P, P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -204,6 +216,130 @@ def run(row_ptr, col, w, seed: int = 0, accept_p: int = DEFAULT_ACCEPT,
     L = int(_load().or_run(n0, _p(g.rp), _p(g.col), _p(g.w), seed & (2**64 - 1), accept_p,
                            max_rounds, max_levels, max_out, _p(lab), _p(nc), _p(nq), _p(q),
                            _p(rounds), _p(conv)))
+    out = []
+    for l in range(min(L, max_out)):
+        out.append(dict(labels=lab[l, :n0].copy(), n_c=int(nc[l]), nq=int(nq[l]), q=float(q[l]),
+                        rounds=int(rounds[l]), converged=bool(conv[l])))
+    return out
+
+
+# ---------------------------------------------------------------- null models
+CONFIG, ER, DIRECTED = 0, 1, 2  # kinds of or_null_strengths (Sec. 2.2-2.4)
+
+
+def symmetrize(row_ptr, col, w):
+    """S = W + W^T of a CSR W (sorted columns, diagonal 2 W_ii)."""
+    rp = np.ascontiguousarray(row_ptr, dtype=np.int64)
+    cl = np.ascontiguousarray(col, dtype=np.int32)
+    ww = np.ascontiguousarray(w, dtype=np.int32)
+    n = rp.size - 1
+    rp2 = np.zeros(n + 1, np.int64)
+    col2 = np.zeros(max(2 * cl.size, 1), np.int32)
+    w2 = np.zeros(max(2 * cl.size, 1), np.int32)
+    m = int(_load().or_symmetrize(n, _p(rp), _p(cl), _p(ww), _p(rp2), _p(col2), _p(w2)))
+    return rp2, col2[:m].copy(), w2[:m].copy()
+
+
+class NullGraph:
+    """The level-0 graph of a run under a null model: the matrix the levels
+    run on (S = W + W^T for DIRECTED, else the symmetric input), the
+    strengths x and y, the scale A and M2 = sum of that matrix."""
+
+    def __init__(self, row_ptr, col, w, kind: int = CONFIG, num: int = 1, den: int = 1):
+        rp = np.ascontiguousarray(row_ptr, dtype=np.int64)
+        cl = np.ascontiguousarray(col, dtype=np.int32)
+        ww = np.ascontiguousarray(w, dtype=np.int32)
+        self.n = int(rp.size - 1)
+        self.kind, self.num, self.den = kind, num, den
+        x = np.zeros(max(self.n, 1), np.int64)
+        y = np.zeros(max(self.n, 1), np.int64)
+        A, m2 = C.c_int64(), C.c_int64()
+        st = int(_load().or_null_strengths(kind, num, den, self.n, _p(rp), _p(cl), _p(ww),
+                                           _p(x), _p(y), C.byref(A), C.byref(m2)))
+        if st == 1:
+            raise ValueError("invalid null model")
+        if st == 2:
+            raise OverflowError("gains of this model could leave int64")
+        self.A, self.m2 = int(A.value), int(m2.value)
+        self.x, self.y = x, y
+        if kind == DIRECTED:
+            self.rp, self.col, self.w = symmetrize(rp, cl, ww)
+        else:
+            self.rp, self.col, self.w = rp, cl, ww
+        self._ynull = None if kind != DIRECTED else self.y
+
+    def _g(self):
+        return (self.n, _p(self.rp), _p(self.col), _p(self.w), _p(self.x),
+                _p(self._ynull) if self._ynull is not None else None, self.A)
+
+
+def assign_nm(g: NullGraph) -> np.ndarray:
+    a = np.zeros(max(g.n, 1), np.int32)
+    _load().or_assign_nm(*g._g(), _p(a))
+    return a[: g.n]
+
+
+def local_gain_nm(g: NullGraph, lab, nc: int) -> np.ndarray:
+    lab = np.ascontiguousarray(lab, dtype=np.int32)
+    out = np.zeros(max(g.n, 1), np.int64)
+    _load().or_local_gain_nm(*g._g(), _p(lab), nc, _p(out))
+    return out[: g.n]
+
+
+def positive_nm(g: NullGraph, a):
+    a = np.array(a, dtype=np.int32, copy=True)
+    s = int(_load().or_positive_nm(*g._g(), _p(a)))
+    return a, s
+
+
+def sweep_nm(g: NullGraph, lab, nc: int):
+    lab = np.ascontiguousarray(lab, dtype=np.int32)
+    n = max(g.n, 1)
+    best = np.zeros(n, np.int32)
+    delta = np.zeros(n, np.int64)
+    wown = np.zeros(n, np.int32)
+    _load().or_sweep_nm(*g._g(), _p(lab), nc, _p(best), _p(delta), _p(wown))
+    return best[: g.n], delta[: g.n], wown[: g.n]
+
+
+def maximal_round_nm(g: NullGraph, a, seed: int, level: int, rnd: int,
+                     accept_p: int = DEFAULT_ACCEPT):
+    a = np.array(a, dtype=np.int32, copy=True)
+    st = np.zeros(4, np.int64)
+    valid = int(_load().or_maximal_round_nm(*g._g(), _p(a), seed & (2**64 - 1), level, rnd,
+                                            accept_p, _p(st), None))
+    return a, valid, dict(candidates=int(st[0]), valid=int(st[1]), accepted=int(st[2]),
+                          splits=int(st[3]))
+
+
+def modularity_num_nm(g: NullGraph, lab, nc: int) -> int:
+    lab = np.ascontiguousarray(lab, dtype=np.int32)
+    return int(_load().or_modularity_num_nm(*g._g(), _p(lab), nc))
+
+
+def run_null(row_ptr, col, w, kind: int = CONFIG, num: int = 1, den: int = 1, seed: int = 0,
+             accept_p: int = DEFAULT_ACCEPT, max_rounds: int = 64, max_levels: int = 0,
+             max_out: int = 32):
+    """Full run of Algorithm 1 under a null model; the same per-level dicts
+    as run().  The input is symmetric for CONFIG and ER, any CSR for
+    DIRECTED."""
+    rp = np.ascontiguousarray(row_ptr, dtype=np.int64)
+    cl = np.ascontiguousarray(col, dtype=np.int32)
+    ww = np.ascontiguousarray(w, dtype=np.int32)
+    n0 = rp.size - 1
+    lab = np.zeros((max_out, max(n0, 1)), np.int32)
+    nc = np.zeros(max_out, np.int64)
+    nq = np.zeros(max_out, np.int64)
+    q = np.zeros(max_out, np.float64)
+    rounds = np.zeros(max_out, np.int32)
+    conv = np.zeros(max_out, np.int32)
+    L = int(_load().or_run_null(n0, _p(rp), _p(cl), _p(ww), kind, num, den,
+                                seed & (2**64 - 1), accept_p, max_rounds, max_levels, max_out,
+                                _p(lab), _p(nc), _p(nq), _p(q), _p(rounds), _p(conv)))
+    if L == -1:
+        raise ValueError("invalid null model")
+    if L == -2:
+        raise OverflowError("gains of this model could leave int64")
     out = []
     for l in range(min(L, max_out)):
         out.append(dict(labels=lab[l, :n0].copy(), n_c=int(nc[l]), nq=int(nq[l]), q=float(q[l]),

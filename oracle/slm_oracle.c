@@ -47,6 +47,25 @@ typedef struct {
     const int32_t *w;
 } graph;
 
+/* The null model of the quality function (Sec. 2.2 energy with alpha and
+ * beta, Sec. 2.3 null models, Sec. 2.4 weighted modularity with out- and
+ * in-strengths).  Every gain is
+ *     A * w(P,R) - nu(P,R),   nu(P,R) = X_P * X_R - Y_P * Y_R
+ * for merging disjoint node sets P and R, where w(P,R) sums the symmetric
+ * matrix the level runs on, X and Y sum the per-node strengths x and y, and
+ * A > 0 scales the edge term.  The undirected modularity of the rest of this
+ * file is x = k, y = 0, A = M2.  y == NULL means y = 0. */
+typedef struct {
+    const int64_t *x;
+    const int64_t *y;
+    int64_t A;
+} nullm;
+
+static inline int64_t ny(const nullm *nm, int64_t i)
+{
+    return nm->y ? nm->y[i] : 0;
+}
+
 static void *xmalloc(size_t bytes)
 {
     void *p = malloc(bytes ? bytes : 1);
@@ -106,15 +125,18 @@ int64_t or_strength(int64_t n, const int64_t *rp, const int32_t *col,
 /* ASSIGN (Sec. 3.1 and the appendix ASSIGN): best neighbour of every node.  */
 /* ------------------------------------------------------------------------ */
 
-void or_assign(int64_t n, const int64_t *rp, const int32_t *col,
-               const int32_t *w, const int64_t *k, int64_t m2, int32_t *a_out)
+void or_assign_nm(int64_t n, const int64_t *rp, const int32_t *col,
+                  const int32_t *w, const int64_t *x, const int64_t *y, int64_t A,
+                  int32_t *a_out)
 {
+    const nullm nm = {x, y, A};
     for (int64_t i = 0; i < n; i++) {
         int64_t best_j = -1, best_key = 0;
         for (int64_t e = rp[i]; e < rp[i + 1]; e++) {
             int64_t j = col[e];
             if (j == i) continue;
-            int64_t key = m2 * (int64_t)w[e] - k[i] * k[j];
+            /* pair(i,j): the gain of merging the singletons {i} and {j} */
+            int64_t key = A * (int64_t)w[e] - (x[i] * x[j] - ny(&nm, i) * ny(&nm, j));
             if (best_j < 0 || key > best_key || (key == best_key && j < best_j)) {
                 best_j = j;
                 best_key = key;
@@ -123,6 +145,12 @@ void or_assign(int64_t n, const int64_t *rp, const int32_t *col,
         /* a node whose best gain is not positive is self-assigned */
         a_out[i] = (best_j >= 0 && best_key > 0) ? (int32_t)best_j : (int32_t)i;
     }
+}
+
+void or_assign(int64_t n, const int64_t *rp, const int32_t *col,
+               const int32_t *w, const int64_t *k, int64_t m2, int32_t *a_out)
+{
+    or_assign_nm(n, rp, col, w, k, NULL, m2, a_out);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -197,7 +225,8 @@ int64_t or_components(int64_t n, const int32_t *a, int32_t *lab_out,
 /* Community totals and local gains (Sec. 3.3, appendix POSITIVE).           */
 /* ------------------------------------------------------------------------ */
 
-/* S_C for every community C of the labelling `lab`. */
+/* S_C for every community C of the labelling `lab` (the sum of k, or of any
+ * per-node strength, over its members). */
 static void community_totals(int64_t n, const int64_t *k, const int32_t *lab,
                              int64_t nc, int64_t *sig)
 {
@@ -205,20 +234,40 @@ static void community_totals(int64_t n, const int64_t *k, const int32_t *lab,
     for (int64_t i = 0; i < n; i++) sig[lab[i]] += k[i];
 }
 
-/* g(i) = stay(i): the gain of i being in its community rather than alone. */
-void or_local_gain(int64_t n, const int64_t *rp, const int32_t *col,
-                   const int32_t *w, const int64_t *k, int64_t m2,
-                   const int32_t *lab, int64_t nc, int64_t *g_out)
+/* X_C and Y_C of every community (Y all zero when the model has no y). */
+static void null_totals(int64_t n, const nullm *nm, const int32_t *lab, int64_t nc,
+                        int64_t *sx, int64_t *sy)
 {
-    int64_t *sig = xmalloc((size_t)(nc ? nc : 1) * sizeof(int64_t));
-    community_totals(n, k, lab, nc, sig);
+    community_totals(n, nm->x, lab, nc, sx);
+    if (nm->y) community_totals(n, nm->y, lab, nc, sy);
+    else for (int64_t c = 0; c < nc; c++) sy[c] = 0;
+}
+
+/* g(i) = stay(i): the gain of i being in its community rather than alone. */
+void or_local_gain_nm(int64_t n, const int64_t *rp, const int32_t *col,
+                      const int32_t *w, const int64_t *x, const int64_t *y, int64_t A,
+                      const int32_t *lab, int64_t nc, int64_t *g_out)
+{
+    const nullm nm = {x, y, A};
+    int64_t *sx = xmalloc((size_t)(nc ? nc : 1) * sizeof(int64_t));
+    int64_t *sy = xmalloc((size_t)(nc ? nc : 1) * sizeof(int64_t));
+    null_totals(n, &nm, lab, nc, sx, sy);
     for (int64_t i = 0; i < n; i++) {
         int64_t w_in = 0; /* w(i, c_i \ i) */
         for (int64_t e = rp[i]; e < rp[i + 1]; e++)
             if (col[e] != i && lab[col[e]] == lab[i]) w_in += w[e];
-        g_out[i] = m2 * w_in - k[i] * (sig[lab[i]] - k[i]);
+        int32_t c = lab[i];
+        g_out[i] = A * w_in - (x[i] * (sx[c] - x[i]) - ny(&nm, i) * (sy[c] - ny(&nm, i)));
     }
-    free(sig);
+    free(sy);
+    free(sx);
+}
+
+void or_local_gain(int64_t n, const int64_t *rp, const int32_t *col,
+                   const int32_t *w, const int64_t *k, int64_t m2,
+                   const int32_t *lab, int64_t nc, int64_t *g_out)
+{
+    or_local_gain_nm(n, rp, col, w, k, NULL, m2, lab, nc, g_out);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -238,7 +287,8 @@ typedef struct {
     int32_t *pos;      /* cycle position of the hanging tree of a node   */
     int32_t *head;     /* children lists: head[u], next[v]               */
     int32_t *next;
-    int64_t *sub;      /* sum of k over the subtree                      */
+    int64_t *sub;      /* sum of x over the subtree                      */
+    int64_t *suby;     /* sum of y over the subtree                      */
     int64_t *gl;       /* local gain                                     */
 } pwork;
 
@@ -246,7 +296,7 @@ typedef struct {
  * needed: the caller passes the member list. Builds cycle order, DFS times
  * and subtree sums for the members `mem[0..m-1]` of one part. Returns the
  * cycle length; the cycle in pointer order is written to `cycle`. */
-static int64_t part_structure(const int32_t *a, const int64_t *k, pwork *W,
+static int64_t part_structure(const int32_t *a, const nullm *nm, pwork *W,
                               const int32_t *mem, int64_t m, int32_t *cycle)
 {
     /* cycle: follow pointers from any member for m steps; the node reached
@@ -309,40 +359,54 @@ static int64_t part_structure(const int32_t *a, const int64_t *k, pwork *W,
     }
     free(stack);
     /* subtree sums in reverse DFS order (children are entered after parents) */
-    for (int64_t s = 0; s < m; s++) W->sub[mem[s]] = k[mem[s]];
+    for (int64_t s = 0; s < m; s++) {
+        W->sub[mem[s]] = nm->x[mem[s]];
+        W->suby[mem[s]] = ny(nm, mem[s]);
+    }
     for (int64_t s = t - 1; s >= 0; s--) {
         int32_t u = W->order[s];
-        if (!W->cyc[u]) W->sub[a[u]] += W->sub[u];
+        if (!W->cyc[u]) {
+            W->sub[a[u]] += W->sub[u];
+            W->suby[a[u]] += W->suby[u];
+        }
     }
     return L;
 }
 
 /* Local gains of the members of one part, from the part's own totals. */
-static void part_gains(const graph *g, const int64_t *k, int64_t m2, pwork *W,
+static void part_gains(const graph *g, const nullm *nm, pwork *W,
                        const int32_t *mem, int64_t m)
 {
     int32_t p = W->part[mem[0]];
-    int64_t sp = 0;
-    for (int64_t s = 0; s < m; s++) sp += k[mem[s]];
+    int64_t sp = 0, spy = 0;
+    for (int64_t s = 0; s < m; s++) {
+        sp += nm->x[mem[s]];
+        spy += ny(nm, mem[s]);
+    }
     for (int64_t s = 0; s < m; s++) {
         int32_t u = mem[s];
         int64_t w_in = 0;
         for (int64_t e = g->rp[u]; e < g->rp[u + 1]; e++)
             if (g->col[e] != u && W->part[g->col[e]] == p) w_in += g->w[e];
-        W->gl[u] = m2 * w_in - k[u] * (sp - k[u]);
+        const int64_t xu = nm->x[u], yu = ny(nm, u);
+        W->gl[u] = nm->A * w_in - (xu * (sp - xu) - yu * (spy - yu));
     }
 }
 
 /* Best bisection of one part (Sec. 3.3): returns the key and the cut pair. */
-static int64_t best_split(const graph *g, const int32_t *a, const int64_t *k,
-                          int64_t m2, pwork *W, const int32_t *mem, int64_t m,
+static int64_t best_split(const graph *g, const int32_t *a, const nullm *nm,
+                          pwork *W, const int32_t *mem, int64_t m,
                           int32_t *cut1, int32_t *cut2)
 {
     int32_t *cycle = xmalloc((size_t)m * sizeof(int32_t));
-    int64_t L = part_structure(a, k, W, mem, m, cycle);
+    int64_t L = part_structure(a, nm, W, mem, m, cycle);
     int32_t p = W->part[mem[0]];
-    int64_t sp = 0;
-    for (int64_t s = 0; s < m; s++) sp += k[mem[s]];
+    const int64_t A = nm->A;
+    int64_t sp = 0, spy = 0;
+    for (int64_t s = 0; s < m; s++) {
+        sp += nm->x[mem[s]];
+        spy += ny(nm, mem[s]);
+    }
 
     int have = 0;
     int64_t best = 0;
@@ -375,20 +439,21 @@ static int64_t best_split(const graph *g, const int32_t *a, const int64_t *k,
                 if (!in_tx) cut += g->w[e];
             }
         }
-        int64_t s1 = W->sub[x];
-        CONSIDER(s1 * (sp - s1) - m2 * cut, x, x);
+        int64_t s1 = W->sub[x], t1 = W->suby[x];
+        CONSIDER(s1 * (sp - s1) - t1 * (spy - t1) - A * cut, x, x);
     }
     /* cycle cuts: remove the assignments of two cycle nodes c_p and c_q
      * (p < q); the side rooted at c_q holds the hanging trees of cycle
      * positions p+1..q, the other side the rest */
     for (int64_t pp = 0; pp < L; pp++) {
         for (int64_t qq = pp + 1; qq < L; qq++) {
-            int64_t sy = 0, cut = 0;
+            int64_t sy = 0, ty = 0, cut = 0;
             for (int64_t s = 0; s < m; s++) {
                 int32_t u = mem[s];
                 int in_y = W->pos[u] > pp && W->pos[u] <= qq;
                 if (!in_y) continue;
-                sy += k[u];
+                sy += nm->x[u];
+                ty += ny(nm, u);
                 for (int64_t e = g->rp[u]; e < g->rp[u + 1]; e++) {
                     int32_t v = g->col[e];
                     if (W->part[v] != p) continue;
@@ -398,7 +463,7 @@ static int64_t best_split(const graph *g, const int32_t *a, const int64_t *k,
             }
             int32_t x = cycle[pp], y = cycle[qq];
             int32_t f = x < y ? x : y, sc = x < y ? y : x;
-            CONSIDER(sy * (sp - sy) - m2 * cut, f, sc);
+            CONSIDER(sy * (sp - sy) - ty * (spy - ty) - A * cut, f, sc);
         }
     }
 #undef CONSIDER
@@ -445,10 +510,12 @@ static int cmp_i32(const void *x, const void *y)
  * part is split once per visit and both sides go back on the list, which
  * is the per-community loop of the appendix POSITIVE (communities are
  * independent, so the order of visits does not change the result). */
-int64_t or_positive(int64_t n, const int64_t *rp, const int32_t *col,
-                    const int32_t *w, const int64_t *k, int64_t m2, int32_t *a)
+int64_t or_positive_nm(int64_t n, const int64_t *rp, const int32_t *col,
+                       const int32_t *w, const int64_t *x, const int64_t *y, int64_t A,
+                       int32_t *a)
 {
     graph g = {n, rp, col, w};
+    const nullm nm = {x, y, A};
     pwork W;
     W.n = n;
     W.part = xmalloc((size_t)n * sizeof(int32_t));
@@ -460,6 +527,7 @@ int64_t or_positive(int64_t n, const int64_t *rp, const int32_t *col,
     W.head = xmalloc((size_t)n * sizeof(int32_t));
     W.next = xmalloc((size_t)n * sizeof(int32_t));
     W.sub = xmalloc((size_t)n * sizeof(int64_t));
+    W.suby = xmalloc((size_t)n * sizeof(int64_t));
     W.gl = xmalloc((size_t)n * sizeof(int64_t));
     int32_t *rev_head = xmalloc((size_t)n * sizeof(int32_t));
     int32_t *rev_next = xmalloc((size_t)n * sizeof(int32_t));
@@ -502,18 +570,18 @@ int64_t or_positive(int64_t n, const int64_t *rp, const int32_t *col,
         qsort(mem, (size_t)m, sizeof(int32_t), cmp_i32);
         int32_t pid = next_part++;
         for (int64_t s = 0; s < m; s++) W.part[mem[s]] = pid;
-        part_gains(&g, k, m2, &W, mem, m);
+        part_gains(&g, &nm, &W, mem, m);
         int negative = 0;
         for (int64_t s = 0; s < m; s++)
             if (W.gl[mem[s]] < 0) negative = 1;
         if (!negative) continue;
-        int32_t x, y;
-        best_split(&g, a, k, m2, &W, mem, m, &x, &y);
+        int32_t cx, cy;
+        best_split(&g, a, &nm, &W, mem, m, &cx, &cy);
         /* the two sides: a branch cut separates T_x from the part of x's old
          * target; a cycle cut separates the sides rooted at x and at y */
-        int32_t seed_a = x, seed_b = (x == y) ? a[x] : y;
-        int32_t cut_nodes[2] = {x, y};
-        for (int c = 0; c < (x == y ? 1 : 2); c++) {
+        int32_t seed_a = cx, seed_b = (cx == cy) ? a[cx] : cy;
+        int32_t cut_nodes[2] = {cx, cy};
+        for (int c = 0; c < (cx == cy ? 1 : 2); c++) {
             int32_t u = cut_nodes[c];
             int32_t *link = &rev_head[a[u]];
             while (*link != u) link = &rev_next[*link];
@@ -530,6 +598,7 @@ int64_t or_positive(int64_t n, const int64_t *rp, const int32_t *col,
     free(rev_next);
     free(rev_head);
     free(W.gl);
+    free(W.suby);
     free(W.sub);
     free(W.next);
     free(W.head);
@@ -542,6 +611,12 @@ int64_t or_positive(int64_t n, const int64_t *rp, const int32_t *col,
     return splits;
 }
 
+int64_t or_positive(int64_t n, const int64_t *rp, const int32_t *col,
+                    const int32_t *w, const int64_t *k, int64_t m2, int32_t *a)
+{
+    return or_positive_nm(n, rp, col, w, k, NULL, m2, a);
+}
+
 /* ------------------------------------------------------------------------ */
 /* MAXIMAL (Sec. 3.4, appendix MAXIMAL).                                     */
 /* ------------------------------------------------------------------------ */
@@ -551,13 +626,15 @@ int64_t or_positive(int64_t n, const int64_t *rp, const int32_t *col,
  * communities C != c_i (ties to the lowest label) when that beats stay(i),
  * else c_i; delta[i] = join - stay for a move and 0 otherwise; w_own[i] =
  * w(i, c_i \ i).  A dense accumulator with a touched list totals w(i,C). */
-void or_sweep(int64_t n, const int64_t *rp, const int32_t *col,
-              const int32_t *w, const int64_t *k, int64_t m2,
-              const int32_t *lab, int64_t nc, int32_t *best_c, int64_t *delta,
-              int32_t *w_own)
+void or_sweep_nm(int64_t n, const int64_t *rp, const int32_t *col,
+                 const int32_t *w, const int64_t *x, const int64_t *y, int64_t A,
+                 const int32_t *lab, int64_t nc, int32_t *best_c, int64_t *delta,
+                 int32_t *w_own)
 {
+    const nullm nm = {x, y, A};
     int64_t *sig = xmalloc((size_t)(nc ? nc : 1) * sizeof(int64_t));
-    community_totals(n, k, lab, nc, sig);
+    int64_t *sgy = xmalloc((size_t)(nc ? nc : 1) * sizeof(int64_t));
+    null_totals(n, &nm, lab, nc, sig, sgy);
     int64_t *acc = xcalloc((size_t)(nc ? nc : 1), sizeof(int64_t));
     int32_t *touched = xmalloc((size_t)(nc ? nc : 1) * sizeof(int32_t));
     for (int64_t i = 0; i < n; i++) {
@@ -573,12 +650,13 @@ void or_sweep(int64_t n, const int64_t *rp, const int32_t *col,
             if (acc[lab[v]] == 0) touched[nt++] = lab[v];
             acc[lab[v]] += w[e];
         }
-        int64_t stay = m2 * w_in - k[i] * (sig[ci] - k[i]);
+        const int64_t xi = x[i], yi = ny(&nm, i);
+        int64_t stay = A * w_in - (xi * (sig[ci] - xi) - yi * (sgy[ci] - yi));
         int64_t best_key = 0;
         int32_t best = -1;
         for (int64_t t = 0; t < nt; t++) {
             int32_t c = touched[t];
-            int64_t key = m2 * acc[c] - k[i] * sig[c];
+            int64_t key = A * acc[c] - (xi * sig[c] - yi * sgy[c]);
             if (best < 0 || key > best_key || (key == best_key && c < best)) {
                 best = c;
                 best_key = key;
@@ -596,7 +674,16 @@ void or_sweep(int64_t n, const int64_t *rp, const int32_t *col,
     }
     free(touched);
     free(acc);
+    free(sgy);
     free(sig);
+}
+
+void or_sweep(int64_t n, const int64_t *rp, const int32_t *col,
+              const int32_t *w, const int64_t *k, int64_t m2,
+              const int32_t *lab, int64_t nc, int32_t *best_c, int64_t *delta,
+              int32_t *w_own)
+{
+    or_sweep_nm(n, rp, col, w, k, NULL, m2, lab, nc, best_c, delta, w_own);
 }
 
 /* Forest view of an assignment graph: cycle nodes are roots, every other
@@ -684,8 +771,8 @@ static void free_forest(forest *F)
  * applied together; the communities then are the components of the new
  * assignment graph, and POSITIVE runs on them.
  * stats (optional, 4 entries): candidates, valid, accepted, splits. */
-int64_t or_maximal_round_ex(int64_t n, const int64_t *rp, const int32_t *col,
-                            const int32_t *w, const int64_t *k, int64_t m2,
+int64_t or_maximal_round_nm(int64_t n, const int64_t *rp, const int32_t *col,
+                            const int32_t *w, const int64_t *x, const int64_t *y, int64_t A,
                             int32_t *a, uint64_t seed, int32_t level, int32_t round,
                             uint64_t accept_p, int64_t *stats, int32_t *a_repointed);
 
@@ -694,8 +781,8 @@ int64_t or_maximal_round(int64_t n, const int64_t *rp, const int32_t *col,
                          int32_t *a, uint64_t seed, int32_t level, int32_t round,
                          uint64_t accept_p, int64_t *stats)
 {
-    return or_maximal_round_ex(n, rp, col, w, k, m2, a, seed, level, round, accept_p, stats,
-                               NULL);
+    return or_maximal_round_nm(n, rp, col, w, k, NULL, m2, a, seed, level, round, accept_p,
+                               stats, NULL);
 }
 
 /* As or_maximal_round; a_repointed (optional) receives the assignment after
@@ -705,14 +792,26 @@ int64_t or_maximal_round_ex(int64_t n, const int64_t *rp, const int32_t *col,
                             int32_t *a, uint64_t seed, int32_t level, int32_t round,
                             uint64_t accept_p, int64_t *stats, int32_t *a_repointed)
 {
+    return or_maximal_round_nm(n, rp, col, w, k, NULL, m2, a, seed, level, round, accept_p,
+                               stats, a_repointed);
+}
+
+/* The round under any null model (x, y, A); see nullm. */
+int64_t or_maximal_round_nm(int64_t n, const int64_t *rp, const int32_t *col,
+                            const int32_t *w, const int64_t *x, const int64_t *y, int64_t A,
+                            int32_t *a, uint64_t seed, int32_t level, int32_t round,
+                            uint64_t accept_p, int64_t *stats, int32_t *a_repointed)
+{
+    const nullm nm = {x, y, A};
     int32_t *lab = xmalloc((size_t)n * sizeof(int32_t));
     int64_t nc = or_components(n, a, lab, NULL);
     int64_t *sig = xmalloc((size_t)(nc ? nc : 1) * sizeof(int64_t));
-    community_totals(n, k, lab, nc, sig);
+    int64_t *sgy = xmalloc((size_t)(nc ? nc : 1) * sizeof(int64_t));
+    null_totals(n, &nm, lab, nc, sig, sgy);
     int32_t *best_c = xmalloc((size_t)n * sizeof(int32_t));
     int64_t *delta = xmalloc((size_t)n * sizeof(int64_t));
     int32_t *w_own = xmalloc((size_t)n * sizeof(int32_t));
-    or_sweep(n, rp, col, w, k, m2, lab, nc, best_c, delta, w_own);
+    or_sweep_nm(n, rp, col, w, x, y, A, lab, nc, best_c, delta, w_own);
 
     forest F;
     build_forest(n, a, lab, nc, &F);
@@ -732,10 +831,11 @@ int64_t or_maximal_round_ex(int64_t n, const int64_t *rp, const int32_t *col,
             bm = F.order + F.tin[i];
             bcount = F.tout[i] - F.tin[i];
         }
-        int64_t sb = 0, w_bd = 0, w_brest = 0;
+        int64_t sb = 0, tb = 0, w_bd = 0, w_brest = 0;
         for (int64_t s = 0; s < bcount; s++) {
             int32_t u = bm[s];
-            sb += k[u];
+            sb += x[u];
+            tb += ny(&nm, u);
             for (int64_t e = rp[u]; e < rp[u + 1]; e++) {
                 int32_t v = col[e];
                 if (lab[v] == d) w_bd += w[e];
@@ -745,7 +845,8 @@ int64_t or_maximal_round_ex(int64_t n, const int64_t *rp, const int32_t *col,
                 }
             }
         }
-        int64_t mv = m2 * (w_bd - w_brest) - sb * (sig[d] - sig[c] + sb);
+        int64_t mv = A * (w_bd - w_brest) -
+                     (sb * (sig[d] - sig[c] + sb) - tb * (sgy[d] - sgy[c] + tb));
         if (mv <= 0) continue;
         n_valid++;
         if ((uint64_t)or_draw(seed, level, round, (int32_t)i) < accept_p) {
@@ -766,7 +867,7 @@ int64_t or_maximal_round_ex(int64_t n, const int64_t *rp, const int32_t *col,
             for (int64_t e = rp[i]; e < rp[i + 1]; e++) {
                 int64_t j = col[e];
                 if (lab[j] != d) continue;
-                int64_t key = m2 * (int64_t)w[e] - k[i] * k[j];
+                int64_t key = A * (int64_t)w[e] - (x[i] * x[j] - ny(&nm, i) * ny(&nm, j));
                 if (best_j < 0 || key > best_key || (key == best_key && j < best_j)) {
                     best_j = j;
                     best_key = key;
@@ -777,7 +878,7 @@ int64_t or_maximal_round_ex(int64_t n, const int64_t *rp, const int32_t *col,
         memcpy(a, a_new, (size_t)n * sizeof(int32_t));
         free(a_new);
         if (a_repointed) memcpy(a_repointed, a, (size_t)n * sizeof(int32_t));
-        splits = or_positive(n, rp, col, w, k, m2, a);
+        splits = or_positive_nm(n, rp, col, w, x, y, A, a);
     } else if (a_repointed) {
         memcpy(a_repointed, a, (size_t)n * sizeof(int32_t));
     }
@@ -791,6 +892,7 @@ int64_t or_maximal_round_ex(int64_t n, const int64_t *rp, const int32_t *col,
     free(w_own);
     free(delta);
     free(best_c);
+    free(sgy);
     free(sig);
     free(lab);
     return n_valid;
@@ -801,20 +903,30 @@ int64_t or_maximal_round_ex(int64_t n, const int64_t *rp, const int32_t *col,
 /*   N_Q = M2 * sum_C w(C,C) - sum_C S_C^2,   Q = N_Q / M2^2.                */
 /* ------------------------------------------------------------------------ */
 
-int64_t or_modularity_num(int64_t n, const int64_t *rp, const int32_t *col,
-                          const int32_t *w, const int64_t *k, int64_t m2,
-                          const int32_t *lab, int64_t nc)
+int64_t or_modularity_num_nm(int64_t n, const int64_t *rp, const int32_t *col,
+                             const int32_t *w, const int64_t *x, const int64_t *y, int64_t A,
+                             const int32_t *lab, int64_t nc)
 {
+    const nullm nm = {x, y, A};
     int64_t *sig = xmalloc((size_t)(nc ? nc : 1) * sizeof(int64_t));
-    community_totals(n, k, lab, nc, sig);
+    int64_t *sgy = xmalloc((size_t)(nc ? nc : 1) * sizeof(int64_t));
+    null_totals(n, &nm, lab, nc, sig, sgy);
     int64_t inside = 0;
     for (int64_t i = 0; i < n; i++)
         for (int64_t e = rp[i]; e < rp[i + 1]; e++)
             if (lab[col[e]] == lab[i]) inside += w[e];
     int64_t sq = 0;
-    for (int64_t c = 0; c < nc; c++) sq += sig[c] * sig[c];
+    for (int64_t c = 0; c < nc; c++) sq += sig[c] * sig[c] - sgy[c] * sgy[c];
+    free(sgy);
     free(sig);
-    return m2 * inside - sq;
+    return A * inside - sq;
+}
+
+int64_t or_modularity_num(int64_t n, const int64_t *rp, const int32_t *col,
+                          const int32_t *w, const int64_t *k, int64_t m2,
+                          const int32_t *lab, int64_t nc)
+{
+    return or_modularity_num_nm(n, rp, col, w, k, NULL, m2, lab, nc);
 }
 
 double or_modularity(int64_t nq, int64_t m2)
@@ -880,19 +992,19 @@ int64_t or_contract(int64_t n, const int64_t *rp, const int32_t *col,
  * move is left or max_rounds rounds have applied moves.  Writes the final
  * assignment; returns the number of rounds that applied moves, and sets
  * *converged to 1 when the loop ended because no move was valid. */
-int32_t or_level(int64_t n, const int64_t *rp, const int32_t *col,
-                 const int32_t *w, const int64_t *k, int64_t m2, uint64_t seed,
-                 int32_t level, uint64_t accept_p, int32_t max_rounds,
-                 int32_t *a, int32_t *converged, int64_t *totals)
+int32_t or_level_nm(int64_t n, const int64_t *rp, const int32_t *col,
+                    const int32_t *w, const int64_t *x, const int64_t *y, int64_t A,
+                    uint64_t seed, int32_t level, uint64_t accept_p, int32_t max_rounds,
+                    int32_t *a, int32_t *converged, int64_t *totals)
 {
-    or_assign(n, rp, col, w, k, m2, a);
-    int64_t splits = or_positive(n, rp, col, w, k, m2, a);
+    or_assign_nm(n, rp, col, w, x, y, A, a);
+    int64_t splits = or_positive_nm(n, rp, col, w, x, y, A, a);
     int32_t r = 0;
     *converged = 0;
     int64_t st[4], tot_acc = 0, tot_valid = 0;
     while (r < max_rounds) {
-        int64_t valid = or_maximal_round(n, rp, col, w, k, m2, a, seed, level, r,
-                                         accept_p, st);
+        int64_t valid = or_maximal_round_nm(n, rp, col, w, x, y, A, a, seed, level, r,
+                                            accept_p, st, NULL);
         if (valid == 0) {
             *converged = 1;
             break;
@@ -912,6 +1024,15 @@ int32_t or_level(int64_t n, const int64_t *rp, const int32_t *col,
         totals[2] = splits;
     }
     return r;
+}
+
+int32_t or_level(int64_t n, const int64_t *rp, const int32_t *col,
+                 const int32_t *w, const int64_t *k, int64_t m2, uint64_t seed,
+                 int32_t level, uint64_t accept_p, int32_t max_rounds,
+                 int32_t *a, int32_t *converged, int64_t *totals)
+{
+    return or_level_nm(n, rp, col, w, k, NULL, m2, seed, level, accept_p, max_rounds, a,
+                       converged, totals);
 }
 
 /* Full run of Algorithm 1.  Levels whose partition is the identity are not
@@ -980,6 +1101,228 @@ int32_t or_run(int64_t n0, const int64_t *rp0, const int32_t *col0,
     free(lab);
     free(a);
     free(k);
+    free(w);
+    free(col);
+    free(rp);
+    return emitted;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Null models (Sec. 2.2-2.4).  A model is (kind, num, den):                */
+/*   kind 0, configuration model of an undirected graph with resolution     */
+/*     gamma = num/den: the modularity of Sec. 2.4 with the null-model term  */
+/*     scaled by gamma; x = num*k, y = 0, A = num*den*M2 (gains are num      */
+/*     times M2*den*w - gamma*den*... i.e. a positive multiple).             */
+/*   kind 1, Erdos-Renyi null model of Sec. 2.3 with p_ij = p = num/den:    */
+/*     the energy of Sec. 2.2 with alpha = 1 and beta = p for every pair;    */
+/*     x = num*size (size = original nodes a node stands for, 1 at level 0), */
+/*     y = 0, A = num*den.                                                   */
+/*   kind 2, configuration model of a directed graph W (Sec. 2.4 with out-  */
+/*     and in-strengths), resolution gamma = num/den: the level runs on the  */
+/*     symmetric S = W + W^T, x = num*(k_out + k_in), y = num*(k_out - k_in), */
+/*     A = num*den*sum(S).  Merging P and R changes                          */
+/*     sum_ij [den*m*W_ij - num*k_out_i*k_in_j] over pairs in one community  */
+/*     by (A*S(P,R) - X_P X_R + Y_P Y_R) / (2 num), m = sum(W).              */
+/* (0, 1, 1) is the default model, x = k and A = M2.  The modularity value   */
+/* reported is Q = N_Q / A / M2 with N_Q = A*sum_C S(C,C) - sum_C (X^2-Y^2)  */
+/* and M2 = sum(S).                                                          */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    int64_t r, c, w;
+} triple;
+
+static int cmp_triple(const void *p, const void *q)
+{
+    const triple *a = p, *b = q;
+    if (a->r != b->r) return (a->r > b->r) - (a->r < b->r);
+    return (a->c > b->c) - (a->c < b->c);
+}
+
+/* S = W + W^T as a CSR with sorted columns (diagonal entries become 2 W_ii).
+ * rp_out: n+1, col_out and w_out: up to 2 nnz entries.  Returns nnz(S). */
+int64_t or_symmetrize(int64_t n, const int64_t *rp, const int32_t *col, const int32_t *w,
+                      int64_t *rp_out, int32_t *col_out, int32_t *w_out)
+{
+    int64_t nnz = rp[n];
+    triple *t = xmalloc((size_t)(2 * nnz) * sizeof(triple));
+    int64_t m = 0;
+    for (int64_t i = 0; i < n; i++)
+        for (int64_t e = rp[i]; e < rp[i + 1]; e++) {
+            t[m++] = (triple){i, col[e], w[e]};
+            t[m++] = (triple){col[e], i, w[e]};
+        }
+    qsort(t, (size_t)m, sizeof(triple), cmp_triple);
+    int64_t out = 0;
+    for (int64_t i = 0; i <= n; i++) rp_out[i] = 0;
+    for (int64_t s = 0; s < m; s++) {
+        if (out > 0 && s > 0 && t[s].r == t[s - 1].r && t[s].c == t[s - 1].c) {
+            w_out[out - 1] += (int32_t)t[s].w;
+            continue;
+        }
+        col_out[out] = (int32_t)t[s].c;
+        w_out[out] = (int32_t)t[s].w;
+        rp_out[t[s].r + 1]++;
+        out++;
+    }
+    for (int64_t i = 0; i < n; i++) rp_out[i + 1] += rp_out[i];
+    free(t);
+    return out;
+}
+
+#define OR_BOUND ((int64_t)1 << 61)
+
+/* Strengths of a model on the level-0 graph (rp, col, w): for kind 2 that is
+ * the directed W, and (srp, scol, sw) must hold S = W + W^T.  Writes x, y
+ * (n each), *A and *M2 (sum of the matrix the levels run on).  Returns 0,
+ * 1 for an invalid model, 2 when the gains could leave int64 (A*M2 or
+ * sum(x)^2 above 2^61; the default model keeps its own M2 < 2^31 bound). */
+int32_t or_null_strengths(int32_t kind, int64_t num, int64_t den, int64_t n,
+                          const int64_t *rp, const int32_t *col, const int32_t *w,
+                          int64_t *x, int64_t *y, int64_t *A_out, int64_t *M2_out)
+{
+    if (num < 1 || den < 1 || kind < 0 || kind > 2) return 1;
+    int64_t m2 = 0;
+    for (int64_t i = 0; i < n; i++) {
+        x[i] = 0;
+        y[i] = 0;
+    }
+    for (int64_t i = 0; i < n; i++)
+        for (int64_t e = rp[i]; e < rp[i + 1]; e++) {
+            int64_t v = w[e];
+            m2 += v;
+            if (kind == 2) {
+                x[i] += v;      /* k_out(i) */
+                x[col[e]] += v; /* k_in(col) */
+                y[i] += v;
+                y[col[e]] -= v;
+            } else {
+                x[i] += v;
+            }
+        }
+    if (kind == 2) m2 *= 2; /* sum of S = W + W^T */
+    if (m2 >= ((int64_t)1 << 31)) return 2;
+    const int default_model = kind == 0 && num == 1 && den == 1;
+    if (!default_model && num > ((int64_t)1 << 30)) return 2;
+    int64_t xt = 0;
+    for (int64_t i = 0; i < n; i++) {
+        if (kind == 1) x[i] = 1;
+        x[i] *= num;
+        y[i] *= num;
+        xt += x[i];
+    }
+    const int64_t base = kind == 1 ? 1 : m2;
+    if (!default_model) {
+        /* every gain then stays within 2^62 in magnitude */
+        if (xt > ((int64_t)1 << 30)) return 2;
+        if (num > OR_BOUND / den) return 2;
+        const int64_t nd = num * den;
+        if (base > 0 && nd > OR_BOUND / base) return 2;
+        if (m2 > 0 && nd * base > OR_BOUND / m2) return 2;
+    }
+    *A_out = num * den * base;
+    *M2_out = m2;
+    return 0;
+}
+
+double or_modularity_nm(int64_t nq, int64_t A, int64_t m2)
+{
+    if (A == 0 || m2 == 0) return 0.0;
+    return (double)nq / (double)A / (double)m2;
+}
+
+/* Full run under a null model (see above): the input is symmetric for kinds
+ * 0 and 1 and any CSR W for kind 2.  Levels run on S (kind 2) or the input;
+ * x and y of a community are the sums over its members at every
+ * contraction.  Outputs as or_run; returns the emitted level count, or -1
+ * (invalid model) / -2 (bounds). */
+int32_t or_run_null(int64_t n0, const int64_t *rp0, const int32_t *col0,
+                    const int32_t *w0, int32_t kind, int64_t num, int64_t den,
+                    uint64_t seed, uint64_t accept_p, int32_t max_rounds,
+                    int32_t max_levels, int32_t max_out, int32_t *labels_out,
+                    int64_t *nc_out, int64_t *nq_out, double *q_out,
+                    int32_t *rounds_out, int32_t *conv_out)
+{
+    int64_t nnz0 = rp0[n0];
+    int64_t cap = kind == 2 ? 2 * nnz0 : nnz0;
+    int64_t n = n0;
+    int64_t *rp = xmalloc((size_t)(n0 + 1) * sizeof(int64_t));
+    int32_t *col = xmalloc((size_t)(cap ? cap : 1) * sizeof(int32_t));
+    int32_t *w = xmalloc((size_t)(cap ? cap : 1) * sizeof(int32_t));
+    int64_t *x = xmalloc((size_t)(n0 ? n0 : 1) * sizeof(int64_t));
+    int64_t *y = xmalloc((size_t)(n0 ? n0 : 1) * sizeof(int64_t));
+    int64_t A = 0, m2 = 0;
+    int32_t st = or_null_strengths(kind, num, den, n0, rp0, col0, w0, x, y, &A, &m2);
+    if (st != 0) {
+        free(y);
+        free(x);
+        free(w);
+        free(col);
+        free(rp);
+        return st == 1 ? -1 : -2;
+    }
+    int64_t nnz;
+    if (kind == 2) {
+        nnz = or_symmetrize(n0, rp0, col0, w0, rp, col, w);
+    } else {
+        nnz = nnz0;
+        memcpy(rp, rp0, (size_t)(n0 + 1) * sizeof(int64_t));
+        memcpy(col, col0, (size_t)nnz0 * sizeof(int32_t));
+        memcpy(w, w0, (size_t)nnz0 * sizeof(int32_t));
+    }
+    (void)nnz;
+    const int64_t *yy = kind == 2 ? y : NULL;
+    int32_t *a = xmalloc((size_t)(n0 ? n0 : 1) * sizeof(int32_t));
+    int32_t *lab = xmalloc((size_t)(n0 ? n0 : 1) * sizeof(int32_t));
+    int32_t *composed = xmalloc((size_t)(n0 ? n0 : 1) * sizeof(int32_t));
+    int64_t *tmp = xmalloc((size_t)(n0 ? n0 : 1) * sizeof(int64_t));
+    for (int64_t v = 0; v < n0; v++) composed[v] = (int32_t)v;
+    int32_t emitted = 0;
+    int32_t level = 0;
+    while (m2 > 0 && n > 0) {
+        int32_t conv = 0;
+        int32_t rounds = or_level_nm(n, rp, col, w, x, yy, A, seed, level, accept_p,
+                                     max_rounds, a, &conv, NULL);
+        int64_t nc = or_components(n, a, lab, NULL);
+        if (nc == n) break; /* the level partition is the identity */
+        for (int64_t v = 0; v < n0; v++) composed[v] = lab[composed[v]];
+        int64_t nq = or_modularity_num_nm(n, rp, col, w, x, yy, A, lab, nc);
+        if (emitted < max_out) {
+            memcpy(labels_out + (size_t)emitted * (size_t)n0, composed,
+                   (size_t)n0 * sizeof(int32_t));
+            nc_out[emitted] = nc;
+            nq_out[emitted] = nq;
+            q_out[emitted] = or_modularity_nm(nq, A, m2);
+            rounds_out[emitted] = rounds;
+            conv_out[emitted] = conv;
+        }
+        emitted++;
+        /* next level: contracted matrix, strengths summed per community */
+        int64_t nnz_t = rp[n];
+        int64_t *rp2 = xmalloc((size_t)(nc + 1) * sizeof(int64_t));
+        int32_t *col2 = xmalloc((size_t)(nnz_t ? nnz_t : 1) * sizeof(int32_t));
+        int32_t *w2 = xmalloc((size_t)(nnz_t ? nnz_t : 1) * sizeof(int32_t));
+        or_contract(n, rp, col, w, lab, nc, rp2, col2, w2);
+        community_totals(n, x, lab, nc, tmp);
+        memcpy(x, tmp, (size_t)nc * sizeof(int64_t));
+        community_totals(n, y, lab, nc, tmp);
+        memcpy(y, tmp, (size_t)nc * sizeof(int64_t));
+        free(rp);
+        free(col);
+        free(w);
+        rp = rp2;
+        col = col2;
+        w = w2;
+        n = nc;
+        level++;
+        if (max_levels > 0 && emitted >= max_levels) break;
+    }
+    free(tmp);
+    free(composed);
+    free(lab);
+    free(a);
+    free(y);
+    free(x);
     free(w);
     free(col);
     free(rp);

@@ -83,10 +83,13 @@ def on_cycle(a, u):
     return u in cycle_nodes(a, u)
 
 
-def assign(A):
+def assign(A, qual=None):
+    """A gives the neighbours; qual(labels) the quality (default: nq(A, .))."""
+    if qual is None:
+        qual = lambda lab: nq(A, lab)
     n = A.shape[0]
     single = np.arange(n)
-    base = nq(A, single)
+    base = qual(single)
     a = []
     for i in range(n):
         best, bj = None, i
@@ -95,42 +98,46 @@ def assign(A):
                 continue
             lab = single.copy()
             lab[i] = j
-            g = nq(A, lab) - base
+            g = qual(lab) - base
             if best is None or g > best:
                 best, bj = g, j
         a.append(bj if best is not None and best > 0 else i)
     return a
 
 
-def local_gains(A, lab):
-    base = nq(A, lab)
+def local_gains(A, lab, qual=None):
+    if qual is None:
+        qual = lambda lb: nq(A, lb)
+    base = qual(lab)
     n = len(lab)
     out = []
     fresh = max(lab) + 1
     for u in range(n):
         l2 = np.array(lab).copy()
         l2[u] = fresh
-        out.append((base - nq(A, l2)) // 2)
+        out.append((base - qual(l2)) // 2)
     return out
 
 
-def positive(A, a):
+def positive(A, a, qual=None):
     """Split, one optimal bisection at a time, until no node has a negative
     local gain.  Candidate bisections: drop the assignment of one non-cycle
     node, or of two cycle nodes; the best is the largest N_Q gain, ties to
     the lowest (first, second) cut node."""
+    if qual is None:
+        qual = lambda lb: nq(A, lb)
     a = list(a)
     splits = 0
     while True:
         lab = wcc(a)
-        g = local_gains(A, lab)
+        g = local_gains(A, lab, qual)
         bad = sorted({int(lab[u]) for u in range(len(a)) if g[u] < 0})
         if not bad:
             return a, splits
         c = bad[0]
         members = [u for u in range(len(a)) if lab[u] == c]
         cyc = cycle_nodes(a, members[0])
-        base = nq(A, lab)
+        base = qual(lab)
         best = None
         cands = [(x, x) for x in members if x not in cyc]
         cands += [(min(x, y), max(x, y)) for x, y in itertools.combinations(cyc, 2)]
@@ -138,7 +145,7 @@ def positive(A, a):
             a2 = list(a)
             a2[x] = x
             a2[y] = y
-            gain = nq(A, wcc(a2)) - base
+            gain = qual(wcc(a2)) - base
             key = (gain, -x, -y)
             if best is None or key > best[0]:
                 best = (key, x, y)
@@ -148,12 +155,14 @@ def positive(A, a):
         splits += 1
 
 
-def maximal_round(A, a, draw, p_threshold):
+def maximal_round(A, a, draw, p_threshold, qual=None):
     """One MAXIMAL round (then POSITIVE).  ``draw(i)`` gives node i's 32-bit
     draw.  Returns (new a, valid count)."""
+    if qual is None:
+        qual = lambda lb: nq(A, lb)
     n = len(a)
     lab = wcc(a)
-    base = nq(A, lab)
+    base = qual(lab)
     cstar = []
     for i in range(n):
         best, bc = None, lab[i]
@@ -162,7 +171,7 @@ def maximal_round(A, a, draw, p_threshold):
                 continue
             l2 = lab.copy()
             l2[i] = C
-            gain = nq(A, l2) - base
+            gain = qual(l2) - base
             if best is None or gain > best:
                 best, bc = gain, C
         cstar.append(bc if best is not None and best > 0 else int(lab[i]))
@@ -177,20 +186,20 @@ def maximal_round(A, a, draw, p_threshold):
         l2 = lab.copy()
         for u in B:
             l2[u] = D
-        if nq(A, l2) - base <= 0:
+        if qual(l2) - base <= 0:
             continue
         valid += 1
         if draw(i) < p_threshold:
             # best neighbour inside D by the N_Q gain of pairing i with it
             single = np.arange(n)
-            sb = nq(A, single)
+            sb = qual(single)
             best, bj = None, None
             for j in range(n):
                 if j == i or A[i, j] == 0 or lab[j] != D:
                     continue
                 ls = single.copy()
                 ls[i] = j
-                gj = nq(A, ls) - sb
+                gj = qual(ls) - sb
                 if best is None or gj > best:
                     best, bj = gj, j
             moves[i] = bj
@@ -199,7 +208,7 @@ def maximal_round(A, a, draw, p_threshold):
     a2 = list(a)
     for i, j in moves.items():
         a2[i] = j
-    a2, _ = positive(A, a2)
+    a2, _ = positive(A, a2, qual)
     return a2, valid
 
 
@@ -258,3 +267,81 @@ def set_partitions(n):
             yield from rec(i + 1, lab, max(k, c + 1))
             lab.pop()
     yield from rec(0, [], 0)
+
+
+# ---------------------------------------------------------------- null models
+CONFIG, ER, DIRECTED = 0, 1, 2
+
+
+def quality(W, lab, kind, num, den, size):
+    """The quality of a partition, straight from its definition:
+    CONFIG    sum_ij (den*M2*W_ij - num*k_i*k_j)         [same community]
+              (Sec. 2.4 modularity with resolution num/den; W symmetric)
+    ER        sum_ij (den*W_ij - num*size_i*size_j)      [same community]
+              (Sec. 2.2 energy with alpha = 1, beta = p = num/den, the
+              Erdos-Renyi null model of Sec. 2.3; size = original nodes)
+    DIRECTED  sum_ij (den*m*W_ij - num*kout_i*kin_j)     [same community]
+              (Sec. 2.4 with out- and in-strengths; W any nonnegative)
+    Each is a positive multiple of the modularity (energy) it names."""
+    lab = np.asarray(lab)
+    same = lab[:, None] == lab[None, :]
+    if kind == CONFIG:
+        k = W.sum(1)
+        B = den * int(W.sum()) * W - num * np.outer(k, k)
+    elif kind == ER:
+        B = den * W - num * np.outer(size, size)
+    else:
+        B = den * int(W.sum()) * W - num * np.outer(W.sum(1), W.sum(0))
+    return int((B * same).sum())
+
+
+def contract_directed(W, lab):
+    """W'_CD = sum of W_uv over u in C, v in D (any W)."""
+    lab = np.asarray(lab)
+    nc = int(lab.max()) + 1
+    P = np.zeros((W.shape[0], nc), np.int64)
+    P[np.arange(W.shape[0]), lab] = 1
+    return P.T @ W @ P
+
+
+def run_null(W, kind, num, den, seed, draw_fn, p_threshold=1 << 31, max_rounds=64,
+             max_levels=0):
+    """run() under a null model: every decision on differences of quality();
+    neighbours are the nonzeros of W + W^T; each level contracts W (keeping
+    its direction) and sums the node sizes.  Per level: labels, n_c, the
+    quality of the level's partition, rounds, converged."""
+    n0 = W.shape[0]
+    composed = np.arange(n0)
+    size = np.ones(n0, np.int64)
+    out = []
+    level = 0
+    while int(W.sum()) > 0:
+        n = W.shape[0]
+        S = W + W.T
+        qual = (lambda Wc, sz: (lambda lab: quality(Wc, lab, kind, num, den, sz)))(W, size)
+        a = assign(S, qual)
+        a, _ = positive(S, a, qual)
+        r = 0
+        conv = False
+        while r < max_rounds:
+            a, valid = maximal_round(S, a, lambda i: draw_fn(seed, level, r, i), p_threshold,
+                                     qual)
+            if valid == 0:
+                conv = True
+                break
+            r += 1
+        lab = wcc(a)
+        nc = int(lab.max()) + 1
+        if nc == n:
+            break
+        composed = lab[composed]
+        out.append(dict(labels=composed.copy(), n_c=nc, nq=qual(lab), rounds=r,
+                        converged=conv))
+        level += 1
+        if max_levels > 0 and level >= max_levels:
+            break
+        P = np.zeros((n, nc), np.int64)
+        P[np.arange(n), lab] = 1
+        size = P.T @ size
+        W = contract_directed(W, lab)
+    return out
