@@ -118,6 +118,38 @@ slm_status slm_create(int64_t n, int64_t nnz, const void *row_ptr, int row_ptr_b
                       int validate, void *hip_stream, const slm_allocator *alloc,
                       slm_graph **out);
 
+/* Null model of the quality function (Sec. 2.2: the energy with alpha_ij
+ * and beta_ij; Sec. 2.3: null models; Sec. 2.4: weighted modularity).
+ *   SLM_MODEL_CONFIG  configuration model with resolution gamma = num/den:
+ *                     the modularity above with the null-model term scaled
+ *                     by gamma; gains are num * (den*M2*w - num*k*S).
+ *                     num = den = 1 is the default model of slm_create.
+ *   SLM_MODEL_ER      Erdos-Renyi null model p_ij = p = num/den (alpha = 1,
+ *                     beta = p): gains are num * (den*w - num*n_P*n_R) for
+ *                     node sets of n_P and n_R original nodes.
+ * Every gain keeps the form A*w(P,R) - X_P*X_R with a node strength x
+ * (num*k, or num*(original nodes)) summed over node sets and a scale A
+ * (num*den*M2, or num*den), so all tie rules and strict tests above are
+ * unchanged.  N_Q = A * sum_C w(C,C) - sum_C X_C^2 and Q = N_Q / A / M2.
+ * Bounds (SLM_E_OVERFLOW otherwise): sum of x at most 2^30 and A*M2 at most
+ * 2^61 for any model other than the default. */
+typedef enum { SLM_MODEL_CONFIG = 0, SLM_MODEL_ER = 1 } slm_model_kind;
+typedef struct {
+    int32_t kind;
+    int32_t reserved;
+    int64_t num;
+    int64_t den;
+} slm_model;
+
+/* slm_create under a null model (model NULL = the default).  The input is
+ * the symmetric CSR of slm_create.  Batches and servers use the default
+ * model only.  Errors as slm_create, plus SLM_E_INVALID for an unknown kind
+ * or num, den < 1. */
+slm_status slm_create_model(int64_t n, int64_t nnz, const void *row_ptr, int row_ptr_bytes,
+                            const int32_t *col, const int32_t *w, int inputs_on_device,
+                            int validate, const slm_model *model, void *hip_stream,
+                            const slm_allocator *alloc, slm_graph **out);
+
 void slm_destroy(slm_graph *g);
 
 /* Current level index, its node and entry counts, and M2 (the same at

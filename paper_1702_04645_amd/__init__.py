@@ -43,6 +43,20 @@ _ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p)
 _FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p, C.c_void_p)
 
 
+class Model(C.Structure):
+    """Null model of a handle (include/slm.h slm_model): kind CONFIG with
+    resolution num/den, or ER with p = num/den."""
+    _fields_ = [("kind", C.c_int32), ("reserved", C.c_int32), ("num", C.c_int64),
+                ("den", C.c_int64)]
+
+
+MODEL_CONFIG, MODEL_ER = 0, 1
+
+
+def model(kind: int = MODEL_CONFIG, num: int = 1, den: int = 1) -> Model:
+    return Model(kind, 0, num, den)
+
+
 class _AllocatorC(C.Structure):
     """slm_allocator: ctx, alloc(ctx, bytes, stream), free(ctx, p, stream)."""
     _fields_ = [("ctx", C.c_void_p), ("alloc", _ALLOC_FN), ("free", _FREE_FN)]
@@ -121,6 +135,8 @@ def lib():
         "slm_create": (st, [i64, i64, P, C.c_int, P, P, C.c_int, C.c_int, P,
                             C.POINTER(_AllocatorC), C.POINTER(P)]),
         "slm_destroy": (None, [P]),
+        "slm_create_model": (st, [i64, i64, P, C.c_int, P, P, C.c_int, C.c_int,
+                                  C.POINTER(Model), P, C.POINTER(_AllocatorC), C.POINTER(P)]),
         "slm_level_info": (st, [P, pi32, pi64, pi64, pi64]),
         "slm_reset": (st, [P]),
         "slm_export_level": (st, [P, P, P, P]),
@@ -206,7 +222,7 @@ class Graph:
     library's hipMalloc; or an Allocator)."""
 
     def __init__(self, row_ptr, col, w, validate: bool = True, stream=None,
-                 allocator="torch"):
+                 allocator="torch", model: Model | None = None):
         torch = _torch()
         self._h = C.c_void_p()
         self._alloc = _allocator(allocator)
@@ -234,9 +250,15 @@ class Graph:
         if stream is None:
             stream = torch.cuda.current_stream()
         self.stream = stream
-        _check(lib().slm_create(n, nnz, args[0], rp_bytes, args[1], args[2], int(on_dev),
-                                int(validate), C.c_void_p(stream.cuda_stream),
-                                _aptr(self._alloc), C.byref(self._h)))
+        if model is None:
+            _check(lib().slm_create(n, nnz, args[0], rp_bytes, args[1], args[2], int(on_dev),
+                                    int(validate), C.c_void_p(stream.cuda_stream),
+                                    _aptr(self._alloc), C.byref(self._h)))
+        else:
+            _check(lib().slm_create_model(n, nnz, args[0], rp_bytes, args[1], args[2],
+                                          int(on_dev), int(validate), C.byref(model),
+                                          C.c_void_p(stream.cuda_stream), _aptr(self._alloc),
+                                          C.byref(self._h)))
         self._keep = None
         self.n0 = n
         self.nnz0 = nnz

@@ -21,6 +21,11 @@
 #include "slm.h"
 #include "slm_forest.h"
 
+#define REQUIRE(cond, code, msg)                                                      \
+    do {                                                                              \
+        if (!(cond)) throw SlmError{code, msg};                                       \
+    } while (0)
+
 static thread_local std::string g_err;
 
 // The calling thread's last error message (also set by noalloc.hip).
@@ -72,6 +77,15 @@ struct slm_graph {
     double sweep_ms = 0;
     i64 sweeps = 0, entries = 0, bytes = 0;
     DevMem dm;  // every device buffer of the handle (dm.held: bytes held)
+
+    // Null model (Sec. 2.2-2.4): the kind, its rational parameter num/den, and
+    // the scale A of the edge term of every gain (A = M2 for the default
+    // model).  W.k holds the model's node strength x; for the Erdos-Renyi
+    // model it is carried from level to level by community totals (xcarry).
+    int mkind = SLM_MODEL_CONFIG;
+    i64 mnum = 1, mden = 1;
+    i64 keyA = 0;
+    i32 *xcarry = nullptr;
     std::vector<std::pair<void *, size_t>> allocs;  // fixed buffers, freed at destroy
     bool no_fanout = false;  // keep every sweep bin on the handle's stream
 
@@ -154,7 +168,7 @@ static LevelView view(slm_graph *g)
     L.diag = g->W.diag;
     L.n = g->n;
     L.nnz = g->nnz;
-    L.m2 = g->m2;
+    L.m2 = g->keyA;
     L.m2n = nullptr;
     L.gid = nullptr;
     L.gbase = nullptr;
@@ -196,6 +210,24 @@ static void release_bins(slm_graph *g)
     B.hub_cap = cap;
     B.hub_tbits = tbits;
     for (int b = 0; b < NBINS; b++) B.grid_cap[b] = grid[b];
+}
+
+// Bounds of a null model other than the default: every gain within 2^62
+// (A * M2 and (sum of x)^2 at most 2^61).
+static void check_model_bounds(slm_graph *g)
+{
+    const i64 B61 = (i64)1 << 61;
+    REQUIRE(g->m2 < ((i64)1 << 31), SLM_E_OVERFLOW, "total weight M2 must be below 2^31");
+    if (g->mkind == SLM_MODEL_CONFIG && g->mnum == 1 && g->mden == 1) return;
+    const i64 xt_unit = g->mkind == SLM_MODEL_ER ? g->n0 : g->m2;  // sum of x / num
+    REQUIRE(g->mnum <= ((i64)1 << 30) && (xt_unit == 0 || g->mnum <= ((i64)1 << 30) / xt_unit),
+            SLM_E_OVERFLOW, "the model's strengths must sum to at most 2^30");
+    REQUIRE(g->mnum <= B61 / g->mden, SLM_E_OVERFLOW, "num * den too large");
+    const i64 nd = g->mnum * g->mden;
+    const i64 base = g->mkind == SLM_MODEL_ER ? 1 : g->m2;
+    REQUIRE(base == 0 || nd <= B61 / base, SLM_E_OVERFLOW, "the scale A of the gains is too large");
+    REQUIRE(g->m2 == 0 || nd * base <= B61 / g->m2, SLM_E_OVERFLOW,
+            "A * M2 must be at most 2^61");
 }
 
 // Degree bins, hub work lists, strengths and entry rows of the current level.
@@ -317,7 +349,19 @@ static void setup_level(slm_graph *g)
         }
     }
     i64 m2 = level_strengths(W, rp, e, B, n, W.k, W.diag, s);
-    if (g->level == 0) g->m2 = m2;
+    if (g->level == 0) {
+        g->m2 = m2;
+        if (!g->is_union) check_model_bounds(g);
+        g->keyA = g->mkind == SLM_MODEL_ER ? g->mnum * g->mden : g->mnum * g->mden * m2;
+    }
+    // node strengths of the model: num times the row sums (configuration
+    // model), or num times the original nodes a node stands for (Erdos-Renyi)
+    if (n > 0 && g->mkind == SLM_MODEL_CONFIG && g->mnum != 1)
+        launch_scale_i32(W.k, (i32)g->mnum, n, s);
+    if (n > 0 && g->mkind == SLM_MODEL_ER) {
+        if (g->level == 0) launch_fill_i32(W.k, (i32)g->mnum, n, s);
+        else HIPCHK(hipMemcpyAsync(W.k, g->xcarry, sizeof(i32) * n, hipMemcpyDeviceToDevice, s));
+    }
     LevelView L = view(g);
     fill_src(L, B, W.src, s);
 }
@@ -455,10 +499,6 @@ static slm_status fail(const SlmError &e)
     catch (const std::bad_alloc &) { return fail(SlmError{SLM_E_NOMEM, "host allocation failed"}); } \
     return SLM_OK;
 
-#define REQUIRE(cond, code, msg)                                                      \
-    do {                                                                              \
-        if (!(cond)) throw SlmError{code, msg};                                       \
-    } while (0)
 
 // ------------------------------------------------------------------ validation
 static void validate_host(i64 n, i64 nnz, const std::vector<i64> &rp, const i32 *col,
@@ -604,6 +644,12 @@ static void contract_only(slm_graph *g, const i32 *lab, i64 nc)
 
 static void do_contract(slm_graph *g, const i32 *lab, i64 nc)
 {
+    if (g->mkind == SLM_MODEL_ER && nc < g->n) {
+        // a community's strength at the next level is the sum over its members
+        community_totals(g->W, view(g), lab, nc, g->s);
+        HIPCHK(hipMemcpyAsync(g->xcarry, g->W.sigma, sizeof(i32) * nc, hipMemcpyDeviceToDevice,
+                              g->s));
+    }
     contract_only(g, lab, nc);
     setup_level(g);
 }
@@ -944,14 +990,21 @@ void slm_destroy(slm_graph *g)
     delete g;
 }
 
-slm_status slm_create(int64_t n, int64_t nnz, const void *row_ptr, int row_ptr_bytes,
-                      const int32_t *col, const int32_t *w, int inputs_on_device, int validate,
-                      void *hip_stream, const slm_allocator *alloc, slm_graph **out)
+static slm_status create_impl(int64_t n, int64_t nnz, const void *row_ptr, int row_ptr_bytes,
+                              const int32_t *col, const int32_t *w, int inputs_on_device,
+                              int validate, const slm_model *model, void *hip_stream,
+                              const slm_allocator *alloc, slm_graph **out)
 {
     slm_graph *g = nullptr;
     try {
         REQUIRE(out != nullptr, SLM_E_INVALID, "null output handle");
         *out = nullptr;
+        if (model) {
+            REQUIRE(model->kind == SLM_MODEL_CONFIG || model->kind == SLM_MODEL_ER,
+                    SLM_E_INVALID, "unknown null model kind");
+            REQUIRE(model->num >= 1 && model->den >= 1, SLM_E_INVALID,
+                    "the model parameter num/den needs num >= 1 and den >= 1");
+        }
         REQUIRE(n >= 0 && nnz >= 0, SLM_E_INVALID, "negative size");
         REQUIRE(row_ptr_bytes == 4 || row_ptr_bytes == 8, SLM_E_INVALID, "row_ptr_bytes must be 4 or 8");
         REQUIRE(row_ptr != nullptr, SLM_E_INVALID, "null row_ptr");
@@ -960,6 +1013,11 @@ slm_status slm_create(int64_t n, int64_t nnz, const void *row_ptr, int row_ptr_b
         REQUIRE(nnz < ((i64)1 << 40), SLM_E_OVERFLOW, "too many entries");
         g = new slm_graph();
         g->s = (hipStream_t)hip_stream;
+        if (model) {
+            g->mkind = model->kind;
+            g->mnum = model->num;
+            g->mden = model->den;
+        }
         set_allocator(g, alloc);
         HIPCHK(hipGetDevice(&g->device));
         g->n0 = g->n = n;
@@ -1000,6 +1058,7 @@ slm_status slm_create(int64_t n, int64_t nnz, const void *row_ptr, int row_ptr_b
         alloc_work(g);
         g->rp0 = dalloc<i64>(g, n + 1);
         g->e0 = dalloc<int2>(g, nnz);
+        if (g->mkind == SLM_MODEL_ER) g->xcarry = dalloc<i32>(g, n);
         if (!inputs_on_device) {
             HIPCHK(hipMemcpyAsync(g->rp0, rp_h.data(), sizeof(i64) * (n + 1), hipMemcpyHostToDevice, g->s));
             if (nnz) {
@@ -1028,6 +1087,23 @@ slm_status slm_create(int64_t n, int64_t nnz, const void *row_ptr, int row_ptr_b
         if (g) slm_destroy(g);
         return fail(SlmError{SLM_E_NOMEM, "host allocation failed"});
     }
+}
+
+slm_status slm_create(int64_t n, int64_t nnz, const void *row_ptr, int row_ptr_bytes,
+                      const int32_t *col, const int32_t *w, int inputs_on_device, int validate,
+                      void *hip_stream, const slm_allocator *alloc, slm_graph **out)
+{
+    return create_impl(n, nnz, row_ptr, row_ptr_bytes, col, w, inputs_on_device, validate,
+                       nullptr, hip_stream, alloc, out);
+}
+
+slm_status slm_create_model(int64_t n, int64_t nnz, const void *row_ptr, int row_ptr_bytes,
+                            const int32_t *col, const int32_t *w, int inputs_on_device,
+                            int validate, const slm_model *model, void *hip_stream,
+                            const slm_allocator *alloc, slm_graph **out)
+{
+    return create_impl(n, nnz, row_ptr, row_ptr_bytes, col, w, inputs_on_device, validate,
+                       model, hip_stream, alloc, out);
 }
 
 slm_status slm_level_info(const slm_graph *g, int32_t *level, int64_t *n_t, int64_t *nnz_t,
@@ -1214,7 +1290,7 @@ slm_status slm_modularity(slm_graph *g, const int32_t *lab_dev, int64_t n_c, int
         v = modularity_num(g->W, view(g), g->bins, lab_dev, n_c, g->s);
     }
     if (nq) *nq = v;
-    if (q) *q = g->m2 > 0 ? (double)v / (double)g->m2 / (double)g->m2 : 0.0;
+    if (q) *q = g->m2 > 0 && g->keyA > 0 ? (double)v / (double)g->keyA / (double)g->m2 : 0.0;
     API_END
 }
 
@@ -1256,7 +1332,7 @@ slm_status slm_run(slm_graph *g, const slm_params *p, slm_result **out)
             r->labels.push_back(std::move(lab));
             r->nc.push_back(nc);
             r->nq.push_back(nq);
-            r->q.push_back((double)nq / (double)g->m2 / (double)g->m2);
+            r->q.push_back((double)nq / (double)g->keyA / (double)g->m2);
             r->rounds.push_back(rounds);
             r->conv.push_back(conv);
             level++;

@@ -9,6 +9,13 @@ __global__ void k_fill(T *p, T v, i64 n)
     for (; i < n; i += stride) p[i] = v;
 }
 
+__global__ void k_scale_i32(i32 *p, i32 f, i64 n)
+{
+    i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+    i64 stride = (i64)gridDim.x * blockDim.x;
+    for (; i < n; i += stride) p[i] *= f;
+}
+
 __global__ void k_iota(i32 *p, i64 n)
 {
     i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x;
@@ -27,6 +34,10 @@ static unsigned fill_grid(i64 n)
 void launch_fill_i32(i32 *p, i32 v, i64 n, hipStream_t s)
 {
     if (n > 0) k_fill<i32><<<fill_grid(n), SLM_BS, 0, s>>>(p, v, n);
+}
+void launch_scale_i32(i32 *p, i32 f, i64 n, hipStream_t s)
+{
+    if (n > 0) k_scale_i32<<<fill_grid(n), SLM_BS, 0, s>>>(p, f, n);
 }
 void launch_fill_i64(i64 *p, i64 v, i64 n, hipStream_t s)
 {

@@ -254,6 +254,7 @@ static inline unsigned grid_for(i64 items, int per_block)
 
 // ---------------------------------------------------------------- utilities (k_util.hip)
 void launch_fill_i32(i32 *p, i32 v, i64 n, hipStream_t s);
+void launch_scale_i32(i32 *p, i32 f, i64 n, hipStream_t s);  // p[i] *= f
 void launch_fill_i64(i64 *p, i64 v, i64 n, hipStream_t s);
 void launch_fill_u8(uint8_t *p, uint8_t v, i64 n, hipStream_t s);
 void launch_iota_i32(i32 *p, i64 n, hipStream_t s);
