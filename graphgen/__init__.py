@@ -337,6 +337,32 @@ def random_directed(n: int, m: int, w_max: int, seed: int, loops: bool = False):
     return csr_from_pairs(n, u, v, wt, symmetrise=False)
 
 
+def orient(row_ptr, col, w, seed: int, both: float = 0.3, w_max: int = 0):
+    """A directed graph from a symmetric CSR: every undirected pair i < j
+    keeps both arcs with probability ``both``, else one arc in a random
+    direction; loops stay.  Arc weights are the edge's weight, or uniform
+    1..w_max per arc when w_max > 0."""
+    n = len(row_ptr) - 1
+    u = np.repeat(np.arange(n, dtype=np.int64), np.diff(row_ptr))
+    v = np.asarray(col, np.int64)
+    wt = np.asarray(w, np.int64)
+    up = u <= v
+    u, v, wt = u[up], v[up], wt[up]
+    g = rng(seed)
+    keep2 = g.random(u.size) < both
+    flip = g.random(u.size) < 0.5
+    loop = u == v
+    su = np.where(flip & ~loop, v, u)
+    sv = np.where(flip & ~loop, u, v)
+    extra = keep2 & ~loop
+    uu = np.concatenate([su, sv[extra]])
+    vv = np.concatenate([sv, su[extra]])
+    ww = np.concatenate([wt, wt[extra]])
+    if w_max > 0:
+        ww = g.integers(1, w_max + 1, uu.size)
+    return csr_from_pairs(n, uu, vv, ww, symmetrise=False)
+
+
 def random_sparse(n: int, m: int, w_max: int, seed: int, loops: bool = False):
     """m random pairs (repeats summed), weights uniform 1..w_max; with
     ``loops`` some diagonal entries appear."""

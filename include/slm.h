@@ -127,13 +127,21 @@ slm_status slm_create(int64_t n, int64_t nnz, const void *row_ptr, int row_ptr_b
  *   SLM_MODEL_ER      Erdos-Renyi null model p_ij = p = num/den (alpha = 1,
  *                     beta = p): gains are num * (den*w - num*n_P*n_R) for
  *                     node sets of n_P and n_R original nodes.
- * Every gain keeps the form A*w(P,R) - X_P*X_R with a node strength x
- * (num*k, or num*(original nodes)) summed over node sets and a scale A
- * (num*den*M2, or num*den), so all tie rules and strict tests above are
- * unchanged.  N_Q = A * sum_C w(C,C) - sum_C X_C^2 and Q = N_Q / A / M2.
+ *   SLM_MODEL_DIRECTED  the weighted modularity of Sec. 2.4 of a directed
+ *                     graph W (out- and in-strengths) with resolution
+ *                     gamma = num/den.  The input CSR is W itself (row i
+ *                     holds the arcs leaving i; no symmetry asked); the
+ *                     levels run on S = W + W^T, with x = num*(k_out+k_in)
+ *                     and a second strength y = num*(k_out-k_in), since
+ *                     k_out_i K_in_C + k_in_i K_out_C = (x_i X_C - y_i Y_C)/2.
+ * Every gain keeps the form A*w(P,R) - (X_P*X_R - Y_P*Y_R) with strengths
+ * x, y (y = 0 but for the directed model) summed over node sets and a scale
+ * A (num*den*M2, or num*den for Erdos-Renyi; M2 = sum of S for the directed
+ * model), so all tie rules and strict tests above are unchanged.
+ * N_Q = A * sum_C w(C,C) - sum_C (X_C^2 - Y_C^2) and Q = N_Q / A / M2.
  * Bounds (SLM_E_OVERFLOW otherwise): sum of x at most 2^30 and A*M2 at most
  * 2^61 for any model other than the default. */
-typedef enum { SLM_MODEL_CONFIG = 0, SLM_MODEL_ER = 1 } slm_model_kind;
+typedef enum { SLM_MODEL_CONFIG = 0, SLM_MODEL_ER = 1, SLM_MODEL_DIRECTED = 2 } slm_model_kind;
 typedef struct {
     int32_t kind;
     int32_t reserved;
@@ -142,8 +150,10 @@ typedef struct {
 } slm_model;
 
 /* slm_create under a null model (model NULL = the default).  The input is
- * the symmetric CSR of slm_create.  Batches and servers use the default
- * model only.  Errors as slm_create, plus SLM_E_INVALID for an unknown kind
+ * the symmetric CSR of slm_create, or for SLM_MODEL_DIRECTED any CSR with
+ * sorted unique columns and weights >= 1 (sum of W + W^T below 2^31); the
+ * handle's level 0 is then S = W + W^T (slm_level_info, slm_export_level).
+ * Batches and servers use the default model only.  Errors as slm_create, plus SLM_E_INVALID for an unknown kind
  * or num, den < 1. */
 slm_status slm_create_model(int64_t n, int64_t nnz, const void *row_ptr, int row_ptr_bytes,
                             const int32_t *col, const int32_t *w, int inputs_on_device,

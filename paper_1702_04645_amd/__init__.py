@@ -50,7 +50,7 @@ class Model(C.Structure):
                 ("den", C.c_int64)]
 
 
-MODEL_CONFIG, MODEL_ER = 0, 1
+MODEL_CONFIG, MODEL_ER, MODEL_DIRECTED = 0, 1, 2
 
 
 def model(kind: int = MODEL_CONFIG, num: int = 1, den: int = 1) -> Model:

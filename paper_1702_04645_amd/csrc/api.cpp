@@ -86,6 +86,10 @@ struct slm_graph {
     i64 mnum = 1, mden = 1;
     i64 keyA = 0;
     i32 *xcarry = nullptr;
+    // directed model: y = num * (k_out - k_in) of the input at level 0 (y0),
+    // carried by community totals to the next level (ycarry); W.y holds the
+    // current level's
+    i32 *y0 = nullptr, *ycarry = nullptr;
     std::vector<std::pair<void *, size_t>> allocs;  // fixed buffers, freed at destroy
     bool no_fanout = false;  // keep every sweep bin on the handle's stream
 
@@ -169,6 +173,8 @@ static LevelView view(slm_graph *g)
     L.n = g->n;
     L.nnz = g->nnz;
     L.m2 = g->keyA;
+    L.y = g->mkind == SLM_MODEL_DIRECTED ? g->W.y : nullptr;
+    L.sy = g->mkind == SLM_MODEL_DIRECTED ? g->W.sigy : nullptr;
     L.m2n = nullptr;
     L.gid = nullptr;
     L.gbase = nullptr;
@@ -356,8 +362,12 @@ static void setup_level(slm_graph *g)
     }
     // node strengths of the model: num times the row sums (configuration
     // model), or num times the original nodes a node stands for (Erdos-Renyi)
-    if (n > 0 && g->mkind == SLM_MODEL_CONFIG && g->mnum != 1)
+    if (n > 0 && (g->mkind == SLM_MODEL_CONFIG || g->mkind == SLM_MODEL_DIRECTED) &&
+        g->mnum != 1)
         launch_scale_i32(W.k, (i32)g->mnum, n, s);
+    if (n > 0 && g->mkind == SLM_MODEL_DIRECTED)
+        HIPCHK(hipMemcpyAsync(W.y, g->level == 0 ? g->y0 : g->ycarry, sizeof(i32) * n,
+                              hipMemcpyDeviceToDevice, s));
     if (n > 0 && g->mkind == SLM_MODEL_ER) {
         if (g->level == 0) launch_fill_i32(W.k, (i32)g->mnum, n, s);
         else HIPCHK(hipMemcpyAsync(W.k, g->xcarry, sizeof(i32) * n, hipMemcpyDeviceToDevice, s));
@@ -502,7 +512,7 @@ static slm_status fail(const SlmError &e)
 
 // ------------------------------------------------------------------ validation
 static void validate_host(i64 n, i64 nnz, const std::vector<i64> &rp, const i32 *col,
-                          const i32 *w, i64 *m2_out)
+                          const i32 *w, i64 *m2_out, bool symmetric = true)
 {
     REQUIRE(rp[0] == 0 && rp[n] == nnz, SLM_E_INVALID, "row_ptr must start at 0 and end at nnz");
     i64 m2 = 0;
@@ -516,7 +526,7 @@ static void validate_host(i64 n, i64 nnz, const std::vector<i64> &rp, const i32 
             m2 += w[e];
         }
     }
-    for (i64 i = 0; i < n; i++) {
+    for (i64 i = 0; i < n && symmetric; i++) {
         for (i64 e = rp[i]; e < rp[i + 1]; e++) {
             const i32 j = col[e];
             const i32 *b = col + rp[j], *en = col + rp[j + 1];
@@ -644,11 +654,17 @@ static void contract_only(slm_graph *g, const i32 *lab, i64 nc)
 
 static void do_contract(slm_graph *g, const i32 *lab, i64 nc)
 {
-    if (g->mkind == SLM_MODEL_ER && nc < g->n) {
-        // a community's strength at the next level is the sum over its members
+    if ((g->mkind == SLM_MODEL_ER || g->mkind == SLM_MODEL_DIRECTED) && nc < g->n) {
+        // a community's strengths at the next level are the sums over its
+        // members (x for Erdos-Renyi; y for the directed model, whose x is
+        // num times the row sums again)
         community_totals(g->W, view(g), lab, nc, g->s);
-        HIPCHK(hipMemcpyAsync(g->xcarry, g->W.sigma, sizeof(i32) * nc, hipMemcpyDeviceToDevice,
-                              g->s));
+        if (g->mkind == SLM_MODEL_ER)
+            HIPCHK(hipMemcpyAsync(g->xcarry, g->W.sigma, sizeof(i32) * nc,
+                                  hipMemcpyDeviceToDevice, g->s));
+        else
+            HIPCHK(hipMemcpyAsync(g->ycarry, g->W.sigy, sizeof(i32) * nc,
+                                  hipMemcpyDeviceToDevice, g->s));
     }
     contract_only(g, lab, nc);
     setup_level(g);
@@ -1000,7 +1016,8 @@ static slm_status create_impl(int64_t n, int64_t nnz, const void *row_ptr, int r
         REQUIRE(out != nullptr, SLM_E_INVALID, "null output handle");
         *out = nullptr;
         if (model) {
-            REQUIRE(model->kind == SLM_MODEL_CONFIG || model->kind == SLM_MODEL_ER,
+            REQUIRE(model->kind == SLM_MODEL_CONFIG || model->kind == SLM_MODEL_ER ||
+                        model->kind == SLM_MODEL_DIRECTED,
                     SLM_E_INVALID, "unknown null model kind");
             REQUIRE(model->num >= 1 && model->den >= 1, SLM_E_INVALID,
                     "the model parameter num/den needs num >= 1 and den >= 1");
@@ -1049,16 +1066,26 @@ static slm_status create_impl(int64_t n, int64_t nnz, const void *row_ptr, int r
                                                  : ((const i32 *)row_ptr)[i];
             }
             if (validate) {
-                validate_host(n, nnz, rp_h, colp, wp, &m2);
+                validate_host(n, nnz, rp_h, colp, wp, &m2, g->mkind != SLM_MODEL_DIRECTED);
+                if (g->mkind == SLM_MODEL_DIRECTED) m2 *= 2;  // the sum of W + W^T
                 REQUIRE(m2 < ((i64)1 << 31), SLM_E_OVERFLOW, "total weight M2 must be below 2^31");
             } else {
                 REQUIRE(rp_h[0] == 0 && rp_h[n] == nnz, SLM_E_INVALID, "row_ptr must start at 0 and end at nnz");
             }
         }
+        // the directed model runs on S = W + W^T: room for up to 2 nnz entries
+        if (g->mkind == SLM_MODEL_DIRECTED) g->nnz0 = g->nnz = 2 * nnz;
         alloc_work(g);
         g->rp0 = dalloc<i64>(g, n + 1);
-        g->e0 = dalloc<int2>(g, nnz);
+        g->e0 = dalloc<int2>(g, g->nnz0);
         if (g->mkind == SLM_MODEL_ER) g->xcarry = dalloc<i32>(g, n);
+        if (g->mkind == SLM_MODEL_DIRECTED) {
+            g->y0 = dalloc<i32>(g, n);
+            g->ycarry = dalloc<i32>(g, n);
+            g->W.y = dalloc<i32>(g, n);
+            g->W.sigy = dalloc<i32>(g, n);
+            g->W.suby = dalloc<i64>(g, n);
+        }
         if (!inputs_on_device) {
             HIPCHK(hipMemcpyAsync(g->rp0, rp_h.data(), sizeof(i64) * (n + 1), hipMemcpyHostToDevice, g->s));
             if (nnz) {
@@ -1076,6 +1103,12 @@ static slm_status create_impl(int64_t n, int64_t nnz, const void *row_ptr, int r
         }
         HIPCHK(hipEventCreate(&g->ev0));
         HIPCHK(hipEventCreate(&g->ev1));
+        if (g->mkind == SLM_MODEL_DIRECTED) {
+            // y0 = num (k_out - k_in) of W, then the level-0 matrix becomes S
+            const i64 nnz_s = symmetrize_level(g->W, g->rp0, g->e0, n, nnz, g->y0, g->s);
+            if (g->mnum != 1) launch_scale_i32(g->y0, (i32)g->mnum, n, g->s);
+            g->nnz0 = g->nnz = nnz_s;
+        }
         setup_level(g);
         REQUIRE(g->m2 < ((i64)1 << 31), SLM_E_OVERFLOW, "total weight M2 must be below 2^31");
         *out = g;

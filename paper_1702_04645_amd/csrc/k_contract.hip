@@ -176,21 +176,12 @@ static void radix_sort(Work &W, u64 *&k, i32 *&v, u64 *&k2, i32 *&v2, i64 n, int
     }
 }
 
-i64 contract_level(Work &W, const LevelView &Lv, const Bins &B, const i32 *lab, i64 nc,
-                   i64 *rp_out, int2 *e_out, hipStream_t s)
+// Records (row << bits | column, weight) in (k, v), alternates (k2, v2): the
+// CSR of nrows rows that sums the weights of equal keys, rows sorted by
+// column.  Returns its entry count.
+static i64 records_to_csr(Work &W, u64 *k, i32 *v, u64 *k2, i32 *v2, i64 recs, int bits,
+                          i64 nrows, i64 *rp_out, int2 *e_out, hipStream_t s)
 {
-    const i64 n = Lv.n, nnz = Lv.nnz;
-    const int bits = bits_for(nc);
-    launch_fill_i32(W.cnt, 0, n, s);
-    run_contract_rows(Lv, B, lab, bits, W.rk0, W.rv0, W.cnt, s);
-    launch_scan_i32(W.cnt, W.roff, n, W.scan_tmp, s);
-    read_scalars(W, W.roff + n, 1, s);
-    const i64 recs = W.h_scal[0];
-    if (nnz > 0)
-        k_compact_records<<<flat_grid(nnz), SLM_BS, 0, s>>>(W.src, Lv.rp, W.cnt, W.roff, nnz,
-                                                          W.rk0, W.rv0, W.rk1, W.rv1);
-    u64 *k = W.rk1, *k2 = W.rk0;
-    i32 *v = W.rv1, *v2 = W.rv0;
     if (recs > 0) radix_sort(W, k, v, k2, v2, recs, 2 * bits, s);
     // merge equal keys: heads -> positions -> sums
     uint8_t *head = W.head_e;
@@ -204,11 +195,70 @@ i64 contract_level(Work &W, const LevelView &Lv, const Bins &B, const i32 *lab, 
         launch_fill_i32(v2, 0, uniq, s);
         k_seg_sum<<<flat_grid(recs), SLM_BS, 0, s>>>(k, v, recs, head, hpos, k2, v2);
     }
-    // rows of the next level
-    i32 *rc = W.cnt;  // nc <= n
-    launch_fill_i32(rc, 0, nc, s);
+    // rows of the result
+    i32 *rc = W.cnt;  // nrows <= n0
+    launch_fill_i32(rc, 0, nrows, s);
     if (uniq > 0) k_row_count<<<flat_grid(uniq), SLM_BS, 0, s>>>(k2, uniq, bits, rc);
-    launch_scan_i32(rc, rp_out, nc, W.scan_tmp, s);
+    launch_scan_i32(rc, rp_out, nrows, W.scan_tmp, s);
     if (uniq > 0) k_emit_entries<<<flat_grid(uniq), SLM_BS, 0, s>>>(k2, v2, uniq, bits, e_out);
     return uniq;
+}
+
+i64 contract_level(Work &W, const LevelView &Lv, const Bins &B, const i32 *lab, i64 nc,
+                   i64 *rp_out, int2 *e_out, hipStream_t s)
+{
+    const i64 n = Lv.n, nnz = Lv.nnz;
+    const int bits = bits_for(nc);
+    launch_fill_i32(W.cnt, 0, n, s);
+    run_contract_rows(Lv, B, lab, bits, W.rk0, W.rv0, W.cnt, s);
+    launch_scan_i32(W.cnt, W.roff, n, W.scan_tmp, s);
+    read_scalars(W, W.roff + n, 1, s);
+    const i64 recs = W.h_scal[0];
+    if (nnz > 0)
+        k_compact_records<<<flat_grid(nnz), SLM_BS, 0, s>>>(W.src, Lv.rp, W.cnt, W.roff, nnz,
+                                                          W.rk0, W.rv0, W.rk1, W.rv1);
+    return records_to_csr(W, W.rk1, W.rv1, W.rk0, W.rv0, recs, bits, nc, rp_out, e_out, s);
+}
+
+// Both records (u, v, w) and (v, u, w) of every entry of row u; one thread
+// per row.
+__global__ void k_sym_records(const i64 *__restrict__ rp, const int2 *__restrict__ e, i64 n,
+                              int bits, u64 *__restrict__ kout, i32 *__restrict__ vout)
+{
+    for (i64 u = (i64)blockIdx.x * blockDim.x + threadIdx.x; u < n;
+         u += (i64)gridDim.x * blockDim.x) {
+        for (i64 j = rp[u]; j < rp[u + 1]; j++) {
+            const int2 ed = e[j];
+            kout[2 * j] = ((u64)u << bits) | (u64)(u32)ed.x;
+            kout[2 * j + 1] = ((u64)(u32)ed.x << bits) | (u64)u;
+            vout[2 * j] = ed.y;
+            vout[2 * j + 1] = ed.y;
+        }
+    }
+}
+
+// y[u] = sum of the row of u minus the sum of its column (k_out - k_in) of
+// the directed matrix in (rp, e).
+__global__ void k_out_minus_in(const i64 *__restrict__ rp, const int2 *__restrict__ e, i64 n,
+                               i32 *__restrict__ y)
+{
+    for (i64 u = (i64)blockIdx.x * blockDim.x + threadIdx.x; u < n;
+         u += (i64)gridDim.x * blockDim.x) {
+        i64 out = 0;
+        for (i64 j = rp[u]; j < rp[u + 1]; j++) {
+            const int2 ed = e[j];
+            out += ed.y;
+            atomicSub(&y[ed.x], ed.y);
+        }
+        atomicAdd(&y[u], (i32)out);
+    }
+}
+
+i64 symmetrize_level(Work &W, i64 *rp, int2 *e, i64 n, i64 nnz, i32 *y, hipStream_t s)
+{
+    launch_fill_i32(y, 0, n, s);
+    if (n > 0) k_out_minus_in<<<flat_grid(n), SLM_BS, 0, s>>>(rp, e, n, y);
+    const int bits = bits_for(n);
+    if (n > 0) k_sym_records<<<flat_grid(n), SLM_BS, 0, s>>>(rp, e, n, bits, W.rk0, W.rv0);
+    return records_to_csr(W, W.rk0, W.rv0, W.rk1, W.rv1, 2 * nnz, bits, n, rp, e, s);
 }

@@ -334,11 +334,12 @@ static void agg_min_index(const i32 *key, i64 n, i32 *out, hipStream_t s)
 }
 
 // ------------------------------------------------------------------ POSITIVE set-up
-// g(u) = M2*(wc - A_uu) - k*(S_c - k) < 0 flags community c; the first such
-// node numbers it.
+// g(u) = M2*(wc - A_uu) - k*(S_c - k) (+ y*(Y_c - y), directed model) < 0
+// flags community c; the first such node numbers it.
 __global__ void k_pos_flag(const i32 *__restrict__ comp, const i32 *__restrict__ k,
                            const i32 *__restrict__ diag, const i32 *__restrict__ wc,
                            const i32 *__restrict__ sig, const i32 *__restrict__ m2n, i64 m2,
+                           const i32 *__restrict__ y, const i32 *__restrict__ sigy,
                            i64 n, i32 *__restrict__ fidx, i32 *__restrict__ flist,
                            i64 *__restrict__ counters)
 {
@@ -348,6 +349,7 @@ __global__ void k_pos_flag(const i32 *__restrict__ comp, const i32 *__restrict__
         i64 ku = k[u_];
         const i64 m2u = m2n ? (i64)m2n[u_] : m2;
         i64 g = m2u * (i64)(wc[u_] - diag[u_]) - ku * ((i64)sig[c] - ku);
+        if (y) g += (i64)y[u_] * ((i64)sigy[c] - (i64)y[u_]);
         if (g >= 0) continue;
         if (atomicCAS(&fidx[c], -1, -2) == -1) {
             i32 f = (i32)atomicAdd((unsigned long long *)&counters[0], 1ull);
@@ -524,6 +526,7 @@ __device__ __forceinline__ u32 accept_draw(u64 seed, int level, int round, i32 n
 __global__ void k_max_valid(LevelView L, const i32 *__restrict__ lab,
                             const i32 *__restrict__ best_c, const uint8_t *__restrict__ cyc,
                             const i32 *__restrict__ sig, const i64 *__restrict__ subk,
+                            const i64 *__restrict__ suby,
                             const i64 *__restrict__ cut, const i32 *__restrict__ wbd, u64 seed,
                             int level, int round, u64 accept_p, uint8_t *__restrict__ accept,
                             i64 *__restrict__ counters, unsigned long long *__restrict__ gvalid)
@@ -542,16 +545,19 @@ __global__ void k_max_valid(LevelView L, const i32 *__restrict__ lab,
             const i32 c = lab[i], D = best_c[i];
             accept[i] = 0;
             if (D != c) {
-                i64 sb, cb;
+                i64 sb, tb, cb;
                 if (cyc[i]) {
                     sb = sig[c];
+                    tb = comm_y(L, c);
                     cb = 0;
                 } else {
                     sb = subk[i];
+                    tb = L.y ? suby[i] : 0;
                     cb = cut[i];
                 }
                 const i64 mv = node_m2(L, i) * ((i64)wbd[i] - cb) -
-                               sb * ((i64)sig[D] - (i64)sig[c] + sb);
+                               sb * ((i64)sig[D] - (i64)sig[c] + sb) +
+                               tb * (comm_y(L, D) - comm_y(L, c) + tb);
                 if (mv > 0) {
                     ok = true;
                     nv++;
@@ -582,14 +588,17 @@ __global__ void k_max_valid(LevelView L, const i32 *__restrict__ lab,
 
 // ------------------------------------------------------------------ modularity / compose
 __global__ void k_nq_parts(const i32 *__restrict__ wc, i64 n, const i32 *__restrict__ sig,
-                           i64 nc, i64 *__restrict__ acc)
+                           const i32 *__restrict__ sigy, i64 nc, i64 *__restrict__ acc)
 {
     __shared__ i64 red[32];
     i64 a = 0, b = 0;
     for (i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x; i < n || i < nc;
          i += (i64)gridDim.x * blockDim.x) {
         if (i < n) a += wc[i];
-        if (i < nc) b += (i64)sig[i] * (i64)sig[i];
+        if (i < nc) {
+            b += (i64)sig[i] * (i64)sig[i];
+            if (sigy) b -= (i64)sigy[i] * (i64)sigy[i];
+        }
     }
     a = block_sum<i64>(a, red);
     b = block_sum<i64>(b, red);
@@ -731,11 +740,15 @@ i64 positive(Work &W, const LevelView &Lv, const Bins &B, i64 *nc_out, hipStream
     // communities (ids = cycle minima) holding a node of negative local gain
     launch_fill_i32(W.sigma, 0, n, s);
     agg_add(W.comp, Lv.k, n, W.sigma, s);
+    if (Lv.y) {
+        launch_fill_i32(W.sigy, 0, n, s);
+        agg_add(W.comp, Lv.y, n, W.sigy, s);
+    }
     run_own_weight(Lv, B, W.comp, nullptr, W.wc, s);
     launch_fill_i32(W.fidx, -1, n, s);
     launch_fill_i64(W.counters, 0, 8, s);
-    k_pos_flag<<<g, SLM_BS, 0, s>>>(W.comp, Lv.k, Lv.diag, W.wc, W.sigma, Lv.m2n, Lv.m2, n, W.fidx,
-                                    W.flist, W.counters);
+    k_pos_flag<<<g, SLM_BS, 0, s>>>(W.comp, Lv.k, Lv.diag, W.wc, W.sigma, Lv.m2n, Lv.m2, Lv.y,
+                                    W.sigy, n, W.fidx, W.flist, W.counters);
     read_scalars(W, W.counters, 1, s);
     const i64 nflag = W.h_scal[0];
     i64 splits = 0;
@@ -785,7 +798,8 @@ i64 positive(Work &W, const LevelView &Lv, const Bins &B, i64 *nc_out, hipStream
         A.splits = W.counters;
         HIPCHK(hipMemsetAsync(W.changed, 0, sizeof(int), s));
         A.err = W.changed;
-        launch_positive_wg(A, nflag, s);
+        if (Lv.y) launch_positive_dir(A, nflag, s);
+        else launch_positive_wg(A, nflag, s);
         read_scalars(W, W.counters, 1, s);
         splits = W.h_scal[0];
         HIPCHK(hipMemcpyAsync(W.h_scal + 8, W.changed, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -802,6 +816,10 @@ void community_totals(Work &W, const LevelView &Lv, const i32 *lab, i64 nc, hipS
 {
     launch_fill_i32(W.sigma, 0, nc, s);
     agg_add(lab, Lv.k, Lv.n, W.sigma, s);
+    if (Lv.y) {
+        launch_fill_i32(W.sigy, 0, nc, s);
+        agg_add(lab, Lv.y, Lv.n, W.sigy, s);
+    }
 }
 
 i64 maximal_moves(Work &W, const LevelView &Lv, const Bins &B, i64 nc, u64 seed, int level,
@@ -834,6 +852,7 @@ i64 maximal_moves(Work &W, const LevelView &Lv, const Bins &B, i64 nc, u64 seed,
     // forest of the communities with non-cycle candidates
     Forest F = build_forest(W, W.a, W.lab, W.act, n, s);
     subtree_sums(W, W.lab, W.act, n, F, Lv.k, nullptr, W.subk, s);
+    if (Lv.y) subtree_sums(W, W.lab, W.act, n, F, Lv.y, nullptr, W.suby, s);
     subtree_cuts(W, Lv, B, W.lab, W.act, F, W.w_own, W.cut, s);
     // nearest candidate ancestors
     k_nca_init<<<g, SLM_BS, 0, s>>>(W.lab, W.act, W.best_c, W.cyc, W.J, n, W.nca0);
@@ -849,7 +868,8 @@ i64 maximal_moves(Work &W, const LevelView &Lv, const Bins &B, i64 nc, u64 seed,
     if (entries > 0)
         visit_rows(Lv, B, CrossVisit{W.lab, W.hasc, W.act, Fi, W.J, W.best_c, W.coff, W.clist,
                                      W.wbd}, s);
-    k_max_valid<<<g, SLM_BS, 0, s>>>(Lv, W.lab, W.best_c, W.cyc, W.sigma, W.subk, W.cut, W.wbd,
+    k_max_valid<<<g, SLM_BS, 0, s>>>(Lv, W.lab, W.best_c, W.cyc, W.sigma, W.subk, W.suby, W.cut,
+                                     W.wbd,
                                      seed, level, round, accept_p, W.accept, W.counters,
                                      gvalid);
     read_scalars(W, W.counters, 3, s);
@@ -872,7 +892,8 @@ i64 modularity_num(Work &W, const LevelView &Lv, const Bins &B, const i32 *lab, 
     run_own_weight(Lv, B, lab, nullptr, W.wc, s);
     launch_fill_i64(W.counters, 0, 2, s);
     i64 m = Lv.n > nc ? Lv.n : nc;
-    k_nq_parts<<<node_grid(m), SLM_BS, 0, s>>>(W.wc, Lv.n, W.sigma, nc, W.counters);
+    k_nq_parts<<<node_grid(m), SLM_BS, 0, s>>>(W.wc, Lv.n, W.sigma, Lv.y ? W.sigy : nullptr, nc,
+                                               W.counters);
     read_scalars(W, W.counters, 2, s);
     return Lv.m2 * W.h_scal[0] - W.h_scal[1];
 }

@@ -165,6 +165,7 @@ __global__ __launch_bounds__(GroupGeom<G>::BSZ) void k_argmax(
     i32 bj = INT32_MAX;
     if (active) {
         const i64 ki = L.k[node];
+        const i64 yi = node_y(L, node);
         const i64 m2 = node_m2(L, node);
         const i32 D = REPOINT ? best_c[node] : 0;
         for (i64 j = L.rp[node] + gl; j < L.rp[node + 1]; j += G) {
@@ -172,7 +173,7 @@ __global__ __launch_bounds__(GroupGeom<G>::BSZ) void k_argmax(
             const i32 v = ed.x;
             if (v == node) continue;
             if (REPOINT && lab[v] != D) continue;
-            i64 key = m2 * (i64)ed.y - ki * (i64)L.k[v];
+            i64 key = m2 * (i64)ed.y - ki * (i64)L.k[v] + yi * node_y(L, v);
             if (better_key(key, v, bk, bj)) {
                 bk = key;
                 bj = v;
@@ -231,15 +232,17 @@ __global__ __launch_bounds__(SLM_BS) void k_argmax_reg(
         ed[u] = (active && j < rd.y) ? L.e[e0 + j] : make_int2(-1, 0);
     }
     const i64 ki = active ? (i64)L.k[node] : 0;
+    const i64 yi = active ? node_y(L, node) : 0;
     const i64 m2 = active ? node_m2(L, node) : 0;
     const i32 D = (REPOINT && active) ? best_c[node] : 0;
-    i32 kv[U], lv[U];
+    i32 kv[U], lv[U], yv[U];
 #pragma unroll
     for (int u = 0; u < U; u++) {
         const i32 v = ed[u].x;
         const bool ok = v >= 0 && v != node;
         kv[u] = ok ? L.k[v] : 0;
         lv[u] = (REPOINT && ok) ? lab[v] : 0;
+        yv[u] = ok ? (i32)node_y(L, v) : 0;
     }
     i64 bk = INT64_MIN;
     i32 bj = INT32_MAX;
@@ -248,7 +251,7 @@ __global__ __launch_bounds__(SLM_BS) void k_argmax_reg(
         const i32 v = ed[u].x;
         if (v < 0 || v == node) continue;
         if (REPOINT && lv[u] != D) continue;
-        const i64 key = m2 * (i64)ed[u].y - ki * (i64)kv[u];
+        const i64 key = m2 * (i64)ed[u].y - ki * (i64)kv[u] + yi * (i64)yv[u];
         if (better_key(key, v, bk, bj)) {
             bk = key;
             bj = v;
@@ -405,6 +408,7 @@ __global__ __launch_bounds__(SLM_BS) void k_hub_argmax(
         i64 end = b + HUB_CHUNK;
         if (end > L.rp[node + 1]) end = L.rp[node + 1];
         const i64 ki = L.k[node];
+        const i64 yi = node_y(L, node);
         const i64 m2 = node_m2(L, node);
         const i32 D = REPOINT ? best_c[node] : 0;
         for (i64 j = b + threadIdx.x; j < end; j += blockDim.x) {
@@ -412,7 +416,7 @@ __global__ __launch_bounds__(SLM_BS) void k_hub_argmax(
             const i32 v = ed.x;
             if (v == node) continue;
             if (REPOINT && lab[v] != D) continue;
-            i64 key = m2 * (i64)ed.y - ki * (i64)L.k[v];
+            i64 key = m2 * (i64)ed.y - ki * (i64)L.k[v] + yi * node_y(L, v);
             if (better_key(key, v, bk, bj)) {
                 bk = key;
                 bj = v;

@@ -59,7 +59,9 @@ __device__ __forceinline__ void write_move(const LevelView &L, i32 node, i32 ci,
                                            i32 *__restrict__ best_c, i64 *__restrict__ delta,
                                            i32 *__restrict__ w_own)
 {
-    const i64 stay = node_m2(L, node) * win - ki * ((i64)sigma[ci] - ki);
+    const i64 yi = node_y(L, node);
+    const i64 stay = node_m2(L, node) * win - ki * ((i64)sigma[ci] - ki) +
+                     yi * (comm_y(L, ci) - yi);
     if (bc != INT32_MAX && bk > stay) {
         best_c[node] = bc;
         delta[node] = bk - stay;
@@ -160,7 +162,7 @@ __global__ __launch_bounds__(SLM_BS) void k_sweep_reg(LevelView L, const int4 *_
 #pragma unroll
     for (int u = 0; u < U; u++) {
         if (!first[u]) continue;
-        const i64 key = m2 * tot[u] - ki * (i64)lc[u].y;
+        const i64 key = m2 * tot[u] - ki * (i64)lc[u].y + node_y(L, node) * comm_y(L, lc[u].x);
         if (better_key(key, lc[u].x, bk, bc)) {
             bk = key;
             bc = lc[u].x;
@@ -169,7 +171,8 @@ __global__ __launch_bounds__(SLM_BS) void k_sweep_reg(LevelView L, const int4 *_
     win = group_sum<G, i64>(win);
     group_best<G>(bk, bc);
     if (valid && gl == 0) {
-        const i64 stay = m2 * win - ki * ((i64)own.y - ki);
+        const i64 yi = node_y(L, node);
+        const i64 stay = m2 * win - ki * ((i64)own.y - ki) + yi * (comm_y(L, own.x) - yi);
         if (bc != INT32_MAX && bk > stay) {
             best_c[node] = bc;
             delta[node] = bk - stay;
@@ -286,7 +289,8 @@ __global__ __launch_bounds__(G <= 64 ? SLM_BS : G) void k_sweep_hash(
         for (int i = gl; i < nd; i += G) {
             const i32 h = list[i];
             const i32 cc = keys[h];
-            const i64 key = m2 * (i64)vals[h] - ki * (i64)sigma[cc];
+            const i64 key = m2 * (i64)vals[h] - ki * (i64)sigma[cc] +
+                            node_y(L, node) * comm_y(L, cc);
             if (better_key(key, cc, bk, bc)) {
                 bk = key;
                 bc = cc;
@@ -401,7 +405,7 @@ __global__ __launch_bounds__(SLM_BS) void k_sweep_pipe(LevelView L, const int4 *
         for (int i = gl; i < nd; i += G) {
             const i32 h = list[i];
             const i32 cc = keys[h];
-            const i64 key = m2 * (i64)vals[h] - ki * (i64)lsig[i];
+            const i64 key = m2 * (i64)vals[h] - ki * (i64)lsig[i] + node_y(L, rd.x) * comm_y(L, cc);
             if (better_key(key, cc, bk, bc)) {
                 bk = key;
                 bc = cc;
@@ -413,7 +417,8 @@ __global__ __launch_bounds__(SLM_BS) void k_sweep_pipe(LevelView L, const int4 *
         group_best<G>(bk, bc);
         if (gl == 0) {
             const i32 node = rd.x;
-            const i64 stay = m2 * win - ki * ((i64)own.y - ki);
+            const i64 yi = node_y(L, node);
+            const i64 stay = m2 * win - ki * ((i64)own.y - ki) + yi * (comm_y(L, own.x) - yi);
             if (bc != INT32_MAX && bk > stay) {
                 best_c[node] = bc;
                 delta[node] = bk - stay;
@@ -671,7 +676,8 @@ __global__ __launch_bounds__(SLM_BS) void k_sweep_hub_tile(
             for (int i = threadIdx.x; i < (1 << tbits); i += SLM_BS) {
                 const i32 cc = keys[i];
                 if (cc >= 0) {
-                    const i64 key = m2 * (i64)vals[i] - ki * (i64)sigma[cc];
+                    const i64 key = m2 * (i64)vals[i] - ki * (i64)sigma[cc] +
+                                    node_y(L, node) * comm_y(L, cc);
                     if (better_key(key, cc, bk, bc)) {
                         bk = key;
                         bc = cc;

@@ -13,6 +13,8 @@ struct Work {
     // per node (n0 entries)
     i32 *a = nullptr, *lab = nullptr, *comp = nullptr, *best_c = nullptr, *w_own = nullptr;
     i32 *wc = nullptr, *sigma = nullptr, *k = nullptr, *diag = nullptr;
+    i32 *y = nullptr, *sigy = nullptr;  // directed model: y and its totals
+    i64 *suby = nullptr;                // directed model: subtree sums of y
     i64 *delta = nullptr;
     uint8_t *cyc = nullptr, *act = nullptr, *hasc = nullptr, *exam = nullptr,
             *exam_next = nullptr, *accept = nullptr, *head = nullptr;
@@ -95,6 +97,13 @@ struct PosArgs {
     int *err;            // 0, or the first tripped loop bound
 };
 void launch_positive_wg(const PosArgs &A, i64 nflag, hipStream_t s);
+// S = W + W^T of the directed matrix in (rp, e) (n rows, nnz entries),
+// written back in place (e must hold 2 nnz entries; the records need 2 nnz
+// slots of the work space), and y = num-free k_out - k_in of W.  Returns
+// nnz(S).
+i64 symmetrize_level(Work &W, i64 *rp, int2 *e, i64 n, i64 nnz, i32 *y, hipStream_t s);
+// POSITIVE under the directed model (node strengths x and y).
+void launch_positive_dir(const PosArgs &A, i64 nflag, hipStream_t s);
 
 struct Forest {
     int K = 0;            // highest jump table index in use

@@ -129,11 +129,16 @@ struct Bins {
 struct LevelView {
     const i64 *rp;   // n+1 offsets
     const int2 *e;   // nnz entries: x = column, y = weight
-    const i32 *k;    // strengths
+    const i32 *k;    // strengths (the null model's x; the row sums by default)
     const i32 *diag; // A_ii (0 if absent)
+    // Second strength of the directed model and its community totals (null
+    // otherwise): every gain A*w - x_i*X_C gains + y_i*Y_C.  sy holds the
+    // totals of the labelling the current step works on.
+    const i32 *y;
+    const i32 *sy;
     i64 n;
     i64 nnz;
-    i64 m2;
+    i64 m2;  // scale A of the edge term (M2 for the default model)
     // A batch is the disjoint union of independent graphs.  Every key of a
     // node then uses the total weight of its own graph, and the acceptance
     // draw uses its graph's seed, level and local node number.  All null for
@@ -148,6 +153,16 @@ struct LevelView {
 __device__ __forceinline__ i64 node_m2(const LevelView &L, i64 i)
 {
     return L.m2n ? (i64)L.m2n[i] : L.m2;
+}
+
+// y_i, and Y_C of community c, of the directed model (0 for the others).
+__device__ __forceinline__ i64 node_y(const LevelView &L, i64 i)
+{
+    return L.y ? (i64)L.y[i] : 0;
+}
+__device__ __forceinline__ i64 comm_y(const LevelView &L, i32 c)
+{
+    return L.y ? (i64)L.sy[c] : 0;
 }
 
 // Adds v to acc[key] for every lane of the wavefront, where the keys are
