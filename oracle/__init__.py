@@ -68,6 +68,8 @@ def _load():
         "or_null_strengths": (i32, [i32, i64, i64, i64, P, P, P, P, P, P]),
         "or_run_null": (i32, [i64, P, P, P, i32, i64, i64, u64, u64, i32, i32, i32, P, P, P,
                               P, P, P]),
+        "or_louvain_level": (i64, [i64, P, P, P, P, i64, i32, P, P, P, P]),
+        "or_louvain_run": (i32, [i64, P, P, P, i32, i32, i32, P, P, P, P, P, P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -345,3 +347,32 @@ def run_null(row_ptr, col, w, kind: int = CONFIG, num: int = 1, den: int = 1, se
         out.append(dict(labels=lab[l, :n0].copy(), n_c=int(nc[l]), nq=int(nq[l]), q=float(q[l]),
                         rounds=int(rounds[l]), converged=bool(conv[l])))
     return out
+
+
+# ---------------------------------------------------------------- classical Louvain
+def louvain_level(g: Graph, max_passes: int = 64):
+    """Sequential local moving of one level: (canonical labels, n_c, passes
+    that moved a node, converged, moves)."""
+    lab = np.zeros(max(g.n, 1), np.int32)
+    p, cv, mv = C.c_int32(), C.c_int32(), C.c_int64()
+    nc = int(_load().or_louvain_level(*g._g(), g.m2, max_passes, _p(lab), C.byref(p),
+                                      C.byref(cv), C.byref(mv)))
+    return lab[: g.n], nc, int(p.value), bool(cv.value), int(mv.value)
+
+
+def louvain_run(row_ptr, col, w, max_passes: int = 64, max_levels: int = 0, max_out: int = 32):
+    """Full classical Louvain run; per-level dicts as run(), with the passes
+    of each level under "rounds"."""
+    g = Graph(row_ptr, col, w)
+    n0 = g.n
+    lab = np.zeros((max_out, max(n0, 1)), np.int32)
+    nc = np.zeros(max_out, np.int64)
+    nq = np.zeros(max_out, np.int64)
+    q = np.zeros(max_out, np.float64)
+    passes = np.zeros(max_out, np.int32)
+    conv = np.zeros(max_out, np.int32)
+    L = int(_load().or_louvain_run(n0, _p(g.rp), _p(g.col), _p(g.w), max_passes, max_levels,
+                                   max_out, _p(lab), _p(nc), _p(nq), _p(q), _p(passes),
+                                   _p(conv)))
+    return [dict(labels=lab[l, :n0].copy(), n_c=int(nc[l]), nq=int(nq[l]), q=float(q[l]),
+                 rounds=int(passes[l]), converged=bool(conv[l])) for l in range(min(L, max_out))]

@@ -1328,3 +1328,160 @@ int32_t or_run_null(int64_t n0, const int64_t *rp0, const int32_t *col0,
     free(rp);
     return emitted;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Classical Louvain: the sequential method the SLM is built on, named in    */
+/* Sec. 6 as the comparison the paper leaves open.  A level moves nodes one  */
+/* at a time, in id order, each to its best neighbouring community with the  */
+/* state left by the moves before it (the SLM instead decides every move of  */
+/* a round from the same state, Sec. 3.4); passes over all nodes repeat      */
+/* until one moves nothing (or max_passes), then AGGREGATE as in Sec. 3.5.   */
+/* Same exact keys and ties as the SLM sweep: node i in community c moves to */
+/* argmax_{C != c} join(i,C) (lowest C on ties) iff that beats stay(i).      */
+/* During a level a community is named by the node it started from, so the  */
+/* tie order is that of those ids; the level's labels are then made          */
+/* canonical.                                                                */
+/* ------------------------------------------------------------------------ */
+
+/* Local moving of one level; lab_out gets the canonical labels.  Returns the
+ * community count; *passes = passes that moved a node, *converged = 1 when
+ * the last pass moved nothing, *moves = nodes moved in all passes. */
+int64_t or_louvain_level(int64_t n, const int64_t *rp, const int32_t *col,
+                         const int32_t *w, const int64_t *k, int64_t m2,
+                         int32_t max_passes, int32_t *lab_out, int32_t *passes,
+                         int32_t *converged, int64_t *moves)
+{
+    int32_t *c = xmalloc((size_t)(n ? n : 1) * sizeof(int32_t));
+    int64_t *sig = xmalloc((size_t)(n ? n : 1) * sizeof(int64_t));
+    int64_t *acc = xcalloc((size_t)(n ? n : 1), sizeof(int64_t));
+    int32_t *touched = xmalloc((size_t)(n ? n : 1) * sizeof(int32_t));
+    for (int64_t i = 0; i < n; i++) {
+        c[i] = (int32_t)i;
+        sig[i] = k[i];
+    }
+    int32_t p = 0;
+    int64_t total = 0;
+    *converged = 0;
+    while (p < max_passes) {
+        int64_t moved = 0;
+        for (int64_t i = 0; i < n; i++) {
+            int32_t ci = c[i];
+            int64_t nt = 0, w_in = 0;
+            for (int64_t e = rp[i]; e < rp[i + 1]; e++) {
+                int32_t v = col[e];
+                if (v == i) continue;
+                if (c[v] == ci) {
+                    w_in += w[e];
+                    continue;
+                }
+                if (acc[c[v]] == 0) touched[nt++] = c[v];
+                acc[c[v]] += w[e];
+            }
+            int64_t stay = m2 * w_in - k[i] * (sig[ci] - k[i]);
+            int64_t best_key = 0;
+            int32_t best = -1;
+            for (int64_t t = 0; t < nt; t++) {
+                int32_t cc = touched[t];
+                int64_t key = m2 * acc[cc] - k[i] * sig[cc];
+                if (best < 0 || key > best_key || (key == best_key && cc < best)) {
+                    best = cc;
+                    best_key = key;
+                }
+                acc[cc] = 0;
+            }
+            if (best >= 0 && best_key > stay) {
+                sig[ci] -= k[i];
+                sig[best] += k[i];
+                c[i] = best;
+                moved++;
+            }
+        }
+        if (moved == 0) {
+            *converged = 1;
+            break;
+        }
+        total += moved;
+        p++;
+    }
+    /* canonical labels: communities numbered by their smallest member */
+    int32_t *name = xmalloc((size_t)(n ? n : 1) * sizeof(int32_t));
+    for (int64_t i = 0; i < n; i++) name[i] = -1;
+    int64_t nc = 0;
+    for (int64_t i = 0; i < n; i++) {
+        if (name[c[i]] < 0) name[c[i]] = (int32_t)nc++;
+        lab_out[i] = name[c[i]];
+    }
+    free(name);
+    free(touched);
+    free(acc);
+    free(sig);
+    free(c);
+    *passes = p;
+    *moves = total;
+    return nc;
+}
+
+/* Full classical Louvain run: levels until one leaves the identity (not
+ * emitted) or max_levels; per emitted level the composed labels, n_c, N_Q,
+ * Q (as or_run), the passes that moved nodes and the converged flag. */
+int32_t or_louvain_run(int64_t n0, const int64_t *rp0, const int32_t *col0,
+                       const int32_t *w0, int32_t max_passes, int32_t max_levels,
+                       int32_t max_out, int32_t *labels_out, int64_t *nc_out,
+                       int64_t *nq_out, double *q_out, int32_t *passes_out,
+                       int32_t *conv_out)
+{
+    int64_t nnz0 = rp0[n0];
+    int64_t n = n0;
+    int64_t *rp = xmalloc((size_t)(n0 + 1) * sizeof(int64_t));
+    int32_t *col = xmalloc((size_t)(nnz0 ? nnz0 : 1) * sizeof(int32_t));
+    int32_t *w = xmalloc((size_t)(nnz0 ? nnz0 : 1) * sizeof(int32_t));
+    memcpy(rp, rp0, (size_t)(n0 + 1) * sizeof(int64_t));
+    memcpy(col, col0, (size_t)nnz0 * sizeof(int32_t));
+    memcpy(w, w0, (size_t)nnz0 * sizeof(int32_t));
+    int64_t *k = xmalloc((size_t)(n0 ? n0 : 1) * sizeof(int64_t));
+    int32_t *lab = xmalloc((size_t)(n0 ? n0 : 1) * sizeof(int32_t));
+    int32_t *composed = xmalloc((size_t)(n0 ? n0 : 1) * sizeof(int32_t));
+    for (int64_t v = 0; v < n0; v++) composed[v] = (int32_t)v;
+    int64_t m2 = or_strength(n, rp, col, w, k);
+    int32_t emitted = 0;
+    while (m2 > 0 && n > 0) {
+        int32_t passes = 0, conv = 0;
+        int64_t moves = 0;
+        int64_t nc = or_louvain_level(n, rp, col, w, k, m2, max_passes, lab, &passes, &conv,
+                                      &moves);
+        if (nc == n) break;
+        for (int64_t v = 0; v < n0; v++) composed[v] = lab[composed[v]];
+        int64_t nq = or_modularity_num(n, rp, col, w, k, m2, lab, nc);
+        if (emitted < max_out) {
+            memcpy(labels_out + (size_t)emitted * (size_t)n0, composed,
+                   (size_t)n0 * sizeof(int32_t));
+            nc_out[emitted] = nc;
+            nq_out[emitted] = nq;
+            q_out[emitted] = or_modularity(nq, m2);
+            passes_out[emitted] = passes;
+            conv_out[emitted] = conv;
+        }
+        emitted++;
+        int64_t nnz = rp[n];
+        int64_t *rp2 = xmalloc((size_t)(nc + 1) * sizeof(int64_t));
+        int32_t *col2 = xmalloc((size_t)(nnz ? nnz : 1) * sizeof(int32_t));
+        int32_t *w2 = xmalloc((size_t)(nnz ? nnz : 1) * sizeof(int32_t));
+        or_contract(n, rp, col, w, lab, nc, rp2, col2, w2);
+        free(rp);
+        free(col);
+        free(w);
+        rp = rp2;
+        col = col2;
+        w = w2;
+        n = nc;
+        or_strength(n, rp, col, w, k);
+        if (max_levels > 0 && emitted >= max_levels) break;
+    }
+    free(composed);
+    free(lab);
+    free(k);
+    free(w);
+    free(col);
+    free(rp);
+    return emitted;
+}

@@ -345,3 +345,56 @@ def run_null(W, kind, num, den, seed, draw_fn, p_threshold=1 << 31, max_rounds=6
         size = P.T @ size
         W = contract_directed(W, lab)
     return out
+
+
+# ---------------------------------------------------------------- classical Louvain
+def louvain_level(A, max_passes=64):
+    """Sequential local moving on a dense symmetric matrix: nodes in id
+    order; node i moves to the neighbouring community whose N_Q gain (the
+    whole partition recomputed from scratch) is largest, lowest name on ties,
+    when that gain is positive.  Communities are named by the node they
+    started from.  Returns (canonical labels, passes that moved, converged)."""
+    n = A.shape[0]
+    c = np.arange(n)
+    p = 0
+    conv = False
+    while p < max_passes:
+        moved = 0
+        for i in range(n):
+            base = nq(A, c)
+            best, bc = None, None
+            for C in sorted({int(c[j]) for j in range(n) if A[i, j] > 0 and j != i}):
+                if C == c[i]:
+                    continue
+                c2 = c.copy()
+                c2[i] = C
+                g = nq(A, c2) - base
+                if best is None or g > best:
+                    best, bc = g, C
+            if best is not None and best > 0:
+                c[i] = bc
+                moved += 1
+        if moved == 0:
+            conv = True
+            break
+        p += 1
+    return canonical(c), p, conv
+
+
+def louvain_run(A, max_passes=64, max_levels=0):
+    n0 = A.shape[0]
+    composed = np.arange(n0)
+    out = []
+    while int(A.sum()) > 0:
+        n = A.shape[0]
+        lab, p, conv = louvain_level(A, max_passes)
+        nc = int(lab.max()) + 1
+        if nc == n:
+            break
+        composed = lab[composed]
+        out.append(dict(labels=composed.copy(), n_c=nc, nq=nq(A, lab), rounds=p,
+                        converged=conv))
+        if max_levels > 0 and len(out) >= max_levels:
+            break
+        A = contract(A, lab)
+    return out
