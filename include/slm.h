@@ -240,6 +240,24 @@ slm_status slm_contract(slm_graph *g, const int32_t *lab_dev, int64_t n_c);
  * original nodes, n_c, N_Q, Q, rounds and the converged flag. */
 slm_status slm_run(slm_graph *g, const slm_params *p, slm_result **out);
 
+/* Classical Louvain, the sequential method the SLM builds on, which Sec. 6
+ * names as the comparison the paper leaves open.  A level moves nodes one
+ * at a time in id order, each to its best neighbouring community (largest
+ * join, lowest name on ties; communities are named by the node they started
+ * from during the level) when that beats stay, seeing every earlier move;
+ * passes repeat until one moves nothing or p->max_rounds passes, then
+ * AGGREGATE (Sec. 3.5) as in the SLM.  The result is exactly the sequential
+ * one: chunks of nodes decide at once from the same state and only the
+ * decisions no earlier move of their chunk could change are kept.
+ * slm_louvain_level: one level on the current level of the handle; writes
+ * canonical labels (lab_dev, n_t entries), n_c, the passes that moved a node
+ * and the converged flag.  slm_louvain_run: the full run from level 0, with
+ * the result of slm_run (rounds = passes per level).  Plain handles under
+ * the default model only (SLM_E_STATE otherwise).  Synchronise. */
+slm_status slm_louvain_level(slm_graph *g, const slm_params *p, int32_t *lab_dev, int64_t *n_c,
+                             int32_t *passes, int32_t *converged);
+slm_status slm_louvain_run(slm_graph *g, const slm_params *p, slm_result **out);
+
 slm_status slm_result_num_levels(const slm_result *r, int32_t *levels);
 /* labels: n_0 entries owned by the result. */
 slm_status slm_result_level(const slm_result *r, int32_t level, int64_t *n_c,

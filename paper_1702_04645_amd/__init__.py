@@ -149,6 +149,8 @@ def lib():
         "slm_modularity": (st, [P, P, i64, pi64, C.POINTER(C.c_double)]),
         "slm_contract": (st, [P, P, i64]),
         "slm_run": (st, [P, C.POINTER(Params), C.POINTER(P)]),
+        "slm_louvain_level": (st, [P, C.POINTER(Params), P, pi64, pi32, pi32]),
+        "slm_louvain_run": (st, [P, C.POINTER(Params), C.POINTER(P)]),
         "slm_result_num_levels": (st, [P, pi32]),
         "slm_result_level": (st, [P, i32, pi64, C.POINTER(C.POINTER(C.c_int32)), pi64,
                                   C.POINTER(C.c_double), pi32, pi32]),
@@ -365,6 +367,26 @@ class Graph:
             p = params()
         res = C.c_void_p()
         _check(lib().slm_run(self._h, C.byref(p), C.byref(res)))
+        return _take_result(res, self.n0)
+
+    def louvain_level(self, p: Params | None = None):
+        """Classical Louvain local moving of the current level: (labels, n_c,
+        passes, converged)."""
+        if p is None:
+            p = params()
+        n = self.level_info()["n"]
+        lab = _dev_i32(n)
+        nc, ps, cv = C.c_int64(), C.c_int32(), C.c_int32()
+        _check(lib().slm_louvain_level(self._h, C.byref(p), _ptr(lab), C.byref(nc),
+                                       C.byref(ps), C.byref(cv)))
+        return lab[:n], nc.value, ps.value, bool(cv.value)
+
+    def louvain_run(self, p: Params | None = None):
+        """Full classical Louvain run (rounds = passes per level)."""
+        if p is None:
+            p = params()
+        res = C.c_void_p()
+        _check(lib().slm_louvain_run(self._h, C.byref(p), C.byref(res)))
         return _take_result(res, self.n0)
 
     # -------------------------------------------------------------- timing

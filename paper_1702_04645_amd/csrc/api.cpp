@@ -1380,6 +1380,88 @@ slm_status slm_run(slm_graph *g, const slm_params *p, slm_result **out)
     API_END
 }
 
+// Classical Louvain (the sequential comparison method): local moving in id
+// order with exact sequential semantics, then canonical labels.
+static void louvain_labels(slm_graph *g, const slm_params *p, i64 *nc, int32_t *passes,
+                           int32_t *conv)
+{
+    int cv = 0;
+    i64 mv = 0;
+    *passes = louvain_level(g->W, view(g), p->max_rounds, &cv, &mv, g->s);
+    *conv = cv;
+    *nc = canonical_labels(g->W, g->n, g->s);
+}
+
+static void louvain_checks(slm_graph *g, const slm_params *p)
+{
+    REQUIRE(p->max_rounds >= 0 && p->max_levels >= 0, SLM_E_INVALID, "negative cap");
+    REQUIRE(!g->is_union, SLM_E_STATE, "classical Louvain runs on a plain handle");
+    REQUIRE(g->mkind == SLM_MODEL_CONFIG && g->mnum == 1 && g->mden == 1, SLM_E_STATE,
+            "classical Louvain runs under the default null model");
+}
+
+slm_status slm_louvain_level(slm_graph *g, const slm_params *p, int32_t *lab_dev, int64_t *n_c,
+                             int32_t *passes, int32_t *converged)
+{
+    API_BEGIN
+    REQUIRE(g != nullptr && p != nullptr, SLM_E_INVALID, "null argument");
+    REQUIRE(g->n == 0 || lab_dev, SLM_E_INVALID, "null labels");
+    louvain_checks(g, p);
+    i64 nc = 0;
+    int32_t ps = 0, cv = 1;
+    if (g->n > 0) {
+        louvain_labels(g, p, &nc, &ps, &cv);
+        HIPCHK(hipMemcpyAsync(lab_dev, g->W.lab, sizeof(i32) * g->n, hipMemcpyDeviceToDevice,
+                              g->s));
+        HIPCHK(hipStreamSynchronize(g->s));
+    }
+    if (n_c) *n_c = nc;
+    if (passes) *passes = ps;
+    if (converged) *converged = cv;
+    API_END
+}
+
+slm_status slm_louvain_run(slm_graph *g, const slm_params *p, slm_result **out)
+{
+    API_BEGIN
+    REQUIRE(g != nullptr && p != nullptr && out != nullptr, SLM_E_INVALID, "null argument");
+    louvain_checks(g, p);
+    *out = nullptr;
+    do_reset(g);
+    slm_result *r = new slm_result();
+    r->n0 = g->n0;
+    try {
+        launch_iota_i32(g->composed, g->n0, g->s);
+        int level = 0;
+        while (g->m2 > 0 && g->n > 0) {
+            i64 nc;
+            int32_t passes, conv;
+            louvain_labels(g, p, &nc, &passes, &conv);
+            if (nc == g->n) break;  // no node moved: the identity
+            compose_labels(g->composed, g->W.lab, g->n0, g->s);
+            i64 nq = modularity_num(g->W, view(g), g->bins, g->W.lab, nc, g->s);
+            std::vector<i32> lab(g->n0);
+            HIPCHK(hipMemcpyAsync(lab.data(), g->composed, sizeof(i32) * g->n0,
+                                  hipMemcpyDeviceToHost, g->s));
+            HIPCHK(hipStreamSynchronize(g->s));
+            r->labels.push_back(std::move(lab));
+            r->nc.push_back(nc);
+            r->nq.push_back(nq);
+            r->q.push_back((double)nq / (double)g->keyA / (double)g->m2);
+            r->rounds.push_back(passes);
+            r->conv.push_back(conv);
+            level++;
+            if (p->max_levels > 0 && level >= p->max_levels) break;
+            do_contract(g, g->W.lab, nc);
+        }
+    } catch (...) {
+        delete r;
+        throw;
+    }
+    *out = r;
+    API_END
+}
+
 slm_status slm_result_num_levels(const slm_result *r, int32_t *levels)
 {
     API_BEGIN

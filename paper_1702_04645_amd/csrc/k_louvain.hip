@@ -1,0 +1,222 @@
+// Classical Louvain local moving (the sequential method the SLM builds on,
+// named in Sec. 6 as the comparison left open) with its exact sequential
+// result on the GPU.  In id order, node i moves to its best neighbouring
+// community C (join(i,C) = M2 w(i,C) - k_i S_C, lowest name on ties) when
+// that beats stay(i) = M2 w(i, c\i) - k_i (S_c - k_i), seeing every move made
+// before it.  Communities are named by the node they started from.
+//
+// Speculation by chunks.  The next B nodes decide at once from the state at
+// the chunk's start.  Node i's decision reads the names of its neighbours and
+// the totals S of its own and its neighbours' communities; a move of node j
+// writes j's name and the totals of j's old and new communities.  Every
+// moving node marks what it writes with its position in the chunk (atomic
+// min), so node i is exact iff no earlier mover of the chunk marked anything
+// i reads.  The moves before the first node that is not exact are applied --
+// exactly the sequential result -- and the next chunk starts at that node.
+// The first node of a chunk is always exact, so every chunk makes progress.
+#include "slm_forest.h"
+
+#define LV_BS 256
+#define LV_NODES (LV_BS / 64)  // one wavefront per node
+
+// Node i = p + t of the chunk: its decision from the current names c[] and
+// totals sig[], with a hash table of its neighbours' communities in global
+// memory at slots [2 (rp[i] - rp[p]), 2 (rp[i+1] - rp[p])) (twice its degree,
+// filled with -1 beforehand).  dest[t] = the community to move to, or -1.  A
+// moving node marks its own name and the totals of its old and new
+// communities with t.
+__global__ __launch_bounds__(LV_BS) void k_lv_decide(LevelView L, i64 p, i64 cnt,
+                                                    const i32 *__restrict__ c,
+                                                    const i32 *__restrict__ sig,
+                                                    i32 *__restrict__ tkey,
+                                                    i32 *__restrict__ tval,
+                                                    i32 *__restrict__ dest,
+                                                    i32 *__restrict__ mark_node,
+                                                    i32 *__restrict__ mark_comm)
+{
+    const int lane = threadIdx.x & 63;
+    const i64 t = (i64)blockIdx.x * LV_NODES + threadIdx.x / 64;
+    if (t >= cnt) return;  // a whole wavefront leaves together
+    const i64 i = p + t;
+    const i64 e0 = L.rp[i], e1 = L.rp[i + 1];
+    const i64 H = 2 * (e1 - e0);
+    const i64 tb = 2 * (e0 - L.rp[p]);
+    i32 *keys = tkey + tb;
+    i32 *vals = tval + tb;
+    const i32 ci = c[i];
+    i64 w_in = 0;
+    for (i64 j = e0 + lane; j < e1; j += 64) {
+        const int2 ed = L.e[j];
+        if (ed.x == i) continue;
+        const i32 cv = c[ed.x];
+        if (cv == ci) {
+            w_in += ed.y;
+            continue;
+        }
+        u64 h = ((u64)hash_label(cv) * (u64)H) >> 32;
+        for (i64 probe = 0; probe < H; probe++) {
+            const i32 old = atomicCAS(&keys[h], -1, cv);
+            if (old == -1 || old == cv) {
+                atomicAdd(&vals[h], ed.y);
+                break;
+            }
+            h = h + 1 == (u64)H ? 0 : h + 1;
+        }
+    }
+    // every insert of the wavefront is done and visible before the read-out
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "agent");
+    __builtin_amdgcn_wave_barrier();
+    const i64 ki = L.k[i], m2 = L.m2;
+    i64 bk = INT64_MIN;
+    i32 bc = INT32_MAX;
+    for (i64 h = lane; h < H; h += 64) {
+        const i32 cc = __hip_atomic_load(&keys[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (cc < 0) continue;
+        const i32 wv = __hip_atomic_load(&vals[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const i64 key = m2 * (i64)wv - ki * (i64)sig[cc];
+        if (better_key(key, cc, bk, bc)) {
+            bk = key;
+            bc = cc;
+        }
+    }
+    w_in = group_sum<64, i64>(w_in);
+    group_best<64>(bk, bc);
+    if (lane == 0) {
+        const i64 stay = m2 * w_in - ki * ((i64)sig[ci] - ki);
+        const bool mv = bc != INT32_MAX && bk > stay;
+        dest[t] = mv ? bc : -1;
+        if (mv) {
+            atomicMin(&mark_node[i], (i32)t);
+            atomicMin(&mark_comm[ci], (i32)t);
+            atomicMin(&mark_comm[bc], (i32)t);
+        }
+    }
+}
+
+// first = the smallest t whose decision read something an earlier mover of
+// the chunk wrote.
+__global__ __launch_bounds__(LV_BS) void k_lv_conflict(LevelView L, i64 p, i64 cnt,
+                                                      const i32 *__restrict__ c,
+                                                      const i32 *__restrict__ mark_node,
+                                                      const i32 *__restrict__ mark_comm,
+                                                      int *__restrict__ first)
+{
+    const int lane = threadIdx.x & 63;
+    const i64 t = (i64)blockIdx.x * LV_NODES + threadIdx.x / 64;
+    if (t >= cnt) return;
+    const i64 i = p + t;
+    bool hit = lane == 0 && mark_comm[c[i]] < t;
+    for (i64 j = L.rp[i] + lane; j < L.rp[i + 1] && !hit; j += 64) {
+        const i32 v = L.e[j].x;
+        if (v == i) continue;
+        if (mark_node[v] < t || mark_comm[c[v]] < t) hit = true;
+    }
+    if (__ballot(hit) != 0 && lane == 0) atomicMin(first, (int)t);
+}
+
+// Applies the moves before `first` and clears every mark of the chunk.
+__global__ __launch_bounds__(LV_BS) void k_lv_apply(LevelView L, i64 p, i64 cnt,
+                                                   const int *__restrict__ first,
+                                                   const i32 *__restrict__ dest,
+                                                   i32 *__restrict__ c, i32 *__restrict__ sig,
+                                                   i32 *__restrict__ mark_node,
+                                                   i32 *__restrict__ mark_comm,
+                                                   unsigned long long *__restrict__ moves)
+{
+    const i64 t = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= cnt) return;
+    const i32 d = dest[t];
+    if (d < 0) return;
+    const i64 i = p + t;
+    const i32 old = c[i];
+    mark_node[i] = INT32_MAX;
+    mark_comm[old] = INT32_MAX;
+    mark_comm[d] = INT32_MAX;
+    if (t < (i64)*first) {
+        c[i] = d;
+        atomicSub(&sig[old], L.k[i]);
+        atomicAdd(&sig[d], L.k[i]);
+        atomicAdd(moves, 1ull);
+    }
+}
+
+// c[i] = i, sig[i] = k_i, no marks.
+__global__ void k_lv_init(LevelView L, i32 *__restrict__ c, i32 *__restrict__ sig,
+                          i32 *__restrict__ mark_node, i32 *__restrict__ mark_comm)
+{
+    for (i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x; i < L.n;
+         i += (i64)gridDim.x * blockDim.x) {
+        c[i] = (i32)i;
+        sig[i] = L.k[i];
+        mark_node[i] = INT32_MAX;
+        mark_comm[i] = INT32_MAX;
+    }
+}
+
+static unsigned lv_grid(i64 items, int per_block)
+{
+    i64 g = (items + per_block - 1) / per_block;
+    return (unsigned)(g < 1 ? 1 : g);
+}
+
+// One level of local moving on the level in L; W.comp gets the community
+// names.  Returns the passes that moved a node; *converged = the last pass
+// moved nothing; *moves = nodes moved.  Tables use W.rk0 / W.rk1 (2 nnz int32
+// slots each), names and totals W.comp / W.sigma, decisions W.best_c, marks
+// W.M0 / W.M1, the first conflict and the move count W.changed / W.counters.
+int louvain_level(Work &W, const LevelView &L, int max_passes, int *converged, i64 *moves,
+                  hipStream_t s)
+{
+    const i64 n = L.n;
+    i32 *c = W.comp, *sig = W.sigma, *dest = W.best_c, *mn = W.M0, *mc = W.M1;
+    i32 *tkey = (i32 *)W.rk0, *tval = (i32 *)W.rk1;
+    int *first = W.changed;
+    unsigned long long *mv = (unsigned long long *)W.counters;
+    *converged = 0;
+    *moves = 0;
+    if (n == 0) {
+        *converged = 1;
+        return 0;
+    }
+    std::vector<i64> rp_h(n + 1);
+    HIPCHK(hipMemcpyAsync(rp_h.data(), L.rp, sizeof(i64) * (n + 1), hipMemcpyDeviceToHost, s));
+    k_lv_init<<<lv_grid(n, SLM_BS) > 4096 ? 4096 : lv_grid(n, SLM_BS), SLM_BS, 0, s>>>(L, c, sig,
+                                                                                     mn, mc);
+    HIPCHK(hipStreamSynchronize(s));
+    int passes = 0;
+    i64 B = 1024;
+    while (passes < max_passes) {
+        launch_fill_i64((i64 *)mv, 0, 1, s);
+        i64 p = 0;
+        while (p < n) {
+            const i64 cnt = p + B < n ? B : n - p;
+            const i64 slots = 2 * (rp_h[p + cnt] - rp_h[p]);
+            launch_fill_i32(tkey, -1, slots, s);
+            launch_fill_i32(tval, 0, slots, s);
+            launch_fill_i32((i32 *)first, INT32_MAX, 1, s);
+            k_lv_decide<<<lv_grid(cnt, LV_NODES), LV_BS, 0, s>>>(L, p, cnt, c, sig, tkey, tval,
+                                                                 dest, mn, mc);
+            k_lv_conflict<<<lv_grid(cnt, LV_NODES), LV_BS, 0, s>>>(L, p, cnt, c, mn, mc, first);
+            k_lv_apply<<<lv_grid(cnt, LV_BS), LV_BS, 0, s>>>(L, p, cnt, first, dest, c, sig, mn,
+                                                             mc, mv);
+            int f = 0;
+            HIPCHK(hipMemcpyAsync(&f, first, sizeof(int), hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+            const i64 done = f < cnt ? f : cnt;
+            if (done < 1) throw SlmError{4, "Louvain chunk made no progress"};
+            p += done;
+            // chunk size: grow while whole chunks hold, shrink when they break early
+            if (done == cnt && B < 16384) B *= 2;
+            else if (done < cnt / 4 && B > 64) B /= 2;
+        }
+        read_scalars(W, (const i64 *)mv, 1, s);
+        const i64 moved = W.h_scal[0];
+        if (moved == 0) {
+            *converged = 1;
+            break;
+        }
+        *moves += moved;
+        passes++;
+    }
+    return passes;
+}

@@ -121,6 +121,10 @@ i64 components(Work &W, const i32 *a, i64 n, bool want_lab, hipStream_t s);
 
 // Canonical labels of the node-id community ids in W.comp; returns n_c.
 i64 canonical_labels(Work &W, i64 n, hipStream_t s);
+// Classical Louvain local moving of one level (k_louvain.hip): W.comp gets
+// the community names; returns the passes that moved a node.
+int louvain_level(Work &W, const LevelView &L, int max_passes, int *converged, i64 *moves,
+                  hipStream_t s);
 
 // POSITIVE (Sec. 3.3) on W.a (modified).  Expects W.comp / W.cyc from
 // components(); leaves W.lab canonical.  Returns splits; *nc = n_c.
