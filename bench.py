@@ -8,10 +8,17 @@ weights uniform 1-16), resident in HBM before the timed region.  The
 headline value is the throughput of the synchronous move sweep measured
 live with HIP events on the library's stream: CSR entries swept per second
 over every sweep of the timed steps (GTEPS).  After the timed steps the same
-line reports the batched run of the 2048-graph planted-partition family
-against the plain per-graph path (graphs/s) and a served Poisson mix with
-R-MAT scale-20 requests (p50/p99 latency), each measured outside the timed
-region.
+line reports, each measured outside the timed region:
+  - null_models: the same graph under the resolution (gamma = 1/2) and
+    Erdos-Renyi (p = 1/4000) null models of Sec. 2.2-2.3;
+  - louvain: the classical sequential Louvain method (exact sequential
+    result) against the Synchronised Louvain Method on the same graph;
+  - directed: a directed weighted LFR-shaped graph of the paper's experiments
+    (Table 1: 10^6 nodes, mean degree 50, max 100, mixing 0.5 / 0.4) under
+    the directed modularity of Sec. 2.4, with the oracle's sweep beside it;
+  - batch: the 2048-graph planted-partition family batched against the plain
+    per-graph path (graphs/s);
+  - serve: a served Poisson mix with R-MAT scale-20 requests (p50/p99).
 
 Prints one JSON line.  Usage: python bench.py [--steps K] [--warmup W]
 [--workload lfr4m|rmat20|sbm4096|batch2048|serve] [--no-extras]
@@ -434,6 +441,118 @@ def serve_bench(args):
     print(json.dumps(out), flush=True)
 
 
+def _run_timed(g, p, runs: int, louvain: bool = False):
+    """Full runs on a handle: one warm-up, then `runs` timed by the host
+    clock around synchronised runs, the sweeps timed by the library's HIP
+    events.  Returns (ms per run, sweep stats, last result)."""
+    import torch
+    run = g.louvain_run if louvain else g.run
+    run(p)
+    torch.cuda.synchronize()
+    g.timing(True)
+    g.timing_read()
+    t = time.perf_counter()
+    for _ in range(runs):
+        res = run(p)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t) * 1e3 / runs
+    tm = g.timing_read()
+    g.timing(False)
+    return ms, tm, res
+
+
+def _sweep_stats(tm):
+    sweep_s = tm["sweep_ms"] / 1e3
+    if sweep_s <= 0:
+        return dict(sweeps=tm["sweeps"], gteps=None, achieved_gbs=None, frac=None)
+    gbs = tm["bytes"] / sweep_s / 1e9
+    return dict(sweeps=tm["sweeps"], gteps=round(tm["entries"] / sweep_s / 1e9, 3),
+                achieved_gbs=round(gbs, 1), frac=round(gbs / HBM_PEAK_GBS, 4))
+
+
+def models_gpu(args, rp, col, w, cfg):
+    """The LFR-style 4M graph under the resolution and Erdos-Renyi null
+    models (Sec. 2.2-2.3): full-run time, sweep rate, levels and Q."""
+    import paper_1702_04645_amd as slm
+    out = {}
+    for name, kind, num, den in (("config_gamma_1_2", slm.MODEL_CONFIG, 1, 2),
+                                 ("er_p_1_4000", slm.MODEL_ER, 1, 4000)):
+        with slm.Graph(rp, col, w, validate=False, model=slm.model(kind, num, den)) as g:
+            ms, tm, res = _run_timed(g, slm.params(seed=args.seed), args.extra_runs)
+        out[name] = dict(model=dict(kind="config" if kind == slm.MODEL_CONFIG else "er",
+                                    num=num, den=den),
+                         ms_per_run=round(ms, 3), levels=len(res),
+                         final_q=res[-1].q if res else None,
+                         final_communities=res[-1].n_c if res else None,
+                         sweep=_sweep_stats(tm))
+        log("model %s: %.1f ms per run" % (name, ms))
+    out["workload"] = cfg["workload"]
+    return out
+
+
+def louvain_gpu(args, rp, col, w, cfg):
+    """Classical Louvain (the sequential comparison method, exact sequential
+    result) against the Synchronised Louvain Method on the same graph."""
+    import paper_1702_04645_amd as slm
+    p = slm.params(seed=args.seed)
+    with slm.Graph(rp, col, w, validate=False) as g:
+        ms_l, _, res_l = _run_timed(g, p, 1, louvain=True)
+        ms_s, _, res_s = _run_timed(g, p, args.extra_runs)
+    log("louvain: %.1f ms per run, slm %.1f ms" % (ms_l, ms_s))
+    return dict(workload=cfg["workload"], louvain_ms_per_run=round(ms_l, 3),
+                louvain_levels=len(res_l), louvain_passes=[r.rounds for r in res_l],
+                louvain_final_q=res_l[-1].q if res_l else None,
+                louvain_final_communities=res_l[-1].n_c if res_l else None,
+                slm_ms_per_run=round(ms_s, 3), slm_levels=len(res_s),
+                slm_final_q=res_s[-1].q if res_s else None,
+                slm_final_communities=res_s[-1].n_c if res_s else None)
+
+
+def _gen_directed(seed):
+    import graphgen as gg
+    return gg.config_graph("lfr1m_dir")
+
+
+def directed_cpu(rp, col, w, budget_s: float):
+    """The oracle's sweep under the directed model on the labels after its
+    own ASSIGN and POSITIVE, repeated for about budget_s seconds."""
+    import oracle
+    g = oracle.NullGraph(rp, col, w, oracle.DIRECTED, 1, 1)
+    a = oracle.assign_nm(g)
+    a, _ = oracle.positive_nm(g, a)
+    lab, nc, _ = oracle.components(a)
+    reps, t0 = 0, time.perf_counter()
+    while True:
+        oracle.sweep_nm(g, lab, nc)
+        reps += 1
+        el = time.perf_counter() - t0
+        if el >= budget_s:
+            break
+    return dict(value=int(g.rp[-1]) * reps / el / 1e9, unit="GTEPS", cores=1, kind="oracle",
+                cpu=cpu_model(), sample="%d oracle sweeps of S = W + W^T (%d entries), %.1f s"
+                % (reps, int(g.rp[-1]), el))
+
+
+def directed_gpu(args, rp, col, w, cpu):
+    """The directed weighted LFR-shaped graph of the paper's experiments
+    (Table 1: N = 10^6, mean degree 50, max 100, mixing 0.5 / 0.4) under the
+    directed modularity of Sec. 2.4."""
+    import paper_1702_04645_amd as slm
+    with slm.Graph(rp, col, w, validate=False,
+                   model=slm.model(slm.MODEL_DIRECTED, 1, 1)) as g:
+        info = g.level_info()
+        ms, tm, res = _run_timed(g, slm.params(seed=args.seed), args.extra_runs)
+    log("directed: %.1f ms per run" % ms)
+    out = dict(workload="lfr1m_dir", kind="LFR-style directed, weighted", nodes=rp.size - 1,
+               arcs=int(col.size), entries_of_s=info["nnz"], mean_degree=50, max_degree=100,
+               mixing=[0.5, 0.4], ms_per_run=round(ms, 3), levels=len(res),
+               final_q=res[-1].q if res else None,
+               final_communities=res[-1].n_c if res else None, sweep=_sweep_stats(tm))
+    if cpu:
+        out["cpu_baseline"] = cpu
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -449,6 +568,8 @@ def main():
     ap.add_argument("--serve-rate", type=float, default=400.0)
     ap.add_argument("--serve-lanes", type=int, default=4)
     ap.add_argument("--batch-steps", type=int, default=1)
+    ap.add_argument("--extra-runs", type=int, default=2,
+                    help="timed runs of each null-model, directed and Louvain measurement")
     ap.add_argument("--batch-warmup", type=int, default=1)
     ap.add_argument("--no-extras", action="store_true",
                     help="only the sweep line: no batched and served measurements")
@@ -484,12 +605,25 @@ def main():
     # everything that runs on host cores (generators, oracle pools) comes
     # before the GPU is touched
     extras = not args.no_extras
-    binp = batch_inputs(args) if extras else None
-    sinp = serve_inputs(args) if extras else None
     cpu = None
     if rank == 0 and not args.no_cpu:
         log("cpu baseline (oracle sweep, about %.0f s)" % args.cpu_seconds)
         cpu = cpu_baseline(rp, col, w, args.cpu_seconds)
+    dpool = dres = None
+    if extras:
+        import multiprocessing as mp
+        dpool = mp.get_context("fork").Pool(1)
+        dres = dpool.apply_async(_gen_directed, (0,))
+    binp = batch_inputs(args) if extras else None
+    sinp = serve_inputs(args) if extras else None
+    dgraph = dcpu = None
+    if extras:
+        dgraph = dres.get()
+        dpool.close()
+        dpool.join()
+        log("directed graph: %d nodes, %d arcs" % (dgraph[0].size - 1, dgraph[1].size))
+        if rank == 0 and not args.no_cpu:
+            dcpu = directed_cpu(*dgraph, 5.0)
 
     import torch
     import paper_1702_04645_amd as slm
@@ -559,7 +693,14 @@ def main():
     if cpu:
         out["cpu_baseline"] = cpu
     if extras:
+        log("null models")
+        out["null_models"] = models_gpu(args, rp, col, w, cfg)
+        log("classical Louvain")
+        out["louvain"] = louvain_gpu(args, rp, col, w, cfg)
         del rp, col, w
+        log("directed")
+        out["directed"] = directed_gpu(args, *dgraph, dcpu)
+        del dgraph
         log("batched run of the 2048-graph family")
         out["batch"], _ = batch_gpu(args, binp)
         del binp

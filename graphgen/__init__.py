@@ -29,14 +29,15 @@ import math
 import numpy as np
 
 __all__ = [
-    "rng", "csr_from_pairs", "sbm", "rmat", "lfr_style", "sbm_batch_sizes",
+    "rng", "csr_from_pairs", "sbm", "rmat", "lfr_style", "lfr_directed", "orient", "random_directed",
+    "sbm_batch_sizes",
     "sbm_batch_graph", "sbm_batch", "batch_member_seed", "cliques", "path", "star", "random_sparse", "CONFIG_SEEDS",
     "config_graph",
 ]
 
 # default seed of each named workload
 CONFIG_SEEDS = {"sbm4096": 0x5EED0000, "rmat20": 0x5EED0001, "lfr4m": 0x5EED0002,
-                "batch2048": 0x5EED0003, "serve": 0x5EED0004}
+                "batch2048": 0x5EED0003, "serve": 0x5EED0004, "lfr1m_dir": 0x5EED0005}
 
 
 def rng(seed: int) -> np.random.Generator:
@@ -251,6 +252,39 @@ def lfr_style(n: int, mean_deg: float, max_deg: int, deg_expo: float, comm_expo:
     return rp, col, w, comm.astype(np.int32)
 
 
+def lfr_directed(n: int, mean_deg: float, max_deg: int, mu_t: float, mu_w: float, seed: int,
+                 deg_expo: float = 2.1, comm_expo: float = 1.1, comm_min: int = 60,
+                 comm_max: int = 600, both: float = 0.25, w_max_in: int = 12):
+    """A weighted directed graph of the LFR shape: the undirected structure of
+    lfr_style (topological mixing mu_t), each edge kept as one arc in a random
+    direction or, with probability ``both``, as two arcs; arc weights uniform
+    in 1..w_max_in inside a community and in 1..w_max_out across, w_max_out
+    chosen so that the share of weight across communities is about mu_w.
+    Returns (row_ptr, col, w, community_of_node)."""
+    rp, col, _, comm = lfr_style(n, mean_deg, max_deg, deg_expo, comm_expo, comm_min, comm_max,
+                                 mu_t, 1, seed)
+    # mean external / mean internal weight = (mu_w / mu_t) / ((1 - mu_w) / (1 - mu_t))
+    ratio = (mu_w / mu_t) / ((1.0 - mu_w) / (1.0 - mu_t))
+    w_max_out = max(1, int(round(ratio * (w_max_in + 1) - 1)))
+    n = len(rp) - 1
+    u = np.repeat(np.arange(n, dtype=np.int64), np.diff(rp))
+    v = col.astype(np.int64)
+    up = u < v
+    u, v = u[up], v[up]
+    g = rng(seed + 1)
+    flip = g.random(u.size) < 0.5
+    two = g.random(u.size) < both
+    su = np.where(flip, v, u)
+    sv = np.where(flip, u, v)
+    uu = np.concatenate([su, sv[two]])
+    vv = np.concatenate([sv, su[two]])
+    inside = comm[uu] == comm[vv]
+    wt = np.where(inside, g.integers(1, w_max_in + 1, uu.size),
+                  g.integers(1, w_max_out + 1, uu.size))
+    rpd, cold, wd = csr_from_pairs(n, uu, vv, wt, symmetrise=False)
+    return rpd, cold, wd, comm
+
+
 def sbm_batch_sizes(count: int, n_lo: int, n_hi: int, seed: int):
     """Node counts log-uniform in [n_lo, n_hi] and block sizes uniform in
     16..256 for a batch of planted-partition graphs."""
@@ -293,6 +327,9 @@ def config_graph(name: str, seed: int | None = None):
         return rmat(20, 16, 0.57, 0.19, 0.19, s)
     if name == "lfr4m":
         rp, col, w, _ = lfr_style(4_000_000, 20.0, 2000, 2.5, 1.5, 20, 5000, 0.3, 16, s)
+        return rp, col, w
+    if name == "lfr1m_dir":
+        rp, col, w, _ = lfr_directed(1_000_000, 50.0, 100, 0.5, 0.4, s)
         return rp, col, w
     raise KeyError(name)
 
