@@ -466,8 +466,8 @@ static void alloc_work(slm_graph *g)
     W.src = dalloc<i32>(g, nnz);
     W.rk0 = dalloc<u64>(g, nnz);
     W.rk1 = dalloc<u64>(g, nnz);
-    W.rv0 = dalloc<i32>(g, nnz);
-    W.rv1 = dalloc<i32>(g, nnz);
+    W.rv0 = dalloc<i32>(g, nnz + 1);  // + 1: the segment starts of AGGREGATE
+    W.rv1 = dalloc<i32>(g, nnz + 1);
     W.cnt = dalloc<i32>(g, n);
     W.roff = dalloc<i64>(g, n + 1);
     W.head_e = dalloc<uint8_t>(g, nnz);

@@ -111,22 +111,43 @@ __global__ void k_seg_heads(const u64 *__restrict__ keys, i64 n, uint8_t *__rest
     FLAT_LOOP(n) head[j] = (j == 0 || keys[j] != keys[j - 1]) ? 1 : 0;
 }
 
-// Segment s = (number of heads up to j) - 1 gets the weight; heads write keys.
-__global__ void k_seg_sum(const u64 *__restrict__ keys, const i32 *__restrict__ w, i64 n,
-                          const uint8_t *__restrict__ head, const i64 *__restrict__ hpos,
-                          u64 *__restrict__ ukey, i32 *__restrict__ uw)
+// The head of segment s (record j, s = hpos[j]) writes the segment's key and
+// its first record; start[u] = n closes the last segment.
+__global__ void k_seg_starts(const u64 *__restrict__ keys, i64 n, const uint8_t *__restrict__ head,
+                             const i64 *__restrict__ hpos, i64 u, u64 *__restrict__ ukey,
+                             i32 *__restrict__ start)
 {
     FLAT_LOOP(n)
     {
-        i64 sidx = hpos[j] + head[j] - 1;
-        if (head[j]) ukey[sidx] = keys[j];
-        atomicAdd(&uw[sidx], w[j]);
+        if (head[j]) {
+            ukey[hpos[j]] = keys[j];
+            start[hpos[j]] = (i32)j;
+        }
     }
+    if (blockIdx.x == 0 && threadIdx.x == 0) start[u] = (i32)n;
 }
 
-__global__ void k_row_count(const u64 *__restrict__ ukey, i64 u, int bits, i32 *__restrict__ rc)
+// Weight of segment s from the exclusive prefix sums P of the sorted
+// records' weights: P[start[s+1]] - P[start[s]] (no atomics: equal keys are
+// adjacent after the sort).
+__global__ void k_seg_sums(const i64 *__restrict__ P, const i32 *__restrict__ start, i64 u,
+                           i32 *__restrict__ uw)
 {
-    FLAT_LOOP(u) atomicAdd(&rc[(i64)(ukey[j] >> bits)], 1);
+    FLAT_LOOP(u) uw[j] = (i32)(P[start[j + 1]] - P[start[j]]);
+}
+
+// Row offsets of the sorted unique keys: rp[r] = the first key whose row is
+// at least r.  Key j writes the rows after the previous key's row up to its
+// own (rows without an entry included); j = u closes the rows up to nrows.
+__global__ void k_row_ptr(const u64 *__restrict__ ukey, i64 u, int bits, i64 nrows,
+                          i64 *__restrict__ rp)
+{
+    for (i64 j = (i64)blockIdx.x * blockDim.x + threadIdx.x; j <= u;
+         j += (i64)gridDim.x * blockDim.x) {
+        const i64 r0 = j == 0 ? 0 : (i64)(ukey[j - 1] >> bits) + 1;
+        const i64 r1 = j == u ? nrows : (i64)(ukey[j] >> bits);
+        for (i64 r = r0; r <= r1; r++) rp[r] = j;
+    }
 }
 
 __global__ void k_emit_entries(const u64 *__restrict__ ukey, const i32 *__restrict__ uw, i64 u,
@@ -183,7 +204,9 @@ static i64 records_to_csr(Work &W, u64 *k, i32 *v, u64 *k2, i32 *v2, i64 recs, i
                           i64 nrows, i64 *rp_out, int2 *e_out, hipStream_t s)
 {
     if (recs > 0) radix_sort(W, k, v, k2, v2, recs, 2 * bits, s);
-    // merge equal keys: heads -> positions -> sums
+    // merge equal keys: heads -> segment starts and keys (into k2, v2) ->
+    // prefix sums of the weights (into rank_e, once the head positions are
+    // used) -> segment sums (into v)
     uint8_t *head = W.head_e;
     i64 *hpos = W.rank_e;
     i64 uniq = 0;
@@ -192,15 +215,14 @@ static i64 records_to_csr(Work &W, u64 *k, i32 *v, u64 *k2, i32 *v2, i64 recs, i
         launch_scan_u8(head, hpos, recs, W.scan_tmp, s);
         read_scalars(W, hpos + recs, 1, s);
         uniq = W.h_scal[0];
-        launch_fill_i32(v2, 0, uniq, s);
-        k_seg_sum<<<flat_grid(recs), SLM_BS, 0, s>>>(k, v, recs, head, hpos, k2, v2);
+        k_seg_starts<<<flat_grid(recs), SLM_BS, 0, s>>>(k, recs, head, hpos, uniq, k2, v2);
+        i64 *P = W.rank_e;
+        launch_scan_i32(v, P, recs, W.scan_tmp, s);
+        k_seg_sums<<<flat_grid(uniq), SLM_BS, 0, s>>>(P, v2, uniq, v);
     }
-    // rows of the result
-    i32 *rc = W.cnt;  // nrows <= n0
-    launch_fill_i32(rc, 0, nrows, s);
-    if (uniq > 0) k_row_count<<<flat_grid(uniq), SLM_BS, 0, s>>>(k2, uniq, bits, rc);
-    launch_scan_i32(rc, rp_out, nrows, W.scan_tmp, s);
-    if (uniq > 0) k_emit_entries<<<flat_grid(uniq), SLM_BS, 0, s>>>(k2, v2, uniq, bits, e_out);
+    // rows of the result (no atomics: the keys are sorted by row)
+    k_row_ptr<<<flat_grid(uniq + 1), SLM_BS, 0, s>>>(k2, uniq, bits, nrows, rp_out);
+    if (uniq > 0) k_emit_entries<<<flat_grid(uniq), SLM_BS, 0, s>>>(k2, v, uniq, bits, e_out);
     return uniq;
 }
 
