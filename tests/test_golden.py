@@ -2,6 +2,7 @@
 the committed oracle computes (checked on a sample of the batch members,
 which the oracle runs in seconds)."""
 import hashlib
+import os
 
 import numpy as np
 
@@ -44,3 +45,21 @@ def test_lfr4m_golden_is_well_formed():
     assert all(b[2] >= a[2] for a, b in zip(lv, lv[1:]))
     assert all(b[0] < a[0] for a, b in zip(lv, lv[1:]))
     assert np.all(rows[:, 2] <= rows[:, 1]) and np.all(rows[:, 3] <= rows[:, 2])
+
+
+def test_more_full_size_goldens_are_well_formed():
+    """The stored directed LFR-1M run and the LFR-4M runs under the resolution
+    and Erdos-Renyi models and with classical Louvain: per run, communities
+    only merge, Q never decreases, at most 64 rounds, and one hash a level."""
+    from test_gpu_goldens_more import read_levels
+    here = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+    runs = read_levels(os.path.join(here, "lfr1m_dir_seed1_levels.txt"))
+    runs.update(read_levels(os.path.join(here, "lfr4m_models_levels.txt"), named=True))
+    assert sorted(runs) == ["", "config_1_2", "er_1_4000", "louvain"]
+    for name, lv in runs.items():
+        assert len(lv) >= 2, name
+        assert all(b[0] < a[0] for a, b in zip(lv, lv[1:])), name
+        assert all(b[2] >= a[2] and b[1] >= a[1] for a, b in zip(lv, lv[1:])), name
+        assert all(0 <= x[3] <= 64 and 0 < x[2] < 1 for x in lv), name
+        assert all(len(x[5]) == 64 and int(x[5], 16) >= 0 for x in lv), name
+        assert lv[-1][4], name  # the last level converged
