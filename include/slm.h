@@ -404,6 +404,12 @@ slm_status slm_timing_read(slm_graph *g, double *sweep_ms, int64_t *sweeps,
  *                         0..65535 (0: the default);
  *   "fanout_min_entries"  the degree bins run on the handle's side streams at
  *                         levels of at least this many entries (default 2^22).
+ *   "union_shrink_min_nodes"  batch handles only: a union of at least this many
+ *                         nodes shrinks, within a level, to its graphs that
+ *                         still move once the others (no valid move in their
+ *                         last round: their state is final for the level) hold
+ *                         half of its nodes (default 2^16; 0: any size; < 0:
+ *                         never).
  * Results never depend on these.  Takes effect from the next sweep.
  * SLM_E_INVALID for an unknown name or a value out of range (nothing
  * changes). */

@@ -111,6 +111,11 @@ struct slm_graph {
     u64 *d_gseed = nullptr;
     i32 *d_glev = nullptr, *d_newpos = nullptr;
     i32 *lab2 = nullptr;
+    // shrinking a union within a level to the graphs that still move
+    SubMember *d_sub = nullptr;
+    SaveMember *d_save = nullptr;
+    i64 *d_lbn = nullptr, *d_rpb = nullptr;
+    i64 shrink_min = (i64)1 << 16;  // fewest union nodes worth a shrink (< 0: never)
 };
 
 // ------------------------------------------------------------------ helpers
@@ -742,6 +747,10 @@ static void alloc_union(slm_graph *g, int P_cap)
     g->d_gseed = dalloc<u64>(g, P_cap);
     g->d_glev = dalloc<i32>(g, P_cap);
     g->d_newpos = dalloc<i32>(g, P_cap);
+    g->d_sub = dalloc<SubMember>(g, P_cap + 1);
+    g->d_save = dalloc<SaveMember>(g, P_cap);
+    g->d_lbn = dalloc<i64>(g, P_cap + 1);
+    g->d_rpb = dalloc<i64>(g, P_cap + 1);
 }
 
 // Per-node position and M2 of the members at positions [p0, G).
@@ -807,6 +816,164 @@ static void union_append(slm_graph *g, std::vector<Member> &add)
     union_meta(g, p0, g->gidL[g->cur], g->m2nL[g->cur]);
 }
 
+// ------------------------------------------------------- shrinking a union
+// A member whose round finds no valid move keeps its state for the rest of
+// the level (nothing is accepted, so the next round sees the same labels and
+// finds no valid move again).  Once such members hold most of the union's
+// nodes, the level goes on in a union of the others: their CSR and round
+// state (assignment, labels, cycle marks) are gathered into a free level
+// buffer, with every node, entry and label range shifted by its member's new
+// base, so local node numbers, draws and the order of labels within a member
+// are those of the full union.  At the end of the level every member's labels
+// are put back in the full union's numbering.
+struct UnionCut {
+    bool on = false;
+    int full_cur = 0;
+    i64 full_n = 0, full_nnz = 0;
+    std::vector<int> fpos;   // position in the current union -> in the full one
+    std::vector<i64> ubase;  // node ranges of the current union's members
+    std::vector<i64> ncq;    // per full position: its communities, once saved
+};
+
+// First label of every member of the current union (labels are canonical, so
+// a member's are contiguous and start at its first node's), and nc at the end.
+static std::vector<i64> union_label_bases(slm_graph *g, int Gc, i64 nc)
+{
+    std::vector<i64> first;
+    batch_first_labels(g->W.lab, g->d_gbase, Gc, g->d_first, g->s);
+    to_host(first, g->d_first, Gc, g->s);
+    std::vector<i64> gcb(Gc + 1);
+    gcb[Gc] = nc;
+    for (int q = Gc - 1; q >= 0; q--) gcb[q] = first[q] >= 0 ? first[q] : gcb[q + 1];
+    return gcb;
+}
+
+// Every member's labels, less its first label, into g->lab2 at the nodes'
+// ids in the full union, and its community count into cut.ncq.
+static void union_save(slm_graph *g, UnionCut &cut, const std::vector<i64> &gcb)
+{
+    const int Gc = (int)cut.fpos.size();
+    std::vector<SaveMember> sv(Gc);
+    for (int q = 0; q < Gc; q++) {
+        sv[q] = SaveMember{cut.ubase[q], gcb[q], g->base[cut.fpos[q]]};
+        cut.ncq[cut.fpos[q]] = gcb[q + 1] - gcb[q];
+    }
+    hipStream_t s = g->s;
+    HIPCHK(hipMemcpyAsync(g->d_save, sv.data(), sizeof(SaveMember) * Gc, hipMemcpyHostToDevice, s));
+    const int c = g->cur < 0 ? 2 : g->cur;
+    batch_sub_save(g->gidL[c], g->n, g->W.lab, g->d_save, g->lab2, s);
+    HIPCHK(hipStreamSynchronize(s));  // sv is freed on return
+}
+
+// The current union shrinks to the members with moving[q] set, into level
+// buffer `target`; *nc becomes the shrunk union's community count.
+static void union_shrink(slm_graph *g, UnionCut &cut, const std::vector<char> &moving, int target,
+                         i64 *nc)
+{
+    hipStream_t s = g->s;
+    Work &W = g->W;
+    const int Gc = (int)cut.fpos.size();
+    if (!cut.on) {
+        cut.on = true;
+        cut.full_cur = g->cur;
+        cut.full_n = g->n;
+        cut.full_nnz = g->nnz;
+        cut.ncq.assign(g->G, 0);
+    }
+    const std::vector<i64> gcb = union_label_bases(g, Gc, *nc);
+    union_save(g, cut, gcb);
+    const i64 *rp_u = g->cur < 0 ? g->rp0 : g->rpL[g->cur];
+    const int2 *e_u = g->cur < 0 ? g->e0 : g->eL[g->cur];
+    std::vector<i64> erb;
+    batch_member_rows(rp_u, g->d_gbase, Gc, g->d_rpb, s);
+    to_host(erb, g->d_rpb, Gc + 1, s);
+    std::vector<SubMember> sm;
+    std::vector<int> fpos2;
+    std::vector<i64> base2(1, 0), m2;
+    std::vector<u64> sd;
+    std::vector<i32> lv;
+    i64 nn = 0, ne = 0, nl = 0, maxn = 0;
+    for (int q = 0; q < Gc; q++) {
+        if (!moving[q]) continue;
+        const i64 dn = cut.ubase[q + 1] - cut.ubase[q];
+        sm.push_back(SubMember{nn, ne, nl, cut.ubase[q], erb[q], gcb[q]});
+        nn += dn;
+        ne += erb[q + 1] - erb[q];
+        nl += gcb[q + 1] - gcb[q];
+        maxn = std::max(maxn, dn);
+        fpos2.push_back(cut.fpos[q]);
+        base2.push_back(nn);
+        const Member &m = g->mem[cut.fpos[q]];
+        sd.push_back(m.seed);
+        lv.push_back(m.level);
+        m2.push_back(m.m2);
+    }
+    sm.push_back(SubMember{nn, ne, nl, 0, 0, 0});
+    const int G2 = (int)fpos2.size();
+    HIPCHK(hipMemcpyAsync(g->d_sub, sm.data(), sizeof(SubMember) * (G2 + 1), hipMemcpyHostToDevice, s));
+    batch_sub_gather(g->d_sub, G2, nn, ne, rp_u, e_u, W.a, W.lab, W.cyc, g->rpL[target],
+                     g->eL[target], W.A0, W.A1, W.exam, s);
+    HIPCHK(hipMemcpyAsync(W.a, W.A0, sizeof(i32) * nn, hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipMemcpyAsync(W.lab, W.A1, sizeof(i32) * nn, hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipMemcpyAsync(W.cyc, W.exam, nn, hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipMemcpyAsync(g->d_gbase, base2.data(), sizeof(i64) * (G2 + 1), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(g->d_gseed, sd.data(), sizeof(u64) * G2, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(g->d_glev, lv.data(), sizeof(i32) * G2, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(g->d_m2p, m2.data(), sizeof(i64) * G2, hipMemcpyHostToDevice, s));
+    batch_meta(g->d_gbase, 0, G2, g->d_m2p, maxn, g->gidL[target], g->m2nL[target], s);
+    HIPCHK(hipStreamSynchronize(s));  // the host vectors are freed on return
+    g->cur = target;
+    g->n = nn;
+    g->nnz = ne;
+    setup_level(g);
+    cut.fpos = std::move(fpos2);
+    cut.ubase = std::move(base2);
+    *nc = nl;
+}
+
+// After a round: shrink when the members still moving hold at most half of
+// the union's nodes and a level buffer is free (both while the full union is
+// in the level-0 arrays, the other one otherwise, so once per level then).
+static void union_maybe_shrink(slm_graph *g, UnionCut &cut, const std::vector<i32> &rounds, i64 *nc)
+{
+    if (g->shrink_min < 0 || g->n < g->shrink_min) return;
+    const int Gc = (int)cut.fpos.size();
+    std::vector<char> moving(Gc, 0);
+    i64 act = 0;
+    for (int q = 0; q < Gc; q++) {
+        moving[q] = rounds[cut.fpos[q]] < 0;
+        if (moving[q]) act += cut.ubase[q + 1] - cut.ubase[q];
+    }
+    if (act == 0 || 2 * act > g->n) return;
+    const int full = cut.on ? cut.full_cur : g->cur;
+    int target;
+    if (full < 0) target = g->cur == 0 ? 1 : 0;
+    else if (!cut.on) target = 1 - g->cur;
+    else return;
+    union_shrink(g, cut, moving, target, nc);
+}
+
+// Back to the full union, with every member's labels in its numbering.
+static void union_unshrink(slm_graph *g, UnionCut &cut, i64 *nc)
+{
+    hipStream_t s = g->s;
+    const std::vector<i64> gcb = union_label_bases(g, (int)cut.fpos.size(), *nc);
+    union_save(g, cut, gcb);
+    g->cur = cut.full_cur;
+    g->n = cut.full_n;
+    g->nnz = cut.full_nnz;
+    union_upload(g);
+    setup_level(g);
+    std::vector<i64> lb(g->G + 1, 0);
+    for (int q = 0; q < g->G; q++) lb[q + 1] = lb[q] + cut.ncq[q];
+    HIPCHK(hipMemcpyAsync(g->d_lbn, lb.data(), sizeof(i64) * (g->G + 1), hipMemcpyHostToDevice, s));
+    const int c = g->cur < 0 ? 2 : g->cur;
+    batch_sub_restore(g->gidL[c], g->n, g->lab2, g->d_lbn, g->W.lab, s);
+    HIPCHK(hipStreamSynchronize(s));
+    *nc = lb[g->G];
+    cut.on = false;
+}
+
 // One level of Algorithm 1 for every member of the union, all in the same
 // launches.  Member q draws with its own seed and level; its keys use its own
 // M2.  A member whose round finds no valid move is unchanged by the rounds
@@ -829,19 +996,28 @@ static void union_level(slm_graph *g, const slm_params *p, std::vector<Member> &
     level_start(g, &nc);
     std::vector<i32> rounds(G, -1), conv(G, 0);
     std::vector<i64> hv, first, accI, accS;
+    UnionCut cut;
+    cut.fpos.resize(G);
+    for (int q = 0; q < G; q++) cut.fpos[q] = q;
+    cut.ubase = g->base;
     int r = 0;
     while (r < p->max_rounds) {
-        launch_fill_i64(g->d_gvalid, 0, G, s);
+        const int Gc = (int)cut.fpos.size();
+        launch_fill_i64(g->d_gvalid, 0, Gc, s);
         const i64 valid = level_round(g, p, 0, r, &nc, nullptr, (unsigned long long *)g->d_gvalid);
-        to_host(hv, g->d_gvalid, G, s);
-        for (int q = 0; q < G; q++)
-            if (rounds[q] < 0 && hv[q] == 0) {
-                rounds[q] = r;
-                conv[q] = 1;
+        to_host(hv, g->d_gvalid, Gc, s);
+        for (int q = 0; q < Gc; q++) {
+            const int f = cut.fpos[q];
+            if (rounds[f] < 0 && hv[q] == 0) {
+                rounds[f] = r;
+                conv[f] = 1;
             }
+        }
         if (valid == 0) break;
         r++;
+        if (r < p->max_rounds) union_maybe_shrink(g, cut, rounds, &nc);
     }
+    if (cut.on) union_unshrink(g, cut, &nc);
     for (int q = 0; q < G; q++)
         if (rounds[q] < 0) rounds[q] = r;
     batch_first_labels(W.lab, g->d_gbase, G, g->d_first, s);
@@ -1528,6 +1704,9 @@ slm_status slm_set_option(slm_graph *g, const char *name, int64_t value)
         REQUIRE(b >= 0, SLM_E_INVALID, "grid_<d> needs d in 64..4096, a bin's largest degree");
         REQUIRE(value >= 0 && value <= 65535, SLM_E_INVALID, "grid_<d> must be in 0..65535");
         g->bins.grid_cap[b] = (i32)value;
+    } else if (k == "union_shrink_min_nodes") {
+        REQUIRE(g->is_union, SLM_E_INVALID, "union_shrink_min_nodes applies to batch handles");
+        g->shrink_min = value;
     } else if (k == "fanout_min_entries") {
         REQUIRE(value >= 0, SLM_E_INVALID, "fanout_min_entries must be >= 0");
         g->W.fan.min_entries = value;

@@ -4,7 +4,8 @@
 // are those of a run on its own.  These kernels move the per-graph
 // bookkeeping between levels: the first label of every graph, the removal of
 // finished graphs before AGGREGATE (with the renumbering of the graphs that
-// stay), and the per-node graph data of graphs joining the union.
+// stay), the per-node graph data of graphs joining the union, and the
+// shrinking of a union to the graphs that still move within a level.
 #include "slm_forest.h"
 
 #define FLAT_LOOP(n)                                                                  \
@@ -91,4 +92,103 @@ void batch_meta(const i64 *gbase, int p0, int count, const i64 *m2p, i64 max_nod
         dim3 grid((unsigned)gx, (unsigned)cnt);
         k_batch_meta<<<grid, SLM_BS, 0, s>>>(gbase, p0 + c0, cnt, m2p, gid, m2n);
     }
+}
+
+// Record of sm whose range [F(q), F(q+1)) holds j, F = nb_s (FIELD 0) or
+// eb_s (FIELD 1); F(0) = 0 <= j < F(G).  Records with empty ranges are never
+// returned.
+template <int FIELD>
+__device__ __forceinline__ int sub_find(const SubMember *__restrict__ sm, int G, i64 j)
+{
+    int lo = 0, hi = G;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        const i64 f = FIELD == 0 ? sm[mid].nb_s : sm[mid].eb_s;
+        if (f <= j) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+__global__ void k_member_rows(const i64 *__restrict__ rp, const i64 *__restrict__ gbase, int G,
+                              i64 *__restrict__ out)
+{
+    FLAT_LOOP((i64)G + 1) out[j] = rp[gbase[j]];
+}
+
+// Node j of the shrunk union is node j - nb_s + nb_u of its graph's union;
+// row offsets, pointers and labels move with the graph's bases.
+__global__ void k_sub_nodes(const SubMember *__restrict__ sm, int G, i64 n_s,
+                            const i64 *__restrict__ rp_u, const i32 *__restrict__ a_u,
+                            const i32 *__restrict__ lab_u, const uint8_t *__restrict__ cyc_u,
+                            i64 *__restrict__ rp_s, i32 *__restrict__ a_s,
+                            i32 *__restrict__ lab_s, uint8_t *__restrict__ cyc_s)
+{
+    FLAT_LOOP(n_s)
+    {
+        const SubMember m = sm[sub_find<0>(sm, G, j)];
+        const i64 v = j - m.nb_s + m.nb_u;
+        rp_s[j] = rp_u[v] - m.eb_u + m.eb_s;
+        a_s[j] = (i32)(a_u[v] - m.nb_u + m.nb_s);
+        lab_s[j] = (i32)(lab_u[v] - m.lb_u + m.lb_s);
+        cyc_s[j] = cyc_u[v];
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) rp_s[n_s] = sm[G].eb_s;
+}
+
+// Entries keep their weight; a column moves with its graph's node base (an
+// entry never leaves its graph).
+__global__ void k_sub_entries(const SubMember *__restrict__ sm, int G, i64 e_s,
+                              const int2 *__restrict__ e_u, int2 *__restrict__ e_out)
+{
+    FLAT_LOOP(e_s)
+    {
+        const SubMember m = sm[sub_find<1>(sm, G, j)];
+        const int2 ed = e_u[j - m.eb_s + m.eb_u];
+        e_out[j] = make_int2((i32)(ed.x - m.nb_u + m.nb_s), ed.y);
+    }
+}
+
+__global__ void k_sub_save(const i32 *__restrict__ gid, i64 n, const i32 *__restrict__ lab,
+                           const SaveMember *__restrict__ sv, i32 *__restrict__ saved)
+{
+    FLAT_LOOP(n)
+    {
+        const SaveMember m = sv[gid[j]];
+        saved[j - m.nb_u + m.nb_f] = (i32)(lab[j] - m.lb_u);
+    }
+}
+
+__global__ void k_sub_restore(const i32 *__restrict__ gid, i64 n, const i32 *__restrict__ saved,
+                              const i64 *__restrict__ lbase, i32 *__restrict__ lab)
+{
+    FLAT_LOOP(n) lab[j] = (i32)(saved[j] + lbase[gid[j]]);
+}
+
+void batch_member_rows(const i64 *rp, const i64 *gbase, int G, i64 *out, hipStream_t s)
+{
+    k_member_rows<<<flat_grid((i64)G + 1), SLM_BS, 0, s>>>(rp, gbase, G, out);
+}
+
+void batch_sub_gather(const SubMember *sm, int G, i64 n_s, i64 e_s, const i64 *rp_u,
+                      const int2 *e_u, const i32 *a_u, const i32 *lab_u, const uint8_t *cyc_u,
+                      i64 *rp_s, int2 *e_s_out, i32 *a_s, i32 *lab_s, uint8_t *cyc_s,
+                      hipStream_t s)
+{
+    if (G <= 0) return;
+    k_sub_nodes<<<flat_grid(n_s), SLM_BS, 0, s>>>(sm, G, n_s, rp_u, a_u, lab_u, cyc_u, rp_s, a_s,
+                                                  lab_s, cyc_s);
+    if (e_s > 0) k_sub_entries<<<flat_grid(e_s), SLM_BS, 0, s>>>(sm, G, e_s, e_u, e_s_out);
+}
+
+void batch_sub_save(const i32 *gid, i64 n, const i32 *lab, const SaveMember *sv, i32 *saved,
+                    hipStream_t s)
+{
+    if (n > 0) k_sub_save<<<flat_grid(n), SLM_BS, 0, s>>>(gid, n, lab, sv, saved);
+}
+
+void batch_sub_restore(const i32 *gid, i64 n, const i32 *saved, const i64 *lbase, i32 *lab,
+                       hipStream_t s)
+{
+    if (n > 0) k_sub_restore<<<flat_grid(n), SLM_BS, 0, s>>>(gid, n, saved, lbase, lab);
 }

@@ -174,3 +174,32 @@ void batch_relabel(const i32 *lab, const i32 *gid, const i32 *m2n, const i64 *sh
                    const i32 *newpos, i64 n, i32 *lab2, i32 *gid2, i32 *m2n2, hipStream_t s);
 void batch_meta(const i64 *gbase, int p0, int count, const i64 *m2p, i64 max_nodes, i32 *gid,
                 i32 *m2n, hipStream_t s);
+
+// A union shrunk to the graphs that still move during a level: one record per
+// kept graph (its first node, entry and label in the shrunk union and in the
+// union it comes from), then a closing record whose nb_s / eb_s / lb_s are
+// the shrunk union's node, entry and label counts.
+struct SubMember {
+    i64 nb_s, eb_s, lb_s;
+    i64 nb_u, eb_u, lb_u;
+};
+// Per graph of a union: its first node and first label there, and its first
+// node in the union the level started with.
+struct SaveMember {
+    i64 nb_u, lb_u, nb_f;
+};
+// out[q] = rp[gbase[q]] for q = 0..G.
+void batch_member_rows(const i64 *rp, const i64 *gbase, int G, i64 *out, hipStream_t s);
+// The shrunk union's CSR (rp_s, e_s) and round state (a_s, lab_s, cyc_s) from
+// the union's, for the G records of sm.
+void batch_sub_gather(const SubMember *sm, int G, i64 n_s, i64 e_s, const i64 *rp_u,
+                      const int2 *e_u, const i32 *a_u, const i32 *lab_u, const uint8_t *cyc_u,
+                      i64 *rp_s, int2 *e_s_out, i32 *a_s, i32 *lab_s, uint8_t *cyc_s,
+                      hipStream_t s);
+// saved[node's id in the starting union] = its label minus its graph's first
+// label, for the n nodes of a union (gid: per node, its graph's position).
+void batch_sub_save(const i32 *gid, i64 n, const i32 *lab, const SaveMember *sv, i32 *saved,
+                    hipStream_t s);
+// lab[v] = saved[v] + lbase[gid[v]] over the starting union's n nodes.
+void batch_sub_restore(const i32 *gid, i64 n, const i32 *saved, const i64 *lbase, i32 *lab,
+                       hipStream_t s);

@@ -61,6 +61,37 @@ def test_batch_mixed_members(slm):
             _compare(res2[i], oracle.run(*members[i], seed=seeds[i]), ("again", i))
 
 
+@pytest.mark.parametrize("rounds,levels", [(64, 0), (5, 0), (64, 2)])
+def test_batch_union_shrinks(slm, rounds, levels):
+    """With no size floor the union shrinks to its members that still move
+    after every round that lets it (several times at level 0, once per later
+    level): each member still equals its oracle run alone."""
+    members = _mixed_members() + gg.sbm_batch(24, 64, 4096, 77)
+    seeds = [3 + 5 * i for i in range(len(members))]
+    p = slm.params(max_rounds=rounds, max_levels=levels)
+    say("batch shrink", len(members), rounds, levels)
+    with slm.Batch(members) as b:
+        b.set_option("union_shrink_min_nodes", 0)
+        for rep in range(2):
+            res = b.run(p, seeds=seeds)
+            for i, (rp, col, w) in enumerate(members):
+                _compare(res[i], oracle.run(rp, col, w, seed=seeds[i], max_rounds=rounds,
+                                            max_levels=levels), (rep, i))
+
+
+def test_union_shrink_option(slm):
+    rp, col, w = gg.sbm(200, 10, 0.3, 0.02, 3)
+    with slm.Graph(rp, col, w) as g:
+        with pytest.raises(slm.SlmError) as e:
+            g.set_option("union_shrink_min_nodes", 0)
+        assert e.value.status == slm.SLM_E_INVALID
+    with slm.Batch([(rp, col, w)] * 3) as b:
+        b.set_option("union_shrink_min_nodes", -1)
+        res = b.run(slm.params(seed=2))
+    for i in range(3):
+        _compare(res[i], oracle.run(rp, col, w, seed=2), i)
+
+
 @pytest.mark.parametrize("acc,rounds,levels", [(1 << 32, 64, 0), (1 << 31, 2, 0),
                                                (1 << 31, 64, 1), (1 << 30, 3, 2)])
 def test_batch_parameters(slm, acc, rounds, levels):
