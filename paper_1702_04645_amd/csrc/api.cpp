@@ -257,12 +257,10 @@ static void setup_level(slm_graph *g)
     const int2 *e = g->cur < 0 ? g->e0 : g->eL[g->cur];
     for (int b = 0; b <= NBINS; b++) B.off[b] = 0;
     if (n > 0) {
-        launch_fill_i64(W.counters, 0, NBINS, s);
-        launch_bin_count(rp, n, W.counters, s);
-        read_scalars(W, W.counters, NBINS, s);
-        for (int b = 0; b < NBINS; b++) B.off[b + 1] = B.off[b] + W.h_scal[b];
-        HIPCHK(hipMemcpyAsync(W.counters, B.off, sizeof(i64) * NBINS, hipMemcpyHostToDevice, s));
-        launch_bin_scatter(rp, n, W.counters, B.nodes, s);
+        grow_buf(g, W.bscan, W.bscan_cap, bin_scan_elems(n));
+        launch_bins(rp, n, W.bscan, W.counters, B.nodes, s);
+        read_scalars(W, W.counters, NBINS + 1, s);
+        for (int b = 0; b <= NBINS; b++) B.off[b] = W.h_scal[b];
         launch_rowdesc(B.nodes, rp, n, B.rowd, s);
         const i64 nhub = B.off[BIN_HUB + 1] - B.off[BIN_HUB];
         B.nhub = (i32)nhub;
@@ -1164,6 +1162,7 @@ void slm_destroy(slm_graph *g)
     DevMem &dm = g->dm;
     dm.put(W.W, sizeof(i64) * W.W_cap);
     dm.put(W.hist, sizeof(i64) * 2 * W.hist_cap);
+    dm.put(W.bscan, sizeof(i64) * W.bscan_cap);
     dm.put(W.hub_part, sizeof(int2) * W.hub_part_cap);
     dm.put(W.hub_poff, sizeof(i64) * W.hub_poff_cap);
     dm.put(W.hub_cwin, sizeof(i32) * W.hub_cwin_cap);

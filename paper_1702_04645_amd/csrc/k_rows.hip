@@ -109,7 +109,7 @@ template <int G> __device__ __forceinline__ int gscan(int v, int &total, i64 *re
 template <int G>
 __global__ __launch_bounds__(GroupGeom<G>::BSZ) void k_strength(
     const i64 *__restrict__ rp, const int2 *__restrict__ e, const i32 *__restrict__ nodes,
-    i64 count, i32 *__restrict__ k, i32 *__restrict__ diag, i64 *__restrict__ m2_acc)
+    i64 count, i32 *__restrict__ k, i32 *__restrict__ diag)
 {
     __shared__ i64 red[32];
     GROUP_PROLOGUE(G)
@@ -123,13 +123,23 @@ __global__ __launch_bounds__(GroupGeom<G>::BSZ) void k_strength(
     }
     s = gsum<G>(s, red);
     d = gsum<G>(d, red);
-    i64 contrib = (valid && gl == 0) ? s : 0;
     if (valid && gl == 0) {
         k[node] = (i32)s;
         diag[node] = (i32)d;
     }
-    contrib = block_sum<i64>(contrib, red);
-    if (threadIdx.x == 0 && contrib) atomicAdd((unsigned long long *)m2_acc, (unsigned long long)contrib);
+}
+
+// *acc += sum of k[0..n): a bounded grid, one atomic per workgroup.
+__global__ __launch_bounds__(SLM_BS) void k_sum_i32(const i32 *__restrict__ k, i64 n,
+                                                   i64 *__restrict__ acc)
+{
+    __shared__ i64 red[SLM_BS / 64];
+    i64 t = 0;
+    for (i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (i64)gridDim.x * blockDim.x)
+        t += k[i];
+    t = block_sum<i64>(t, red);
+    if (threadIdx.x == 0 && t) atomicAdd((unsigned long long *)acc, (unsigned long long)t);
 }
 
 // ------------------------------------------------------------------ ASSIGN / re-point
@@ -366,7 +376,7 @@ __global__ __launch_bounds__(SLM_BS) void k_hub_zero(const i32 *__restrict__ hub
 __global__ __launch_bounds__(SLM_BS) void k_hub_strength(
     const i64 *__restrict__ rp, const int2 *__restrict__ e, const i32 *__restrict__ hub_node,
     const i32 *__restrict__ chunk_hub, const i64 *__restrict__ chunk_beg, i32 *__restrict__ k,
-    i32 *__restrict__ diag, i64 *__restrict__ m2_acc)
+    i32 *__restrict__ diag)
 {
     __shared__ i64 red[32];
     const i32 h = chunk_hub[blockIdx.x];
@@ -385,7 +395,6 @@ __global__ __launch_bounds__(SLM_BS) void k_hub_strength(
     if (threadIdx.x == 0) {
         atomicAdd(&k[node], (i32)s);
         if (d) atomicAdd(&diag[node], (i32)d);
-        atomicAdd((unsigned long long *)m2_acc, (unsigned long long)s);
     }
 }
 
@@ -522,17 +531,27 @@ __device__ __forceinline__ int bin_of_degree(i64 d)
     return BIN_HUB;
 }
 
+// Bins are filled without global atomics and in increasing node order: per
+// workgroup of SLM_BS nodes, the count of each bin (bin-major:
+// cnt[b * nblk + workgroup]); an exclusive scan of these counts gives every
+// workgroup's first slot in every bin.
 __global__ __launch_bounds__(SLM_BS) void k_bin_count(const i64 *__restrict__ rp, i64 n,
-                                                     i64 *__restrict__ bin_cnt)
+                                                     i64 nblk, i64 *__restrict__ cnt)
 {
-    __shared__ int cnt[NBINS];
-    if (threadIdx.x < NBINS) cnt[threadIdx.x] = 0;
+    __shared__ int c[NBINS];
+    if (threadIdx.x < NBINS) c[threadIdx.x] = 0;
     __syncthreads();
-    i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) atomicAdd(&cnt[bin_of_degree(rp[i + 1] - rp[i])], 1);
+    const i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) atomicAdd(&c[bin_of_degree(rp[i + 1] - rp[i])], 1);
     __syncthreads();
-    if (threadIdx.x < NBINS && cnt[threadIdx.x])
-        atomicAdd((unsigned long long *)&bin_cnt[threadIdx.x], (unsigned long long)cnt[threadIdx.x]);
+    if (threadIdx.x < NBINS) cnt[threadIdx.x * nblk + blockIdx.x] = c[threadIdx.x];
+}
+
+// off[b] = first slot of bin b (from the scanned counts), off[NBINS] = n.
+__global__ void k_bin_bounds(const i64 *__restrict__ scanned, i64 nblk, i64 *__restrict__ off)
+{
+    const int b = threadIdx.x;
+    if (b <= NBINS) off[b] = scanned[(i64)b * nblk];
 }
 
 // Row descriptors in bin order: one coalesced load gives a row its node, its
@@ -557,26 +576,27 @@ void launch_rowdesc(const i32 *nodes, const i64 *rp, i64 n, int4 *rowd, hipStrea
     k_rowdesc<<<(unsigned)g, SLM_BS, 0, s>>>(nodes, rp, n, rowd);
 }
 
-// bin_fill[b] starts at the bin's offset; waves reserve runs of consecutive ids.
+// Node i goes to slot scanned[b * nblk + workgroup] + (its rank among the
+// workgroup's nodes of bin b).
 __global__ __launch_bounds__(SLM_BS) void k_bin_scatter(const i64 *__restrict__ rp, i64 n,
-                                                       i64 *__restrict__ bin_fill,
+                                                       i64 nblk, const i64 *__restrict__ scanned,
                                                        i32 *__restrict__ bin_nodes)
 {
-    i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+    constexpr int NW = SLM_BS / 64;
+    __shared__ int wc[NBINS][NW];
+    const i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x;
     const int b = i < n ? bin_of_degree(rp[i + 1] - rp[i]) : -1;
-    const int lane = threadIdx.x & 63;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x / 64;
+    int rank = 0;
     for (int bb = 0; bb < NBINS; bb++) {
-        u64 mask = __ballot(b == bb);
-        if (!mask) continue;
-        const int leader = __ffsll((unsigned long long)mask) - 1;
-        i64 base = 0;
-        if (lane == leader)
-            base = (i64)atomicAdd((unsigned long long *)&bin_fill[bb], (unsigned long long)__popcll(mask));
-        base = __shfl(base, leader, 64);
-        if (b == bb) {
-            const u64 below = mask & ((1ull << lane) - 1ull);
-            bin_nodes[base + __popcll(below)] = (i32)i;
-        }
+        const u64 mask = __ballot(b == bb);
+        if (lane == 0) wc[bb][wid] = __popcll(mask);
+        if (b == bb) rank = __popcll(mask & ((1ull << lane) - 1ull));
+    }
+    __syncthreads();
+    if (b >= 0) {
+        for (int w = 0; w < wid; w++) rank += wc[b][w];
+        bin_nodes[scanned[(i64)b * nblk + blockIdx.x] + rank] = (i32)i;
     }
 }
 
@@ -591,13 +611,21 @@ __global__ void k_hub_degrees(const i64 *__restrict__ rp, const i32 *__restrict_
     }
 }
 
-void launch_bin_count(const i64 *rp, i64 n, i64 *bin_cnt, hipStream_t s)
+i64 bin_scan_elems(i64 n)
 {
-    if (n > 0) k_bin_count<<<grid_for(n, SLM_BS), SLM_BS, 0, s>>>(rp, n, bin_cnt);
+    const i64 m = NBINS * ((n + SLM_BS - 1) / SLM_BS);
+    return 2 * (m + 1) + scan_tmp_elems(m + 1);
 }
-void launch_bin_scatter(const i64 *rp, i64 n, i64 *bin_fill, i32 *bin_nodes, hipStream_t s)
+
+void launch_bins(const i64 *rp, i64 n, i64 *tmp, i64 *off_dev, i32 *bin_nodes, hipStream_t s)
 {
-    if (n > 0) k_bin_scatter<<<grid_for(n, SLM_BS), SLM_BS, 0, s>>>(rp, n, bin_fill, bin_nodes);
+    if (n <= 0) return;
+    const i64 nblk = (n + SLM_BS - 1) / SLM_BS, m = NBINS * nblk;
+    i64 *cnt = tmp, *scanned = tmp + (m + 1), *stmp = tmp + 2 * (m + 1);
+    k_bin_count<<<(unsigned)nblk, SLM_BS, 0, s>>>(rp, n, nblk, cnt);
+    launch_scan_i64(cnt, scanned, m, stmp, s);
+    k_bin_bounds<<<1, 64, 0, s>>>(scanned, nblk, off_dev);
+    k_bin_scatter<<<(unsigned)nblk, SLM_BS, 0, s>>>(rp, n, nblk, scanned, bin_nodes);
 }
 void launch_hub_degrees(const i64 *rp, const i32 *hub_node, i32 nhub, i64 *deg_out, hipStream_t s)
 {
@@ -626,7 +654,7 @@ static void bin_launch_geom(const Bins &Bn, i64 &count, const i32 *&nodes, unsig
     X(BIN_ZERO) X(BIN_128) X(BIN_256) X(BIN_512) X(BIN_1024) X(BIN_2048) X(BIN_4096)
 
 void run_strength_binned(const i64 *rp, const int2 *e, const Bins &Bn, i32 *k, i32 *diag,
-                         i64 *m2_acc, hipStream_t s)
+                         hipStream_t s)
 {
 #define X(B)                                                                          \
     {                                                                                 \
@@ -635,14 +663,14 @@ void run_strength_binned(const i64 *rp, const int2 *e, const Bins &Bn, i32 *k, i
         unsigned gr, bl;                                                              \
         bin_launch_geom<B>(Bn, cnt, nd, gr, bl);                                      \
         if (cnt > 0)                                                                  \
-            k_strength<BinShape<B>::G><<<gr, bl, 0, s>>>(rp, e, nd, cnt, k, diag, m2_acc); \
+            k_strength<BinShape<B>::G><<<gr, bl, 0, s>>>(rp, e, nd, cnt, k, diag);         \
     }
     FOR_LDS_BINS(X)
 #undef X
     if (Bn.nhub > 0) {
         k_hub_zero<<<grid_for(Bn.nhub, SLM_BS), SLM_BS, 0, s>>>(Bn.hub_node, Bn.nhub, k, diag);
         k_hub_strength<<<(unsigned)Bn.nchunk, SLM_BS, 0, s>>>(rp, e, Bn.hub_node, Bn.chunk_hub,
-                                                             Bn.chunk_beg, k, diag, m2_acc);
+                                                             Bn.chunk_beg, k, diag);
     }
 }
 
@@ -806,9 +834,13 @@ void fill_src(const LevelView &L, const Bins &Bn, i32 *src, hipStream_t s)
 i64 level_strengths(Work &W, const i64 *rp, const int2 *e, const Bins &B, i64 n, i32 *k,
                     i32 *diag, hipStream_t s)
 {
-    (void)n;
     launch_fill_i64(W.counters, 0, 1, s);
-    run_strength_binned(rp, e, B, k, diag, W.counters, s);
+    run_strength_binned(rp, e, B, k, diag, s);
+    if (n > 0) {
+        i64 g = (n + SLM_BS - 1) / SLM_BS;
+        if (g > 1024) g = 1024;
+        k_sum_i32<<<(unsigned)g, SLM_BS, 0, s>>>(k, n, W.counters);
+    }
     read_scalars(W, W.counters, 1, s);
     return W.h_scal[0];
 }

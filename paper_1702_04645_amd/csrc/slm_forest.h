@@ -55,6 +55,8 @@ struct Work {
     i64 *roff = nullptr;  // n0 + 1
     i64 *hist = nullptr;  // radix histograms
     i64 hist_cap = 0;
+    i64 *bscan = nullptr;  // degree-bin counts and their scan
+    i64 bscan_cap = 0;
     uint8_t *head_e = nullptr; // nnz0 segment heads
     i64 *rank_e = nullptr;     // nnz0 + 1
 
@@ -166,7 +168,7 @@ i64 contract_level(Work &W, const LevelView &Lv, const Bins &B, const i32 *lab, 
 i64 level_strengths(Work &W, const i64 *rp, const int2 *e, const Bins &B, i64 n, i32 *k,
                     i32 *diag, hipStream_t s);
 void run_strength_binned(const i64 *rp, const int2 *e, const Bins &Bn, i32 *k, i32 *diag,
-                         i64 *m2_acc, hipStream_t s);
+                         hipStream_t s);
 
 // ---------------------------------------------------------------- batches
 void batch_first_labels(const i32 *lab, const i64 *gbase, int G, i64 *first, hipStream_t s);

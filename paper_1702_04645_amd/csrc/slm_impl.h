@@ -281,8 +281,11 @@ void launch_scan_i64(const i64 *in, i64 *out, i64 n, i64 *tmp, hipStream_t s);
 void launch_scan_u8(const uint8_t *in, i64 *out, i64 n, i64 *tmp, hipStream_t s);
 
 // ---------------------------------------------------------------- level setup (k_rows.hip)
-void launch_bin_count(const i64 *rp, i64 n, i64 *bin_cnt, hipStream_t s);
-void launch_bin_scatter(const i64 *rp, i64 n, i64 *bin_fill, i32 *bin_nodes, hipStream_t s);
+// Degree bins: bin_nodes = the nodes of bin 0, then bin 1, ..., each in
+// increasing order; off_dev[0..NBINS] = the bins' first slots and n.  tmp
+// holds bin_scan_elems(n) i64.
+i64 bin_scan_elems(i64 n);
+void launch_bins(const i64 *rp, i64 n, i64 *tmp, i64 *off_dev, i32 *bin_nodes, hipStream_t s);
 void launch_rowdesc(const i32 *nodes, const i64 *rp, i64 n, int4 *rowd, hipStream_t s);
 // span_out[2h], span_out[2h+1] = entry range of hub h's row.
 void launch_hub_degrees(const i64 *rp, const i32 *hub_node, i32 nhub, i64 *span_out,
