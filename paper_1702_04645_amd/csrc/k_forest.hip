@@ -169,10 +169,15 @@ __device__ __forceinline__ i32 lift(i32 u, int d, const i32 *J, i64 n)
     return u;
 }
 
-__device__ __forceinline__ i32 lca(i32 u, i32 v, const i32 *__restrict__ depth,
+// Lowest common ancestor of u (depth du) and v in one tree.  Most pairs meet
+// within a few levels, so the deeper node climbs and both then climb
+// together by parents (J_0) for up to LCA_WALK steps each; only pairs further
+// apart take the jump tables.
+#define LCA_WALK 8
+__device__ __forceinline__ i32 lca(i32 u, int du, i32 v, const i32 *__restrict__ depth,
                                    const i32 *__restrict__ J, i64 n, int K)
 {
-    int du = depth[u], dv = depth[v];
+    int dv = depth[v];
     if (du < dv) {
         i32 t = u;
         u = v;
@@ -181,8 +186,18 @@ __device__ __forceinline__ i32 lca(i32 u, i32 v, const i32 *__restrict__ depth,
         du = dv;
         dv = s;
     }
-    u = lift(u, du - dv, J, n);
+    const int dd = du - dv;
+    if (dd <= LCA_WALK) {
+        for (int i = 0; i < dd; i++) u = J[u];
+    } else {
+        u = lift(u, dd, J, n);
+    }
     if (u == v) return u;
+    for (int st = 0; st < LCA_WALK; st++) {
+        u = J[u];
+        v = J[v];
+        if (u == v) return u;
+    }
     for (int k = K; k >= 0; k--) {
         i32 pu = J[(i64)k * n + u], pv = J[(i64)k * n + v];
         if (pu != pv) {
@@ -248,7 +263,8 @@ static void visit_rows(const LevelView &L, const Bins &Bn, const Op &op, hipStre
 }
 
 // val[lca(u,v)] -= A_uv for every ordered pair (u,v), u != v, of one tree of
-// an active community.
+// an active community.  The matrix is symmetric, so each unordered pair is
+// taken once, from its smaller end, with twice its weight.
 struct LcaVisit {
     const i32 *comp;
     const uint8_t *act;
@@ -257,7 +273,7 @@ struct LcaVisit {
     int K;
     i64 *val;
     struct Row {
-        i32 u, c, r;
+        i32 u, c, r, du;
     };
     __device__ bool begin(i32 u, Row &R) const
     {
@@ -265,14 +281,15 @@ struct LcaVisit {
         R.c = comp[u];
         if (!act[R.c]) return false;
         R.r = root[u];
+        R.du = depth[u];
         return true;
     }
     __device__ void visit(const Row &R, int2 ed) const
     {
         const i32 v = ed.x;
-        if (v == R.u || comp[v] != R.c || root[v] != R.r) return;
-        const i32 l = lca(R.u, v, depth, J, n, K);
-        atomicAdd((unsigned long long *)&val[l], (unsigned long long)(-(i64)ed.y));
+        if (v <= R.u || comp[v] != R.c || root[v] != R.r) return;
+        const i32 l = lca(R.u, R.du, v, depth, J, n, K);
+        atomicAdd((unsigned long long *)&val[l], (unsigned long long)(-2 * (i64)ed.y));
     }
 };
 
