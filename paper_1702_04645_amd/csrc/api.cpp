@@ -465,6 +465,7 @@ static void alloc_work(slm_graph *g)
     W.rank = dalloc<i64>(g, n + 1);
     W.scan_tmp = dalloc<i64>(g, scan_tmp_elems(std::max(n, nnz) + 1) + 16);
     W.counters = dalloc<i64>(g, 16);
+    W.stepf = dalloc<i32>(g, 64);
     W.changed = dalloc<int>(g, 4);
     W.src = dalloc<i32>(g, nnz);
     W.rk0 = dalloc<u64>(g, nnz);

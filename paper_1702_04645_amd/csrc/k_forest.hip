@@ -44,37 +44,45 @@ static unsigned node_grid(i64 n)
 }
 
 // ------------------------------------------------------------------ components
-__global__ void k_comp_init(const i32 *__restrict__ a, i64 n, i32 *__restrict__ A,
-                            i32 *__restrict__ M)
+// Pointer doubling over the functional graph a, with (A, M) packed per node
+// so that a step gathers one 8-byte pair: A = the node 2^k steps ahead, M =
+// the smallest node id among the 2^k nodes from here.
+__global__ void k_comp_init(const i32 *__restrict__ a, i64 n, int2 *__restrict__ AM)
 {
     NODE_LOOP(n)
     {
         i32 u = (i32)u_, x = a[u];
-        A[u] = x;
-        M[u] = u < x ? u : x;
+        AM[u] = make_int2(x, u < x ? u : x);
     }
 }
 
-__global__ void k_comp_step(const i32 *__restrict__ Ai, const i32 *__restrict__ Mi,
-                            i32 *__restrict__ Ao, i32 *__restrict__ Mo, i64 n)
+// One doubling step.  A step that changes nothing leaves both buffers equal
+// to the final state (A maps every node onto a cycle whose length divides
+// the steps taken, and M of a cycle node covers its cycle), so the steps
+// after it return at once: step k runs only if step k-1 set prev_changed.
+__global__ void k_comp_step(const int2 *__restrict__ Ii, int2 *__restrict__ Io, i64 n,
+                            const int *__restrict__ prev_changed, int *__restrict__ changed)
 {
+    if (prev_changed && *prev_changed == 0) return;
+    bool ch = false;
     NODE_LOOP(n)
     {
-        i32 x = Ai[u_];
-        Ao[u_] = Ai[x];
-        i32 m1 = Mi[u_], m2 = Mi[x];
-        Mo[u_] = m1 < m2 ? m1 : m2;
+        const int2 p = Ii[u_];
+        const int2 q = Ii[p.x];
+        Io[u_] = make_int2(q.x, p.y < q.y ? p.y : q.y);
+        ch |= q.x != p.x || q.y < p.y;
     }
+    if (__ballot(ch) != 0 && (threadIdx.x & 63) == 0) *changed = 1;
 }
 
 // cmin[u] = the minimum of u's cycle; cyc marks the image of A = cycle nodes.
-__global__ void k_comp_mark(const i32 *__restrict__ A, const i32 *__restrict__ M, i64 n,
-                            i32 *__restrict__ cmin, uint8_t *__restrict__ cyc)
+__global__ void k_comp_mark(const int2 *__restrict__ AM, i64 n, i32 *__restrict__ cmin,
+                            uint8_t *__restrict__ cyc)
 {
     NODE_LOOP(n)
     {
-        i32 z = A[u_];
-        cmin[u_] = M[z];
+        const i32 z = AM[u_].x;
+        cmin[u_] = AM[z].y;
         cyc[z] = 1;
     }
 }
@@ -668,19 +676,17 @@ i64 components(Work &W, const i32 *a, i64 n, bool want_lab, hipStream_t s)
     if (n == 0) return 0;
     const unsigned g = node_grid(n);
     const int K = ceil_log2(n) + 1;
-    i32 *A = W.A0, *M = W.M0, *A2 = W.A1, *M2 = W.M1;
-    k_comp_init<<<g, SLM_BS, 0, s>>>(a, n, A, M);
+    int2 *I = (int2 *)W.S0, *I2 = (int2 *)W.S1;
+    k_comp_init<<<g, SLM_BS, 0, s>>>(a, n, I);
+    launch_fill_i32(W.stepf, 0, K, s);
     for (int k = 0; k < K; k++) {
-        k_comp_step<<<g, SLM_BS, 0, s>>>(A, M, A2, M2, n);
-        i32 *t = A;
-        A = A2;
-        A2 = t;
-        t = M;
-        M = M2;
-        M2 = t;
+        k_comp_step<<<g, SLM_BS, 0, s>>>(I, I2, n, k ? W.stepf + k - 1 : nullptr, W.stepf + k);
+        int2 *t = I;
+        I = I2;
+        I2 = t;
     }
     launch_fill_u8(W.cyc, 0, n, s);
-    k_comp_mark<<<g, SLM_BS, 0, s>>>(A, M, n, W.comp, W.cyc);
+    k_comp_mark<<<g, SLM_BS, 0, s>>>(I, n, W.comp, W.cyc);
     if (!want_lab) return -1;
     return canonical_labels(W, n, s);
 }

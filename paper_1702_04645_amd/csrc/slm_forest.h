@@ -44,6 +44,7 @@ struct Work {
     i64 W_cap = 0;
 
     i64 *counters = nullptr;  // device, 8 entries
+    i32 *stepf = nullptr;     // device, 64 entries: per doubling step, "changed something"
     int *changed = nullptr;   // device flag
     i64 *h_scal = nullptr;    // pinned host, 16 entries
 
