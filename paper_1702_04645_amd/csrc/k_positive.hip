@@ -820,7 +820,12 @@ __global__ __launch_bounds__(PW_BS) void k_positive_wg(PosArgs A)
                     }
 #pragma unroll
                     for (int j = 0; j < SU; j++) {
-                        if (uu[j] < 0 || pp[j] != pid) continue;
+                        const int i = i0 + j * PW_BS;
+                        if (uu[j] < 0) continue;
+                        // the branch key and bucket of position i, for the
+                        // pass below (INT64_MIN: no branch cut there)
+                        DP[i] = INT64_MIN;
+                        if (pp[j] != pid) continue;
                         const i32 u = uu[j];
                         live++;
                         const i64 ku = kk[j];
@@ -837,6 +842,8 @@ __global__ __launch_bounds__(PW_BS) void k_positive_wg(PosArgs A)
                             i64 ck = sxv[j] * (sig - sxv[j]) - m2 * (i64)cxv[j];
                             u64 cp = ((u64)(u32)u << 32) | (u64)(u32)u;
                             i64 cs = sxv[j];
+                            DP[i] = ck;
+                            TMP[i] = pw_bucket(cs);
                             // insert into the sorted top list; what falls off
                             // the end goes to its bucket
 #pragma unroll
@@ -862,19 +869,22 @@ __global__ __launch_bounds__(PW_BS) void k_positive_wg(PosArgs A)
                 neg = gm < 0 ? 1 : 0;
                 __syncthreads();
                 // lowest pair among the bucket nodes that hold their bucket's
-                // maximum key (the lane bests are candidates, not bucket nodes)
+                // maximum key (the lane bests are candidates, not bucket
+                // nodes); the keys and buckets were kept by position, so this
+                // pass reads three coalesced arrays (each position is read by
+                // the thread that wrote it)
                 for (int i = threadIdx.x; i < m; i += PW_BS) {
+                    const i64 key = DP[i];
+                    if (key == INT64_MIN) continue;
                     const i32 u = P[i];
+                    const u64 pr = ((u64)(u32)u << 32) | (u64)(u32)u;
                     bool top = false;
 #pragma unroll
-                    for (int q = 0; q < PW_TOP; q++) top |= tp[q] == (((u64)(u32)u << 32) | (u64)(u32)u);
-                    if (top || A.part[u] != pid || cyc[u]) continue;
-                    const i64 sx = A.subk[u];
-                    const int b = pw_bucket(sx);
-                    const i64 key = sx * (sig - sx) - m2 * (i64)A.cut[u];
+                    for (int q = 0; q < PW_TOP; q++) top |= tp[q] == pr;
+                    if (top) continue;
+                    const int b = TMP[i];
                     if (ord_map(key) == S.kmax[b])
-                        atomicMin((unsigned long long *)&S.kpair[b],
-                                  (unsigned long long)(((u64)(u32)u << 32) | (u64)(u32)u));
+                        atomicMin((unsigned long long *)&S.kpair[b], (unsigned long long)pr);
                 }
                 __syncthreads();
 #pragma unroll
