@@ -119,15 +119,26 @@ def first_sweep(g, nnz: int, n: int, reps: int = 20):
 
 
 def cpu_model() -> str:
-    """The host CPU's model name (as lscpu reports it)."""
+    """The host CPU's model name as the kernel reports it (lscpu reads the
+    same), with its family / model / stepping numbers, which identify the
+    part where a virtual machine shortens the name."""
+    info = {}
     try:
         with open("/proc/cpuinfo") as f:
             for ln in f:
-                if ln.startswith("model name"):
-                    return ln.split(":", 1)[1].strip()
+                if ":" not in ln:
+                    if info:
+                        break
+                    continue
+                k, v = ln.split(":", 1)
+                info.setdefault(k.strip(), v.strip())
     except OSError:
         pass
-    return "unknown"
+    name = info.get("model name", "unknown")
+    ids = [(k, info[k]) for k in ("cpu family", "model", "stepping") if k in info]
+    if ids:
+        name += " (%s)" % ", ".join("%s %s" % kv for kv in ids)
+    return name
 
 
 def cpu_baseline(rp, col, w, budget_s: float):
