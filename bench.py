@@ -210,7 +210,9 @@ def batch_inputs(args):
     nnz_tot = sum(m[1].size for m in members)
     log("batch: %d graphs, %d nodes, %d entries, generated in %.1fs"
         % (count, n_tot, nnz_tot, time.time() - t))
-    stride = max(1, count // args.plain_sample)
+    # the sample of the plain path and of the oracle (--plain-sample 0 skips
+    # the plain path; the oracle still takes every 16-th member)
+    stride = max(1, count // (args.plain_sample if args.plain_sample > 0 else 128))
     sample = list(range(0, count, stride))
     cpu = None
     if not args.no_cpu:
@@ -256,6 +258,27 @@ def batch_gpu(args, inp):
     b.close()
     del b
     levels = sum(len(r) for r in res)
+    sweep_s = tm["sweep_ms"] / 1e3
+    achieved = tm["bytes"] / sweep_s / 1e9 if sweep_s > 0 else 0.0
+    out = dict(
+        graphs_per_s=round(count / t_batch, 2),
+        ms_per_batched_run=round(t_batch * 1e3, 3),
+        plain_graphs_per_s=None,
+        sample_batched_graphs_per_s=None,
+        plain_sample=None,
+        create_s=round(t_create, 3),
+        sweep_gteps=round(tm["entries"] / sweep_s / 1e9, 3) if sweep_s > 0 else 0.0,
+        sweeps_timed=tm["sweeps"],
+        sweep_frac_of_hbm_peak=round(achieved / HBM_PEAK_GBS, 4),
+        emitted_levels=levels,
+        config=dict(workload="batch2048", graphs=count, nodes=inp["n_tot"],
+                    entries=inp["nnz_tot"], n_range=[64, 65536], block=[16, 256], p_in=0.2,
+                    mean_ext_deg=2, seed=inp["seed"]),
+    )
+    if inp["cpu"]:
+        out["cpu_baseline"] = inp["cpu"]
+    if args.plain_sample <= 0:
+        return out, achieved
     # plain path on the sample: one handle per graph, created outside the timing
     handles = [slm.Graph(*members[i], validate=False) for i in sample]
     for h, i in zip(handles, sample):
@@ -277,25 +300,9 @@ def batch_gpu(args, inp):
     torch.cuda.synchronize()
     t_sample_batch = time.perf_counter() - t
     sb.close()
-    sweep_s = tm["sweep_ms"] / 1e3
-    achieved = tm["bytes"] / sweep_s / 1e9 if sweep_s > 0 else 0.0
-    out = dict(
-        graphs_per_s=round(count / t_batch, 2),
-        ms_per_batched_run=round(t_batch * 1e3, 3),
-        plain_graphs_per_s=round(len(sample) / t_plain, 2),
-        sample_batched_graphs_per_s=round(len(sample) / t_sample_batch, 2),
-        plain_sample="%d members (every %d-th)" % (len(sample), inp["stride"]),
-        create_s=round(t_create, 3),
-        sweep_gteps=round(tm["entries"] / sweep_s / 1e9, 3) if sweep_s > 0 else 0.0,
-        sweeps_timed=tm["sweeps"],
-        sweep_frac_of_hbm_peak=round(achieved / HBM_PEAK_GBS, 4),
-        emitted_levels=levels,
-        config=dict(workload="batch2048", graphs=count, nodes=inp["n_tot"],
-                    entries=inp["nnz_tot"], n_range=[64, 65536], block=[16, 256], p_in=0.2,
-                    mean_ext_deg=2, seed=inp["seed"]),
-    )
-    if inp["cpu"]:
-        out["cpu_baseline"] = inp["cpu"]
+    out.update(plain_graphs_per_s=round(len(sample) / t_plain, 2),
+               sample_batched_graphs_per_s=round(len(sample) / t_sample_batch, 2),
+               plain_sample="%d members (every %d-th)" % (len(sample), inp["stride"]))
     return out, achieved
 
 
@@ -574,7 +581,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--batch-count", type=int, default=2048)
-    ap.add_argument("--plain-sample", type=int, default=128)
+    ap.add_argument("--plain-sample", type=int, default=128,
+                    help="members run on the plain path (0: skip it)")
     ap.add_argument("--serve-count", type=int, default=2000)
     ap.add_argument("--serve-rate", type=float, default=400.0)
     ap.add_argument("--serve-lanes", type=int, default=4)
