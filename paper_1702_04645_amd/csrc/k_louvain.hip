@@ -18,14 +18,34 @@
 
 #define LV_BS 256
 #define LV_NODES (LV_BS / 64)  // one wavefront per node
+#define LV_BMIN 64
+#define LV_BMAX 16384
+#define LV_BATCH 16            // chunks launched between two host reads
+
+// Chunk state on the device, so that the GPU moves from chunk to chunk
+// without the host: the chunk is [p, p + min(B, n - p)); first = the first
+// position whose decision read something an earlier mover of the chunk wrote;
+// err = a chunk made no progress.  Kernels of a chunk that starts at or past
+// n do nothing, so the host can launch several chunks ahead of its reads.
+struct LvState {
+    i64 p, B;
+    int first, err;
+};
+
+__device__ __forceinline__ i64 lv_count(const LvState *st, i64 n)
+{
+    const i64 p = st->p;
+    if (p >= n) return 0;
+    return st->B < n - p ? st->B : n - p;
+}
 
 // Node i = p + t of the chunk: its decision from the current names c[] and
 // totals sig[], with a hash table of its neighbours' communities in global
-// memory at slots [2 (rp[i] - rp[p]), 2 (rp[i+1] - rp[p])) (twice its degree,
-// filled with -1 beforehand).  dest[t] = the community to move to, or -1.  A
-// moving node marks its own name and the totals of its old and new
+// memory at slots [2 (rp[i] - rp[p]), 2 (rp[i+1] - rp[p])) (twice its degree),
+// which its wavefront clears first.  dest[t] = the community to move to, or
+// -1.  A moving node marks its own name and the totals of its old and new
 // communities with t.
-__global__ __launch_bounds__(LV_BS) void k_lv_decide(LevelView L, i64 p, i64 cnt,
+__global__ __launch_bounds__(LV_BS) void k_lv_decide(LevelView L, const LvState *__restrict__ st,
                                                     const i32 *__restrict__ c,
                                                     const i32 *__restrict__ sig,
                                                     i32 *__restrict__ tkey,
@@ -35,14 +55,23 @@ __global__ __launch_bounds__(LV_BS) void k_lv_decide(LevelView L, i64 p, i64 cnt
                                                     i32 *__restrict__ mark_comm)
 {
     const int lane = threadIdx.x & 63;
+    const i64 cnt = lv_count(st, L.n);
     const i64 t = (i64)blockIdx.x * LV_NODES + threadIdx.x / 64;
     if (t >= cnt) return;  // a whole wavefront leaves together
+    const i64 p = st->p;
     const i64 i = p + t;
     const i64 e0 = L.rp[i], e1 = L.rp[i + 1];
     const i64 H = 2 * (e1 - e0);
     const i64 tb = 2 * (e0 - L.rp[p]);
     i32 *keys = tkey + tb;
     i32 *vals = tval + tb;
+    for (i64 h = lane; h < H; h += 64) {
+        keys[h] = -1;
+        vals[h] = 0;
+    }
+    // the cleared slots are visible to the wavefront's inserts
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "agent");
+    __builtin_amdgcn_wave_barrier();
     const i32 ci = c[i];
     i64 w_in = 0;
     for (i64 j = e0 + lane; j < e1; j += 64) {
@@ -94,50 +123,79 @@ __global__ __launch_bounds__(LV_BS) void k_lv_decide(LevelView L, i64 p, i64 cnt
 }
 
 // first = the smallest t whose decision read something an earlier mover of
-// the chunk wrote.
-__global__ __launch_bounds__(LV_BS) void k_lv_conflict(LevelView L, i64 p, i64 cnt,
+// the chunk wrote (it starts at INT32_MAX).
+__global__ __launch_bounds__(LV_BS) void k_lv_conflict(LevelView L, LvState *__restrict__ st,
                                                       const i32 *__restrict__ c,
                                                       const i32 *__restrict__ mark_node,
-                                                      const i32 *__restrict__ mark_comm,
-                                                      int *__restrict__ first)
+                                                      const i32 *__restrict__ mark_comm)
 {
     const int lane = threadIdx.x & 63;
+    const i64 cnt = lv_count(st, L.n);
     const i64 t = (i64)blockIdx.x * LV_NODES + threadIdx.x / 64;
     if (t >= cnt) return;
-    const i64 i = p + t;
+    const i64 i = st->p + t;
     bool hit = lane == 0 && mark_comm[c[i]] < t;
     for (i64 j = L.rp[i] + lane; j < L.rp[i + 1] && !hit; j += 64) {
         const i32 v = L.e[j].x;
         if (v == i) continue;
         if (mark_node[v] < t || mark_comm[c[v]] < t) hit = true;
     }
-    if (__ballot(hit) != 0 && lane == 0) atomicMin(first, (int)t);
+    if (__ballot(hit) != 0 && lane == 0) atomicMin(&st->first, (int)t);
 }
 
 // Applies the moves before `first` and clears every mark of the chunk.
-__global__ __launch_bounds__(LV_BS) void k_lv_apply(LevelView L, i64 p, i64 cnt,
-                                                   const int *__restrict__ first,
+__global__ __launch_bounds__(LV_BS) void k_lv_apply(LevelView L, const LvState *__restrict__ st,
                                                    const i32 *__restrict__ dest,
                                                    i32 *__restrict__ c, i32 *__restrict__ sig,
                                                    i32 *__restrict__ mark_node,
                                                    i32 *__restrict__ mark_comm,
                                                    unsigned long long *__restrict__ moves)
 {
+    const i64 cnt = lv_count(st, L.n);
     const i64 t = (i64)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= cnt) return;
     const i32 d = dest[t];
     if (d < 0) return;
-    const i64 i = p + t;
+    const i64 i = st->p + t;
     const i32 old = c[i];
     mark_node[i] = INT32_MAX;
     mark_comm[old] = INT32_MAX;
     mark_comm[d] = INT32_MAX;
-    if (t < (i64)*first) {
+    if (t < (i64)st->first) {
         c[i] = d;
         atomicSub(&sig[old], L.k[i]);
         atomicAdd(&sig[d], L.k[i]);
         atomicAdd(moves, 1ull);
     }
+}
+
+// The next chunk starts at the first node that was not exact; the chunk size
+// grows while whole chunks hold and shrinks when they break early.
+__global__ void k_lv_advance(i64 n, LvState *__restrict__ st)
+{
+    if (st->p >= n) return;
+    const i64 cnt = lv_count(st, n);
+    const i64 done = st->first < cnt ? st->first : cnt;
+    if (done < 1) {
+        st->err = 1;
+        st->p = n;  // the pass stops; the host reports the error
+        return;
+    }
+    st->p += done;
+    if (done == cnt && st->B < LV_BMAX) st->B *= 2;
+    else if (done < cnt / 4 && st->B > LV_BMIN) st->B /= 2;
+    st->first = INT32_MAX;
+}
+
+// A pass starts at node 0 (the chunk size carries over).
+__global__ void k_lv_pass_start(LvState *__restrict__ st, unsigned long long *__restrict__ moves,
+                                int reset_b)
+{
+    st->p = 0;
+    if (reset_b) st->B = 1024;
+    st->first = INT32_MAX;
+    st->err = 0;
+    *moves = 0;
 }
 
 // c[i] = i, sig[i] = k_i, no marks.
@@ -163,53 +221,43 @@ static unsigned lv_grid(i64 items, int per_block)
 // names.  Returns the passes that moved a node; *converged = the last pass
 // moved nothing; *moves = nodes moved.  Tables use W.rk0 / W.rk1 (2 nnz int32
 // slots each), names and totals W.comp / W.sigma, decisions W.best_c, marks
-// W.M0 / W.M1, the first conflict and the move count W.changed / W.counters.
+// W.M0 / W.M1, the chunk state W.counters[2..4] and the move count
+// W.counters[0].  The host launches LV_BATCH chunks at a time and reads the
+// chunk state after each batch.
 int louvain_level(Work &W, const LevelView &L, int max_passes, int *converged, i64 *moves,
                   hipStream_t s)
 {
     const i64 n = L.n;
     i32 *c = W.comp, *sig = W.sigma, *dest = W.best_c, *mn = W.M0, *mc = W.M1;
     i32 *tkey = (i32 *)W.rk0, *tval = (i32 *)W.rk1;
-    int *first = W.changed;
     unsigned long long *mv = (unsigned long long *)W.counters;
+    LvState *st = (LvState *)(W.counters + 2);
+    static_assert(sizeof(LvState) <= 3 * sizeof(i64), "chunk state must fit three counters");
     *converged = 0;
     *moves = 0;
     if (n == 0) {
         *converged = 1;
         return 0;
     }
-    std::vector<i64> rp_h(n + 1);
-    HIPCHK(hipMemcpyAsync(rp_h.data(), L.rp, sizeof(i64) * (n + 1), hipMemcpyDeviceToHost, s));
     k_lv_init<<<lv_grid(n, SLM_BS) > 4096 ? 4096 : lv_grid(n, SLM_BS), SLM_BS, 0, s>>>(L, c, sig,
                                                                                      mn, mc);
-    HIPCHK(hipStreamSynchronize(s));
+    const i64 bmax = n < LV_BMAX ? n : LV_BMAX;
     int passes = 0;
-    i64 B = 1024;
     while (passes < max_passes) {
-        launch_fill_i64((i64 *)mv, 0, 1, s);
-        i64 p = 0;
-        while (p < n) {
-            const i64 cnt = p + B < n ? B : n - p;
-            const i64 slots = 2 * (rp_h[p + cnt] - rp_h[p]);
-            launch_fill_i32(tkey, -1, slots, s);
-            launch_fill_i32(tval, 0, slots, s);
-            launch_fill_i32((i32 *)first, INT32_MAX, 1, s);
-            k_lv_decide<<<lv_grid(cnt, LV_NODES), LV_BS, 0, s>>>(L, p, cnt, c, sig, tkey, tval,
-                                                                 dest, mn, mc);
-            k_lv_conflict<<<lv_grid(cnt, LV_NODES), LV_BS, 0, s>>>(L, p, cnt, c, mn, mc, first);
-            k_lv_apply<<<lv_grid(cnt, LV_BS), LV_BS, 0, s>>>(L, p, cnt, first, dest, c, sig, mn,
-                                                             mc, mv);
-            int f = 0;
-            HIPCHK(hipMemcpyAsync(&f, first, sizeof(int), hipMemcpyDeviceToHost, s));
-            HIPCHK(hipStreamSynchronize(s));
-            const i64 done = f < cnt ? f : cnt;
-            if (done < 1) throw SlmError{4, "Louvain chunk made no progress"};
-            p += done;
-            // chunk size: grow while whole chunks hold, shrink when they break early
-            if (done == cnt && B < 16384) B *= 2;
-            else if (done < cnt / 4 && B > 64) B /= 2;
+        k_lv_pass_start<<<1, 1, 0, s>>>(st, mv, passes == 0);
+        while (true) {
+            for (int b = 0; b < LV_BATCH; b++) {
+                k_lv_decide<<<lv_grid(bmax, LV_NODES), LV_BS, 0, s>>>(L, st, c, sig, tkey, tval,
+                                                                      dest, mn, mc);
+                k_lv_conflict<<<lv_grid(bmax, LV_NODES), LV_BS, 0, s>>>(L, st, c, mn, mc);
+                k_lv_apply<<<lv_grid(bmax, LV_BS), LV_BS, 0, s>>>(L, st, dest, c, sig, mn, mc, mv);
+                k_lv_advance<<<1, 1, 0, s>>>(n, st);
+            }
+            read_scalars(W, W.counters, 5, s);
+            const LvState *h = (const LvState *)(W.h_scal + 2);
+            if (h->err) throw SlmError{4, "Louvain chunk made no progress"};
+            if (h->p >= n) break;
         }
-        read_scalars(W, (const i64 *)mv, 1, s);
         const i64 moved = W.h_scal[0];
         if (moved == 0) {
             *converged = 1;
