@@ -10,10 +10,17 @@
 // the totals S of its own and its neighbours' communities; a move of node j
 // writes j's name and the totals of j's old and new communities.  Every
 // moving node marks what it writes with its position in the chunk (atomic
-// min), so node i is exact iff no earlier mover of the chunk marked anything
-// i reads.  The moves before the first node that is not exact are applied --
-// exactly the sequential result -- and the next chunk starts at that node.
-// The first node of a chunk is always exact, so every chunk makes progress.
+// min), so node i is exact if no earlier mover of the chunk marked anything
+// i reads.  A node whose neighbours kept their names but some of whose
+// communities' totals changed is still exact when its decision holds for
+// every value those totals can have: each such total lies between its value
+// at the chunk's start less the strengths of the chunk's movers out of the
+// community and plus those of its movers into it (all strengths are
+// non-negative), and the chosen option must beat every other one strictly
+// over that box.  The moves before the first node that is not exact are
+// applied -- exactly the sequential result -- and the next chunk starts at
+// that node.  The first node of a chunk is always exact, so every chunk makes
+// progress.
 #include "slm_forest.h"
 
 #define LV_BS 256
@@ -42,17 +49,22 @@ __device__ __forceinline__ i64 lv_count(const LvState *st, i64 n)
 // Node i = p + t of the chunk: its decision from the current names c[] and
 // totals sig[], with a hash table of its neighbours' communities in global
 // memory at slots [2 (rp[i] - rp[p]), 2 (rp[i+1] - rp[p])) (twice its degree),
-// which its wavefront clears first.  dest[t] = the community to move to, or
-// -1.  A moving node marks its own name and the totals of its old and new
-// communities with t.
+// which its wavefront clears first and which stays for the conflict check.
+// dest[t] = the community to move to, or -1; win[t] = w(i, c_i \ i).  A
+// moving node marks its own name and the totals of its old and new
+// communities with t, and adds its strength to the chunk's movers out of its
+// old community (kout) and into its new one (kin).
 __global__ __launch_bounds__(LV_BS) void k_lv_decide(LevelView L, const LvState *__restrict__ st,
                                                     const i32 *__restrict__ c,
                                                     const i32 *__restrict__ sig,
                                                     i32 *__restrict__ tkey,
                                                     i32 *__restrict__ tval,
                                                     i32 *__restrict__ dest,
+                                                    i32 *__restrict__ win,
                                                     i32 *__restrict__ mark_node,
-                                                    i32 *__restrict__ mark_comm)
+                                                    i32 *__restrict__ mark_comm,
+                                                    i32 *__restrict__ kin,
+                                                    i32 *__restrict__ kout)
 {
     const int lane = threadIdx.x & 63;
     const i64 cnt = lv_count(st, L.n);
@@ -114,41 +126,111 @@ __global__ __launch_bounds__(LV_BS) void k_lv_decide(LevelView L, const LvState 
         const i64 stay = m2 * w_in - ki * ((i64)sig[ci] - ki);
         const bool mv = bc != INT32_MAX && bk > stay;
         dest[t] = mv ? bc : -1;
+        win[t] = (i32)w_in;
         if (mv) {
             atomicMin(&mark_node[i], (i32)t);
             atomicMin(&mark_comm[ci], (i32)t);
             atomicMin(&mark_comm[bc], (i32)t);
+            atomicAdd(&kout[ci], (i32)ki);
+            atomicAdd(&kin[bc], (i32)ki);
         }
     }
 }
 
-// first = the smallest t whose decision read something an earlier mover of
-// the chunk wrote (it starts at INT32_MAX).
+__device__ __forceinline__ i64 lv_wave_max(i64 v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        const i64 o = __shfl_xor(v, off, 64);
+        v = o > v ? o : v;
+    }
+    return v;
+}
+
+// Range of community C's total as node t of the chunk sees it: its value at
+// the chunk's start when no earlier mover marked it, else that value less
+// the chunk's movers out of C and plus its movers into C.
+__device__ __forceinline__ void lv_total_range(i32 C, i64 t, const i32 *__restrict__ sig,
+                                               const i32 *__restrict__ mark_comm,
+                                               const i32 *__restrict__ kin,
+                                               const i32 *__restrict__ kout, i64 &lo, i64 &hi)
+{
+    const i64 s0 = sig[C];
+    lo = hi = s0;
+    if (mark_comm[C] < t) {
+        lo = s0 - kout[C];
+        hi = s0 + kin[C];
+    }
+}
+
+// first = the smallest t whose decision may differ from the one it would
+// take after the chunk's earlier moves (it starts at INT32_MAX): a neighbour
+// that moved earlier in the chunk, or a total that changed and could change
+// the decision (the box test of the file header).
 __global__ __launch_bounds__(LV_BS) void k_lv_conflict(LevelView L, LvState *__restrict__ st,
                                                       const i32 *__restrict__ c,
+                                                      const i32 *__restrict__ sig,
+                                                      const i32 *__restrict__ tkey,
+                                                      const i32 *__restrict__ tval,
+                                                      const i32 *__restrict__ dest,
+                                                      const i32 *__restrict__ win,
                                                       const i32 *__restrict__ mark_node,
-                                                      const i32 *__restrict__ mark_comm)
+                                                      const i32 *__restrict__ mark_comm,
+                                                      const i32 *__restrict__ kin,
+                                                      const i32 *__restrict__ kout)
 {
     const int lane = threadIdx.x & 63;
     const i64 cnt = lv_count(st, L.n);
     const i64 t = (i64)blockIdx.x * LV_NODES + threadIdx.x / 64;
     if (t >= cnt) return;
-    const i64 i = st->p + t;
-    bool hit = lane == 0 && mark_comm[c[i]] < t;
-    for (i64 j = L.rp[i] + lane; j < L.rp[i + 1] && !hit; j += 64) {
+    const i64 p = st->p;
+    const i64 i = p + t;
+    const i32 ci = c[i];
+    const i64 e0 = L.rp[i], e1 = L.rp[i + 1];
+    bool moved_nb = false, changed = lane == 0 && mark_comm[ci] < t;
+    for (i64 j = e0 + lane; j < e1; j += 64) {
         const i32 v = L.e[j].x;
         if (v == i) continue;
-        if (mark_node[v] < t || mark_comm[c[v]] < t) hit = true;
+        if (mark_node[v] < t) moved_nb = true;
+        if (mark_comm[c[v]] < t) changed = true;
     }
-    if (__ballot(hit) != 0 && lane == 0) atomicMin(&st->first, (int)t);
+    if (__ballot(moved_nb) != 0) {
+        if (lane == 0) atomicMin(&st->first, (int)t);
+        return;
+    }
+    if (__ballot(changed) == 0) return;  // read nothing an earlier mover wrote
+    // the decision must hold over the box of the changed totals
+    const i64 ki = L.k[i], m2 = L.m2;
+    const i32 d = dest[t];
+    i64 lo, hi;
+    lv_total_range(ci, t, sig, mark_comm, kin, kout, lo, hi);
+    const i64 wi = win[t];
+    const i64 stay_lo = m2 * wi - ki * (hi - ki), stay_hi = m2 * wi - ki * (lo - ki);
+    const i64 H = 2 * (e1 - e0);
+    const i64 tb = 2 * (e0 - L.rp[p]);
+    i64 other_hi = INT64_MIN, d_lo = INT64_MIN;
+    for (i64 h = lane; h < H; h += 64) {
+        const i32 cc = tkey[tb + h];
+        if (cc < 0) continue;
+        const i64 wv = tval[tb + h];
+        lv_total_range(cc, t, sig, mark_comm, kin, kout, lo, hi);
+        if (cc == d) d_lo = m2 * wv - ki * hi;
+        else other_hi = max(other_hi, m2 * wv - ki * lo);
+    }
+    other_hi = lv_wave_max(other_hi);
+    d_lo = lv_wave_max(d_lo);
+    const bool holds = d < 0 ? other_hi <= stay_lo : (d_lo > stay_hi && d_lo > other_hi);
+    if (!holds && lane == 0) atomicMin(&st->first, (int)t);
 }
 
-// Applies the moves before `first` and clears every mark of the chunk.
+// Applies the moves before `first` and clears every mark and mover sum of
+// the chunk.
 __global__ __launch_bounds__(LV_BS) void k_lv_apply(LevelView L, const LvState *__restrict__ st,
                                                    const i32 *__restrict__ dest,
                                                    i32 *__restrict__ c, i32 *__restrict__ sig,
                                                    i32 *__restrict__ mark_node,
                                                    i32 *__restrict__ mark_comm,
+                                                   i32 *__restrict__ kin, i32 *__restrict__ kout,
                                                    unsigned long long *__restrict__ moves)
 {
     const i64 cnt = lv_count(st, L.n);
@@ -161,6 +243,8 @@ __global__ __launch_bounds__(LV_BS) void k_lv_apply(LevelView L, const LvState *
     mark_node[i] = INT32_MAX;
     mark_comm[old] = INT32_MAX;
     mark_comm[d] = INT32_MAX;
+    kout[old] = 0;
+    kin[d] = 0;
     if (t < (i64)st->first) {
         c[i] = d;
         atomicSub(&sig[old], L.k[i]);
@@ -198,9 +282,10 @@ __global__ void k_lv_pass_start(LvState *__restrict__ st, unsigned long long *__
     *moves = 0;
 }
 
-// c[i] = i, sig[i] = k_i, no marks.
+// c[i] = i, sig[i] = k_i, no marks, no movers.
 __global__ void k_lv_init(LevelView L, i32 *__restrict__ c, i32 *__restrict__ sig,
-                          i32 *__restrict__ mark_node, i32 *__restrict__ mark_comm)
+                          i32 *__restrict__ mark_node, i32 *__restrict__ mark_comm,
+                          i32 *__restrict__ kin, i32 *__restrict__ kout)
 {
     for (i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x; i < L.n;
          i += (i64)gridDim.x * blockDim.x) {
@@ -208,6 +293,8 @@ __global__ void k_lv_init(LevelView L, i32 *__restrict__ c, i32 *__restrict__ si
         sig[i] = L.k[i];
         mark_node[i] = INT32_MAX;
         mark_comm[i] = INT32_MAX;
+        kin[i] = 0;
+        kout[i] = 0;
     }
 }
 
@@ -221,7 +308,8 @@ static unsigned lv_grid(i64 items, int per_block)
 // names.  Returns the passes that moved a node; *converged = the last pass
 // moved nothing; *moves = nodes moved.  Tables use W.rk0 / W.rk1 (2 nnz int32
 // slots each), names and totals W.comp / W.sigma, decisions W.best_c, marks
-// W.M0 / W.M1, the chunk state W.counters[2..4] and the move count
+// W.M0 / W.M1, w(i, c_i \ i) of the chunk's nodes W.wc, the movers' sums
+// W.A0 (into) / W.A1 (out of), the chunk state W.counters[2..4] and the move count
 // W.counters[0].  The host launches LV_BATCH chunks at a time and reads the
 // chunk state after each batch.
 int louvain_level(Work &W, const LevelView &L, int max_passes, int *converged, i64 *moves,
@@ -229,6 +317,7 @@ int louvain_level(Work &W, const LevelView &L, int max_passes, int *converged, i
 {
     const i64 n = L.n;
     i32 *c = W.comp, *sig = W.sigma, *dest = W.best_c, *mn = W.M0, *mc = W.M1;
+    i32 *win = W.wc, *kin = W.A0, *kout = W.A1;
     i32 *tkey = (i32 *)W.rk0, *tval = (i32 *)W.rk1;
     unsigned long long *mv = (unsigned long long *)W.counters;
     LvState *st = (LvState *)(W.counters + 2);
@@ -239,18 +328,20 @@ int louvain_level(Work &W, const LevelView &L, int max_passes, int *converged, i
         *converged = 1;
         return 0;
     }
-    k_lv_init<<<lv_grid(n, SLM_BS) > 4096 ? 4096 : lv_grid(n, SLM_BS), SLM_BS, 0, s>>>(L, c, sig,
-                                                                                     mn, mc);
+    k_lv_init<<<lv_grid(n, SLM_BS) > 4096 ? 4096 : lv_grid(n, SLM_BS), SLM_BS, 0, s>>>(
+        L, c, sig, mn, mc, kin, kout);
     const i64 bmax = n < LV_BMAX ? n : LV_BMAX;
     int passes = 0;
     while (passes < max_passes) {
         k_lv_pass_start<<<1, 1, 0, s>>>(st, mv, passes == 0);
         while (true) {
             for (int b = 0; b < LV_BATCH; b++) {
-                k_lv_decide<<<lv_grid(bmax, LV_NODES), LV_BS, 0, s>>>(L, st, c, sig, tkey, tval,
-                                                                      dest, mn, mc);
-                k_lv_conflict<<<lv_grid(bmax, LV_NODES), LV_BS, 0, s>>>(L, st, c, mn, mc);
-                k_lv_apply<<<lv_grid(bmax, LV_BS), LV_BS, 0, s>>>(L, st, dest, c, sig, mn, mc, mv);
+                k_lv_decide<<<lv_grid(bmax, LV_NODES), LV_BS, 0, s>>>(
+                    L, st, c, sig, tkey, tval, dest, win, mn, mc, kin, kout);
+                k_lv_conflict<<<lv_grid(bmax, LV_NODES), LV_BS, 0, s>>>(
+                    L, st, c, sig, tkey, tval, dest, win, mn, mc, kin, kout);
+                k_lv_apply<<<lv_grid(bmax, LV_BS), LV_BS, 0, s>>>(L, st, dest, c, sig, mn, mc,
+                                                                  kin, kout, mv);
                 k_lv_advance<<<1, 1, 0, s>>>(n, st);
             }
             read_scalars(W, W.counters, 5, s);
