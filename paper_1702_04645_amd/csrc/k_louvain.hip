@@ -28,6 +28,7 @@
 #define LV_BMIN 64
 #define LV_BMAX 16384
 #define LV_BATCH 16            // chunks launched between two host reads
+#define LV_LT 1024             // LDS table slots per wavefront (rows of degree <= 512)
 
 // Chunk state on the device, so that the GPU moves from chunk to chunk
 // without the host: the chunk is [p, p + min(B, n - p)); first = the first
@@ -47,9 +48,10 @@ __device__ __forceinline__ i64 lv_count(const LvState *st, i64 n)
 }
 
 // Node i = p + t of the chunk: its decision from the current names c[] and
-// totals sig[], with a hash table of its neighbours' communities in global
-// memory at slots [2 (rp[i] - rp[p]), 2 (rp[i+1] - rp[p])) (twice its degree),
-// which its wavefront clears first and which stays for the conflict check.
+// totals sig[], with a hash table of its neighbours' communities of twice its
+// degree in slots: in LDS for rows of degree <= LV_LT / 2, else in global
+// memory; either way the table ends at the row's global slots [2 (rp[i] -
+// rp[p]), 2 (rp[i+1] - rp[p])) for the conflict check.
 // dest[t] = the community to move to, or -1; win[t] = w(i, c_i \ i).  A
 // moving node marks its own name and the totals of its old and new
 // communities with t, and adds its strength to the chunk's movers out of its
@@ -75,49 +77,94 @@ __global__ __launch_bounds__(LV_BS) void k_lv_decide(LevelView L, const LvState 
     const i64 e0 = L.rp[i], e1 = L.rp[i + 1];
     const i64 H = 2 * (e1 - e0);
     const i64 tb = 2 * (e0 - L.rp[p]);
-    i32 *keys = tkey + tb;
-    i32 *vals = tval + tb;
-    for (i64 h = lane; h < H; h += 64) {
-        keys[h] = -1;
-        vals[h] = 0;
-    }
-    // the cleared slots are visible to the wavefront's inserts
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "agent");
-    __builtin_amdgcn_wave_barrier();
     const i32 ci = c[i];
-    i64 w_in = 0;
-    for (i64 j = e0 + lane; j < e1; j += 64) {
-        const int2 ed = L.e[j];
-        if (ed.x == i) continue;
-        const i32 cv = c[ed.x];
-        if (cv == ci) {
-            w_in += ed.y;
-            continue;
-        }
-        u64 h = ((u64)hash_label(cv) * (u64)H) >> 32;
-        for (i64 probe = 0; probe < H; probe++) {
-            const i32 old = atomicCAS(&keys[h], -1, cv);
-            if (old == -1 || old == cv) {
-                atomicAdd(&vals[h], ed.y);
-                break;
-            }
-            h = h + 1 == (u64)H ? 0 : h + 1;
-        }
-    }
-    // every insert of the wavefront is done and visible before the read-out
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "agent");
-    __builtin_amdgcn_wave_barrier();
     const i64 ki = L.k[i], m2 = L.m2;
+    i64 w_in = 0;
     i64 bk = INT64_MIN;
     i32 bc = INT32_MAX;
-    for (i64 h = lane; h < H; h += 64) {
-        const i32 cc = __hip_atomic_load(&keys[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (cc < 0) continue;
-        const i32 wv = __hip_atomic_load(&vals[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        const i64 key = m2 * (i64)wv - ki * (i64)sig[cc];
-        if (better_key(key, cc, bk, bc)) {
-            bk = key;
-            bc = cc;
+    if (H <= LV_LT) {
+        // the wavefront's table in LDS, copied out for the conflict check
+        __shared__ i32 lkey[LV_NODES][LV_LT];
+        __shared__ i32 lval[LV_NODES][LV_LT];
+        const int wid = threadIdx.x / 64;
+        for (int h = lane; h < (int)H; h += 64) {
+            lkey[wid][h] = -1;
+            lval[wid][h] = 0;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+        for (i64 j = e0 + lane; j < e1; j += 64) {
+            const int2 ed = L.e[j];
+            if (ed.x == i) continue;
+            const i32 cv = c[ed.x];
+            if (cv == ci) {
+                w_in += ed.y;
+                continue;
+            }
+            u32 h = (u32)(((u64)hash_label(cv) * (u64)H) >> 32);
+            for (int probe = 0; probe < (int)H; probe++) {
+                const i32 old = atomicCAS(&lkey[wid][h], -1, cv);
+                if (old == -1 || old == cv) {
+                    atomicAdd(&lval[wid][h], ed.y);
+                    break;
+                }
+                h = h + 1 == (u32)H ? 0u : h + 1;
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+        for (int h = lane; h < (int)H; h += 64) {
+            const i32 cc = lkey[wid][h];
+            const i32 wv = lval[wid][h];
+            tkey[tb + h] = cc;
+            tval[tb + h] = wv;
+            if (cc < 0) continue;
+            const i64 key = m2 * (i64)wv - ki * (i64)sig[cc];
+            if (better_key(key, cc, bk, bc)) {
+                bk = key;
+                bc = cc;
+            }
+        }
+    } else {
+        i32 *keys = tkey + tb;
+        i32 *vals = tval + tb;
+        for (i64 h = lane; h < H; h += 64) {
+            keys[h] = -1;
+            vals[h] = 0;
+        }
+        // the cleared slots are visible to the wavefront's inserts
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "agent");
+        __builtin_amdgcn_wave_barrier();
+        for (i64 j = e0 + lane; j < e1; j += 64) {
+            const int2 ed = L.e[j];
+            if (ed.x == i) continue;
+            const i32 cv = c[ed.x];
+            if (cv == ci) {
+                w_in += ed.y;
+                continue;
+            }
+            u64 h = ((u64)hash_label(cv) * (u64)H) >> 32;
+            for (i64 probe = 0; probe < H; probe++) {
+                const i32 old = atomicCAS(&keys[h], -1, cv);
+                if (old == -1 || old == cv) {
+                    atomicAdd(&vals[h], ed.y);
+                    break;
+                }
+                h = h + 1 == (u64)H ? 0 : h + 1;
+            }
+        }
+        // every insert of the wavefront is done and visible before the read-out
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "agent");
+        __builtin_amdgcn_wave_barrier();
+        for (i64 h = lane; h < H; h += 64) {
+            const i32 cc = __hip_atomic_load(&keys[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (cc < 0) continue;
+            const i32 wv = __hip_atomic_load(&vals[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const i64 key = m2 * (i64)wv - ki * (i64)sig[cc];
+            if (better_key(key, cc, bk, bc)) {
+                bk = key;
+                bc = cc;
+            }
         }
     }
     w_in = group_sum<64, i64>(w_in);
