@@ -47,15 +47,37 @@ __device__ __forceinline__ i64 lv_count(const LvState *st, i64 n)
     return st->B < n - p ? st->B : n - p;
 }
 
-// Node i = p + t of the chunk: its decision from the current names c[] and
-// totals sig[], with a hash table of its neighbours' communities of twice its
-// degree in slots: in LDS for rows of degree <= LV_LT / 2, else in global
-// memory; either way the table ends at the row's global slots [2 (rp[i] -
-// rp[p]), 2 (rp[i+1] - rp[p])) for the conflict check.
-// dest[t] = the community to move to, or -1; win[t] = w(i, c_i \ i).  A
-// moving node marks its own name and the totals of its old and new
-// communities with t, and adds its strength to the chunk's movers out of its
-// old community (kout) and into its new one (kin).
+// The decision of node i = p + t from w(i, c_i \ i) and its best neighbouring
+// community (bk, bc): dest[t] = the community to move to, or -1; win[t] =
+// w(i, c_i \ i).  A moving node marks its own name and the totals of its old
+// and new communities with t, and adds its strength to the chunk's movers out
+// of its old community (kout) and into its new one (kin).
+__device__ __forceinline__ void lv_finish(i64 t, i64 i, i32 ci, i64 ki, i64 m2, i64 w_in, i64 bk,
+                                          i32 bc, const i32 *__restrict__ sig,
+                                          i32 *__restrict__ dest, i32 *__restrict__ win,
+                                          i32 *__restrict__ mark_node, i32 *__restrict__ mark_comm,
+                                          i32 *__restrict__ kin, i32 *__restrict__ kout)
+{
+    const i64 stay = m2 * w_in - ki * ((i64)sig[ci] - ki);
+    const bool mv = bc != INT32_MAX && bk > stay;
+    dest[t] = mv ? bc : -1;
+    win[t] = (i32)w_in;
+    if (mv) {
+        atomicMin(&mark_node[i], (i32)t);
+        atomicMin(&mark_comm[ci], (i32)t);
+        atomicMin(&mark_comm[bc], (i32)t);
+        atomicAdd(&kout[ci], (i32)ki);
+        atomicAdd(&kin[bc], (i32)ki);
+    }
+}
+
+// Node i = p + t of the chunk decides from the current names c[] and totals
+// sig[], with a hash table of its neighbours' communities of twice its
+// degree in slots: rows of degree <= LV_LT / 2 in their wavefront's LDS
+// table, rows of degree <= LV_NODES * LV_LT / 2 one after another by the
+// whole workgroup in the LDS of all four, longer rows in global memory.
+// Either way the table ends at the row's global slots [2 (rp[i] - rp[p]),
+// 2 (rp[i+1] - rp[p])) for the conflict check.
 __global__ __launch_bounds__(LV_BS) void k_lv_decide(LevelView L, const LvState *__restrict__ st,
                                                     const i32 *__restrict__ c,
                                                     const i32 *__restrict__ sig,
@@ -68,32 +90,142 @@ __global__ __launch_bounds__(LV_BS) void k_lv_decide(LevelView L, const LvState 
                                                     i32 *__restrict__ kin,
                                                     i32 *__restrict__ kout)
 {
-    const int lane = threadIdx.x & 63;
+    __shared__ i32 lkey[LV_NODES][LV_LT];
+    __shared__ i32 lval[LV_NODES][LV_LT];
+    __shared__ i64 red[2 * LV_NODES];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x / 64;
     const i64 cnt = lv_count(st, L.n);
-    const i64 t = (i64)blockIdx.x * LV_NODES + threadIdx.x / 64;
-    if (t >= cnt) return;  // a whole wavefront leaves together
+    const i64 blk0 = (i64)blockIdx.x * LV_NODES;
+    if (blk0 >= cnt) return;  // the whole workgroup leaves together
     const i64 p = st->p;
-    const i64 i = p + t;
-    const i64 e0 = L.rp[i], e1 = L.rp[i + 1];
-    const i64 H = 2 * (e1 - e0);
-    const i64 tb = 2 * (e0 - L.rp[p]);
-    const i32 ci = c[i];
-    const i64 ki = L.k[i], m2 = L.m2;
-    i64 w_in = 0;
-    i64 bk = INT64_MIN;
-    i32 bc = INT32_MAX;
-    if (H <= LV_LT) {
-        // the wavefront's table in LDS, copied out for the conflict check
-        __shared__ i32 lkey[LV_NODES][LV_LT];
-        __shared__ i32 lval[LV_NODES][LV_LT];
-        const int wid = threadIdx.x / 64;
-        for (int h = lane; h < (int)H; h += 64) {
-            lkey[wid][h] = -1;
-            lval[wid][h] = 0;
+    const i64 rp0 = L.rp[p];
+    const i64 m2 = L.m2;
+    const i64 t = blk0 + wid;
+    if (t < cnt) {
+        const i64 i = p + t;
+        const i64 e0 = L.rp[i], e1 = L.rp[i + 1];
+        const i64 H = 2 * (e1 - e0);
+        const i64 tb = 2 * (e0 - rp0);
+        const i32 ci = c[i];
+        const i64 ki = L.k[i];
+        i64 w_in = 0;
+        i64 bk = INT64_MIN;
+        i32 bc = INT32_MAX;
+        if (H <= LV_LT) {
+            // the wavefront's table in LDS, copied out for the conflict check
+            for (int h = lane; h < (int)H; h += 64) {
+                lkey[wid][h] = -1;
+                lval[wid][h] = 0;
+            }
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+            __builtin_amdgcn_wave_barrier();
+            for (i64 j = e0 + lane; j < e1; j += 64) {
+                const int2 ed = L.e[j];
+                if (ed.x == i) continue;
+                const i32 cv = c[ed.x];
+                if (cv == ci) {
+                    w_in += ed.y;
+                    continue;
+                }
+                u32 h = (u32)(((u64)hash_label(cv) * (u64)H) >> 32);
+                for (int probe = 0; probe < (int)H; probe++) {
+                    const i32 old = atomicCAS(&lkey[wid][h], -1, cv);
+                    if (old == -1 || old == cv) {
+                        atomicAdd(&lval[wid][h], ed.y);
+                        break;
+                    }
+                    h = h + 1 == (u32)H ? 0u : h + 1;
+                }
+            }
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+            __builtin_amdgcn_wave_barrier();
+            for (int h = lane; h < (int)H; h += 64) {
+                const i32 cc = lkey[wid][h];
+                const i32 wv = lval[wid][h];
+                tkey[tb + h] = cc;
+                tval[tb + h] = wv;
+                if (cc < 0) continue;
+                const i64 key = m2 * (i64)wv - ki * (i64)sig[cc];
+                if (better_key(key, cc, bk, bc)) {
+                    bk = key;
+                    bc = cc;
+                }
+            }
+        } else if (H > LV_NODES * LV_LT) {
+            i32 *keys = tkey + tb;
+            i32 *vals = tval + tb;
+            for (i64 h = lane; h < H; h += 64) {
+                keys[h] = -1;
+                vals[h] = 0;
+            }
+            // the cleared slots are visible to the wavefront's inserts
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "agent");
+            __builtin_amdgcn_wave_barrier();
+            for (i64 j = e0 + lane; j < e1; j += 64) {
+                const int2 ed = L.e[j];
+                if (ed.x == i) continue;
+                const i32 cv = c[ed.x];
+                if (cv == ci) {
+                    w_in += ed.y;
+                    continue;
+                }
+                u64 h = ((u64)hash_label(cv) * (u64)H) >> 32;
+                for (i64 probe = 0; probe < H; probe++) {
+                    const i32 old = atomicCAS(&keys[h], -1, cv);
+                    if (old == -1 || old == cv) {
+                        atomicAdd(&vals[h], ed.y);
+                        break;
+                    }
+                    h = h + 1 == (u64)H ? 0 : h + 1;
+                }
+            }
+            // every insert of the wavefront is done and visible before the read-out
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "agent");
+            __builtin_amdgcn_wave_barrier();
+            for (i64 h = lane; h < H; h += 64) {
+                const i32 cc =
+                    __hip_atomic_load(&keys[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (cc < 0) continue;
+                const i32 wv =
+                    __hip_atomic_load(&vals[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                const i64 key = m2 * (i64)wv - ki * (i64)sig[cc];
+                if (better_key(key, cc, bk, bc)) {
+                    bk = key;
+                    bc = cc;
+                }
+            }
         }
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-        __builtin_amdgcn_wave_barrier();
-        for (i64 j = e0 + lane; j < e1; j += 64) {
+        if (H <= LV_LT || H > LV_NODES * LV_LT) {
+            w_in = group_sum<64, i64>(w_in);
+            group_best<64>(bk, bc);
+            if (lane == 0)
+                lv_finish(t, i, ci, ki, m2, w_in, bk, bc, sig, dest, win, mark_node, mark_comm,
+                          kin, kout);
+        }
+    }
+    // the workgroup's medium-long rows, one after another, in one LDS table
+    // of LV_NODES * LV_LT slots (every thread reads the same row sizes, so
+    // the loop and its barriers are uniform)
+    i32 *fk = &lkey[0][0];
+    i32 *fv = &lval[0][0];
+    for (int q = 0; q < LV_NODES; q++) {
+        const i64 tq = blk0 + q;
+        if (tq >= cnt) break;
+        const i64 i = p + tq;
+        const i64 e0 = L.rp[i], e1 = L.rp[i + 1];
+        const i64 H = 2 * (e1 - e0);
+        if (H <= LV_LT || H > LV_NODES * LV_LT) continue;
+        const i64 tb = 2 * (e0 - rp0);
+        const i32 ci = c[i];
+        const i64 ki = L.k[i];
+        __syncthreads();  // the tables of the previous row (or of the wavefronts) are done
+        for (int h = threadIdx.x; h < (int)H; h += LV_BS) {
+            fk[h] = -1;
+            fv[h] = 0;
+        }
+        __syncthreads();
+        i64 w_in = 0;
+        for (i64 j = e0 + threadIdx.x; j < e1; j += LV_BS) {
             const int2 ed = L.e[j];
             if (ed.x == i) continue;
             const i32 cv = c[ed.x];
@@ -103,19 +235,20 @@ __global__ __launch_bounds__(LV_BS) void k_lv_decide(LevelView L, const LvState 
             }
             u32 h = (u32)(((u64)hash_label(cv) * (u64)H) >> 32);
             for (int probe = 0; probe < (int)H; probe++) {
-                const i32 old = atomicCAS(&lkey[wid][h], -1, cv);
+                const i32 old = atomicCAS(&fk[h], -1, cv);
                 if (old == -1 || old == cv) {
-                    atomicAdd(&lval[wid][h], ed.y);
+                    atomicAdd(&fv[h], ed.y);
                     break;
                 }
                 h = h + 1 == (u32)H ? 0u : h + 1;
             }
         }
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-        __builtin_amdgcn_wave_barrier();
-        for (int h = lane; h < (int)H; h += 64) {
-            const i32 cc = lkey[wid][h];
-            const i32 wv = lval[wid][h];
+        __syncthreads();
+        i64 bk = INT64_MIN;
+        i32 bc = INT32_MAX;
+        for (int h = threadIdx.x; h < (int)H; h += LV_BS) {
+            const i32 cc = fk[h];
+            const i32 wv = fv[h];
             tkey[tb + h] = cc;
             tval[tb + h] = wv;
             if (cc < 0) continue;
@@ -125,62 +258,11 @@ __global__ __launch_bounds__(LV_BS) void k_lv_decide(LevelView L, const LvState 
                 bc = cc;
             }
         }
-    } else {
-        i32 *keys = tkey + tb;
-        i32 *vals = tval + tb;
-        for (i64 h = lane; h < H; h += 64) {
-            keys[h] = -1;
-            vals[h] = 0;
-        }
-        // the cleared slots are visible to the wavefront's inserts
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "agent");
-        __builtin_amdgcn_wave_barrier();
-        for (i64 j = e0 + lane; j < e1; j += 64) {
-            const int2 ed = L.e[j];
-            if (ed.x == i) continue;
-            const i32 cv = c[ed.x];
-            if (cv == ci) {
-                w_in += ed.y;
-                continue;
-            }
-            u64 h = ((u64)hash_label(cv) * (u64)H) >> 32;
-            for (i64 probe = 0; probe < H; probe++) {
-                const i32 old = atomicCAS(&keys[h], -1, cv);
-                if (old == -1 || old == cv) {
-                    atomicAdd(&vals[h], ed.y);
-                    break;
-                }
-                h = h + 1 == (u64)H ? 0 : h + 1;
-            }
-        }
-        // every insert of the wavefront is done and visible before the read-out
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "agent");
-        __builtin_amdgcn_wave_barrier();
-        for (i64 h = lane; h < H; h += 64) {
-            const i32 cc = __hip_atomic_load(&keys[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            if (cc < 0) continue;
-            const i32 wv = __hip_atomic_load(&vals[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            const i64 key = m2 * (i64)wv - ki * (i64)sig[cc];
-            if (better_key(key, cc, bk, bc)) {
-                bk = key;
-                bc = cc;
-            }
-        }
-    }
-    w_in = group_sum<64, i64>(w_in);
-    group_best<64>(bk, bc);
-    if (lane == 0) {
-        const i64 stay = m2 * w_in - ki * ((i64)sig[ci] - ki);
-        const bool mv = bc != INT32_MAX && bk > stay;
-        dest[t] = mv ? bc : -1;
-        win[t] = (i32)w_in;
-        if (mv) {
-            atomicMin(&mark_node[i], (i32)t);
-            atomicMin(&mark_comm[ci], (i32)t);
-            atomicMin(&mark_comm[bc], (i32)t);
-            atomicAdd(&kout[ci], (i32)ki);
-            atomicAdd(&kin[bc], (i32)ki);
-        }
+        w_in = block_sum<i64>(w_in, red);
+        block_best(bk, bc, red);
+        if (threadIdx.x == 0)
+            lv_finish(tq, i, ci, ki, m2, w_in, bk, bc, sig, dest, win, mark_node, mark_comm, kin,
+                      kout);
     }
 }
 
