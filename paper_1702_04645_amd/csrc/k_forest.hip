@@ -170,6 +170,50 @@ __global__ void k_sub_scatter(const i32 *__restrict__ comp, const uint8_t *__res
     }
 }
 
+// The same for two value arrays at once (subtree strengths and cut
+// corrections share the forest's loads): Sa from va32, Sb from vb64.
+__global__ void k_sub_init2(const i32 *__restrict__ comp, const uint8_t *__restrict__ act, i64 n,
+                            const i32 *__restrict__ va32, const i64 *__restrict__ vb64,
+                            i64 *__restrict__ Sa, i64 *__restrict__ Sb)
+{
+    NODE_LOOP(n)
+    {
+        if (!act[comp[u_]]) continue;
+        Sa[u_] = va32[u_];
+        Sb[u_] = vb64[u_];
+    }
+}
+
+__global__ void k_sub_copy2(const i32 *__restrict__ comp, const uint8_t *__restrict__ act, i64 n,
+                            const i64 *__restrict__ Sai, const i64 *__restrict__ Sbi,
+                            i64 *__restrict__ Sao, i64 *__restrict__ Sbo)
+{
+    NODE_LOOP(n)
+    {
+        if (!act[comp[u_]]) continue;
+        Sao[u_] = Sai[u_];
+        Sbo[u_] = Sbi[u_];
+    }
+}
+
+__global__ void k_sub_scatter2(const i32 *__restrict__ comp, const uint8_t *__restrict__ act,
+                               i64 n, const i32 *__restrict__ Jk, const i32 *__restrict__ depth,
+                               int step, const i64 *__restrict__ Sai, const i64 *__restrict__ Sbi,
+                               i64 *__restrict__ Sao, i64 *__restrict__ Sbo)
+{
+    NODE_LOOP(n)
+    {
+        i32 u = (i32)u_;
+        if (!act[comp[u]]) continue;
+        if (depth[u] >= (1 << step)) {
+            const i32 x = Jk[u];
+            const i64 va = Sai[u], vb = Sbi[u];
+            if (va) atomicAdd((unsigned long long *)&Sao[x], (unsigned long long)va);
+            if (vb) atomicAdd((unsigned long long *)&Sbo[x], (unsigned long long)vb);
+        }
+    }
+}
+
 __device__ __forceinline__ i32 lift(i32 u, int d, const i32 *J, i64 n)
 {
     for (int k = 0; d; k++, d >>= 1)
@@ -735,12 +779,13 @@ static void subtree_sums(Work &W, const i32 *comp, const uint8_t *act, i64 n, co
     HIPCHK(hipMemcpyAsync(out, Si, sizeof(i64) * n, hipMemcpyDeviceToDevice, s));
 }
 
-// cut(T_x) = w(T_x, c \ T_x) for every node of the active communities:
-// subtree sums of w(u, c \ u) minus, at every lowest common ancestor, the
-// weight of the tree pairs meeting there.
-static void subtree_cuts(Work &W, const LevelView &Lv, const Bins &B, const i32 *comp,
-                         const uint8_t *act, const Forest &F, const i32 *w_other, i64 *cut,
-                         hipStream_t s)
+// subk = subtree sums of the strengths k, and cut(T_x) = w(T_x, c \ T_x) for
+// every node of the active communities: subtree sums of w(u, c \ u) minus,
+// at every lowest common ancestor, the weight of the tree pairs meeting
+// there.  Both sums run in the same doubling passes.
+static void subtree_strengths_cuts(Work &W, const LevelView &Lv, const Bins &B, const i32 *comp,
+                                   const uint8_t *act, const Forest &F, const i32 *w_other,
+                                   i64 *subk, i64 *cut, hipStream_t s)
 {
     const i64 n = Lv.n;
     const unsigned g = node_grid(n);
@@ -748,7 +793,21 @@ static void subtree_cuts(Work &W, const LevelView &Lv, const Bins &B, const i32 
     k_sub_init<<<g, SLM_BS, 0, s>>>(comp, act, n, w_other, nullptr, val);
     if (Lv.nnz > 0)
         visit_rows(Lv, B, LcaVisit{comp, act, F.root, F.depth, W.J, n, F.K, val}, s);
-    subtree_sums(W, comp, act, n, F, nullptr, val, cut, s);
+    i64 *Ai = W.S0, *Ao = W.S1, *Bi = W.bestkey, *Bo = W.cbest_key;
+    k_sub_init2<<<g, SLM_BS, 0, s>>>(comp, act, n, Lv.k, val, Ai, Bi);
+    for (int k = 0; k <= F.K; k++) {
+        k_sub_copy2<<<g, SLM_BS, 0, s>>>(comp, act, n, Ai, Bi, Ao, Bo);
+        k_sub_scatter2<<<g, SLM_BS, 0, s>>>(comp, act, n, W.J + (i64)k * n, F.depth, k, Ai, Bi,
+                                            Ao, Bo);
+        i64 *t = Ai;
+        Ai = Ao;
+        Ao = t;
+        t = Bi;
+        Bi = Bo;
+        Bo = t;
+    }
+    HIPCHK(hipMemcpyAsync(subk, Ai, sizeof(i64) * n, hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipMemcpyAsync(cut, Bi, sizeof(i64) * n, hipMemcpyDeviceToDevice, s));
 }
 
 
@@ -874,9 +933,8 @@ i64 maximal_moves(Work &W, const LevelView &Lv, const Bins &B, i64 nc, u64 seed,
     k_max_clist<<<g, SLM_BS, 0, s>>>(W.lab, W.best_c, W.cyc, n, W.coff, W.cfill, W.clist);
     // forest of the communities with non-cycle candidates
     Forest F = build_forest(W, W.a, W.lab, W.act, n, s);
-    subtree_sums(W, W.lab, W.act, n, F, Lv.k, nullptr, W.subk, s);
     if (Lv.y) subtree_sums(W, W.lab, W.act, n, F, Lv.y, nullptr, W.suby, s);
-    subtree_cuts(W, Lv, B, W.lab, W.act, F, W.w_own, W.cut, s);
+    subtree_strengths_cuts(W, Lv, B, W.lab, W.act, F, W.w_own, W.subk, W.cut, s);
     // nearest candidate ancestors
     k_nca_init<<<g, SLM_BS, 0, s>>>(W.lab, W.act, W.best_c, W.cyc, W.J, n, W.nca0);
     i32 *Fi = W.nca0, *Fo = W.nca1;
