@@ -660,18 +660,29 @@ __global__ __launch_bounds__(PW_BS) void k_positive_wg(PosArgs A)
                     i32 u = P[slot];
                     int2 ed = G.e[G.rp[u] + (t - d0)];
                     i32 v = ed.x;
-                    if (v != u && A.part[v] == pid && A.root[u] == A.root[v]) {
+                    // the matrix is symmetric: each pair once, from its
+                    // smaller end, with both directions' weight
+                    if (v > u && A.part[v] == pid && A.root[u] == A.root[v]) {
                         i32 x = u, y = v;
+                        int dx = A.dep[u], dy = A.dep[v];
                         int guard = 0;
-                        // a walk takes at most 2 (m - 1) steps
-                        while (A.dep[x] > A.dep[y] && guard++ < 2 * m) x = a[x];
-                        while (A.dep[y] > A.dep[x] && guard++ < 2 * m) y = a[y];
+                        // inside a tree a parent is one level up, so the
+                        // depths are counted down; a walk takes at most
+                        // 2 (m - 1) steps
+                        while (dx > dy && guard++ < 2 * m) {
+                            x = a[x];
+                            dx--;
+                        }
+                        while (dy > dx && guard++ < 2 * m) {
+                            y = a[y];
+                            dy--;
+                        }
                         while (x != y && guard++ < 2 * m) {
                             x = a[x];
                             y = a[y];
                         }
                         if (guard >= 2 * m) report(A.err, 1);
-                        else if (!cyc[x]) atomicSub(&A.cut[x], ed.y);
+                        else if (!cyc[x]) atomicSub(&A.cut[x], 2 * ed.y);
                     }
                 }
             }
