@@ -405,6 +405,8 @@ static void alloc_work(slm_graph *g)
     W.hasc = dalloc<uint8_t>(g, n);
     W.exam = dalloc<uint8_t>(g, n);
     W.exam_next = dalloc<uint8_t>(g, n);
+    W.moved = dalloc<uint8_t>(g, n);
+    W.pact = dalloc<uint8_t>(g, n);
     W.accept = dalloc<uint8_t>(g, n);
     W.head = dalloc<uint8_t>(g, n);
     W.claim = dalloc<i32>(g, n);
@@ -614,7 +616,8 @@ static i64 level_round(slm_graph *g, const slm_params *p, int level, int round, 
     i64 splits = 0;
     if (valid > 0) {
         components(W, W.a, g->n, false, g->s);
-        splits = positive(W, L, g->bins, nc, g->s);
+        mark_changed_communities(W, g->n, g->s);
+        splits = positive(W, L, g->bins, nc, g->s, W.pact);
     }
     if (stats4) {
         stats4[0] = st[0];

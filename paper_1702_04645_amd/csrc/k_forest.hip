@@ -409,12 +409,13 @@ __global__ void k_pos_flag(const i32 *__restrict__ comp, const i32 *__restrict__
                            const i32 *__restrict__ diag, const i32 *__restrict__ wc,
                            const i32 *__restrict__ sig, const i32 *__restrict__ m2n, i64 m2,
                            const i32 *__restrict__ y, const i32 *__restrict__ sigy,
-                           i64 n, i32 *__restrict__ fidx, i32 *__restrict__ flist,
-                           i64 *__restrict__ counters)
+                           const uint8_t *__restrict__ active, i64 n, i32 *__restrict__ fidx,
+                           i32 *__restrict__ flist, i64 *__restrict__ counters)
 {
     NODE_LOOP(n)
     {
         i32 c = comp[u_];
+        if (active && !active[c]) continue;
         i64 ku = k[u_];
         const i64 m2u = m2n ? (i64)m2n[u_] : m2;
         i64 g = m2u * (i64)(wc[u_] - diag[u_]) - ku * ((i64)sig[c] - ku);
@@ -811,7 +812,40 @@ static void subtree_strengths_cuts(Work &W, const LevelView &Lv, const Bins &B, 
 }
 
 
-i64 positive(Work &W, const LevelView &Lv, const Bins &B, i64 *nc_out, hipStream_t s)
+// Nodes that an accepted move changes: the mover (it ends in its target's
+// community) and its old parent (it stays in what is left of the old one).
+__global__ void k_mark_moves(const uint8_t *__restrict__ accept, const i32 *__restrict__ a, i64 n,
+                             uint8_t *__restrict__ moved)
+{
+    NODE_LOOP(n)
+    {
+        if (!accept[u_]) continue;
+        moved[u_] = 1;
+        moved[a[u_]] = 1;
+    }
+}
+
+__global__ void k_mark_comms(const i32 *__restrict__ comp, const uint8_t *__restrict__ moved,
+                             i64 n, uint8_t *__restrict__ pact)
+{
+    NODE_LOOP(n)
+    {
+        if (moved[u_]) pact[comp[u_]] = 1;
+    }
+}
+
+void mark_changed_communities(Work &W, i64 n, hipStream_t s)
+{
+    if (n == 0) return;
+    launch_fill_u8(W.pact, 0, n, s);
+    k_mark_comms<<<node_grid(n), SLM_BS, 0, s>>>(W.comp, W.moved, n, W.pact);
+}
+
+// With `active` (per community id of W.comp), only those communities are
+// checked for a node of negative local gain: the caller knows the others
+// are unchanged since POSITIVE left all their gains non-negative.
+i64 positive(Work &W, const LevelView &Lv, const Bins &B, i64 *nc_out, hipStream_t s,
+             const uint8_t *active)
 {
     const i64 n = Lv.n;
     if (n == 0) {
@@ -826,11 +860,11 @@ i64 positive(Work &W, const LevelView &Lv, const Bins &B, i64 *nc_out, hipStream
         launch_fill_i32(W.sigy, 0, n, s);
         agg_add(W.comp, Lv.y, n, W.sigy, s);
     }
-    run_own_weight(Lv, B, W.comp, nullptr, W.wc, s);
+    run_own_weight(Lv, B, W.comp, active, W.wc, s);
     launch_fill_i32(W.fidx, -1, n, s);
     launch_fill_i64(W.counters, 0, 8, s);
     k_pos_flag<<<g, SLM_BS, 0, s>>>(W.comp, Lv.k, Lv.diag, W.wc, W.sigma, Lv.m2n, Lv.m2, Lv.y,
-                                    W.sigy, n, W.fidx, W.flist, W.counters);
+                                    W.sigy, active, n, W.fidx, W.flist, W.counters);
     read_scalars(W, W.counters, 1, s);
     const i64 nflag = W.h_scal[0];
     i64 splits = 0;
@@ -958,6 +992,9 @@ i64 maximal_moves(Work &W, const LevelView &Lv, const Bins &B, i64 nc, u64 seed,
     stats[2] = W.h_scal[2];
     if (stats[1] == 0) return 0;
     HIPCHK(hipMemsetAsync(W.changed + 2, 0, sizeof(int), s));
+    // the nodes whose communities the moves change, before the pointers do
+    launch_fill_u8(W.moved, 0, n, s);
+    k_mark_moves<<<g, SLM_BS, 0, s>>>(W.accept, W.a, n, W.moved);
     run_repoint(Lv, B, W.lab, W.best_c, W.accept, W.a, W.hub_ckey, W.hub_cid, W.changed + 2, s);
     HIPCHK(hipMemcpyAsync(W.h_scal, W.changed + 2, sizeof(int), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));

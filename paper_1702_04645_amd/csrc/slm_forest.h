@@ -16,6 +16,9 @@ struct Work {
     i32 *y = nullptr, *sigy = nullptr;  // directed model: y and its totals
     i64 *suby = nullptr;                // directed model: subtree sums of y
     i64 *delta = nullptr;
+    // moved: a node that moved in the last MAXIMAL round, or its old parent;
+    // pact: per community id, holds such a node (its membership changed)
+    uint8_t *moved = nullptr, *pact = nullptr;
     uint8_t *cyc = nullptr, *act = nullptr, *hasc = nullptr, *exam = nullptr,
             *exam_next = nullptr, *accept = nullptr, *head = nullptr;
     i32 *claim = nullptr, *L = nullptr, *pos = nullptr, *cnode = nullptr, *mlist = nullptr;
@@ -131,7 +134,12 @@ int louvain_level(Work &W, const LevelView &L, int max_passes, int *converged, i
 
 // POSITIVE (Sec. 3.3) on W.a (modified).  Expects W.comp / W.cyc from
 // components(); leaves W.lab canonical.  Returns splits; *nc = n_c.
-i64 positive(Work &W, const LevelView &Lv, const Bins &B, i64 *nc, hipStream_t s);
+i64 positive(Work &W, const LevelView &Lv, const Bins &B, i64 *nc, hipStream_t s,
+             const uint8_t *active = nullptr);
+// After the components of a MAXIMAL round's assignment: W.pact[c] = 1 for the
+// communities holding a node that W.moved marks (the others are unchanged
+// since the last POSITIVE, so none of their nodes has a negative gain).
+void mark_changed_communities(Work &W, i64 n, hipStream_t s);
 
 // One MAXIMAL round (Sec. 3.4) on W.a with the canonical labels W.lab (n_c
 // communities): sweep, tails, validity, draws, re-pointing.  Returns the
