@@ -1042,22 +1042,47 @@ static void union_level(slm_graph *g, const slm_params *p, std::vector<Member> &
         to_host(accS, g->d_accS, G, s);
         std::vector<i32> lab_h;
         to_host(lab_h, W.lab, g->n, s);
-        for (int q = 0; q < G; q++) {
-            if (!emit[q]) continue;
-            Member &m = g->mem[q];
-            const i32 *lq = lab_h.data() + g->base[q];
-            const i32 c0 = (i32)gcb[q];
-            for (i64 v = 0; v < m.n0; v++) m.comp[v] = lq[m.comp[v]] - c0;
-            const i64 nq = m.m2 * accI[q] - accS[q];
-            slm_result *R = m.res;
-            R->labels.push_back(m.comp);
-            R->nc.push_back(gcb[q + 1] - gcb[q]);
-            R->nq.push_back(nq);
-            R->q.push_back((double)nq / (double)m.m2 / (double)m.m2);
-            R->rounds.push_back(rounds[q]);
-            R->conv.push_back(conv[q]);
-            m.level++;
-            if (p->max_levels > 0 && (int)R->nc.size() >= p->max_levels) leave[q] = 1;
+        // each member composes its labels and records its level on its own
+        // (members of one range per host thread when the union is large)
+        auto emit_range = [&](int q0, int q1) {
+            for (int q = q0; q < q1; q++) {
+                if (!emit[q]) continue;
+                Member &m = g->mem[q];
+                const i32 *lq = lab_h.data() + g->base[q];
+                const i32 c0 = (i32)gcb[q];
+                for (i64 v = 0; v < m.n0; v++) m.comp[v] = lq[m.comp[v]] - c0;
+                const i64 nq = m.m2 * accI[q] - accS[q];
+                slm_result *R = m.res;
+                R->labels.push_back(m.comp);
+                R->nc.push_back(gcb[q + 1] - gcb[q]);
+                R->nq.push_back(nq);
+                R->q.push_back((double)nq / (double)m.m2 / (double)m.m2);
+                R->rounds.push_back(rounds[q]);
+                R->conv.push_back(conv[q]);
+                m.level++;
+                if (p->max_levels > 0 && (int)R->nc.size() >= p->max_levels) leave[q] = 1;
+            }
+        };
+        i64 work = 0;
+        for (int q = 0; q < G; q++)
+            if (emit[q]) work += g->mem[q].n0;
+        const int hw = (int)std::thread::hardware_concurrency();
+        const int T = std::min(std::min(hw > 0 ? hw : 1, 16), G);
+        if (T <= 1 || work < ((i64)1 << 20)) {
+            emit_range(0, G);
+        } else {
+            // contiguous member ranges of about work / T original nodes each
+            std::vector<int> cut_at(1, 0);
+            i64 acc = 0;
+            for (int q = 0; q < G && (int)cut_at.size() < T; q++) {
+                if (emit[q]) acc += g->mem[q].n0;
+                if (acc * T >= work * (i64)cut_at.size()) cut_at.push_back(q + 1);
+            }
+            cut_at.push_back(G);
+            std::vector<std::thread> th;
+            for (size_t r = 0; r + 1 < cut_at.size(); r++)
+                if (cut_at[r] < cut_at[r + 1]) th.emplace_back(emit_range, cut_at[r], cut_at[r + 1]);
+            for (std::thread &t : th) t.join();
         }
     }
     // the members that stay form the next level's union, in order
