@@ -315,8 +315,9 @@ static void visit_rows(const LevelView &L, const Bins &Bn, const Op &op, hipStre
 }
 
 // val[lca(u,v)] -= A_uv for every ordered pair (u,v), u != v, of one tree of
-// an active community.  The matrix is symmetric, so each unordered pair is
-// taken once, from its smaller end, with twice its weight.
+// an active community whose common ancestor is not the tree's root.  The
+// matrix is symmetric, so each unordered pair is taken once, from its
+// smaller end, with twice its weight.
 struct LcaVisit {
     const i32 *comp;
     const uint8_t *act;
@@ -339,8 +340,12 @@ struct LcaVisit {
     __device__ void visit(const Row &R, int2 ed) const
     {
         const i32 v = ed.x;
-        if (v <= R.u || comp[v] != R.c || root[v] != R.r) return;
+        // pairs meeting at their tree's root (a cycle node) are left out: no
+        // cut uses the root's value, since a cycle node's move takes its
+        // whole community
+        if (R.du == 0 || v <= R.u || comp[v] != R.c || root[v] != R.r) return;
         const i32 l = lca(R.u, R.du, v, depth, J, n, K);
+        if (l == R.r) return;
         atomicAdd((unsigned long long *)&val[l], (unsigned long long)(-2 * (i64)ed.y));
     }
 };

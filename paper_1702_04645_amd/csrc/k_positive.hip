@@ -662,7 +662,10 @@ __global__ __launch_bounds__(PW_BS) void k_positive_wg(PosArgs A)
                     i32 v = ed.x;
                     // the matrix is symmetric: each pair once, from its
                     // smaller end, with both directions' weight
-                    if (v > u && A.part[v] == pid && A.root[u] == A.root[v]) {
+                    if (v > u && A.part[v] == pid && A.root[u] == A.root[v] && A.dep[u] != 0 &&
+                        A.dep[v] != 0) {
+                        // (a pair with the root meets at a cycle node, which
+                        // takes no correction)
                         i32 x = u, y = v;
                         int dx = A.dep[u], dy = A.dep[v];
                         int guard = 0;
