@@ -93,6 +93,47 @@ def workload(name: str):
     raise SystemExit("unknown workload " + name)
 
 
+def singleton_sweep(g, nnz: int, n: int, reps: int = 10):
+    """The sweep with every node in a community of its own (labels 0..n-1,
+    the most distinct communities per row), timed like first_sweep."""
+    import torch
+    lab = torch.arange(n, dtype=torch.int32, device="cuda")
+    g.sweep(lab, n)
+    torch.cuda.synchronize()
+    g.timing(True)
+    g.timing_read()
+    for _ in range(reps):
+        g.sweep(lab, n)
+    tm = g.timing_read()
+    g.timing(False)
+    ms = tm["sweep_ms"] / max(tm["sweeps"], 1)
+    gbs = tm["bytes"] / max(tm["sweeps"], 1) / (ms * 1e-3) / 1e9
+    return {"ms": round(ms, 4), "gteps": round(nnz / (ms * 1e-3) / 1e9, 3),
+            "achieved_gbs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4),
+            "repetitions": reps}
+
+
+def copy_gbs(reps: int = 10) -> float:
+    """Bandwidth of a plain device-to-device copy of 1 GiB (bytes read plus
+    bytes written per second): what a streaming kernel reaches on this GPU."""
+    import torch
+    a = torch.ones(1 << 28, dtype=torch.int32, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    s = e0.elapsed_time(e1) / 1e3
+    out = 2.0 * a.numel() * 4 * reps / s / 1e9
+    del a, b
+    torch.cuda.empty_cache()
+    return round(out, 1)
+
+
 def first_sweep(g, nnz: int, n: int, reps: int = 20):
     """The sweep on the labels of the level's first MAXIMAL round (ASSIGN,
     POSITIVE, COMPONENTS), timed like the run's sweeps (HIP events on the
@@ -656,6 +697,10 @@ def main():
         log("launch options from tuned/%s.json" % args.workload)
     first = first_sweep(g, nnz, n)
     log("first level-0 sweep: %.4f ms" % first["ms"])
+    single = singleton_sweep(g, nnz, n)
+    log("singleton-label sweep: %.4f ms" % single["ms"])
+    copy = copy_gbs()
+    log("device copy: %.1f GB/s" % copy)
     for i in range(args.warmup):
         log("warmup %d" % i)
         g.run(params)
@@ -693,6 +738,7 @@ def main():
                        accept_p="1/2", max_rounds=64),
         "launch_options": tuned or "library defaults",
         "level0_first_sweep": first,
+        "singleton_label_sweep": single,
         "sweeps_timed": tm["sweeps"],
         "sweep_ms_mean": round(tm["sweep_ms"] / max(tm["sweeps"], 1), 4),
         "levels": len(last) if last else 0,
@@ -707,6 +753,8 @@ def main():
             "traffic": measured_traffic(args.workload),
             "traffic_unit": "GB per sweep (HBM read + write, counters scaled by a copy)",
             "algorithmic_gb_per_sweep": round(tm["bytes"] / max(tm["sweeps"], 1) / 1e9, 4),
+            "copy_gbs": copy,
+            "frac_of_copy": round(achieved / copy, 4) if copy > 0 else None,
         },
     }
     if cpu:
