@@ -713,7 +713,8 @@ def main():
     last = None
     for i in range(args.steps):
         last = g.run(params)
-        log("step %d done: %d levels" % (i, len(last)))
+        log("step %d done: %d levels, %.1f ms into the timed steps"
+            % (i, len(last), 1e3 * (time.perf_counter() - t0)))
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     tm = g.timing_read()

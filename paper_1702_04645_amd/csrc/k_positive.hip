@@ -224,39 +224,11 @@ __device__ __forceinline__ i64 wg_sum(i64 v, PwShared &S)
     return t;
 }
 
-// Best (key desc, pair asc) over the workgroup.
-__device__ __forceinline__ void wg_best(i64 &key, u64 &pair, PwShared &S)
-{
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-        i64 ok = __shfl_xor(key, off, 64);
-        u64 op = __shfl_xor(pair, off, 64);
-        if (ok > key || (ok == key && op < pair)) {
-            key = ok;
-            pair = op;
-        }
-    }
-    const int wid = threadIdx.x / 64;
-    __syncthreads();
-    if ((threadIdx.x & 63) == 0) {
-        S.red[2 * wid] = key;
-        S.red[2 * wid + 1] = (i64)pair;
-    }
-    __syncthreads();
-    key = S.red[0];
-    pair = (u64)S.red[1];
-    for (int w = 1; w < PW_NW; w++) {
-        i64 k2 = S.red[2 * w];
-        u64 p2 = (u64)S.red[2 * w + 1];
-        if (k2 > key || (k2 == key && p2 < pair)) {
-            key = k2;
-            pair = p2;
-        }
-    }
-    __syncthreads();
-}
-
-// wg_best plus the OR of one flag per thread, in the same two barriers.
+// Best (key desc, pair asc) over the workgroup plus the OR of one flag per
+// thread, with one barrier.  It relies on its caller for the other two: every
+// earlier reader of S.red has passed a barrier since (the other reductions end
+// with one, and the split loop passes one between two calls), and no thread
+// writes S.red again before the next barrier.
 __device__ __forceinline__ void wg_best_or(i64 &key, u64 &pair, int &flag, PwShared &S)
 {
 #pragma unroll
@@ -270,7 +242,6 @@ __device__ __forceinline__ void wg_best_or(i64 &key, u64 &pair, int &flag, PwSha
         }
     }
     const int wid = threadIdx.x / 64;
-    __syncthreads();
     if ((threadIdx.x & 63) == 0) {
         S.red[2 * wid] = key;
         S.red[2 * wid + 1] = (i64)pair;
@@ -289,7 +260,6 @@ __device__ __forceinline__ void wg_best_or(i64 &key, u64 &pair, int &flag, PwSha
             pair = p2;
         }
     }
-    __syncthreads();
 }
 
 // Exclusive scan of one value per thread over the workgroup; *total = sum.
@@ -925,12 +895,15 @@ __global__ __launch_bounds__(PW_BS) void k_positive_wg(PosArgs A)
                     const i32 u = S.cand[i];
                     int4 cv;
                     if (fl & CF_DIRTY) {
-                        if (A.part[u] != pid) {
+                        // the part id and the terms are loaded together
+                        // (all in bounds for any node id)
+                        const i32 pu = A.part[u];
+                        cv = make_int4(A.subk[u], A.cut[u], A.win[u],
+                                       G.k[u] | (cyc[u] ? (i32)0x80000000 : 0));
+                        if (pu != pid) {
                             S.cflag[i] = CF_GONE;
                             continue;
                         }
-                        cv = make_int4(A.subk[u], A.cut[u], A.win[u],
-                                       G.k[u] | (cyc[u] ? (i32)0x80000000 : 0));
                         CV[i] = cv;
                         S.cflag[i] = 0;
                     } else {
@@ -1045,7 +1018,8 @@ __global__ __launch_bounds__(PW_BS) void k_positive_wg(PosArgs A)
             const i64 sx = A.subk[x];
             const bool leaf = A.chc[x] == 0;  // a node without children is T_x by itself
             const i64 rpx0 = G.rp[x], rpx1 = G.rp[x + 1];
-            const int dpx = A.dep[px];
+            // x is no cycle node, so its parent is in the part one level up
+            const int dpx = A.dep[x] - 1;
             // T_x in level order: TMP[0..t)
             if (threadIdx.x == 0) {
                 TMP[0] = x;
@@ -1122,7 +1096,11 @@ __global__ __launch_bounds__(PW_BS) void k_positive_wg(PosArgs A)
                     v = tcount == 1 ? x : TMP[slot];
                     int2 ed = G.e[(tcount == 1 ? rpx0 : G.rp[v]) + (t - d0)];
                     i32 u = ed.x;
-                    if (A.part[u] == pid) {
+                    // u's part id, depth and parent in one round of loads
+                    // (in bounds for any node id)
+                    const i32 pu = A.part[u], au = a[u];
+                    const int du = A.dep[u];
+                    if (pu == pid) {
                         val = ed.y;
                         const i32 A_ = ed.y;
                         atomicSub(&A.win[u], A_);
@@ -1133,8 +1111,15 @@ __global__ __launch_bounds__(PW_BS) void k_positive_wg(PosArgs A)
                         // loaded, and each step loads the next node before
                         // its candidate add
                         i32 p1 = u, p2 = px;
-                        int d1 = A.dep[u], d2 = dpx;
+                        int d1 = du, d2 = dpx;
                         int guard = 0;
+                        if (d1 > d2) {  // the first step up from u
+                            guard++;
+                            atomicSub(&A.cut[p1], A_);
+                            pw_add_cand(S, p1);
+                            p1 = au;
+                            d1--;
+                        }
                         while (d1 > d2 && guard++ < 2 * m) {
                             const i32 n1 = a[p1];
                             atomicSub(&A.cut[p1], A_);
