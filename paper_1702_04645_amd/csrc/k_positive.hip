@@ -180,8 +180,10 @@ __device__ __forceinline__ void pw_add_cand(PwShared &S, i32 v)
     S.cand_over = 1;  // table full (not reached: it has room for every add)
 }
 
-// A candidate that leaves the part with a cut-off subtree (no add runs
-// concurrently, so the table and its indices are settled).
+// A candidate that leaves the part with a cut-off subtree.  Adds of other
+// nodes may run concurrently (the entry pass of a one-node cut); v itself is
+// never being added then, and its slot and index were settled by an earlier
+// barrier, so a probe either finds them or ends at an empty slot.
 __device__ __forceinline__ void pw_drop_cand(PwShared &S, i32 v)
 {
     u32 h = pw_ct_hash(v);
@@ -1029,7 +1031,13 @@ __global__ __launch_bounds__(PW_BS) void k_positive_wg(PosArgs A)
                 A.part[x] = x;
                 pw_drop_cand(S, x);
             }
-            __syncthreads();
+            // a cut of a node without children goes on without a barrier:
+            // its entry pass reads nothing that thread 0 writes here (it skips
+            // x by id, and no path correction reaches a node without
+            // children), and x's own root, parent and cycle mark, which other
+            // threads may still be loading, are written after the split's last
+            // barrier; leaf is the same in every thread
+            if (!leaf) __syncthreads();
             while (!leaf) {
                 const int lb = S.head, le = S.lev_end;
                 if (lb == le) break;
@@ -1053,11 +1061,13 @@ __global__ __launch_bounds__(PW_BS) void k_positive_wg(PosArgs A)
                 }
                 __syncthreads();
             }
-            const int tcount = S.tail;
-            for (int i = threadIdx.x; i < tcount; i += PW_BS) A.root[TMP[i]] = x;
+            const int tcount = leaf ? 1 : S.tail;
+            if (!leaf)
+                for (int i = threadIdx.x; i < tcount; i += PW_BS) A.root[TMP[i]] = x;
             // The ancestors of x lose S_{T_x}; the last thread walks them while
             // the others take the entries below.  The two touch disjoint data:
-            // the walk writes subk, a[x] and cyc[x], and the entry pass reads
+            // the walk writes subk (and a[x] and cyc[x] when x has children),
+            // and the entry pass reads
             // only nodes outside T_x and paths that never reach x (nothing
             // else there writes subk).  A cut of more than one node computes a
             // degree prefix first, whose barriers the walk precedes.
@@ -1077,8 +1087,10 @@ __global__ __launch_bounds__(PW_BS) void k_positive_wg(PosArgs A)
                     if (top) break;
                     yv = ny;
                 }
-                a[x] = x;
-                cyc[x] = 1;
+                if (!leaf) {
+                    a[x] = x;
+                    cyc[x] = 1;
+                }
             }
             // entries between T_x and the rest of the part (a single node's
             // entries need no degree prefix)
@@ -1100,7 +1112,7 @@ __global__ __launch_bounds__(PW_BS) void k_positive_wg(PosArgs A)
                     // (in bounds for any node id)
                     const i32 pu = A.part[u], au = a[u];
                     const int du = A.dep[u];
-                    if (pu == pid) {
+                    if (u != x && pu == pid) {
                         val = ed.y;
                         const i32 A_ = ed.y;
                         atomicSub(&A.win[u], A_);
@@ -1172,6 +1184,11 @@ __global__ __launch_bounds__(PW_BS) void k_positive_wg(PosArgs A)
                 S.sig = sig - sx;
             }
             __syncthreads();
+            if (leaf && threadIdx.x == 0) {
+                A.root[x] = x;
+                a[x] = x;
+                cyc[x] = 1;
+            }
         }
         // the subtrees cut off this part take their ranges inside it
         if (threadIdx.x == 0) pw_assign(STK, S.sp0, S.sp, s);
