@@ -1950,17 +1950,28 @@ static slm_graph *make_engine(i64 cap_n, i64 cap_e, int cap_m, hipStream_t s,
     return g;
 }
 
-// A failed level leaves the lane's graphs undefined: fail all of them.
-static void lane_fail(slm_server *sv, Lane *L, const std::string &msg)
+// A failed level leaves the lane's graphs undefined: fail all of them, the
+// resident ones, those taken from the queue but not yet in the union (`add`)
+// and those that finished the level but were not handed over yet (`done`).
+// A step that failed while moving members between these lists leaves
+// moved-from entries behind, which keep their ticket and result pointer, so
+// a ticket can appear in two lists: each is failed and its result freed once.
+static void lane_fail(slm_server *sv, Lane *L, std::vector<Member> &add, std::vector<Member> &done,
+                      const std::string &msg)
 {
     slm_graph *g = L->eng;
     std::lock_guard<std::mutex> lk(sv->mu);
-    for (Member &m : g->mem) {
-        if (sv->cancel_req.erase(m.ticket)) sv->cancelled.insert(m.ticket);
-        else sv->failed[m.ticket] = msg;
-        delete m.res;
-    }
+    std::unordered_set<u64> seen;
+    for (std::vector<Member> *list : {&g->mem, &add, &done})
+        for (Member &m : *list) {
+            if (!m.res || !seen.insert(m.ticket).second) continue;
+            if (sv->cancel_req.erase(m.ticket)) sv->cancelled.insert(m.ticket);
+            else sv->failed[m.ticket] = msg;
+            delete m.res;
+        }
     g->mem.clear();
+    add.clear();
+    done.clear();
     g->G = 0;
     L->dead = true;
     // with no live lane left for its class, the class queue fails too
@@ -1983,10 +1994,10 @@ static void lane_loop(slm_server *sv, Lane *L)
 {
     (void)hipSetDevice(sv->device);
     slm_graph *g = L->eng;
-    std::vector<Member> done;
+    std::vector<Member> add, done;
     try {
         while (true) {
-            std::vector<Member> add;
+            add.clear();
             {
                 std::unique_lock<std::mutex> lk(sv->mu);
                 sv->cv_work.wait(lk, [&] { return sv->stop || !L->queue->empty() || g->G > 0; });
@@ -2049,9 +2060,9 @@ static void lane_loop(slm_server *sv, Lane *L)
             }
         }
     } catch (const SlmError &e) {
-        lane_fail(sv, L, e.msg);
+        lane_fail(sv, L, add, done, e.msg);
     } catch (const std::exception &e) {
-        lane_fail(sv, L, std::string("host failure: ") + e.what());
+        lane_fail(sv, L, add, done, std::string("host failure: ") + e.what());
     }
 }
 
