@@ -205,6 +205,26 @@ def _ptr(t):
     return C.c_void_p(t.data_ptr())
 
 
+def _on_stream(stream, fn, *args, tensors=()):
+    """Runs library call fn(*args), whose device work goes to ``stream``,
+    ordered against torch's current stream when the two differ: ``stream``
+    first waits for the work queued on the current stream (which made the
+    inputs), and the current stream then waits for ``stream`` (whose work
+    writes the outputs); ``tensors`` are marked as used on ``stream``, so the
+    caching allocator does not hand their memory out again before that work
+    is done."""
+    torch = _torch()
+    cur = torch.cuda.current_stream()
+    other = stream is not None and stream != cur
+    if other:
+        stream.wait_stream(cur)
+    _check(fn(*args))
+    if other:
+        for t in tensors:
+            t.record_stream(stream)
+        cur.wait_stream(stream)
+
+
 @dataclass
 class LevelResult:
     labels: np.ndarray
@@ -252,6 +272,8 @@ class Graph:
         if stream is None:
             stream = torch.cuda.current_stream()
         self.stream = stream
+        if on_dev and stream != torch.cuda.current_stream():
+            stream.wait_stream(torch.cuda.current_stream())  # the inputs were made there
         if model is None:
             _check(lib().slm_create(n, nnz, args[0], rp_bytes, args[1], args[2], int(on_dev),
                                     int(validate), C.c_void_p(stream.cuda_stream),
@@ -305,7 +327,7 @@ class Graph:
     def assign(self):
         n = self.level_info()["n"]
         a = _dev_i32(n)
-        _check(lib().slm_assign(self._h, _ptr(a)))
+        _on_stream(self.stream, lib().slm_assign, self._h, _ptr(a), tensors=(a,))
         return a[:n]
 
     def components(self, a):
@@ -315,14 +337,15 @@ class Graph:
         lab = _dev_i32(n)
         cyc = torch.empty(max(n, 1), dtype=torch.uint8, device="cuda")
         nc = C.c_int64()
-        _check(lib().slm_components(self._h, _ptr(a), _ptr(lab), _ptr(cyc), C.byref(nc)))
+        _on_stream(self.stream, lib().slm_components, self._h, _ptr(a), _ptr(lab), _ptr(cyc),
+                   C.byref(nc), tensors=(a, lab, cyc))
         return lab[:n], nc.value, cyc[:n]
 
     def positive(self, a):
         torch = _torch()
         a = a.to(torch.int32).clone()
         sp = C.c_int64()
-        _check(lib().slm_positive(self._h, _ptr(a), C.byref(sp)))
+        _on_stream(self.stream, lib().slm_positive, self._h, _ptr(a), C.byref(sp), tensors=(a,))
         return a, sp.value
 
     def sweep(self, lab, nc: int):
@@ -332,35 +355,38 @@ class Graph:
         best = _dev_i32(n)
         delta = torch.empty(max(n, 1), dtype=torch.int64, device="cuda")
         wown = _dev_i32(n)
-        _check(lib().slm_sweep(self._h, _ptr(lab), int(nc), _ptr(best), _ptr(delta), _ptr(wown)))
+        _on_stream(self.stream, lib().slm_sweep, self._h, _ptr(lab), int(nc), _ptr(best),
+                   _ptr(delta), _ptr(wown), tensors=(lab, best, delta, wown))
         return best[:n], delta[:n], wown[:n]
 
     def round(self, a, p: Params, level: int, rnd: int):
         torch = _torch()
         a = a.to(torch.int32).clone()
         st = (C.c_int64 * 4)()
-        _check(lib().slm_round(self._h, C.byref(p), level, rnd, _ptr(a), st))
+        _on_stream(self.stream, lib().slm_round, self._h, C.byref(p), level, rnd, _ptr(a), st,
+                   tensors=(a,))
         return a, dict(candidates=st[0], valid=st[1], accepted=st[2], splits=st[3])
 
     def level(self, p: Params, level: int):
         n = self.level_info()["n"]
         lab = _dev_i32(n)
         nc, r, cv = C.c_int64(), C.c_int32(), C.c_int32()
-        _check(lib().slm_level(self._h, C.byref(p), level, _ptr(lab), C.byref(nc), C.byref(r),
-                               C.byref(cv)))
+        _on_stream(self.stream, lib().slm_level, self._h, C.byref(p), level, _ptr(lab),
+                   C.byref(nc), C.byref(r), C.byref(cv), tensors=(lab,))
         return lab[:n], nc.value, r.value, bool(cv.value)
 
     def modularity(self, lab, nc: int):
         torch = _torch()
         lab = lab.to(torch.int32).contiguous()
         nq, q = C.c_int64(), C.c_double()
-        _check(lib().slm_modularity(self._h, _ptr(lab), int(nc), C.byref(nq), C.byref(q)))
+        _on_stream(self.stream, lib().slm_modularity, self._h, _ptr(lab), int(nc), C.byref(nq),
+                   C.byref(q), tensors=(lab,))
         return nq.value, q.value
 
     def contract(self, lab, nc: int):
         torch = _torch()
         lab = lab.to(torch.int32).contiguous()
-        _check(lib().slm_contract(self._h, _ptr(lab), int(nc)))
+        _on_stream(self.stream, lib().slm_contract, self._h, _ptr(lab), int(nc), tensors=(lab,))
 
     def run(self, p: Params | None = None):
         if p is None:
@@ -377,8 +403,8 @@ class Graph:
         n = self.level_info()["n"]
         lab = _dev_i32(n)
         nc, ps, cv = C.c_int64(), C.c_int32(), C.c_int32()
-        _check(lib().slm_louvain_level(self._h, C.byref(p), _ptr(lab), C.byref(nc),
-                                       C.byref(ps), C.byref(cv)))
+        _on_stream(self.stream, lib().slm_louvain_level, self._h, C.byref(p), _ptr(lab),
+                   C.byref(nc), C.byref(ps), C.byref(cv), tensors=(lab,))
         return lab[:n], nc.value, ps.value, bool(cv.value)
 
     def louvain_run(self, p: Params | None = None):
@@ -619,7 +645,7 @@ def modularity_noalloc(row_ptr, col, w, lab, nc: int, stream=None):
     if lab.numel() < n:
         raise ValueError("lab holds fewer than n labels")
     nq, q = C.c_int64(), C.c_double()
-    _check(lib().slm_modularity_noalloc(n, col.numel(), _ptr(row_ptr), _ptr(col), _ptr(w),
-                                        _ptr(lab), int(nc), C.byref(nq), C.byref(q),
-                                        C.c_void_p(stream.cuda_stream)))
+    _on_stream(stream, lib().slm_modularity_noalloc, n, col.numel(), _ptr(row_ptr), _ptr(col),
+               _ptr(w), _ptr(lab), int(nc), C.byref(nq), C.byref(q),
+               C.c_void_p(stream.cuda_stream), tensors=(row_ptr, col, w, lab))
     return nq.value, q.value
