@@ -67,13 +67,19 @@ def measured_traffic(workload: str):
     return round(rec["sweep_traffic_bytes"] / 1e9, 4)
 
 
-def tuned_options(workload: str):
-    """Sweep launch options the autotuner picked for this workload, if kept."""
-    path = os.path.join(ROOT, "paper_1702_04645_amd", "tuned", "%s.json" % workload)
-    if not os.path.exists(path):
-        return None
-    with open(path) as f:
-        return json.load(f)["options"]
+def tuned_options(row_ptr, arch=None):
+    """(options, file) that the autotuner kept for this GPU architecture and
+    this graph's degree profile, or (None, None): then the library defaults
+    stand.  arch: the current GPU's when not given.  A cache that cannot be
+    read never stops the bench."""
+    from paper_1702_04645_amd import autotune
+    try:
+        if arch is None:
+            arch = autotune.device_arch()
+        return autotune.find(row_ptr, arch)
+    except Exception as e:  # noqa: BLE001
+        log("tuned launch options not read (%s): library defaults" % e)
+        return None, None
 
 
 def workload(name: str):
@@ -634,7 +640,8 @@ def main():
     ap.add_argument("--no-extras", action="store_true",
                     help="only the sweep line: no batched and served measurements")
     ap.add_argument("--no-tune", action="store_true",
-                    help="library default launch options (no tuned/<workload>.json)")
+                    help="library default launch options (no autotuned values for this "
+                         "device and degree profile)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy 1 GiB device to device (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -690,11 +697,11 @@ def main():
     params = slm.params(seed=args.seed)
     g = slm.Graph(rp, col, w)
     info = g.level_info()
-    tuned = tuned_options(args.workload) if not args.no_tune else None
+    tuned, tuned_file = tuned_options(rp) if not args.no_tune else (None, None)
     if tuned:
         from paper_1702_04645_amd import autotune
         autotune.apply(g, tuned)
-        log("launch options from tuned/%s.json" % args.workload)
+        log("launch options from %s" % os.path.relpath(tuned_file, ROOT))
     first = first_sweep(g, nnz, n)
     log("first level-0 sweep: %.4f ms" % first["ms"])
     single = singleton_sweep(g, nnz, n)

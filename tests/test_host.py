@@ -1,6 +1,7 @@
 """Host-side logic that needs no device: the launch autotuner's walk (on a
-stand-in handle), its JSON round trip, the benchmark's single-GPU guard and
-the gate that keeps a stale HBM-traffic record out of the bench line."""
+stand-in handle), its JSON round trip, its cache keyed by GPU architecture
+and degree profile, the benchmark's single-GPU guard and the gate that keeps
+a stale HBM-traffic record out of the bench line."""
 import json
 import os
 import subprocess
@@ -103,9 +104,64 @@ def test_traffic_record_is_gated_on_the_sweep_sources(monkeypatch):
     assert bench.measured_traffic("no_such_workload") is None
 
 
-def test_tuned_options_name_known_options():
-    import bench
+def test_degree_profile():
     from paper_1702_04645_amd import autotune
-    opts = bench.tuned_options("rmat20")
+    # degrees 0, 3, 2, 0, 100: 5 entries in the bin of rows up to 8, 100 in
+    # the bin of rows of 65..128
+    p = autotune.degree_profile(np.array([0, 0, 3, 5, 5, 105]))
+    assert p == {"entries_log2": 7, "bin_shares": [0, 1, 0, 0, 19, 0, 0, 0, 0, 0, 0]}
+    # a bin's upper limit belongs to it; a row above 4096 is a hub
+    p = autotune.degree_profile(np.array([0, 8, 16, 4112]))
+    assert p["bin_shares"] == [0, 0, 0, 0, 0, 0, 0, 0, 0, 20, 0]
+    p = autotune.degree_profile(np.array([0, 8, 16, 4113]))
+    assert p["bin_shares"] == [0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 20]
+    p = autotune.degree_profile(np.array([0, 8, 16]))
+    assert p["bin_shares"] == [0, 20, 0, 0, 0, 0, 0, 0, 0, 0, 0]
+    assert autotune.degree_profile(np.array([0, 0]))["entries_log2"] == 0
+    assert autotune.profile_key(np.array([0, 8, 16]), "gfx950") == "gfx950|e4|0,20,0,0,0,0,0,0,0,0,0"
+
+
+def test_kept_tuned_files_are_keyed():
+    from paper_1702_04645_amd import autotune
+    d = os.path.join(ROOT, "paper_1702_04645_amd", "tuned")
+    names = sorted(os.listdir(d))
+    assert names
+    for name in names:
+        rec = autotune.load(os.path.join(d, name))
+        assert autotune.cache_path(rec["key"], d) == os.path.join(d, name)
+        p = rec["profile"]
+        assert rec["key"] == "%s|e%d|%s" % (rec["arch"], p["entries_log2"],
+                                           ",".join(str(x) for x in p["bin_shares"]))
+        assert set(rec["options"]) == set(autotune.CANDIDATES)
+        for k, v in rec["options"].items():
+            assert v in autotune.CANDIDATES[k]
+
+
+def test_tuned_options_are_keyed_by_device_and_degree_profile(tmp_path, monkeypatch):
+    import bench
+    import graphgen as gg
+    from paper_1702_04645_amd import autotune
+    monkeypatch.delenv("SLM_TUNE_CACHE", raising=False)
+    rp = gg.config_graph("rmat20")[0]
+    opts, path = bench.tuned_options(rp, arch="gfx950")
     assert opts and set(opts) <= set(autotune.CANDIDATES)
-    assert bench.tuned_options("no_such_workload") is None
+    assert autotune.load(path)["workload"] == "rmat20"
+    assert bench.tuned_options(rp, arch="gfx942") == (None, None)
+    small = gg.config_graph("sbm4096")[0]
+    assert bench.tuned_options(small, arch="gfx950") == (None, None)
+    # a cache folder of the caller's: SLM_TUNE_CACHE
+    monkeypatch.setenv("SLM_TUNE_CACHE", str(tmp_path))
+    assert bench.tuned_options(rp, arch="gfx950") == (None, None)
+    res = {"options": dict(autotune.DEFAULTS, grid_512=512), "us": 1.0, "us_default": 2.0}
+    p = autotune.save_keyed(small, "gfx950", res, workload="sbm4096")
+    assert os.path.dirname(p) == str(tmp_path)
+    assert bench.tuned_options(small, arch="gfx950") == (res["options"], p)
+    # a file whose key is not the graph's is not used
+    rec = autotune.load(p)
+    rec["key"] = rec["key"] + ",0"
+    autotune.save(p, rec)
+    assert autotune.find(small, "gfx950") == (None, None)
+    # an unreadable cache leaves the library defaults
+    with open(p, "w") as f:
+        f.write("{")
+    assert bench.tuned_options(small, arch="gfx950") == (None, None)
